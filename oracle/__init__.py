@@ -1,0 +1,198 @@
+"""FP64 CPU oracle for the differentiable Gaussian rasterizer and the camera ODE.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py`` may import this package.  It shares
+no code with the HIP path (``paper_2501_04782_amd``) and imports nothing from
+it; the only module both sides use is ``gv_synth`` (seeded input draws).
+
+* ``gvo_raster.c``: the tile-free, per-pixel definition of 3D Gaussian
+  splatting image formation (paper Sec. 3.1) and its adjoint, in FP64.
+* ``camera_ode.py``: the camera-motion Neural ODE (Eq. 1, Sec. 3.4) with RK4
+  and its discrete adjoint, in FP64 numpy.
+* this file: ctypes marshalling around ``gvo_raster.c``, a clip loop and the
+  L2 loss of Sec. 4.1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import camera_ode  # noqa: F401  (re-export)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+class _Frame(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("means", _dp), ("log_scales", _dp), ("quats", _dp), ("opacity_logits", _dp),
+        ("colors", _dp), ("mean_coeffs", _dp),
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+        ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+        ("near_plane", ctypes.c_double), ("dilation", ctypes.c_double),
+        ("bg", ctypes.c_double * 3), ("pose", ctypes.c_double * 7), ("t", ctypes.c_double),
+    ]
+
+
+class _Grads(ctypes.Structure):
+    _fields_ = [("means", _dp), ("log_scales", _dp), ("quats", _dp), ("opacity_logits", _dp),
+                ("colors", _dp), ("mean_coeffs", _dp), ("pose", _dp)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.gvo_project.argtypes = [ctypes.POINTER(_Frame), _dp]
+        lib.gvo_project.restype = ctypes.c_int
+        lib.gvo_render.argtypes = [ctypes.POINTER(_Frame), ctypes.c_int64, _i64p, _dp, _dp, _i64p, _dp,
+                                   _dp, ctypes.POINTER(_Grads), ctypes.c_int]
+        lib.gvo_render.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def scene_f64(scene) -> dict:
+    """Accept a gv_synth.Scene or a dict of arrays; return contiguous FP64 arrays."""
+    d = scene.as_f64() if hasattr(scene, "as_f64") else dict(scene)
+    out = {}
+    for k in ("means", "log_scales", "quats", "opacity_logits", "colors"):
+        out[k] = np.ascontiguousarray(np.asarray(d[k], dtype=np.float64))
+    mc = d.get("mean_coeffs")
+    out["mean_coeffs"] = None if mc is None else np.ascontiguousarray(np.asarray(mc, dtype=np.float64))
+    return out
+
+
+def _frame(s: dict, cam, pose7, t: float):
+    fr = _Frame()
+    fr.n = int(s["opacity_logits"].shape[0])
+    fr.means, fr.log_scales, fr.quats = _ptr(s["means"]), _ptr(s["log_scales"]), _ptr(s["quats"])
+    fr.opacity_logits, fr.colors = _ptr(s["opacity_logits"]), _ptr(s["colors"])
+    fr.mean_coeffs = _ptr(s["mean_coeffs"])
+    fr.width, fr.height = int(cam.width), int(cam.height)
+    fr.fx, fr.fy, fr.cx, fr.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    fr.near_plane, fr.dilation = float(cam.near_plane), float(cam.dilation)
+    for k in range(3):
+        fr.bg[k] = float(cam.bg[k])
+    pose7 = np.asarray(pose7, dtype=np.float64).reshape(7)
+    for k in range(7):
+        fr.pose[k] = float(pose7[k])
+    fr.t = float(t)
+    return fr
+
+
+PROJECT_FIELDS = ["valid", "u", "v", "cov00", "cov01", "cov11", "A00", "A01", "A11", "depth", "key",
+                  "opacity", "Sxx", "Sxy", "Sxz", "Syy", "Syz", "Szz", "mx", "my"]
+
+
+def project(scene, cam, pose7, t: float = 0.0) -> dict:
+    """Per-Gaussian projection (mean, EWA covariance, conic, depth, opacity)."""
+    s = scene_f64(scene)
+    fr = _frame(s, cam, pose7, t)
+    out = np.zeros((fr.n, 24))
+    _load().gvo_project(ctypes.byref(fr), _ptr(out))
+    return {k: out[:, i] for i, k in enumerate(PROJECT_FIELDS)}
+
+
+def zero_grads(scene) -> dict:
+    s = scene_f64(scene)
+    n = s["opacity_logits"].shape[0]
+    g = dict(means=np.zeros((3, n)), log_scales=np.zeros((3, n)), quats=np.zeros((4, n)),
+             opacity_logits=np.zeros(n), colors=np.zeros((3, n)), pose=np.zeros(7))
+    g["mean_coeffs"] = None if s["mean_coeffs"] is None else np.zeros((3, 3, n))
+    return g
+
+
+def render_frame(scene, cam, pose7, t: float = 0.0, pixels: Optional[np.ndarray] = None,
+                 dL_dC: Optional[np.ndarray] = None, grads: Optional[dict] = None,
+                 threads: int = 0) -> dict:
+    """Render one frame at the listed pixels (linear y*W+x; None = all).
+
+    Returns color [P][3], T_final [P], n_contrib [P], margins [P][4] and, when
+    dL_dC [P][3] is given, the gradient dict (accumulated into ``grads`` if
+    passed) of sum_p dL_dC[p] . C[p].
+    """
+    s = scene_f64(scene)
+    fr = _frame(s, cam, pose7, t)
+    if pixels is None:
+        npx = int(cam.width) * int(cam.height)
+        pix_p = None
+    else:
+        pixels = np.ascontiguousarray(np.asarray(pixels, dtype=np.int64))
+        npx = int(pixels.shape[0])
+        assert npx == 0 or (pixels.min() >= 0 and pixels.max() < cam.width * cam.height)
+        pix_p = pixels.ctypes.data_as(_i64p)
+    color = np.zeros((npx, 3))
+    T = np.zeros(npx)
+    nc = np.zeros(npx, np.int64)
+    mg = np.zeros((npx, 4))
+    gstruct = None
+    dl = None
+    if dL_dC is not None:
+        dl = np.ascontiguousarray(np.asarray(dL_dC, dtype=np.float64).reshape(npx, 3))
+        if grads is None:
+            grads = zero_grads(s)
+        gstruct = _Grads(_ptr(grads["means"]), _ptr(grads["log_scales"]), _ptr(grads["quats"]),
+                         _ptr(grads["opacity_logits"]), _ptr(grads["colors"]), _ptr(grads["mean_coeffs"]),
+                         _ptr(grads["pose"]))
+    rc = _load().gvo_render(ctypes.byref(fr), npx, pix_p, _ptr(color), _ptr(T), nc.ctypes.data_as(_i64p),
+                            _ptr(mg), _ptr(dl), ctypes.byref(gstruct) if gstruct is not None else None,
+                            int(threads))
+    if rc != 0:
+        raise RuntimeError(f"gvo_render failed with code {rc}")
+    out = dict(color=color, T_final=T, n_contrib=nc, margins=mg)
+    if dl is not None:
+        out["grads"] = grads
+    return out
+
+
+def render_image(scene, cam, pose7, t: float = 0.0, threads: int = 0) -> dict:
+    """Whole frame as planar arrays: image [3][H][W], T_final [H][W], margins [H][W][4]."""
+    r = render_frame(scene, cam, pose7, t, threads=threads)
+    H, W = int(cam.height), int(cam.width)
+    return dict(image=r["color"].T.reshape(3, H, W).copy(), T_final=r["T_final"].reshape(H, W),
+                n_contrib=r["n_contrib"].reshape(H, W), margins=r["margins"].reshape(H, W, 4))
+
+
+def l2_loss_and_grad(images: np.ndarray, targets: np.ndarray):
+    """Standard L2 reconstruction loss (Sec. 4.1), read as the mean over all
+    frames, channels and pixels, and its gradient w.r.t. the images."""
+    images = np.asarray(images, np.float64)
+    targets = np.asarray(targets, np.float64)
+    diff = images - targets
+    return float(np.mean(diff * diff)), 2.0 * diff / diff.size
+
+
+def render_clip_grads(scene, cam, poses: np.ndarray, times: Sequence[float], frames: Sequence[int],
+                      pixels: Sequence[np.ndarray], dL_dC: Sequence[np.ndarray], threads: int = 0):
+    """Sum over the listed frames of the gradient of sum_p dL_dC[f][p] . C_f[p]
+    (shared parameters summed over frames, poses per frame)."""
+    grads = zero_grads(scene)
+    dposes = np.zeros((len(poses), 7))
+    colors = []
+    for f, pix, dl in zip(frames, pixels, dL_dC):
+        grads["pose"][:] = 0.0
+        r = render_frame(scene, cam, poses[f], float(times[f]), pixels=pix, dL_dC=dl, grads=grads,
+                         threads=threads)
+        dposes[f] = grads["pose"]
+        colors.append(r["color"])
+    grads["pose"] = None
+    return grads, dposes, colors

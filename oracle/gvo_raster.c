@@ -1,0 +1,574 @@
+/*
+ * gvo_raster.c -- FP64 reference ("oracle") for 3D Gaussian splatting image
+ * formation and its adjoint.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link, load or
+ * call this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code with the HIP kernels.
+ *
+ * What it computes (paper Sec. 3.1: Gaussians with mean mu, covariance
+ * Sigma = (RS)(RS)^T, colour c and opacity o are projected and rasterized onto
+ * the image plane and fitted by a reconstruction loss; the rasterizer itself is
+ * the one of 3D Gaussian Splatting, which the paper cites).  The plain,
+ * tile-free definition is written out, per pixel, with no binning:
+ *
+ *   1. mu(t) = mu0 + a1 t + a2 t^2 + a3 t^3 when cubic coefficients are given
+ *      (the polynomial motion basis of Sec. 3.2, Fig. 3 / Tab. 2).
+ *   2. s = exp(log_scale), qhat = q/|q|, R = R(qhat) (w first),
+ *      o = 1/(1+exp(-eta)), Sigma = R diag(s)^2 R^T          (Sec. 3.1)
+ *   3. camera: world->camera rotation Rc = R(qc/|qc|), translation tc;
+ *      m = Rc mu + tc; the Gaussian is dropped if m_z <= near_plane.
+ *   4. (u,v) = (fx m_x/m_z + cx, fy m_y/m_z + cy);  J = d(u,v)/dm;
+ *      Sigma' = J Rc Sigma Rc^T J^T + dilation * I2  (EWA local affine
+ *      approximation of the perspective map, plus a low-pass term);
+ *      dropped if det(Sigma') <= 0;  A = Sigma'^{-1} (the conic).
+ *   5. order = ascending (fp32 rounding of m_z, Gaussian index).
+ *   6. per pixel centre p = (x + 1/2, y + 1/2): T = 1, C = 0; for each
+ *      Gaussian in order: d = p - (u,v); q = d^T A d; skip if q > 9;
+ *      alpha = min(0.99, o exp(-q/2)); skip if alpha < 1/255;
+ *      stop (without blending it) if T (1 - alpha) < 1e-4;
+ *      C += c alpha T; T *= 1 - alpha.   Finally C += T * bg.
+ *
+ * Adjoint: given dL/dC at some pixels, the contributor list of each pixel is
+ * walked back to front with the stored transmittances (no division), then
+ * the chain rule is taken through step 4..1 in closed matrix form.  Skip and
+ * stop decisions and the alpha clamp are piecewise constants (their
+ * derivative is zero).  Gradients are with respect to the stored parameters:
+ * means (or mu0 and a1..a3), log-scales, unnormalised quaternions, opacity
+ * logits, colours, and the 7-vector pose (qc unnormalised, tc).
+ *
+ * Per pixel the oracle also reports how close each discrete decision came to
+ * its threshold (relative margins), so that comparisons against an FP32
+ * implementation can set aside pixels whose outcome is decided by rounding.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int64_t n;
+    const double *means;          /* [3][n] (mu0 when cubic) */
+    const double *log_scales;     /* [3][n] */
+    const double *quats;          /* [4][n] w,x,y,z */
+    const double *opacity_logits; /* [n] */
+    const double *colors;         /* [3][n] */
+    const double *mean_coeffs;    /* NULL or [3 coeff][3 xyz][n] */
+    int32_t width, height;
+    double fx, fy, cx, cy, near_plane, dilation;
+    double bg[3];
+    double pose[7];               /* world->camera qw qx qy qz tx ty tz */
+    double t;                     /* frame time for the cubic mean */
+} gvo_frame;
+
+typedef struct {
+    double *means, *log_scales, *quats, *opacity_logits, *colors, *mean_coeffs, *pose;
+} gvo_grads;
+
+typedef struct {
+    int valid;
+    double mu[3], s[3], qhat[4], qnorm;
+    double R[3][3], M[3][3], Sigma[3][3];
+    double m[3], J[2][3], T[2][3];
+    double cov[2][2], A[2][2];
+    double u, v, o;
+    float key;
+} proj_t;
+
+typedef struct {
+    double Rc[3][3], qc_hat[4], qc_norm, tc[3];
+} cam_t;
+
+/* ------------------------------------------------------------------ */
+/* small dense helpers                                                 */
+/* ------------------------------------------------------------------ */
+
+/* Rotation matrix of a unit quaternion (w, x, y, z). */
+static void quat_to_rot(const double q[4], double R[3][3])
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0][0] = 1 - 2 * (y * y + z * z); R[0][1] = 2 * (x * y - w * z);     R[0][2] = 2 * (x * z + w * y);
+    R[1][0] = 2 * (x * y + w * z);     R[1][1] = 1 - 2 * (x * x + z * z); R[1][2] = 2 * (y * z - w * x);
+    R[2][0] = 2 * (x * z - w * y);     R[2][1] = 2 * (y * z + w * x);     R[2][2] = 1 - 2 * (x * x + y * y);
+}
+
+/* dR/dq_k of the map above, for k = w, x, y, z. */
+static void quat_to_rot_partials(const double q[4], double D[4][3][3])
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    memset(D, 0, sizeof(double) * 36);
+    /* d/dw */
+    D[0][0][1] = -2 * z; D[0][0][2] = 2 * y;
+    D[0][1][0] = 2 * z;  D[0][1][2] = -2 * x;
+    D[0][2][0] = -2 * y; D[0][2][1] = 2 * x;
+    /* d/dx */
+    D[1][0][1] = 2 * y;  D[1][0][2] = 2 * z;
+    D[1][1][0] = 2 * y;  D[1][1][1] = -4 * x; D[1][1][2] = -2 * w;
+    D[1][2][0] = 2 * z;  D[1][2][1] = 2 * w;  D[1][2][2] = -4 * x;
+    /* d/dy */
+    D[2][0][0] = -4 * y; D[2][0][1] = 2 * x;  D[2][0][2] = 2 * w;
+    D[2][1][0] = 2 * x;  D[2][1][2] = 2 * z;
+    D[2][2][0] = -2 * w; D[2][2][1] = 2 * z;  D[2][2][2] = -4 * y;
+    /* d/dz */
+    D[3][0][0] = -4 * z; D[3][0][1] = -2 * w; D[3][0][2] = 2 * x;
+    D[3][1][0] = 2 * w;  D[3][1][1] = -4 * z; D[3][1][2] = 2 * y;
+    D[3][2][0] = 2 * x;  D[3][2][1] = 2 * y;
+}
+
+/* Gradient of a loss w.r.t. an unnormalised quaternion q, given the gradient
+ * dR w.r.t. R(q/|q|). */
+static void rot_grad_to_quat(const double qhat[4], double qnorm, const double dR[3][3], double dq[4])
+{
+    double D[4][3][3], dqh[4], dot = 0.0;
+    quat_to_rot_partials(qhat, D);
+    for (int k = 0; k < 4; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) acc += D[k][i][j] * dR[i][j];
+        dqh[k] = acc;
+    }
+    for (int k = 0; k < 4; ++k) dot += qhat[k] * dqh[k];
+    for (int k = 0; k < 4; ++k) dq[k] = (dqh[k] - qhat[k] * dot) / qnorm;
+}
+
+static int all_finite(const double *v, int k)
+{
+    for (int i = 0; i < k; ++i)
+        if (!isfinite(v[i])) return 0;
+    return 1;
+}
+
+static void setup_camera(const gvo_frame *fr, cam_t *c, int *ok)
+{
+    double qn = sqrt(fr->pose[0] * fr->pose[0] + fr->pose[1] * fr->pose[1] +
+                     fr->pose[2] * fr->pose[2] + fr->pose[3] * fr->pose[3]);
+    *ok = (qn > 0.0 && isfinite(qn) && all_finite(fr->pose, 7));
+    if (!*ok) return;
+    c->qc_norm = qn;
+    for (int k = 0; k < 4; ++k) c->qc_hat[k] = fr->pose[k] / qn;
+    quat_to_rot(c->qc_hat, c->Rc);
+    for (int k = 0; k < 3; ++k) c->tc[k] = fr->pose[4 + k];
+}
+
+/* Steps 1-4 for Gaussian g. */
+static void project_one(const gvo_frame *fr, const cam_t *c, int64_t g, proj_t *P)
+{
+    const int64_t n = fr->n;
+    double raw[14];
+    memset(P, 0, sizeof(*P));
+    for (int k = 0; k < 3; ++k) raw[k] = fr->means[k * n + g];
+    for (int k = 0; k < 3; ++k) raw[3 + k] = fr->log_scales[k * n + g];
+    for (int k = 0; k < 4; ++k) raw[6 + k] = fr->quats[k * n + g];
+    raw[10] = fr->opacity_logits[g];
+    for (int k = 0; k < 3; ++k) raw[11 + k] = fr->colors[k * n + g];
+    if (!all_finite(raw, 14)) return;
+
+    /* 1. mean at time t */
+    for (int k = 0; k < 3; ++k) {
+        double mu = raw[k];
+        if (fr->mean_coeffs) {
+            double a1 = fr->mean_coeffs[(0 * 3 + k) * n + g];
+            double a2 = fr->mean_coeffs[(1 * 3 + k) * n + g];
+            double a3 = fr->mean_coeffs[(2 * 3 + k) * n + g];
+            if (!isfinite(a1) || !isfinite(a2) || !isfinite(a3)) return;
+            mu = mu + a1 * fr->t + a2 * fr->t * fr->t + a3 * fr->t * fr->t * fr->t;
+        }
+        P->mu[k] = mu;
+    }
+    /* 2. activations and world covariance */
+    P->qnorm = sqrt(raw[6] * raw[6] + raw[7] * raw[7] + raw[8] * raw[8] + raw[9] * raw[9]);
+    if (!(P->qnorm > 0.0)) return;
+    for (int k = 0; k < 4; ++k) P->qhat[k] = raw[6 + k] / P->qnorm;
+    for (int k = 0; k < 3; ++k) P->s[k] = exp(raw[3 + k]);
+    P->o = 1.0 / (1.0 + exp(-raw[10]));
+    quat_to_rot(P->qhat, P->R);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) P->M[i][j] = P->R[i][j] * P->s[j];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += P->M[i][k] * P->M[j][k];
+            P->Sigma[i][j] = acc;
+        }
+    /* 3. camera space */
+    for (int i = 0; i < 3; ++i) {
+        double acc = c->tc[i];
+        for (int k = 0; k < 3; ++k) acc += c->Rc[i][k] * P->mu[k];
+        P->m[i] = acc;
+    }
+    if (!(P->m[2] > fr->near_plane)) return;
+    /* 4. perspective projection of the mean and EWA covariance */
+    double mx = P->m[0], my = P->m[1], mz = P->m[2];
+    P->u = fr->fx * mx / mz + fr->cx;
+    P->v = fr->fy * my / mz + fr->cy;
+    P->J[0][0] = fr->fx / mz; P->J[0][1] = 0.0;        P->J[0][2] = -fr->fx * mx / (mz * mz);
+    P->J[1][0] = 0.0;        P->J[1][1] = fr->fy / mz; P->J[1][2] = -fr->fy * my / (mz * mz);
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += P->J[i][k] * c->Rc[k][j];
+            P->T[i][j] = acc;
+        }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            double acc = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) acc += P->T[i][a] * P->Sigma[a][b] * P->T[j][b];
+            P->cov[i][j] = acc + (i == j ? fr->dilation : 0.0);
+        }
+    double det = P->cov[0][0] * P->cov[1][1] - P->cov[0][1] * P->cov[1][0];
+    if (!(det > 0.0) || !isfinite(det)) return;
+    P->A[0][0] = P->cov[1][1] / det;
+    P->A[0][1] = -P->cov[0][1] / det;
+    P->A[1][0] = -P->cov[1][0] / det;
+    P->A[1][1] = P->cov[0][0] / det;
+    P->key = (float)mz;
+    P->valid = 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* depth order                                                         */
+/* ------------------------------------------------------------------ */
+
+static const proj_t *g_sort_proj; /* comparator context (sorting is serial) */
+
+static int cmp_order(const void *a, const void *b)
+{
+    int64_t ia = *(const int64_t *)a, ib = *(const int64_t *)b;
+    float ka = g_sort_proj[ia].key, kb = g_sort_proj[ib].key;
+    if (ka < kb) return -1;
+    if (ka > kb) return 1;
+    return (ia < ib) ? -1 : (ia > ib);
+}
+
+/* ------------------------------------------------------------------ */
+/* per-pixel compositing                                               */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t g;
+    double alpha, T, G, dx, dy;
+    int clamped;
+} contrib_t;
+
+typedef struct {
+    contrib_t *v;
+    int64_t len, cap;
+} clist_t;
+
+static int clist_push(clist_t *L, contrib_t c)
+{
+    if (L->len == L->cap) {
+        int64_t nc = L->cap ? 2 * L->cap : 256;
+        contrib_t *nv = (contrib_t *)realloc(L->v, (size_t)nc * sizeof(contrib_t));
+        if (!nv) return -1;
+        L->v = nv;
+        L->cap = nc;
+    }
+    L->v[L->len++] = c;
+    return 0;
+}
+
+#define ALPHA_MAX 0.99
+#define ALPHA_MIN (1.0 / 255.0)
+#define T_MIN 1e-4
+#define Q_MAX 9.0
+
+static void upd(double *m, double v) { if (v < *m) *m = v; }
+
+/* Step 6 at one pixel centre.  margins: [0] |q-9|/9 where the cut-off decides,
+ * [1] |255 alpha - 1|, [2] |T(1-alpha) - 1e-4|/1e-4, [3] |o G - 0.99|/0.99. */
+static int composite_pixel(const gvo_frame *fr, const proj_t *P, const int64_t *order, int64_t nv,
+                           double px, double py, double C[3], double *Tout, int64_t *ncontrib,
+                           double margins[4], clist_t *L)
+{
+    double T = 1.0;
+    int64_t nc = 0;
+    C[0] = C[1] = C[2] = 0.0;
+    for (int k = 0; k < 4; ++k) margins[k] = INFINITY;
+    const double alpha_at_cut_factor = exp(-0.5 * Q_MAX);
+    for (int64_t i = 0; i < nv; ++i) {
+        int64_t g = order[i];
+        const proj_t *p = &P[g];
+        double dx = px - p->u, dy = py - p->v;
+        double q = p->A[0][0] * dx * dx + (p->A[0][1] + p->A[1][0]) * dx * dy + p->A[1][1] * dy * dy;
+        if (p->o * alpha_at_cut_factor >= ALPHA_MIN) upd(&margins[0], fabs(q - Q_MAX) / Q_MAX);
+        if (q > Q_MAX) continue;
+        double G = exp(-0.5 * q);
+        double a = p->o * G;
+        double alpha = a < ALPHA_MAX ? a : ALPHA_MAX;
+        upd(&margins[1], fabs(alpha / ALPHA_MIN - 1.0));
+        if (alpha < ALPHA_MIN) continue;
+        double Tn = T * (1.0 - alpha);
+        upd(&margins[2], fabs(Tn - T_MIN) / T_MIN);
+        if (Tn < T_MIN) break;
+        upd(&margins[3], fabs(a - ALPHA_MAX) / ALPHA_MAX);
+        const int64_t n = fr->n;
+        for (int ch = 0; ch < 3; ++ch) C[ch] += fr->colors[ch * n + g] * alpha * T;
+        if (L) {
+            contrib_t c = {g, alpha, T, G, dx, dy, a >= ALPHA_MAX};
+            if (clist_push(L, c)) return -1;
+        }
+        T = Tn;
+        ++nc;
+    }
+    for (int ch = 0; ch < 3; ++ch) C[ch] += T * fr->bg[ch];
+    *Tout = T;
+    *ncontrib = nc;
+    return 0;
+}
+
+/* Adjoint of step 6 for one pixel: accumulate dL/d(u, v, A00, A01, A11, o, c)
+ * into acc[g*9 + .] (A01 is the single off-diagonal parameter, which enters q
+ * twice).  Walks the contributor list back to front; S is the colour
+ * composited behind the current entry, starting with T_final * bg. */
+static void composite_pixel_adjoint(const gvo_frame *fr, const proj_t *P, const clist_t *L,
+                                    double T_final, const double dC[3], double *acc)
+{
+    const int64_t n = fr->n;
+    double S[3];
+    for (int ch = 0; ch < 3; ++ch) S[ch] = T_final * fr->bg[ch];
+    for (int64_t k = L->len - 1; k >= 0; --k) {
+        const contrib_t *e = &L->v[k];
+        const int64_t g = e->g;
+        const proj_t *p = &P[g];
+        double *d = acc + g * 9;
+        double c[3], dalpha = 0.0;
+        for (int ch = 0; ch < 3; ++ch) c[ch] = fr->colors[ch * n + g];
+        for (int ch = 0; ch < 3; ++ch) {
+            d[6 + ch] += e->alpha * e->T * dC[ch];
+            dalpha += dC[ch] * (c[ch] * e->T - S[ch] / (1.0 - e->alpha));
+        }
+        for (int ch = 0; ch < 3; ++ch) S[ch] += c[ch] * e->alpha * e->T;
+        if (e->clamped) continue;  /* alpha = 0.99 is constant in o and q */
+        /* alpha = o G, G = exp(-q/2) */
+        double dq = dalpha * p->o * e->G * (-0.5);
+        d[5] += dalpha * e->G;
+        /* q = A00 dx^2 + 2 A01 dx dy + A11 dy^2 with d = p - (u, v) */
+        d[2] += dq * e->dx * e->dx;
+        d[3] += dq * 2.0 * e->dx * e->dy;
+        d[4] += dq * e->dy * e->dy;
+        d[0] += dq * (-2.0) * (p->A[0][0] * e->dx + p->A[0][1] * e->dy);
+        d[1] += dq * (-2.0) * (p->A[1][0] * e->dx + p->A[1][1] * e->dy);
+    }
+}
+
+/* Adjoint of steps 1-4 for one Gaussian: from d = dL/d(u, v, A00, A01, A11,
+ * o, c) to the stored parameters; the pose contribution is added to
+ * dRc (3x3) and dtc (3). */
+static void project_adjoint(const gvo_frame *fr, const cam_t *c, int64_t g, const proj_t *P,
+                            const double d[9], gvo_grads *gr, double dRc[3][3], double dtc[3])
+{
+    const int64_t n = fr->n;
+    /* gradient w.r.t. the symmetric conic matrix: A01 appears at (0,1) and (1,0) */
+    double GA[2][2] = {{d[2], 0.5 * d[3]}, {0.5 * d[3], d[4]}};
+    /* A = cov^{-1}  =>  dcov = -A GA A */
+    double AG[2][2], Gc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) AG[i][j] = P->A[i][0] * GA[0][j] + P->A[i][1] * GA[1][j];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) Gc[i][j] = -(AG[i][0] * P->A[0][j] + AG[i][1] * P->A[1][j]);
+    /* cov = T Sigma T^T + dil I,  T = J Rc (2x3) */
+    double GS[3][3], dT[2][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0.0;
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) acc += P->T[i][a] * Gc[i][j] * P->T[j][b];
+            GS[a][b] = acc;
+        }
+    for (int i = 0; i < 2; ++i)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0.0;
+            for (int j = 0; j < 2; ++j)
+                for (int a = 0; a < 3; ++a) acc += Gc[i][j] * P->T[j][a] * P->Sigma[a][b];
+            dT[i][b] = 2.0 * acc;
+        }
+    double dJ[2][3];
+    for (int i = 0; i < 2; ++i)
+        for (int k = 0; k < 3; ++k) {
+            double acc = 0.0;
+            for (int j = 0; j < 3; ++j) acc += dT[i][j] * c->Rc[k][j];
+            dJ[i][k] = acc;
+        }
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int i = 0; i < 2; ++i) acc += P->J[i][k] * dT[i][j];
+            dRc[k][j] += acc;
+        }
+    /* J(m) and (u, v)(m) */
+    double mx = P->m[0], my = P->m[1], mz = P->m[2];
+    double fx = fr->fx, fy = fr->fy;
+    double dm[3];
+    dm[0] = dJ[0][2] * (-fx / (mz * mz)) + d[0] * fx / mz;
+    dm[1] = dJ[1][2] * (-fy / (mz * mz)) + d[1] * fy / mz;
+    dm[2] = dJ[0][0] * (-fx / (mz * mz)) + dJ[0][2] * (2.0 * fx * mx / (mz * mz * mz))
+          + dJ[1][1] * (-fy / (mz * mz)) + dJ[1][2] * (2.0 * fy * my / (mz * mz * mz))
+          - d[0] * fx * mx / (mz * mz) - d[1] * fy * my / (mz * mz);
+    /* m = Rc mu + tc */
+    double dmu[3];
+    for (int k = 0; k < 3; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i < 3; ++i) acc += c->Rc[i][k] * dm[i];
+        dmu[k] = acc;
+        dtc[k] += dm[k];
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) dRc[i][k] += dm[i] * P->mu[k];
+    /* Sigma = M M^T, M = R diag(s) */
+    double dM[3][3], dR[3][3], ds[3] = {0, 0, 0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += GS[i][k] * P->M[k][j];
+            dM[i][j] = 2.0 * acc;
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            dR[i][j] = dM[i][j] * P->s[j];
+            ds[j] += dM[i][j] * P->R[i][j];
+        }
+    double dq[4];
+    rot_grad_to_quat(P->qhat, P->qnorm, dR, dq);
+    /* write (accumulate) */
+    for (int k = 0; k < 3; ++k) {
+        gr->means[k * n + g] += dmu[k];
+        if (gr->mean_coeffs && fr->mean_coeffs) {
+            gr->mean_coeffs[(0 * 3 + k) * n + g] += dmu[k] * fr->t;
+            gr->mean_coeffs[(1 * 3 + k) * n + g] += dmu[k] * fr->t * fr->t;
+            gr->mean_coeffs[(2 * 3 + k) * n + g] += dmu[k] * fr->t * fr->t * fr->t;
+        }
+        gr->log_scales[k * n + g] += ds[k] * P->s[k];
+        gr->colors[k * n + g] += d[6 + k];
+    }
+    for (int k = 0; k < 4; ++k) gr->quats[k * n + g] += dq[k];
+    gr->opacity_logits[g] += d[5] * P->o * (1.0 - P->o);
+}
+
+/* ------------------------------------------------------------------ */
+/* exported entry points                                               */
+/* ------------------------------------------------------------------ */
+
+/* Per-Gaussian projection (steps 1-4).  out: [n][24] with
+ * valid, u, v, cov00, cov01, cov11, A00, A01, A11, m_z, key(float),
+ * o, Sigma xx xy xz yy yz zz, m_x, m_y, (pad x4). */
+int gvo_project(const gvo_frame *fr, double *out)
+{
+    cam_t c;
+    int ok;
+    setup_camera(fr, &c, &ok);
+    for (int64_t g = 0; g < fr->n; ++g) {
+        double *o = out + g * 24;
+        memset(o, 0, 24 * sizeof(double));
+        if (!ok) continue;
+        proj_t P;
+        project_one(fr, &c, g, &P);
+        if (!P.valid) continue;
+        o[0] = 1; o[1] = P.u; o[2] = P.v;
+        o[3] = P.cov[0][0]; o[4] = P.cov[0][1]; o[5] = P.cov[1][1];
+        o[6] = P.A[0][0]; o[7] = P.A[0][1]; o[8] = P.A[1][1];
+        o[9] = P.m[2]; o[10] = (double)P.key; o[11] = P.o;
+        o[12] = P.Sigma[0][0]; o[13] = P.Sigma[0][1]; o[14] = P.Sigma[0][2];
+        o[15] = P.Sigma[1][1]; o[16] = P.Sigma[1][2]; o[17] = P.Sigma[2][2];
+        o[18] = P.m[0]; o[19] = P.m[1];
+    }
+    return 0;
+}
+
+/* Render the listed pixels (linear index y*W + x; pix == NULL means all
+ * pixels in raster order) and, if dL_dC is given, accumulate (+=) the
+ * gradient of sum_p dL_dC[p] . C[p] into grads.  Returns 0, or -1 when out
+ * of memory, -2 for an invalid pose. */
+int gvo_render(const gvo_frame *fr, int64_t n_pix, const int64_t *pix, double *color,
+               double *T_final, int64_t *n_contrib, double *margins, const double *dL_dC,
+               gvo_grads *grads, int n_threads)
+{
+    cam_t cam;
+    int ok;
+    setup_camera(fr, &cam, &ok);
+    if (!ok) return -2;
+    const int64_t n = fr->n;
+    proj_t *P = (proj_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(proj_t));
+    int64_t *order = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!P || !order) { free(P); free(order); return -1; }
+    int64_t nv = 0;
+    for (int64_t g = 0; g < n; ++g) {
+        project_one(fr, &cam, g, &P[g]);
+        if (P[g].valid) order[nv++] = g;
+    }
+    g_sort_proj = P;
+    qsort(order, (size_t)nv, sizeof(int64_t), cmp_order);
+
+    const int bwd = (dL_dC != NULL && grads != NULL);
+    int nt = 1;
+#ifdef _OPENMP
+    nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#endif
+    double *acc = NULL;
+    if (bwd) {
+        acc = (double *)calloc((size_t)nt * (size_t)(n > 0 ? n : 1) * 9, sizeof(double));
+        if (!acc) { free(P); free(order); return -1; }
+    }
+    int err = 0;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        clist_t L = {0, 0, 0};
+        double *my_acc = bwd ? acc + (size_t)tid * (size_t)n * 9 : NULL;
+#ifdef _OPENMP
+#pragma omp for schedule(static, 8)
+#endif
+        for (int64_t i = 0; i < n_pix; ++i) {
+            int64_t lin = pix ? pix[i] : i;
+            int64_t x = lin % fr->width, y = lin / fr->width;
+            double mg[4], C[3], T;
+            int64_t nc;
+            L.len = 0;
+            if (composite_pixel(fr, P, order, nv, (double)x + 0.5, (double)y + 0.5, C, &T, &nc, mg,
+                                bwd ? &L : NULL)) {
+                err = -1;
+                continue;
+            }
+            for (int ch = 0; ch < 3; ++ch) color[i * 3 + ch] = C[ch];
+            if (T_final) T_final[i] = T;
+            if (n_contrib) n_contrib[i] = nc;
+            if (margins)
+                for (int k = 0; k < 4; ++k) margins[i * 4 + k] = mg[k];
+            if (bwd) composite_pixel_adjoint(fr, P, &L, T, dL_dC + i * 3, my_acc);
+        }
+        free(L.v);
+    }
+    if (bwd && !err) {
+        double dRc[3][3] = {{0}}, dtc[3] = {0, 0, 0};
+        for (int64_t g = 0; g < n; ++g) {
+            if (!P[g].valid) continue;
+            double d[9] = {0};
+            int any = 0;
+            for (int t = 0; t < nt; ++t)
+                for (int k = 0; k < 9; ++k) d[k] += acc[((size_t)t * n + g) * 9 + k];
+            for (int k = 0; k < 9; ++k) any |= (d[k] != 0.0);
+            if (any) project_adjoint(fr, &cam, g, &P[g], d, grads, dRc, dtc);
+        }
+        if (grads->pose) {
+            double dq[4];
+            rot_grad_to_quat(cam.qc_hat, cam.qc_norm, dRc, dq);
+            for (int k = 0; k < 4; ++k) grads->pose[k] += dq[k];
+            for (int k = 0; k < 3; ++k) grads->pose[4 + k] += dtc[k];
+        }
+    }
+    free(acc);
+    free(P);
+    free(order);
+    return err;
+}
+
+int gvo_abi_version(void) { return 1; }
