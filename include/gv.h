@@ -1,0 +1,229 @@
+/*
+ * gv.h -- C ABI of the MI355X (gfx950) differentiable Gaussian rasterizer.
+ *
+ * The library renders 3D Gaussians (paper Sec. 3.1: mean mu, covariance
+ * Sigma = (R S)(R S)^T from a rotation quaternion and per-axis scales, colour c,
+ * opacity o) through a pinhole camera with constant intrinsics and per-frame
+ * extrinsics (Sec. 3.4), fits them with the L2 reconstruction loss (Sec. 4.1),
+ * and returns gradients through a hand-written adjoint.  The rasterizer is the
+ * tile-based one of 3D Gaussian Splatting that Sec. 3.1 cites: EWA projection,
+ * 16x16 tile binning with a per-tile depth sort, front-to-back alpha
+ * compositing (alpha <= 0.99, entries with alpha < 1/255 skipped, a pixel stops
+ * before its transmittance drops below 1e-4, footprint cut at q = 9, i.e. 3
+ * sigma).  The camera extrinsics may come from the camera-motion Neural ODE of
+ * Eq. 1 (gv_camera_ode_*).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Memory: every array argument is a DEVICE pointer owned by the caller,
+ *   except the gv_camera / gv_scene / gv_grads / gv_tuning structs themselves
+ *   and explicitly marked host outputs.  The library never allocates device
+ *   memory for rendering; scratch space is the caller's workspace `ws`, sized
+ *   by gv_workspace_bytes.  Arrays are planar: parameters [C][N], images
+ *   [F][3][H][W] (row-major), poses [F][7].
+ * - Poses are world->camera: (qw, qx, qy, qz, tx, ty, tz); the quaternion need
+ *   not be normalised (it is normalised inside, and its gradient is that of
+ *   the unnormalised input).  Pixel (x, y) has its centre at (x+1/2, y+1/2).
+ * - Streams: `stream` is a hipStream_t (NULL = the null stream).  All work is
+ *   enqueued on it; calls return after enqueueing.  Only gv_render_fwd (one
+ *   blocking read of the intersection count), gv_device_status and
+ *   gv_autotune synchronise.
+ * - Errors: a gv_status return code, never an abort or exception.  Arguments
+ *   are validated on the host before anything is enqueued.  Device-side
+ *   conditions (intersection capacity exceeded, non-finite parameters) are
+ *   recorded in a status word inside the workspace (gv_device_status).
+ * - Reentrancy: calls with distinct workspaces may run concurrently on
+ *   different streams.  Two calls sharing one workspace must be ordered.
+ */
+#ifndef GV_H
+#define GV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GV_OK = 0,
+    GV_ERR_INVALID_ARG = 1, /* a null pointer, a non-positive size, an unknown flag or dtype */
+    GV_ERR_WORKSPACE = 2,   /* the workspace is smaller than gv_workspace_bytes requires */
+    GV_ERR_CAPACITY = 3,    /* more (Gaussian, tile) intersections than the workspace holds */
+    GV_ERR_HIP = 4,         /* a HIP runtime call failed (the HIP error is in gv_last_hip_error) */
+    GV_ERR_UNSUPPORTED = 5  /* e.g. no gfx950 device */
+} gv_status;
+
+typedef enum { GV_F32 = 0, GV_BF16 = 1 } gv_dtype;
+
+/* Pinhole intrinsics shared by all frames of a clip (Sec. 3.4), plus the
+ * rasterizer constants: near-plane depth below which a Gaussian is dropped,
+ * the low-pass term added to the diagonal of every projected 2D covariance,
+ * and the background colour composited behind the last Gaussian. */
+typedef struct {
+    int32_t width, height;  /* pixels, 1 .. 16384 each */
+    float fx, fy, cx, cy;   /* focal lengths and principal point, in pixels */
+    float near_plane;       /* > 0; default 0.01 */
+    float dilation;         /* >= 0; default 0.3 (pixel^2) */
+    float bg[3];            /* background RGB */
+} gv_camera;
+
+/* Gaussian parameters in their stored parameterisation, planar [C][N]
+ * (Sec. 3.1 and Eq. 3): means [3][N] (mu0 when mean_coeffs is set),
+ * log-scales [3][N] (s = exp), quaternions [4][N] (w, x, y, z; normalised
+ * inside), opacity logits [N] (o = sigmoid), RGB colours [3][N] (constant in
+ * time, Eq. 3).  mean_coeffs is NULL or [3 coeff][3 xyz][N]: the cubic mean
+ * mu(t) = mu0 + a1 t + a2 t^2 + a3 t^3 (polynomial motion basis, Sec. 3.2).
+ * dtype GV_F32: float arrays; GV_BF16: bfloat16 bit patterns (uint16),
+ * widened to FP32/FP64 on load. */
+typedef struct {
+    int64_t n;              /* number of Gaussians, 0 .. 2^31-1 */
+    int32_t dtype;          /* gv_dtype */
+    const void *means;
+    const void *log_scales;
+    const void *quats;
+    const void *opacity_logits;
+    const void *colors;
+    const void *mean_coeffs; /* may be NULL */
+} gv_scene;
+
+/* FP32 gradient outputs, same layouts as gv_scene (always FP32, even for bf16
+ * parameters).  mean_coeffs may be NULL when the scene has none; any other
+ * NULL member skips that output. */
+typedef struct {
+    float *means;
+    float *log_scales;
+    float *quats;
+    float *opacity_logits;
+    float *colors;
+    float *mean_coeffs;
+} gv_grads;
+
+/* Flags for gv_render_batch / gv_render_bwd. */
+#define GV_FWD 1u        /* forward: images (+ loss with GV_LOSS_L2) */
+#define GV_BWD 2u        /* backward: gradients */
+#define GV_LOSS_L2 4u    /* loss = mean over (F,3,H,W) of (image - target)^2 (Sec. 4.1), fused */
+#define GV_ACCUMULATE 8u /* add gradients into `grads` instead of overwriting them */
+
+/* Tunables of the rasterizer kernels (chosen by gv_autotune, or set directly).
+ * batch: entries staged in LDS per round of a tile's compositing loop
+ * (64, 128 or 256); sort_cap: longest per-tile list sorted in one LDS pass
+ * (1024, 2048 or 4096; longer lists are sorted in chunks and merged). */
+typedef struct {
+    int32_t batch;
+    int32_t sort_cap;
+    int32_t reserved[6];
+} gv_tuning;
+
+/* Bytes of workspace for up to `frames` frames of `n` Gaussians at the
+ * camera's resolution, with room for `k_capacity` (Gaussian, tile)
+ * intersections over all frames (a 16x16 tile grid; a typical random scene
+ * at 960x540 has about 4 intersections per visible Gaussian per frame). */
+gv_status gv_workspace_bytes(const gv_camera *cam, int64_t n, int32_t frames, int64_t k_capacity,
+                             size_t *out_bytes);
+
+/* Largest intersection capacity a workspace of ws_bytes offers. */
+gv_status gv_workspace_capacity(const gv_camera *cam, int64_t n, int32_t frames, size_t ws_bytes,
+                                int64_t *out_k_capacity);
+
+/* Projection only (EWA step of Sec. 3.1 as in 3DGS), for inspection: per
+ * Gaussian, records[g][8] = (u, v, A00, A01, A11, depth, opacity, 0) where
+ * (u, v) is the projected mean in pixels, A the conic (inverse of the dilated
+ * 2D covariance), depth the camera-space z; tile_counts[g] = number of 16x16
+ * tiles its 3-sigma ellipse meets (0 = culled).  pose7: device [7]; t: the
+ * frame time of the cubic mean.  Needs a workspace for frames = 1. */
+gv_status gv_project_fwd(const gv_scene *scene, const gv_camera *cam, const float *pose7, float t,
+                         float *records, int32_t *tile_counts, void *ws, size_t ws_bytes, void *stream);
+
+/* Forward render of one frame (the plain per-frame path).  image [3][H][W];
+ * T_final [H][W] (final transmittance) may be NULL.  Reads the intersection
+ * count back to the host once (synchronises `stream`) and returns
+ * GV_ERR_CAPACITY, with nothing rendered, if it exceeds the workspace.
+ * The workspace then holds what gv_render_bwd needs. */
+gv_status gv_render_fwd(const gv_scene *scene, const gv_camera *cam, const float *pose7, float t,
+                        float *image, float *T_final, void *ws, size_t ws_bytes, void *stream);
+
+/* Backward of the last gv_render_fwd on this workspace (same scene, camera,
+ * pose, t and image buffer).  Upstream gradient: dL_dimage [3][H][W], or,
+ * with GV_LOSS_L2 in flags, the gradient of the L2 loss against `target`
+ * [3][H][W] scaled by loss_scale (2/(3HW) for the mean over one frame).
+ * Gradients are written to `grads` (added with GV_ACCUMULATE); dL_dpose7 [7]
+ * may be NULL.  Transmittances are recomputed back to front from the stored
+ * final transmittance; nothing else per pixel is kept from the forward pass. */
+gv_status gv_render_bwd(const gv_scene *scene, const gv_camera *cam, const float *pose7, float t,
+                        const float *image, const float *dL_dimage, const float *target, float loss_scale,
+                        uint32_t flags, gv_grads *grads, float *dL_dpose7, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/* All frames of a clip in one launch sequence, without host synchronisation
+ * (batched form; capturable into a HIP graph).  poses [F][7] and times [F]
+ * (cubic-mean time of each frame; NULL = all 0) are device arrays.
+ * flags: GV_FWD and/or GV_BWD.  GV_FWD renders images [F][3][H][W]; with
+ * GV_LOSS_L2 it also writes loss[F], each frame's share of the mean over all
+ * F*3*H*W values of (image - target)^2 (targets [F][3][H][W]).  GV_BWD
+ * back-propagates either that loss (GV_LOSS_L2) or an explicit upstream
+ * gradient dL_dimages [F][3][H][W]; without GV_FWD in the same call it is the
+ * backward of the last forward on this workspace (same arguments, `images`
+ * holding its output).  grads: SUM over frames of the shared parameters'
+ * gradients (overwritten, or added with GV_ACCUMULATE); dL_dposes [F][7] per
+ * frame (may be NULL).  An intersection overflow is reported through
+ * gv_device_status; outputs are then undefined and the call must be repeated
+ * with a larger workspace. */
+gv_status gv_render_batch(const gv_scene *scene, const gv_camera *cam, const float *poses, const float *times,
+                          int32_t frames, const float *targets, const float *dL_dimages, uint32_t flags,
+                          float *images, float *loss, gv_grads *grads, float *dL_dposes, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* Capture one gv_render_batch call (same arguments; every pointer is baked
+ * in) into an executable HIP graph; launch it any number of times; destroy
+ * it.  Capture happens on a private stream; nothing runs at creation. */
+typedef struct gv_graph gv_graph;
+gv_status gv_batch_graph_create(const gv_scene *scene, const gv_camera *cam, const float *poses,
+                                const float *times, int32_t frames, const float *targets,
+                                const float *dL_dimages, uint32_t flags, float *images, float *loss,
+                                gv_grads *grads, float *dL_dposes, void *ws, size_t ws_bytes, gv_graph **out);
+gv_status gv_batch_graph_launch(gv_graph *graph, void *stream);
+gv_status gv_batch_graph_destroy(gv_graph *graph);
+
+/* Camera-motion Neural ODE (Eq. 1, Sec. 3.4): state z = (qw,qx,qy,qz,tx,ty,tz),
+ * dz/dt = W3 tanh(W2 tanh(W1 [z; t] + b1) + b2) + b3 with an 8->64->64->7
+ * MLP; theta [5191] = W1[64][8], b1[64], W2[64][64], b2[64], W3[7][64], b3[7]
+ * (device, fp32).  Classic RK4 with `substeps` steps per frame interval over
+ * t in [0, 1] (frame f at t = f/(F-1)); poses [F][7] = (q/|q|, t) of the state
+ * at each frame.  gv_camera_ode_bwd is the discrete adjoint (the exact
+ * gradient of the computed RK4 trajectory) given dL_dposes [F][7]; it writes
+ * dtheta [5191] and dz0 [7] (overwritten) and needs the workspace of the
+ * matching forward call. */
+gv_status gv_camera_ode_workspace_bytes(int32_t frames, int32_t substeps, size_t *out_bytes);
+gv_status gv_camera_ode_fwd(const float *theta, const float *z0, int32_t frames, int32_t substeps, float *poses,
+                            void *ws, size_t ws_bytes, void *stream);
+gv_status gv_camera_ode_bwd(const float *theta, const float *z0, int32_t frames, int32_t substeps,
+                            const float *dL_dposes, float *dtheta, float *dz0, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/* Tunables: read/set the process-wide table; gv_autotune times candidate
+ * settings on the given batch problem (it runs gv_render_batch several times
+ * on the caller's buffers, overwriting its outputs, and synchronises) and
+ * installs the fastest; the choice is also written as one JSON line to
+ * cache_path when cache_path is not NULL. */
+gv_status gv_get_tuning(gv_tuning *out);
+gv_status gv_set_tuning(const gv_tuning *t);
+gv_status gv_autotune(const gv_scene *scene, const gv_camera *cam, const float *poses, const float *times,
+                      int32_t frames, const float *targets, float *images, float *loss, gv_grads *grads,
+                      float *dL_dposes, void *ws, size_t ws_bytes, const char *cache_path, gv_tuning *chosen);
+
+/* Device status word of a workspace (host outputs; synchronises the device):
+ * out[0] = 1 if the intersection capacity overflowed (2: internal binning
+ * inconsistency; outputs invalid), out[1] = number of
+ * Gaussians skipped for non-finite parameters (last projection), out[2..3] =
+ * low/high 32 bits of the intersection count of the last projection. */
+gv_status gv_device_status(const void *ws, uint32_t out[4]);
+
+const char *gv_status_str(gv_status s);
+int32_t gv_last_hip_error(void);
+int32_t gv_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GV_H */

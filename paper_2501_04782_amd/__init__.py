@@ -1,0 +1,14 @@
+"""MI355X-native differentiable 3D Gaussian rasterizer (GaussianVideo's fitting
+hot path): gfx950 HIP kernels behind the C ABI of include/gv.h, with a thin
+torch binding.  Importing the package does not touch the GPU; the first call
+loads libgv.so and raises if it has not been built."""
+from . import _lib
+from .raster import (BatchGraph, Camera, RasterizeClip, RasterizeFrame, Scene, Workspace, estimate_capacity,
+                     grad_buffers, project_fwd, render_batch, render_bwd, render_fwd)
+
+__all__ = ["BatchGraph", "Camera", "RasterizeClip", "RasterizeFrame", "Scene", "Workspace", "estimate_capacity",
+           "grad_buffers", "project_fwd", "render_batch", "render_bwd", "render_fwd", "load_library"]
+
+
+def load_library():
+    return _lib.load()

@@ -1,0 +1,541 @@
+// Host side of the C ABI declared in include/gv.h: argument validation,
+// workspace layout, launch sequencing, HIP graph capture and tunables.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "gv_internal.h"
+
+namespace gv {
+
+// launchers defined next to their kernels
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t stream);
+hipError_t launch_project(const Args& a, hipStream_t stream);
+hipError_t launch_scatter(const Args& a, hipStream_t stream);
+hipError_t launch_export_records(const Args& a, float* records, int32_t* counts, hipStream_t stream);
+hipError_t launch_tile_sort(const Args& a, int64_t segments, hipStream_t stream);
+hipError_t launch_composite_fwd(const Args& a, hipStream_t stream);
+hipError_t launch_loss_finalize(const Args& a, hipStream_t stream);
+hipError_t launch_composite_bwd(const Args& a, hipStream_t stream);
+hipError_t launch_project_bwd(const Args& a, hipStream_t stream);
+int64_t project_bwd_blocks(int64_t n);
+int64_t scan_blocks(int64_t count);
+hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t count, unsigned long long* tmp,
+                          uint32_t* status, int check, int64_t k_cap, hipStream_t stream);
+
+static thread_local int32_t g_last_hip = 0;
+static std::mutex g_tune_mu;
+static Tuning g_tune = {256, 4096, 128};
+
+Tuning current_tuning() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune;
+}
+
+void install_tuning(const Tuning& t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune = t;
+}
+
+static inline size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+constexpr int64_t K_LIMIT = 0x7fffffffLL;        // positions are u32; keep one bit spare
+constexpr size_t PER_ENTRY_BYTES = 8 + 4 + 4 + 4 + 16 + 16 + 4 + 8 + 4;
+
+Layout make_layout(const gv_camera& cam, int64_t n, int frames, int64_t k_cap) {
+    Layout L{};
+    L.n = n;
+    L.frames = frames;
+    L.width = cam.width;
+    L.height = cam.height;
+    L.tiles_x = (cam.width + TILE - 1) / TILE;
+    L.tiles_y = (cam.height + TILE - 1) / TILE;
+    L.tiles = L.tiles_x * L.tiles_y;
+    L.pixels = static_cast<int64_t>(cam.width) * cam.height;
+    L.k_cap = k_cap;
+    const int64_t FN = static_cast<int64_t>(frames) * n;
+    const int64_t FT = static_cast<int64_t>(frames) * L.tiles;
+    L.scan_blocks = std::max(scan_blocks(FN), scan_blocks(FT));
+    L.pose_blocks = project_bwd_blocks(n);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.status = take(ST_WORDS * sizeof(uint32_t));
+    L.col4 = take(sizeof(ColorOp) * static_cast<size_t>(n));
+    L.rec = take(sizeof(Record) * static_cast<size_t>(FN));
+    L.rect = take(sizeof(uint2) * static_cast<size_t>(FN));
+    L.gcnt = take(4 * static_cast<size_t>(FN));
+    L.goff = take(4 * static_cast<size_t>(FN + 1));
+    L.tcnt = take(4 * static_cast<size_t>(FT));
+    L.toff = take(4 * static_cast<size_t>(FT + 1));
+    L.tcur = take(4 * static_cast<size_t>(FT));
+    L.scan_tmp = take(8 * static_cast<size_t>(L.scan_blocks + 1));
+    L.tfin = take(4 * static_cast<size_t>(frames) * L.pixels);
+    L.nlast = take(4 * static_cast<size_t>(frames) * L.pixels);
+    L.loss_part = take(4 * static_cast<size_t>(FT));
+    L.pose_part = take(8 * 12 * static_cast<size_t>(L.pose_blocks) * frames);
+    const size_t K = static_cast<size_t>(k_cap);
+    L.keys = take(8 * K);
+    L.kslot = take(4 * K);
+    L.sgid = take(4 * K);
+    L.sslot = take(4 * K);
+    L.partA = take(16 * K);
+    L.partB = take(16 * K);
+    L.partC = take(4 * K);
+    L.tkeys = take(8 * K);
+    L.tslot = take(4 * K);
+    L.total = off;
+    return L;
+}
+
+// Largest k with make_layout(k).total <= ws_bytes (0 if even k = 0 does not fit).
+static int64_t capacity_for(const gv_camera& cam, int64_t n, int frames, size_t ws_bytes) {
+    const size_t fixed = make_layout(cam, n, frames, 0).total;
+    if (ws_bytes < fixed) return 0;
+    int64_t lo = 0;
+    int64_t hi = std::min<int64_t>(K_LIMIT, static_cast<int64_t>((ws_bytes - fixed) / PER_ENTRY_BYTES) + 1);
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (make_layout(cam, n, frames, mid).total <= ws_bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+static bool camera_ok(const gv_camera* c) {
+    if (!c) return false;
+    if (c->width < 1 || c->height < 1 || c->width > 16384 || c->height > 16384) return false;
+    const float v[] = {c->fx, c->fy, c->cx, c->cy, c->near_plane, c->dilation, c->bg[0], c->bg[1], c->bg[2]};
+    for (float x : v)
+        if (!isfinite(x)) return false;
+    return c->fx > 0.f && c->fy > 0.f && c->near_plane > 0.f && c->dilation >= 0.f;
+}
+
+static bool scene_ok(const gv_scene* s) {
+    if (!s) return false;
+    if (s->n < 0 || s->n > K_LIMIT) return false;
+    if (s->dtype != GV_F32 && s->dtype != GV_BF16) return false;
+    if (s->n > 0 && (!s->means || !s->log_scales || !s->quats || !s->opacity_logits || !s->colors)) return false;
+    return true;
+}
+
+static gv_status hip_status(hipError_t e) {
+    if (e == hipSuccess) return GV_OK;
+    g_last_hip = static_cast<int32_t>(e);
+    return GV_ERR_HIP;
+}
+
+#define GV_TRY(expr)                                  \
+    do {                                              \
+        const hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess) return hip_status(e_);  \
+    } while (0)
+
+// Fill the kernel argument block for `frames` frames over workspace `ws`.
+static gv_status make_args(const gv_scene* s, const gv_camera* c, int frames, const float* poses, const float* times,
+                           void* ws, size_t ws_bytes, Args& a, Layout& L) {
+    if (!scene_ok(s) || !camera_ok(c) || frames < 1 || frames > 65535 || !poses) return GV_ERR_INVALID_ARG;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0u) return GV_ERR_WORKSPACE;
+    const int64_t k = capacity_for(*c, s->n, frames, ws_bytes);
+    L = make_layout(*c, s->n, frames, k);
+    if (L.total > ws_bytes) return GV_ERR_WORKSPACE;
+    memset(&a, 0, sizeof(a));
+    a.n = s->n;
+    a.dtype = s->dtype;
+    a.means = s->means;
+    a.log_scales = s->log_scales;
+    a.quats = s->quats;
+    a.opacity_logits = s->opacity_logits;
+    a.colors = s->colors;
+    a.mean_coeffs = s->mean_coeffs;
+    a.width = c->width;
+    a.height = c->height;
+    a.tiles_x = L.tiles_x;
+    a.tiles_y = L.tiles_y;
+    a.tiles = L.tiles;
+    a.fx = c->fx; a.fy = c->fy; a.cx = c->cx; a.cy = c->cy;
+    a.near_plane = c->near_plane;
+    a.dilation = c->dilation;
+    for (int i = 0; i < 3; ++i) a.bg[i] = c->bg[i];
+    a.frames = frames;
+    a.poses = poses;
+    a.times = times;
+    char* b = static_cast<char*>(ws);
+    a.status = reinterpret_cast<uint32_t*>(b + L.status);
+    a.col4 = reinterpret_cast<ColorOp*>(b + L.col4);
+    a.rec = reinterpret_cast<Record*>(b + L.rec);
+    a.rect = reinterpret_cast<uint2*>(b + L.rect);
+    a.gcnt = reinterpret_cast<uint32_t*>(b + L.gcnt);
+    a.goff = reinterpret_cast<uint32_t*>(b + L.goff);
+    a.tcnt = reinterpret_cast<uint32_t*>(b + L.tcnt);
+    a.toff = reinterpret_cast<uint32_t*>(b + L.toff);
+    a.tcur = reinterpret_cast<uint32_t*>(b + L.tcur);
+    a.tfin = reinterpret_cast<float*>(b + L.tfin);
+    a.nlast = reinterpret_cast<uint32_t*>(b + L.nlast);
+    a.loss_part = reinterpret_cast<float*>(b + L.loss_part);
+    a.pose_part = reinterpret_cast<double*>(b + L.pose_part);
+    a.keys = reinterpret_cast<uint64_t*>(b + L.keys);
+    a.kslot = reinterpret_cast<uint32_t*>(b + L.kslot);
+    a.sgid = reinterpret_cast<uint32_t*>(b + L.sgid);
+    a.sslot = reinterpret_cast<uint32_t*>(b + L.sslot);
+    a.partA = reinterpret_cast<float4*>(b + L.partA);
+    a.partB = reinterpret_cast<float4*>(b + L.partB);
+    a.partC = reinterpret_cast<float*>(b + L.partC);
+    a.tkeys = reinterpret_cast<uint64_t*>(b + L.tkeys);
+    a.tslot = reinterpret_cast<uint32_t*>(b + L.tslot);
+    a.k_cap = L.k_cap;
+    a.tune = current_tuning();
+    return GV_OK;
+}
+
+static unsigned long long* scan_tmp(const Args& a, const Layout& L) {
+    return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(a.status) - L.status + L.scan_tmp);
+}
+
+// Projection, binning and scans; optionally reads the intersection count back.
+static gv_status enqueue_binning(const Args& a, const Layout& L, hipStream_t st, bool readback) {
+    const int64_t FN = static_cast<int64_t>(a.frames) * a.n;
+    const int64_t FT = static_cast<int64_t>(a.frames) * a.tiles;
+    GV_TRY(launch_fill_u32(a.status, 0u, ST_WORDS, st));
+    GV_TRY(launch_fill_u32(a.tcnt, 0u, FT, st));
+    GV_TRY(launch_fill_u32(a.tcur, 0u, FT, st));
+    GV_TRY(launch_project(a, st));
+    GV_TRY(exclusive_scan(a.gcnt, a.goff, FN, scan_tmp(a, L), a.status, 0, a.k_cap, st));
+    GV_TRY(exclusive_scan(a.tcnt, a.toff, FT, scan_tmp(a, L), a.status, 1, a.k_cap, st));
+    if (readback) {
+        uint32_t k2[2] = {0, 0};
+        GV_TRY(hipMemcpyAsync(k2, a.status + ST_K_LO, sizeof(k2), hipMemcpyDeviceToHost, st));
+        GV_TRY(hipStreamSynchronize(st));
+        const uint64_t K = static_cast<uint64_t>(k2[0]) | (static_cast<uint64_t>(k2[1]) << 32);
+        if (K > static_cast<uint64_t>(a.k_cap)) return GV_ERR_CAPACITY;
+    }
+    GV_TRY(launch_scatter(a, st));
+    GV_TRY(launch_tile_sort(a, FT, st));
+    return GV_OK;
+}
+
+static gv_status enqueue_batch(const gv_scene* scene, const gv_camera* cam, const float* poses, const float* times,
+                               int32_t frames, const float* targets, const float* dL_dimages, uint32_t flags,
+                               float* images, float* loss, gv_grads* grads, float* dL_dposes, void* ws,
+                               size_t ws_bytes, hipStream_t st) {
+    if ((flags & ~(GV_FWD | GV_BWD | GV_LOSS_L2 | GV_ACCUMULATE)) != 0u || !(flags & (GV_FWD | GV_BWD)))
+        return GV_ERR_INVALID_ARG;
+    if (!images) return GV_ERR_INVALID_ARG;
+    if ((flags & GV_LOSS_L2) && !targets) return GV_ERR_INVALID_ARG;
+    if ((flags & GV_BWD) && !(flags & GV_LOSS_L2) && !dL_dimages) return GV_ERR_INVALID_ARG;
+    if ((flags & GV_BWD) && !grads) return GV_ERR_INVALID_ARG;
+    Args a;
+    Layout L;
+    gv_status s = make_args(scene, cam, frames, poses, times, ws, ws_bytes, a, L);
+    if (s != GV_OK) return s;
+    a.images = images;
+    const double denom = 3.0 * static_cast<double>(L.pixels) * frames;
+    if (flags & GV_LOSS_L2) {
+        a.targets = targets;
+        a.loss = loss;
+        a.loss_norm = static_cast<float>(1.0 / denom);
+        a.loss_scale = static_cast<float>(2.0 / denom);
+    }
+    a.dl_dimages = (flags & GV_LOSS_L2) ? nullptr : dL_dimages;
+    if (grads) {
+        a.g_means = grads->means;
+        a.g_log_scales = grads->log_scales;
+        a.g_quats = grads->quats;
+        a.g_opacity = grads->opacity_logits;
+        a.g_colors = grads->colors;
+        a.g_coeffs = grads->mean_coeffs;
+    }
+    a.g_poses = dL_dposes;
+    a.accumulate = (flags & GV_ACCUMULATE) ? 1 : 0;
+    if (flags & GV_FWD) {
+        s = enqueue_binning(a, L, st, false);
+        if (s != GV_OK) return s;
+        GV_TRY(launch_composite_fwd(a, st));
+        if (a.loss) GV_TRY(launch_loss_finalize(a, st));
+    }
+    if (flags & GV_BWD) {
+        GV_TRY(launch_composite_bwd(a, st));
+        GV_TRY(launch_project_bwd(a, st));
+    }
+    return GV_OK;
+}
+
+}  // namespace gv
+
+using namespace gv;
+
+struct gv_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+extern "C" {
+
+gv_status gv_workspace_bytes(const gv_camera* cam, int64_t n, int32_t frames, int64_t k_capacity, size_t* out) {
+    if (!camera_ok(cam) || n < 0 || n > K_LIMIT || frames < 1 || frames > 65535 || k_capacity < 0 ||
+        k_capacity > K_LIMIT || !out)
+        return GV_ERR_INVALID_ARG;
+    *out = make_layout(*cam, n, frames, k_capacity).total;
+    return GV_OK;
+}
+
+gv_status gv_workspace_capacity(const gv_camera* cam, int64_t n, int32_t frames, size_t ws_bytes, int64_t* out) {
+    if (!camera_ok(cam) || n < 0 || n > K_LIMIT || frames < 1 || frames > 65535 || !out) return GV_ERR_INVALID_ARG;
+    *out = capacity_for(*cam, n, frames, ws_bytes);
+    return GV_OK;
+}
+
+gv_status gv_project_fwd(const gv_scene* scene, const gv_camera* cam, const float* pose7, float t, float* records,
+                         int32_t* tile_counts, void* ws, size_t ws_bytes, void* stream) {
+    if (!records || !tile_counts) return GV_ERR_INVALID_ARG;
+    Args a;
+    Layout L;
+    gv_status s = make_args(scene, cam, 1, pose7, nullptr, ws, ws_bytes, a, L);
+    if (s != GV_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    a.t0 = t;
+    GV_TRY(launch_fill_u32(a.status, 0u, ST_WORDS, st));
+    GV_TRY(launch_fill_u32(a.tcnt, 0u, a.tiles, st));
+    GV_TRY(launch_project(a, st));
+    GV_TRY(launch_export_records(a, records, tile_counts, st));
+    return GV_OK;
+}
+
+gv_status gv_render_fwd(const gv_scene* scene, const gv_camera* cam, const float* pose7, float t, float* image,
+                        float* T_final, void* ws, size_t ws_bytes, void* stream) {
+    if (!image) return GV_ERR_INVALID_ARG;
+    Args a;
+    Layout L;
+    gv_status s = make_args(scene, cam, 1, pose7, nullptr, ws, ws_bytes, a, L);
+    if (s != GV_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    a.t0 = t;
+    a.images = image;
+    a.tfin_out = T_final;
+    s = enqueue_binning(a, L, st, true);
+    if (s != GV_OK) return s;
+    GV_TRY(launch_composite_fwd(a, st));
+    return GV_OK;
+}
+
+gv_status gv_render_bwd(const gv_scene* scene, const gv_camera* cam, const float* pose7, float t, const float* image,
+                        const float* dL_dimage, const float* target, float loss_scale, uint32_t flags, gv_grads* grads,
+                        float* dL_dpose7, void* ws, size_t ws_bytes, void* stream) {
+    if ((flags & ~(GV_LOSS_L2 | GV_ACCUMULATE | GV_BWD | GV_FWD)) != 0u || !grads || !image) return GV_ERR_INVALID_ARG;
+    if ((flags & GV_LOSS_L2) ? !target : !dL_dimage) return GV_ERR_INVALID_ARG;
+    if (!isfinite(loss_scale)) return GV_ERR_INVALID_ARG;
+    Args a;
+    Layout L;
+    gv_status s = make_args(scene, cam, 1, pose7, nullptr, ws, ws_bytes, a, L);
+    if (s != GV_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    a.t0 = t;
+    a.images = const_cast<float*>(image);
+    if (flags & GV_LOSS_L2) {
+        a.targets = target;
+        a.loss_scale = loss_scale;
+    } else {
+        a.dl_dimages = dL_dimage;
+    }
+    a.g_means = grads->means;
+    a.g_log_scales = grads->log_scales;
+    a.g_quats = grads->quats;
+    a.g_opacity = grads->opacity_logits;
+    a.g_colors = grads->colors;
+    a.g_coeffs = grads->mean_coeffs;
+    a.g_poses = dL_dpose7;
+    a.accumulate = (flags & GV_ACCUMULATE) ? 1 : 0;
+    GV_TRY(launch_composite_bwd(a, st));
+    GV_TRY(launch_project_bwd(a, st));
+    return GV_OK;
+}
+
+gv_status gv_render_batch(const gv_scene* scene, const gv_camera* cam, const float* poses, const float* times,
+                          int32_t frames, const float* targets, const float* dL_dimages, uint32_t flags, float* images,
+                          float* loss, gv_grads* grads, float* dL_dposes, void* ws, size_t ws_bytes, void* stream) {
+    return enqueue_batch(scene, cam, poses, times, frames, targets, dL_dimages, flags, images, loss, grads, dL_dposes,
+                         ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+gv_status gv_batch_graph_create(const gv_scene* scene, const gv_camera* cam, const float* poses, const float* times,
+                                int32_t frames, const float* targets, const float* dL_dimages, uint32_t flags,
+                                float* images, float* loss, gv_grads* grads, float* dL_dposes, void* ws,
+                                size_t ws_bytes, gv_graph** out) {
+    if (!out) return GV_ERR_INVALID_ARG;
+    *out = nullptr;
+    hipStream_t cs;
+    GV_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        hipStreamDestroy(cs);
+        return hip_status(e);
+    }
+    const gv_status s = enqueue_batch(scene, cam, poses, times, frames, targets, dL_dimages, flags, images, loss, grads,
+                                      dL_dposes, ws, ws_bytes, cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    hipStreamDestroy(cs);
+    if (s != GV_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return s;
+    }
+    if (e != hipSuccess) return hip_status(e);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return hip_status(e);
+    }
+    gv_graph* g = new gv_graph;
+    g->graph = graph;
+    g->exec = exec;
+    *out = g;
+    return GV_OK;
+}
+
+gv_status gv_batch_graph_launch(gv_graph* graph, void* stream) {
+    if (!graph) return GV_ERR_INVALID_ARG;
+    GV_TRY(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)));
+    return GV_OK;
+}
+
+gv_status gv_batch_graph_destroy(gv_graph* graph) {
+    if (!graph) return GV_ERR_INVALID_ARG;
+    hipGraphExecDestroy(graph->exec);
+    hipGraphDestroy(graph->graph);
+    delete graph;
+    return GV_OK;
+}
+
+gv_status gv_get_tuning(gv_tuning* out) {
+    if (!out) return GV_ERR_INVALID_ARG;
+    const Tuning t = current_tuning();
+    memset(out, 0, sizeof(*out));
+    out->batch = t.batch;
+    out->sort_cap = t.sort_cap;
+    return GV_OK;
+}
+
+gv_status gv_set_tuning(const gv_tuning* t) {
+    if (!t) return GV_ERR_INVALID_ARG;
+    if (t->batch != 64 && t->batch != 128 && t->batch != 256) return GV_ERR_INVALID_ARG;
+    if (t->sort_cap != 1024 && t->sort_cap != 2048 && t->sort_cap != 4096) return GV_ERR_INVALID_ARG;
+    Tuning n = current_tuning();
+    n.batch = t->batch;
+    n.sort_cap = t->sort_cap;
+    install_tuning(n);
+    return GV_OK;
+}
+
+gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* poses, const float* times,
+                      int32_t frames, const float* targets, float* images, float* loss, gv_grads* grads,
+                      float* dL_dposes, void* ws, size_t ws_bytes, const char* cache_path, gv_tuning* chosen) {
+    if (!targets || !images || !grads) return GV_ERR_INVALID_ARG;
+    const uint32_t flags = GV_FWD | GV_BWD | GV_LOSS_L2;
+    hipStream_t st;
+    GV_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    hipEvent_t e0, e1;
+    GV_TRY(hipEventCreate(&e0));
+    GV_TRY(hipEventCreate(&e1));
+    const Tuning saved = current_tuning();
+    Tuning best = saved;
+    float best_ms = INFINITY;
+    gv_status result = GV_OK;
+    const int batches[] = {64, 128, 256};
+    const int caps[] = {2048, 4096};
+    for (int b : batches) {
+        for (int c : caps) {
+            Tuning t = saved;
+            t.batch = b;
+            t.sort_cap = c;
+            install_tuning(t);
+            gv_status s = enqueue_batch(scene, cam, poses, times, frames, targets, nullptr, flags, images, loss, grads,
+                                        dL_dposes, ws, ws_bytes, st);
+            if (s == GV_OK && hipStreamSynchronize(st) != hipSuccess) s = GV_ERR_HIP;
+            uint32_t w[1] = {0};
+            if (s == GV_OK && hipMemcpy(w, ws, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess) s = GV_ERR_HIP;
+            if (s == GV_OK && w[0]) s = GV_ERR_CAPACITY;
+            if (s != GV_OK) {
+                result = s;
+                break;
+            }
+            constexpr int REPS = 3;
+            hipEventRecord(e0, st);
+            for (int r = 0; r < REPS && s == GV_OK; ++r)
+                s = enqueue_batch(scene, cam, poses, times, frames, targets, nullptr, flags, images, loss, grads,
+                                  dL_dposes, ws, ws_bytes, st);
+            hipEventRecord(e1, st);
+            hipEventSynchronize(e1);
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            ms /= REPS;
+            if (s != GV_OK) {
+                result = s;
+                break;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        }
+        if (result != GV_OK) break;
+    }
+    install_tuning(result == GV_OK ? best : saved);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamDestroy(st);
+    if (result != GV_OK) return result;
+    if (chosen) {
+        memset(chosen, 0, sizeof(*chosen));
+        chosen->batch = best.batch;
+        chosen->sort_cap = best.sort_cap;
+    }
+    if (cache_path) {
+        FILE* fp = fopen(cache_path, "a");
+        if (fp) {
+            fprintf(fp,
+                    "{\"arch\": \"gfx950\", \"width\": %d, \"height\": %d, \"n\": %lld, \"frames\": %d, "
+                    "\"dtype\": %d, \"batch\": %d, \"sort_cap\": %d, \"ms\": %.4f}\n",
+                    cam->width, cam->height, static_cast<long long>(scene->n), frames, scene->dtype, best.batch,
+                    best.sort_cap, best_ms);
+            fclose(fp);
+        }
+    }
+    return GV_OK;
+}
+
+gv_status gv_device_status(const void* ws, uint32_t out[4]) {
+    if (!ws || !out) return GV_ERR_INVALID_ARG;
+    GV_TRY(hipDeviceSynchronize());
+    uint32_t w[4];
+    GV_TRY(hipMemcpy(w, ws, sizeof(w), hipMemcpyDeviceToHost));
+    out[0] = w[ST_OVERFLOW];
+    out[1] = w[ST_NONFINITE];
+    out[2] = w[ST_K_LO];
+    out[3] = w[ST_K_HI];
+    return GV_OK;
+}
+
+const char* gv_status_str(gv_status s) {
+    switch (s) {
+        case GV_OK: return "ok";
+        case GV_ERR_INVALID_ARG: return "invalid argument";
+        case GV_ERR_WORKSPACE: return "workspace too small or misaligned";
+        case GV_ERR_CAPACITY: return "intersection capacity exceeded";
+        case GV_ERR_HIP: return "HIP runtime error";
+        case GV_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+int32_t gv_last_hip_error(void) { return g_last_hip; }
+
+int32_t gv_abi_version(void) { return 1; }
+
+}  // extern "C"

@@ -1,0 +1,264 @@
+// Camera-motion Neural ODE (Eq. 1, Sec. 3.4): fused MLP + RK4 forward and its
+// discrete adjoint, each in one single-wave workgroup.
+//
+// The integration is a serial chain of (F-1) * S * 4 evaluations of the
+// 8 -> 64 -> 64 -> 7 tanh MLP, so latency, not throughput, is what matters:
+// lane j owns hidden unit j and keeps its weights in VGPRs (row j of W1 and W2,
+// column j of W3, and for the adjoint also column j of W2); the hidden layer
+// is exchanged through LDS (broadcast reads) and the 7 outputs are wave
+// reductions (DPP).  The state z is carried in FP64, the MLP runs in FP32.
+// The forward pass records every evaluation's input and both hidden
+// activations so that the adjoint needs no recomputation.
+#include "gv_internal.h"
+
+namespace gv {
+
+constexpr int ODE_H = 64;
+constexpr int ODE_S = 7;
+constexpr int ODE_REC = 8 + ODE_H + ODE_H;  // x, h1, h2 of one evaluation
+// offsets of the parameter blocks in theta
+constexpr int OFF_W1 = 0, OFF_B1 = 512, OFF_W2 = 576, OFF_B2 = 4672, OFF_W3 = 4736, OFF_B3 = 5184, N_THETA = 5191;
+
+struct OdeLayout {
+    size_t acts, zf, total;
+};
+
+static inline size_t ode_align(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+OdeLayout ode_layout(int frames, int substeps) {
+    OdeLayout L;
+    const size_t evals = static_cast<size_t>(frames - 1) * substeps * 4;
+    L.acts = 0;
+    L.zf = ode_align(evals * ODE_REC * sizeof(float));
+    L.total = L.zf + ode_align(static_cast<size_t>(frames) * ODE_S * sizeof(double));
+    return L;
+}
+
+__device__ __forceinline__ float ode_tanh(float x) { return tanhf(x); }
+
+// One MLP evaluation at (y, t); lanes hold hidden unit j = lane.  Returns the
+// 7 outputs (uniform).  If rec != nullptr, stores x, h1, h2 there.
+__device__ __forceinline__ void mlp_eval(const double y[ODE_S], double t, const float w1[8], float b1,
+                                         const float w2[ODE_H], float b2, const float w3[ODE_S],
+                                         const float* b3, float* h1s, float* rec, float out[ODE_S]) {
+    const int j = threadIdx.x;
+    float x[8];
+    for (int k = 0; k < ODE_S; ++k) x[k] = static_cast<float>(y[k]);
+    x[7] = static_cast<float>(t);
+    float a1 = b1;
+    for (int k = 0; k < 8; ++k) a1 = __builtin_fmaf(w1[k], x[k], a1);
+    const float h1 = ode_tanh(a1);
+    h1s[j] = h1;
+    __syncthreads();
+    float a2 = b2;
+    for (int k = 0; k < ODE_H; ++k) a2 = __builtin_fmaf(w2[k], h1s[k], a2);
+    const float h2 = ode_tanh(a2);
+    for (int i = 0; i < ODE_S; ++i) {
+        const float s = wave_sum_to_lane63(w3[i] * h2);
+        out[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s), 63)) + b3[i];
+    }
+    if (rec) {
+        if (j < 8) rec[j] = x[j];
+        rec[8 + j] = h1;
+        rec[8 + ODE_H + j] = h2;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void write_pose(const double z[ODE_S], float* pose) {
+    if (threadIdx.x != 0) return;
+    const double n = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3]);
+    for (int k = 0; k < 4; ++k) pose[k] = static_cast<float>(z[k] / n);
+    for (int k = 4; k < ODE_S; ++k) pose[k] = static_cast<float>(z[k]);
+}
+
+__global__ __launch_bounds__(64) void k_ode_fwd(const float* __restrict__ theta, const float* __restrict__ z0,
+                                                int frames, int substeps, float* __restrict__ poses,
+                                                float* __restrict__ acts, double* __restrict__ zf) {
+    const int j = threadIdx.x;
+    __shared__ float h1s[ODE_H];
+    float w1[8], w2[ODE_H], w3[ODE_S], b3[ODE_S];
+    for (int k = 0; k < 8; ++k) w1[k] = theta[OFF_W1 + j * 8 + k];
+    const float b1 = theta[OFF_B1 + j];
+    for (int k = 0; k < ODE_H; ++k) w2[k] = theta[OFF_W2 + j * ODE_H + k];
+    const float b2 = theta[OFF_B2 + j];
+    for (int i = 0; i < ODE_S; ++i) w3[i] = theta[OFF_W3 + i * ODE_H + j];
+    for (int i = 0; i < ODE_S; ++i) b3[i] = theta[OFF_B3 + i];
+    double z[ODE_S];
+    for (int k = 0; k < ODE_S; ++k) z[k] = z0[k];
+    write_pose(z, poses);
+    if (j < ODE_S) zf[j] = z[j];
+    if (frames < 2) return;
+    const double h = 1.0 / (static_cast<double>(substeps) * (frames - 1));
+    int e = 0;
+    for (int f = 1; f < frames; ++f) {
+        for (int s = 0; s < substeps; ++s) {
+            const double t = (static_cast<double>(f - 1) * substeps + s) * h;
+            float k1[ODE_S], k2[ODE_S], k3[ODE_S], k4[ODE_S];
+            double y[ODE_S];
+            mlp_eval(z, t, w1, b1, w2, b2, w3, b3, h1s, acts + static_cast<size_t>(e++) * ODE_REC, k1);
+            for (int k = 0; k < ODE_S; ++k) y[k] = z[k] + 0.5 * h * k1[k];
+            mlp_eval(y, t + 0.5 * h, w1, b1, w2, b2, w3, b3, h1s, acts + static_cast<size_t>(e++) * ODE_REC, k2);
+            for (int k = 0; k < ODE_S; ++k) y[k] = z[k] + 0.5 * h * k2[k];
+            mlp_eval(y, t + 0.5 * h, w1, b1, w2, b2, w3, b3, h1s, acts + static_cast<size_t>(e++) * ODE_REC, k3);
+            for (int k = 0; k < ODE_S; ++k) y[k] = z[k] + h * k3[k];
+            mlp_eval(y, t + h, w1, b1, w2, b2, w3, b3, h1s, acts + static_cast<size_t>(e++) * ODE_REC, k4);
+            for (int k = 0; k < ODE_S; ++k)
+                z[k] = z[k] + (h / 6.0) * (static_cast<double>(k1[k]) + 2.0 * k2[k] + 2.0 * k3[k] + k4[k]);
+        }
+        write_pose(z, poses + ODE_S * f);
+        if (j < ODE_S) zf[ODE_S * f + j] = z[j];
+    }
+}
+
+// Cotangent of the state from the cotangent of the pose (q/|q|, t).
+__device__ __forceinline__ void pose_cotangent(const double* z, const float* dp, double out[ODE_S]) {
+    const double n = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3]);
+    double qh[4], dot = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        qh[k] = z[k] / n;
+        dot += qh[k] * static_cast<double>(dp[k]);
+    }
+    for (int k = 0; k < 4; ++k) out[k] = (static_cast<double>(dp[k]) - qh[k] * dot) / n;
+    for (int k = 4; k < ODE_S; ++k) out[k] = dp[k];
+}
+
+struct OdeGrad {
+    float gw1[8], gb1, gw2[ODE_H], gb2, gw3[ODE_S], gb3[ODE_S];
+};
+
+// Vector-Jacobian product of one recorded evaluation with upstream dy;
+// accumulates the parameter gradient and returns dL/dy (state part).
+__device__ __forceinline__ void mlp_vjp(const float* rec, const double dy[ODE_S], const float w1[8],
+                                        const float w2c[ODE_H], const float w3[ODE_S], float* h1s, float* da2s,
+                                        OdeGrad& G, double gx[ODE_S]) {
+    const int j = threadIdx.x;
+    float x[8];
+    for (int k = 0; k < 8; ++k) x[k] = rec[k];
+    const float h1 = rec[8 + j];
+    const float h2 = rec[8 + ODE_H + j];
+    float dyf[ODE_S];
+    for (int i = 0; i < ODE_S; ++i) dyf[i] = static_cast<float>(dy[i]);
+    float dh2 = 0.0f;
+    for (int i = 0; i < ODE_S; ++i) {
+        G.gw3[i] = __builtin_fmaf(dyf[i], h2, G.gw3[i]);
+        G.gb3[i] += dyf[i];
+        dh2 = __builtin_fmaf(w3[i], dyf[i], dh2);
+    }
+    const float da2 = dh2 * (1.0f - h2 * h2);
+    h1s[j] = h1;
+    da2s[j] = da2;
+    __syncthreads();
+    for (int k = 0; k < ODE_H; ++k) G.gw2[k] = __builtin_fmaf(da2, h1s[k], G.gw2[k]);
+    G.gb2 += da2;
+    float dh1 = 0.0f;
+    for (int k = 0; k < ODE_H; ++k) dh1 = __builtin_fmaf(w2c[k], da2s[k], dh1);
+    const float da1 = dh1 * (1.0f - h1 * h1);
+    for (int m = 0; m < 8; ++m) G.gw1[m] = __builtin_fmaf(da1, x[m], G.gw1[m]);
+    G.gb1 += da1;
+    for (int m = 0; m < ODE_S; ++m) {
+        const float s = wave_sum_to_lane63(w1[m] * da1);
+        gx[m] = static_cast<double>(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(s), 63)));
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void k_ode_bwd(const float* __restrict__ theta, int frames, int substeps,
+                                                const float* __restrict__ dposes, const float* __restrict__ acts,
+                                                const double* __restrict__ zf, float* __restrict__ dtheta,
+                                                float* __restrict__ dz0) {
+    const int j = threadIdx.x;
+    __shared__ float h1s[ODE_H];
+    __shared__ float da2s[ODE_H];
+    float w1[8], w2c[ODE_H], w3[ODE_S];
+    for (int k = 0; k < 8; ++k) w1[k] = theta[OFF_W1 + j * 8 + k];
+    for (int k = 0; k < ODE_H; ++k) w2c[k] = theta[OFF_W2 + k * ODE_H + j];
+    for (int i = 0; i < ODE_S; ++i) w3[i] = theta[OFF_W3 + i * ODE_H + j];
+    OdeGrad G;
+    for (int k = 0; k < 8; ++k) G.gw1[k] = 0.0f;
+    for (int k = 0; k < ODE_H; ++k) G.gw2[k] = 0.0f;
+    for (int i = 0; i < ODE_S; ++i) G.gw3[i] = G.gb3[i] = 0.0f;
+    G.gb1 = G.gb2 = 0.0f;
+
+    double lam[ODE_S];
+    pose_cotangent(zf + ODE_S * (frames - 1), dposes + ODE_S * (frames - 1), lam);
+    if (frames > 1) {
+        const double h = 1.0 / (static_cast<double>(substeps) * (frames - 1));
+        for (int f = frames - 1; f >= 1; --f) {
+            for (int s = substeps - 1; s >= 0; --s) {
+                const size_t e0 = (static_cast<size_t>(f - 1) * substeps + s) * 4;
+                double dz[ODE_S], dk[4][ODE_S], gx[ODE_S];
+                for (int k = 0; k < ODE_S; ++k) {
+                    dz[k] = lam[k];
+                    dk[0][k] = (h / 6.0) * lam[k];
+                    dk[1][k] = (h / 3.0) * lam[k];
+                    dk[2][k] = (h / 3.0) * lam[k];
+                    dk[3][k] = (h / 6.0) * lam[k];
+                }
+                mlp_vjp(acts + (e0 + 3) * ODE_REC, dk[3], w1, w2c, w3, h1s, da2s, G, gx);
+                for (int k = 0; k < ODE_S; ++k) { dz[k] += gx[k]; dk[2][k] += h * gx[k]; }
+                mlp_vjp(acts + (e0 + 2) * ODE_REC, dk[2], w1, w2c, w3, h1s, da2s, G, gx);
+                for (int k = 0; k < ODE_S; ++k) { dz[k] += gx[k]; dk[1][k] += 0.5 * h * gx[k]; }
+                mlp_vjp(acts + (e0 + 1) * ODE_REC, dk[1], w1, w2c, w3, h1s, da2s, G, gx);
+                for (int k = 0; k < ODE_S; ++k) { dz[k] += gx[k]; dk[0][k] += 0.5 * h * gx[k]; }
+                mlp_vjp(acts + (e0 + 0) * ODE_REC, dk[0], w1, w2c, w3, h1s, da2s, G, gx);
+                for (int k = 0; k < ODE_S; ++k) lam[k] = dz[k] + gx[k];
+            }
+            double c[ODE_S];
+            pose_cotangent(zf + ODE_S * (f - 1), dposes + ODE_S * (f - 1), c);
+            for (int k = 0; k < ODE_S; ++k) lam[k] += c[k];
+        }
+    }
+    for (int k = 0; k < 8; ++k) dtheta[OFF_W1 + j * 8 + k] = G.gw1[k];
+    dtheta[OFF_B1 + j] = G.gb1;
+    for (int k = 0; k < ODE_H; ++k) dtheta[OFF_W2 + j * ODE_H + k] = G.gw2[k];
+    dtheta[OFF_B2 + j] = G.gb2;
+    for (int i = 0; i < ODE_S; ++i) dtheta[OFF_W3 + i * ODE_H + j] = G.gw3[i];
+    if (j == 0) {
+        for (int i = 0; i < ODE_S; ++i) dtheta[OFF_B3 + i] = G.gb3[i];
+        for (int k = 0; k < ODE_S; ++k) dz0[k] = static_cast<float>(lam[k]);
+    }
+}
+
+}  // namespace gv
+
+using namespace gv;
+
+extern "C" {
+
+gv_status gv_camera_ode_workspace_bytes(int32_t frames, int32_t substeps, size_t* out) {
+    if (frames < 1 || frames > 100000 || substeps < 1 || substeps > 64 || !out) return GV_ERR_INVALID_ARG;
+    *out = ode_layout(frames, substeps).total;
+    return GV_OK;
+}
+
+gv_status gv_camera_ode_fwd(const float* theta, const float* z0, int32_t frames, int32_t substeps, float* poses,
+                            void* ws, size_t ws_bytes, void* stream) {
+    if (!theta || !z0 || !poses || frames < 1 || frames > 100000 || substeps < 1 || substeps > 64)
+        return GV_ERR_INVALID_ARG;
+    const OdeLayout L = ode_layout(frames, substeps);
+    if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255u)) return GV_ERR_WORKSPACE;
+    char* b = static_cast<char*>(ws);
+    hipLaunchKernelGGL(k_ode_fwd, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), theta, z0, frames, substeps,
+                       poses, reinterpret_cast<float*>(b + L.acts), reinterpret_cast<double*>(b + L.zf));
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GV_OK : GV_ERR_HIP;
+}
+
+gv_status gv_camera_ode_bwd(const float* theta, const float* z0, int32_t frames, int32_t substeps,
+                            const float* dL_dposes, float* dtheta, float* dz0, void* ws, size_t ws_bytes,
+                            void* stream) {
+    if (!theta || !z0 || !dL_dposes || !dtheta || !dz0 || frames < 1 || frames > 100000 || substeps < 1 ||
+        substeps > 64)
+        return GV_ERR_INVALID_ARG;
+    const OdeLayout L = ode_layout(frames, substeps);
+    if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255u)) return GV_ERR_WORKSPACE;
+    char* b = static_cast<char*>(ws);
+    hipLaunchKernelGGL(k_ode_bwd, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), theta, frames, substeps,
+                       dL_dposes, reinterpret_cast<const float*>(b + L.acts), reinterpret_cast<const double*>(b + L.zf),
+                       dtheta, dz0);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GV_OK : GV_ERR_HIP;
+}
+
+}  // extern "C"

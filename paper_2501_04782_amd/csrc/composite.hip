@@ -1,0 +1,342 @@
+// Front-to-back alpha compositing of each 16x16 tile (forward) and its adjoint
+// (back to front, transmittance recomputed by division from the stored final
+// value).  One 256-thread workgroup per (frame, tile); wave w owns the 8x8
+// quadrant (w & 1, w >> 1), lane l the pixel (l & 7, l >> 3) in it.  The
+// tile's depth-sorted entries are staged through LDS in batches of B; at
+// staging each entry gets a 4-bit mask of the quadrants its 3-sigma ellipse
+// meets, so a wave skips entries that cannot touch its pixels with one scalar
+// branch.  Lanes leave the loop when their pixel terminates and a workgroup
+// stops staging once every pixel has terminated.
+#include "gv_internal.h"
+
+namespace gv {
+
+struct Staged {
+    float4 p0;  // (u, v) in tile-local pixel-centre coordinates, conic a, 2b
+    float4 p1;  // conic c, opacity, r, g
+};
+
+// Gaussian footprint and opacity at a pixel: q = d^T A d with d = pixel - centre,
+// alpha = min(0.99, o exp(-q/2)).  Shared by both kernels so that the backward
+// pass re-derives exactly the forward pass's values and decisions.
+__device__ __forceinline__ float footprint_q(float dx, float dy, const float4& p0, const float4& p1) {
+    return __builtin_fmaf(p1.x * dy, dy, dx * __builtin_fmaf(p0.z, dx, p0.w * dy));
+}
+
+__device__ __forceinline__ float gauss_falloff(float q) { return __builtin_amdgcn_exp2f(q * K_EXP); }
+
+// Stage entry `idx` of the tile: gather its record and colour, move the centre
+// to tile-local coordinates (exact subtraction in FP64, then one rounding),
+// and compute the quadrant mask.
+__device__ __forceinline__ void stage_entry(const Args& a, int f, uint32_t gid, double ox, double oy, int xlim,
+                                            int ylim, Staged& st, float& blue, uint32_t& mask) {
+    if (gid >= static_cast<uint64_t>(a.n)) {  // only after an internal error: stage an inert entry
+        st.p0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        st.p1 = make_float4(0.f, 0.f, 0.f, 0.f);
+        blue = 0.f;
+        mask = 0u;
+        return;
+    }
+    const Record r = a.rec[static_cast<int64_t>(f) * a.n + gid];
+    const ColorOp co = a.col4[gid];
+    const float lu = static_cast<float>(r.u - ox);
+    const float lv = static_cast<float>(r.v - oy);
+    st.p0 = make_float4(lu, lv, r.a, 2.0f * r.b);
+    st.p1 = make_float4(r.c, co.o, co.r, co.g);
+    blue = co.b;
+    uint32_t m = 0;
+    for (int qd = 0; qd < 4; ++qd) {
+        const int x0 = (qd & 1) * 8, y0 = (qd >> 1) * 8;
+        const int x1 = min(x0 + 7, xlim), y1 = min(y0 + 7, ylim);
+        if (x0 > x1 || y0 > y1) continue;
+        if (ellipse_meets_box<float>(lu, lv, r.a, r.b, r.c, static_cast<float>(x0), static_cast<float>(x1),
+                                     static_cast<float>(y0), static_cast<float>(y1), SUB_Q_SLACK))
+            m |= 1u << qd;
+    }
+    mask = m;
+}
+
+template <int B>
+__global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
+    if (overflowed(a.status)) return;
+    const int f = blockIdx.y;
+    const int tile = blockIdx.x;
+    const int txi = tile % a.tiles_x, tyi = tile / a.tiles_x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lx = ((w & 1) << 3) | (lane & 7), ly = ((w >> 1) << 3) | (lane >> 3);
+    const int px = txi * TILE + lx, py = tyi * TILE + ly;
+    const bool inside = px < a.width && py < a.height;
+    const int64_t seg = static_cast<int64_t>(f) * a.tiles + tile;
+    uint32_t s, e;
+    bucket_range(a, seg, s, e);
+    const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
+    const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
+
+    __shared__ Staged sh[B];
+    __shared__ float shb[B];
+    __shared__ uint32_t shm[B];
+    __shared__ float red[WG / 64];
+
+    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    uint32_t last = 0;
+    bool done = !inside;
+    const float fx = static_cast<float>(lx), fy = static_cast<float>(ly);
+
+    for (uint32_t b0 = s; b0 < e; b0 += B) {
+        if (__syncthreads_count(!done) == 0) break;
+        const uint32_t nb = min(static_cast<uint32_t>(B), e - b0);
+        if (tid < static_cast<int>(nb)) {
+            Staged st;
+            float blue;
+            uint32_t m;
+            stage_entry(a, f, a.sgid[b0 + tid], ox, oy, xlim, ylim, st, blue, m);
+            sh[tid] = st;
+            shb[tid] = blue;
+            shm[tid] = m;
+        }
+        __syncthreads();
+        if (!done) {
+            for (uint32_t j = 0; j < nb; ++j) {
+                const uint32_t m = __builtin_amdgcn_readfirstlane(shm[j]);
+                if (!((m >> w) & 1u)) continue;
+                const float4 p0 = sh[j].p0;
+                const float4 p1 = sh[j].p1;
+                const float dx = fx - p0.x, dy = fy - p0.y;
+                const float q = footprint_q(dx, dy, p0, p1);
+                if (q > Q_MAX) continue;
+                const float al = fminf(ALPHA_MAX, p1.y * gauss_falloff(q));
+                if (al < ALPHA_MIN) continue;
+                const float tn = T * (1.0f - al);
+                if (tn < T_MIN) {
+                    done = true;
+                    break;
+                }
+                const float wgt = al * T;
+                c0 = __builtin_fmaf(p1.z, wgt, c0);
+                c1 = __builtin_fmaf(p1.w, wgt, c1);
+                c2 = __builtin_fmaf(shb[j], wgt, c2);
+                T = tn;
+                last = b0 + j - s + 1;
+            }
+        }
+    }
+
+    float sq = 0.0f;
+    if (inside) {
+        const int64_t P = static_cast<int64_t>(a.width) * a.height;
+        const int64_t pix = static_cast<int64_t>(py) * a.width + px;
+        c0 = __builtin_fmaf(T, a.bg[0], c0);
+        c1 = __builtin_fmaf(T, a.bg[1], c1);
+        c2 = __builtin_fmaf(T, a.bg[2], c2);
+        float* img = a.images + static_cast<int64_t>(f) * 3 * P + pix;
+        img[0] = c0;
+        img[P] = c1;
+        img[2 * P] = c2;
+        a.tfin[static_cast<int64_t>(f) * P + pix] = T;
+        a.nlast[static_cast<int64_t>(f) * P + pix] = last;
+        if (a.tfin_out) a.tfin_out[static_cast<int64_t>(f) * P + pix] = T;
+        if (a.targets && a.loss) {
+            const float* tg = a.targets + static_cast<int64_t>(f) * 3 * P + pix;
+            const float d0 = c0 - tg[0], d1 = c1 - tg[P], d2 = c2 - tg[2 * P];
+            sq = d0 * d0 + d1 * d1 + d2 * d2;
+        }
+    }
+    if (a.targets && a.loss) {
+        sq = wave_sum_to_lane63(sq);
+        if (lane == 63) red[w] = sq;
+        __syncthreads();
+        if (tid == 0) a.loss_part[seg] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
+}
+
+// Per-frame loss: fixed-order sum of the tiles' partial sums.
+__global__ __launch_bounds__(WG) void k_loss_finalize(Args a) {
+    const int f = blockIdx.x;
+    __shared__ float red[WG];
+    float s = 0.0f;
+    for (int t = threadIdx.x; t < a.tiles; t += WG) s += a.loss_part[static_cast<int64_t>(f) * a.tiles + t];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = WG / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.loss[f] = overflowed(a.status) ? 0.0f : red[0] * a.loss_norm;
+}
+
+template <int B>
+__global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
+    if (overflowed(a.status)) return;
+    const int f = blockIdx.y;
+    const int tile = blockIdx.x;
+    const int txi = tile % a.tiles_x, tyi = tile / a.tiles_x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lx = ((w & 1) << 3) | (lane & 7), ly = ((w >> 1) << 3) | (lane >> 3);
+    const int px = txi * TILE + lx, py = tyi * TILE + ly;
+    const bool inside = px < a.width && py < a.height;
+    const int64_t seg = static_cast<int64_t>(f) * a.tiles + tile;
+    uint32_t s, e;
+    bucket_range(a, seg, s, e);
+    const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
+    const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
+
+    __shared__ Staged sh[B];
+    __shared__ float shb[B];
+    __shared__ uint32_t shm[B];
+    __shared__ float acc[WG / 64][9][B];
+    __shared__ uint32_t smax;
+
+    // per-pixel state: T after the current entry, colour composited behind it
+    float T = 1.0f, S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+    uint32_t last = 0;
+    if (inside) {
+        const int64_t P = static_cast<int64_t>(a.width) * a.height;
+        const int64_t pix = static_cast<int64_t>(py) * a.width + px;
+        T = a.tfin[static_cast<int64_t>(f) * P + pix];
+        last = a.nlast[static_cast<int64_t>(f) * P + pix];
+        const int64_t o3 = static_cast<int64_t>(f) * 3 * P + pix;
+        if (a.targets) {
+            g0 = (a.images[o3] - a.targets[o3]) * a.loss_scale;
+            g1 = (a.images[o3 + P] - a.targets[o3 + P]) * a.loss_scale;
+            g2 = (a.images[o3 + 2 * P] - a.targets[o3 + 2 * P]) * a.loss_scale;
+        } else {
+            g0 = a.dl_dimages[o3];
+            g1 = a.dl_dimages[o3 + P];
+            g2 = a.dl_dimages[o3 + 2 * P];
+        }
+        S0 = T * a.bg[0];
+        S1 = T * a.bg[1];
+        S2 = T * a.bg[2];
+    }
+    if (tid == 0) smax = 0;
+    __syncthreads();
+    if (last) atomicMax(&smax, last);
+    __syncthreads();
+    const uint32_t used = smax;
+    // entries no pixel reached get zero partials
+    for (uint32_t i = s + used + tid; i < e; i += WG) {
+        const uint32_t slot = a.sslot[i];
+        if (slot >= a.k_cap) continue;
+        a.partA[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
+        a.partB[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
+        a.partC[slot] = 0.f;
+    }
+    const float fx = static_cast<float>(lx), fy = static_cast<float>(ly);
+
+    for (int64_t bend = static_cast<int64_t>(s) + used; bend > s; bend -= B) {
+        const uint32_t b0 = static_cast<uint32_t>(bend - B > s ? bend - B : s);
+        const uint32_t nb = static_cast<uint32_t>(bend - b0);
+        if (tid < static_cast<int>(nb)) {
+            Staged st;
+            float blue;
+            uint32_t m;
+            stage_entry(a, f, a.sgid[b0 + tid], ox, oy, xlim, ylim, st, blue, m);
+            sh[tid] = st;
+            shb[tid] = blue;
+            shm[tid] = m;
+        }
+        for (int k = tid; k < (WG / 64) * 9 * B; k += WG) (&acc[0][0][0])[k] = 0.0f;
+        __syncthreads();
+        for (int j = static_cast<int>(nb) - 1; j >= 0; --j) {
+            const uint32_t m = __builtin_amdgcn_readfirstlane(shm[j]);
+            if (!((m >> w) & 1u)) continue;
+            const uint32_t rel = b0 + j - s;
+            float du = 0.f, dv = 0.f, da = 0.f, db = 0.f, dc = 0.f, dop = 0.f, dr = 0.f, dg = 0.f, dbl = 0.f;
+            bool hit = false;
+            if (rel < last) {
+                const float4 p0 = sh[j].p0;
+                const float4 p1 = sh[j].p1;
+                const float dx = fx - p0.x, dy = fy - p0.y;
+                const float q = footprint_q(dx, dy, p0, p1);
+                if (q <= Q_MAX) {
+                    const float G = gauss_falloff(q);
+                    const float raw = p1.y * G;
+                    const float al = fminf(ALPHA_MAX, raw);
+                    if (al >= ALPHA_MIN) {
+                        hit = true;
+                        const float inv = 1.0f / (1.0f - al);
+                        const float Tj = T * inv;  // transmittance in front of this entry
+                        const float wgt = al * Tj;
+                        const float cb = shb[j];
+                        dr = wgt * g0;
+                        dg = wgt * g1;
+                        dbl = wgt * g2;
+                        const float dal = g0 * (p1.z * Tj - S0 * inv) + g1 * (p1.w * Tj - S1 * inv) +
+                                          g2 * (cb * Tj - S2 * inv);
+                        S0 = __builtin_fmaf(p1.z, wgt, S0);
+                        S1 = __builtin_fmaf(p1.w, wgt, S1);
+                        S2 = __builtin_fmaf(cb, wgt, S2);
+                        T = Tj;
+                        if (raw < ALPHA_MAX) {
+                            dop = dal * G;
+                            const float dq = -0.5f * al * dal;
+                            da = dq * dx * dx;
+                            db = 2.0f * dq * dx * dy;
+                            dc = dq * dy * dy;
+                            const float hb = 0.5f * p0.w;
+                            du = -2.0f * dq * (p0.z * dx + hb * dy);
+                            dv = -2.0f * dq * (hb * dx + p1.x * dy);
+                        }
+                    }
+                }
+            }
+            if (__ballot(hit) != 0ull) {
+                du = wave_sum_to_lane63(du);
+                dv = wave_sum_to_lane63(dv);
+                da = wave_sum_to_lane63(da);
+                db = wave_sum_to_lane63(db);
+                dc = wave_sum_to_lane63(dc);
+                dop = wave_sum_to_lane63(dop);
+                dr = wave_sum_to_lane63(dr);
+                dg = wave_sum_to_lane63(dg);
+                dbl = wave_sum_to_lane63(dbl);
+                if (lane == 63) {
+                    acc[w][0][j] = du; acc[w][1][j] = dv; acc[w][2][j] = da;
+                    acc[w][3][j] = db; acc[w][4][j] = dc; acc[w][5][j] = dop;
+                    acc[w][6][j] = dr; acc[w][7][j] = dg; acc[w][8][j] = dbl;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < static_cast<int>(nb)) {
+            float v[9];
+            for (int k = 0; k < 9; ++k) v[k] = (acc[0][k][tid] + acc[1][k][tid]) + (acc[2][k][tid] + acc[3][k][tid]);
+            const uint32_t slot = a.sslot[b0 + tid];
+            if (slot < a.k_cap) {
+                a.partA[slot] = make_float4(v[0], v[1], v[2], v[3]);
+                a.partB[slot] = make_float4(v[4], v[5], v[6], v[7]);
+                a.partC[slot] = v[8];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_composite_fwd(const Args& a, hipStream_t stream) {
+    const dim3 grid(static_cast<uint32_t>(a.tiles), static_cast<uint32_t>(a.frames)), block(WG);
+    switch (a.tune.batch) {
+        case 64: hipLaunchKernelGGL(k_composite_fwd<64>, grid, block, 0, stream, a); break;
+        case 128: hipLaunchKernelGGL(k_composite_fwd<128>, grid, block, 0, stream, a); break;
+        default: hipLaunchKernelGGL(k_composite_fwd<256>, grid, block, 0, stream, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_finalize(const Args& a, hipStream_t stream) {
+    hipLaunchKernelGGL(k_loss_finalize, dim3(static_cast<uint32_t>(a.frames)), dim3(WG), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_composite_bwd(const Args& a, hipStream_t stream) {
+    const dim3 grid(static_cast<uint32_t>(a.tiles), static_cast<uint32_t>(a.frames)), block(WG);
+    switch (a.tune.batch) {
+        case 64: hipLaunchKernelGGL(k_composite_bwd<64>, grid, block, 0, stream, a); break;
+        case 128: hipLaunchKernelGGL(k_composite_bwd<128>, grid, block, 0, stream, a); break;
+        default: hipLaunchKernelGGL(k_composite_bwd<256>, grid, block, 0, stream, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gv

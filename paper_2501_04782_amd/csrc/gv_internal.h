@@ -1,0 +1,349 @@
+// Internal declarations of the gfx950 rasterizer: workspace layout, kernel
+// argument block, device helpers.  Not part of the public ABI (include/gv.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gv.h"
+
+namespace gv {
+
+// 16x16 pixel tiles; a 256-thread workgroup owns one tile, each of its four
+// waves one 8x8 quadrant, each lane one pixel.
+constexpr int TILE = 16;
+constexpr int WG = 256;
+
+// Compositing constants of the 3DGS forward model.
+constexpr float ALPHA_MAX = 0.99f;
+constexpr float ALPHA_MIN = 1.0f / 255.0f;
+constexpr float T_MIN = 1e-4f;
+constexpr float Q_MAX = 9.0f;
+// -0.5 * log2(e): exp(-q/2) = exp2(q * K_EXP)
+constexpr float K_EXP = -0.72134752044448170368f;
+
+// Conservative slack of the binning tests relative to the per-pixel test
+// (which runs in fp32 on the same rounded conic).
+constexpr double BIN_Q_SLACK = 9.0 * (1.0 + 1e-5) + 1e-6;
+constexpr float SUB_Q_SLACK = 9.0f * (1.0f + 1e-4f) + 1e-4f;
+
+// Per (frame, Gaussian) projected record, 32 bytes (one aligned half-line).
+// (u, v) stays in fp64 so that the tile-local offsets formed at staging time
+// are exact to fp32 rounding of a small number.
+struct __align__(32) Record {
+    double u, v;
+    float a, b, c;   // conic A = [[a, b], [b, c]]
+    float depth;     // camera-space z rounded to fp32 (the sort key)
+};
+
+// Per Gaussian, shared by all frames: RGB + opacity.
+struct __align__(16) ColorOp {
+    float r, g, b, o;
+};
+
+// Status word at the start of every workspace.
+enum : int { ST_OVERFLOW = 0, ST_NONFINITE = 1, ST_K_LO = 2, ST_K_HI = 3, ST_WORDS = 16 };
+
+struct Tuning {
+    int batch;      // 64 / 128 / 256 entries per LDS round of the composite kernels
+    int sort_cap;   // 1024 / 2048 / 4096
+    int bwd_block;  // threads per workgroup of the projection adjoint
+};
+
+// Byte offsets of the workspace regions (host-computed).
+struct Layout {
+    int64_t n;
+    int frames, width, height, tiles_x, tiles_y, tiles;
+    int64_t pixels;        // width * height
+    int64_t k_cap;
+    int64_t scan_blocks;   // for the (frames*n) scan
+    int64_t pose_blocks;   // workgroups of the projection adjoint (upper bound)
+    size_t status, col4, rec, rect, gcnt, goff, tcnt, toff, tcur, scan_tmp, tfin, nlast, loss_part, pose_part,
+        keys, kslot, sgid, sslot, partA, partB, partC, tkeys, tslot;
+    size_t total;
+};
+
+Layout make_layout(const gv_camera& cam, int64_t n, int frames, int64_t k_cap);
+
+// Everything a kernel needs, passed by value.
+struct Args {
+    // scene
+    int64_t n;
+    int dtype;
+    const void* means;
+    const void* log_scales;
+    const void* quats;
+    const void* opacity_logits;
+    const void* colors;
+    const void* mean_coeffs;
+    // camera
+    int width, height, tiles_x, tiles_y, tiles;
+    float fx, fy, cx, cy, near_plane, dilation, bg[3];
+    // frames
+    int frames;
+    const float* poses;   // [F][7]
+    const float* times;   // [F] or nullptr (then every frame uses t0)
+    float t0;
+    // workspace
+    uint32_t* status;
+    ColorOp* col4;
+    Record* rec;          // [F][N]
+    uint2* rect;          // [F][N]: (x0 | x1 << 16, y0 | y1 << 16) in tiles
+    uint32_t* gcnt;       // [F*N]
+    uint32_t* goff;       // [F*N + 1]
+    uint32_t* tcnt;       // [F*T]
+    uint32_t* toff;       // [F*T + 1]
+    uint32_t* tcur;       // [F*T]
+    float* tfin;          // [F][P]
+    uint32_t* nlast;      // [F][P]
+    float* loss_part;     // [F*T]
+    double* pose_part;    // [blocks][F][12]
+    uint64_t* keys;       // [K]
+    uint32_t* kslot;      // [K]
+    uint32_t* sgid;       // [K]
+    uint32_t* sslot;      // [K]
+    float4* partA;        // [K] (du, dv, dA00, dA01)
+    float4* partB;        // [K] (dA11, do, dr, dg)
+    float* partC;         // [K] db
+    uint64_t* tkeys;      // [K] merge scratch of the sort
+    uint32_t* tslot;      // [K]
+    int64_t k_cap;
+    // image-space inputs/outputs
+    float* images;            // [F][3][H][W]
+    const float* targets;     // [F][3][H][W] or nullptr
+    const float* dl_dimages;  // [F][3][H][W] or nullptr
+    float loss_scale;         // d(loss)/d(C) = loss_scale * (C - target)
+    float loss_norm;          // loss = loss_norm * sum (C - target)^2
+    float* loss;              // [F] or nullptr
+    float* tfin_out;          // optional copy of T_final (single frame)
+    // gradients
+    float* g_means;
+    float* g_log_scales;
+    float* g_quats;
+    float* g_opacity;
+    float* g_colors;
+    float* g_coeffs;
+    float* g_poses;           // [F][7]
+    int accumulate;
+    Tuning tune;
+};
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+
+__device__ __forceinline__ double load_param(const void* base, int dtype, int64_t i) {
+    if (dtype == GV_BF16) return static_cast<double>(bf16_to_f32(static_cast<const uint16_t*>(base)[i]));
+    return static_cast<double>(static_cast<const float*>(base)[i]);
+}
+
+// Rotation matrix (row-major) of the unit quaternion (w, x, y, z).
+__device__ __forceinline__ void rot_from_quat(double w, double x, double y, double z, double R[9]) {
+    const double xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z, wx = w * x,
+                 wy = w * y, wz = w * z;
+    R[0] = 1.0 - 2.0 * (yy + zz); R[1] = 2.0 * (xy - wz);       R[2] = 2.0 * (xz + wy);
+    R[3] = 2.0 * (xy + wz);       R[4] = 1.0 - 2.0 * (xx + zz); R[5] = 2.0 * (yz - wx);
+    R[6] = 2.0 * (xz - wy);       R[7] = 2.0 * (yz + wx);       R[8] = 1.0 - 2.0 * (xx + yy);
+}
+
+// Gradient w.r.t. an unnormalised quaternion q (norm qn, unit qh) given the
+// gradient G (row-major 3x3) w.r.t. R(qh).
+__device__ __forceinline__ void quat_grad(const double qh[4], double qn, const double G[9], double dq[4]) {
+    const double w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+    const double gw = 2.0 * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
+    const double gx = 2.0 * (y * G[1] + z * G[2] + y * G[3] - 2.0 * x * G[4] - w * G[5] + z * G[6] + w * G[7] -
+                             2.0 * x * G[8]);
+    const double gy = 2.0 * (-2.0 * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] + z * G[7] -
+                             2.0 * y * G[8]);
+    const double gz = 2.0 * (-2.0 * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2.0 * z * G[4] + y * G[5] +
+                             x * G[6] + y * G[7]);
+    const double dot = w * gw + x * gx + y * gy + z * gz;
+    dq[0] = (gw - w * dot) / qn;
+    dq[1] = (gx - x * dot) / qn;
+    dq[2] = (gy - y * dot) / qn;
+    dq[3] = (gz - z * dot) / qn;
+}
+
+// Camera of frame f: rotation (row-major), translation, normalised quaternion.
+struct CamD {
+    double R[9], t[3], qh[4], qn;
+    bool ok;
+};
+
+__device__ __forceinline__ CamD load_camera(const float* pose7) {
+    CamD c;
+    const double w = pose7[0], x = pose7[1], y = pose7[2], z = pose7[3];
+    c.qn = sqrt(w * w + x * x + y * y + z * z);
+    c.ok = c.qn > 0.0 && isfinite(c.qn);
+    const double qn = c.ok ? c.qn : 1.0;
+    c.qh[0] = w / qn; c.qh[1] = x / qn; c.qh[2] = y / qn; c.qh[3] = z / qn;
+    rot_from_quat(c.qh[0], c.qh[1], c.qh[2], c.qh[3], c.R);
+    c.t[0] = pose7[4]; c.t[1] = pose7[5]; c.t[2] = pose7[6];
+    c.ok = c.ok && isfinite(c.t[0]) && isfinite(c.t[1]) && isfinite(c.t[2]);
+    return c;
+}
+
+// FP64 projection state of one Gaussian in one frame (EWA splatting).
+struct ProjD {
+    double mu[3], s[3], qh[4], qn, R[9], M[9];
+    double Sig[6];        // xx xy xz yy yz zz
+    double m[3];
+    double u, v;
+    double T[6];          // J Rc, 2x3 row-major
+    double cov[3];        // 00 01 11 (dilated)
+    double A[3];          // conic 00 01 11
+    double o;
+    double eta;
+    bool nonfinite;
+};
+
+// Returns true if the Gaussian is in front of the near plane with a valid
+// footprint.  P.nonfinite marks non-finite inputs.
+__device__ __forceinline__ bool project_gaussian(const Args& a, int64_t g, const CamD& cam, double t, ProjD& P) {
+    const int64_t n = a.n;
+    double raw[14];
+    for (int k = 0; k < 3; ++k) raw[k] = load_param(a.means, a.dtype, k * n + g);
+    for (int k = 0; k < 3; ++k) raw[3 + k] = load_param(a.log_scales, a.dtype, k * n + g);
+    for (int k = 0; k < 4; ++k) raw[6 + k] = load_param(a.quats, a.dtype, k * n + g);
+    raw[10] = load_param(a.opacity_logits, a.dtype, g);
+    for (int k = 0; k < 3; ++k) raw[11 + k] = load_param(a.colors, a.dtype, k * n + g);
+    bool fin = true;
+    for (int k = 0; k < 14; ++k) fin = fin && isfinite(raw[k]);
+    for (int k = 0; k < 3; ++k) {
+        double mu = raw[k];
+        if (a.mean_coeffs) {
+            const double c1 = load_param(a.mean_coeffs, a.dtype, (0 * 3 + k) * n + g);
+            const double c2 = load_param(a.mean_coeffs, a.dtype, (1 * 3 + k) * n + g);
+            const double c3 = load_param(a.mean_coeffs, a.dtype, (2 * 3 + k) * n + g);
+            fin = fin && isfinite(c1) && isfinite(c2) && isfinite(c3);
+            // same left-to-right order as mu0 + a1 t + a2 t t + a3 t t t
+            mu = mu + c1 * t + c2 * t * t + c3 * t * t * t;
+        }
+        P.mu[k] = mu;
+    }
+    P.nonfinite = !fin;
+    if (!fin || !cam.ok) return false;
+    P.qn = sqrt(raw[6] * raw[6] + raw[7] * raw[7] + raw[8] * raw[8] + raw[9] * raw[9]);
+    if (!(P.qn > 0.0)) return false;
+    for (int k = 0; k < 4; ++k) P.qh[k] = raw[6 + k] / P.qn;
+    for (int k = 0; k < 3; ++k) P.s[k] = exp(raw[3 + k]);
+    P.eta = raw[10];
+    P.o = 1.0 / (1.0 + exp(-raw[10]));
+    rot_from_quat(P.qh[0], P.qh[1], P.qh[2], P.qh[3], P.R);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) P.M[i * 3 + j] = P.R[i * 3 + j] * P.s[j];
+    const double* M = P.M;
+    P.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+    P.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+    P.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+    P.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+    P.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+    P.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+    const double* Rc = cam.R;
+    // m = tc + Rc mu, summed in this order (with no contraction the fp32
+    // rounding of m_z, the depth sort key, is then reproducible bit for bit)
+    for (int i = 0; i < 3; ++i)
+        P.m[i] = ((cam.t[i] + Rc[i * 3 + 0] * P.mu[0]) + Rc[i * 3 + 1] * P.mu[1]) + Rc[i * 3 + 2] * P.mu[2];
+    if (!(P.m[2] > static_cast<double>(a.near_plane))) return false;
+    const double iz = 1.0 / P.m[2];
+    const double fx = a.fx, fy = a.fy;
+    P.u = fx * P.m[0] * iz + static_cast<double>(a.cx);
+    P.v = fy * P.m[1] * iz + static_cast<double>(a.cy);
+    // J = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]];  T = J Rc
+    const double j00 = fx * iz, j02 = -fx * P.m[0] * iz * iz;
+    const double j11 = fy * iz, j12 = -fy * P.m[1] * iz * iz;
+    for (int j = 0; j < 3; ++j) {
+        P.T[j] = j00 * Rc[0 * 3 + j] + j02 * Rc[2 * 3 + j];
+        P.T[3 + j] = j11 * Rc[1 * 3 + j] + j12 * Rc[2 * 3 + j];
+    }
+    // cov = T Sig T^T + dil I
+    double TS[6];
+    for (int i = 0; i < 2; ++i) {
+        const double t0 = P.T[i * 3 + 0], t1 = P.T[i * 3 + 1], t2 = P.T[i * 3 + 2];
+        TS[i * 3 + 0] = t0 * P.Sig[0] + t1 * P.Sig[1] + t2 * P.Sig[2];
+        TS[i * 3 + 1] = t0 * P.Sig[1] + t1 * P.Sig[3] + t2 * P.Sig[4];
+        TS[i * 3 + 2] = t0 * P.Sig[2] + t1 * P.Sig[4] + t2 * P.Sig[5];
+    }
+    const double dil = a.dilation;
+    P.cov[0] = TS[0] * P.T[0] + TS[1] * P.T[1] + TS[2] * P.T[2] + dil;
+    P.cov[1] = TS[0] * P.T[3] + TS[1] * P.T[4] + TS[2] * P.T[5];
+    P.cov[2] = TS[3] * P.T[3] + TS[4] * P.T[4] + TS[5] * P.T[5] + dil;
+    const double det = P.cov[0] * P.cov[2] - P.cov[1] * P.cov[1];
+    if (!(det > 0.0) || !isfinite(det)) return false;
+    const double idet = 1.0 / det;
+    P.A[0] = P.cov[2] * idet;
+    P.A[1] = -P.cov[1] * idet;
+    P.A[2] = P.cov[0] * idet;
+    return true;
+}
+
+// Does the ellipse {p : (p-c)^T A (p-c) <= thr} meet the axis-aligned box
+// [x0,x1] x [y0,y1]?  Exact minimum of the quadratic over the box: zero when
+// the centre is inside, else the smallest of the four edge minima.
+template <typename F>
+__device__ __forceinline__ bool ellipse_meets_box(F u, F v, F a, F b, F c, F x0, F x1, F y0, F y1, F thr) {
+    const F dx0 = x0 - u, dx1 = x1 - u, dy0 = y0 - v, dy1 = y1 - v;
+    if (dx0 <= F(0) && dx1 >= F(0) && dy0 <= F(0) && dy1 >= F(0)) return true;
+    auto on_x_edge = [&](F dx) {
+        F dy = -b * dx / c;
+        dy = dy < dy0 ? dy0 : (dy > dy1 ? dy1 : dy);
+        return a * dx * dx + F(2) * b * dx * dy + c * dy * dy;
+    };
+    auto on_y_edge = [&](F dy) {
+        F dx = -b * dy / a;
+        dx = dx < dx0 ? dx0 : (dx > dx1 ? dx1 : dx);
+        return a * dx * dx + F(2) * b * dx * dy + c * dy * dy;
+    };
+    F m = on_x_edge(dx0);
+    F t1 = on_x_edge(dx1);
+    m = t1 < m ? t1 : m;
+    t1 = on_y_edge(dy0);
+    m = t1 < m ? t1 : m;
+    t1 = on_y_edge(dy1);
+    m = t1 < m ? t1 : m;
+    return m <= thr;
+}
+
+// Pixel-centre box of tile (tx, ty), clipped to the image.
+__device__ __forceinline__ void tile_box(int tx, int ty, int W, int H, double& x0, double& x1, double& y0,
+                                         double& y1) {
+    x0 = tx * TILE + 0.5;
+    x1 = fmin(tx * TILE + (TILE - 0.5), W - 0.5);
+    y0 = ty * TILE + 0.5;
+    y1 = fmin(ty * TILE + (TILE - 0.5), H - 0.5);
+}
+
+// Sum of v over the 64 lanes of a wave, valid in lane 63 (DPP row shifts
+// within each row of 16, then row broadcasts across rows).
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x111, 0xf, 0xf, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x112, 0xf, 0xf, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x114, 0xf, 0xf, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x118, 0xf, 0xf, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xa, 0xf, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xc, 0xf, false));
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Entry range [s, e) of bucket `seg`, clamped to the intersection capacity.
+__device__ __forceinline__ void bucket_range(const Args& a, int64_t seg, uint32_t& s, uint32_t& e) {
+    const uint32_t cap = static_cast<uint32_t>(a.k_cap);
+    e = min(a.toff[seg + 1], cap);
+    s = min(a.toff[seg], e);
+}
+
+__device__ __forceinline__ bool overflowed(const uint32_t* status) {
+    return status[ST_OVERFLOW] != 0u;
+}
+
+}  // namespace gv

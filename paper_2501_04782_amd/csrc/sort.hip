@@ -1,0 +1,130 @@
+// Per-tile depth sort.  The binning pass already grouped the intersections by
+// (frame, tile) (a counting sort on the tile digit); each tile's bucket is
+// then sorted by the 64-bit key (fp32 depth bits, Gaussian index) in LDS by
+// one workgroup.  Keys are unique within a bucket, so the order is fully
+// determined (depth, ties by lower index) whatever order the atomics of the
+// scatter produced.  Buckets longer than the LDS capacity are sorted in LDS
+// chunks and merged in global memory (each element finds its place in the
+// partner run by binary search).
+#include "gv_internal.h"
+
+namespace gv {
+
+template <int CAP>
+__device__ __forceinline__ void bitonic_lds(uint64_t* K, uint32_t* V, int m) {
+    for (int k = 2; k <= m; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int p = threadIdx.x; p < (m >> 1); p += WG) {
+                const int i = 2 * j * (p / j) + (p % j);
+                const int l = i + j;
+                const bool asc = (i & k) == 0;
+                const uint64_t ki = K[i], kl = K[l];
+                if ((ki > kl) == asc) {
+                    K[i] = kl;
+                    K[l] = ki;
+                    const uint32_t t = V[i];
+                    V[i] = V[l];
+                    V[l] = t;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ __forceinline__ int next_pow2(int x) {
+    int m = 2;
+    while (m < x) m <<= 1;
+    return m;
+}
+
+// Number of elements of the sorted run R[0, len) strictly smaller than key.
+__device__ __forceinline__ int64_t lower_rank(const uint64_t* R, int64_t len, uint64_t key) {
+    int64_t lo = 0, hi = len;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (R[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int CAP>
+__global__ __launch_bounds__(WG) void k_tile_sort(Args a) {
+    if (overflowed(a.status)) return;
+    const int64_t seg = blockIdx.x;
+    uint32_t s, e;
+    bucket_range(a, seg, s, e);
+    const int64_t n = static_cast<int64_t>(e) - s;
+    if (n <= 0) return;
+    __shared__ uint64_t K[CAP];
+    __shared__ uint32_t V[CAP];
+    if (n <= CAP) {
+        const int m = next_pow2(static_cast<int>(n));
+        for (int i = threadIdx.x; i < m; i += WG) {
+            K[i] = i < n ? a.keys[s + i] : ~0ull;
+            V[i] = i < n ? a.kslot[s + i] : 0u;
+        }
+        __syncthreads();
+        bitonic_lds<CAP>(K, V, m);
+        for (int i = threadIdx.x; i < n; i += WG) {
+            a.sgid[s + i] = static_cast<uint32_t>(K[i]);
+            a.sslot[s + i] = V[i];
+        }
+        return;
+    }
+    // Long bucket: sorted runs of CAP in place, then pairwise merges.
+    uint64_t* srcK = a.keys + s;
+    uint32_t* srcV = a.kslot + s;
+    uint64_t* dstK = a.tkeys + s;
+    uint32_t* dstV = a.tslot + s;
+    for (int64_t c0 = 0; c0 < n; c0 += CAP) {
+        const int len = static_cast<int>(n - c0 < CAP ? n - c0 : CAP);
+        const int m = next_pow2(len);
+        for (int i = threadIdx.x; i < m; i += WG) {
+            K[i] = i < len ? srcK[c0 + i] : ~0ull;
+            V[i] = i < len ? srcV[c0 + i] : 0u;
+        }
+        __syncthreads();
+        bitonic_lds<CAP>(K, V, m);
+        for (int i = threadIdx.x; i < len; i += WG) {
+            srcK[c0 + i] = K[i];
+            srcV[c0 + i] = V[i];
+        }
+        __syncthreads();
+    }
+    for (int64_t w = CAP; w < n; w <<= 1) {
+        for (int64_t lo = 0; lo < n; lo += 2 * w) {
+            const int64_t mid = lo + w < n ? lo + w : n;
+            const int64_t hi = lo + 2 * w < n ? lo + 2 * w : n;
+            for (int64_t i = lo + threadIdx.x; i < hi; i += WG) {
+                const uint64_t key = srcK[i];
+                int64_t pos;
+                if (i < mid) pos = lo + (i - lo) + lower_rank(srcK + mid, hi - mid, key);
+                else pos = lo + (i - mid) + lower_rank(srcK + lo, mid - lo, key);
+                dstK[pos] = key;
+                dstV[pos] = srcV[i];
+            }
+        }
+        __syncthreads();
+        uint64_t* tk = srcK; srcK = dstK; dstK = tk;
+        uint32_t* tv = srcV; srcV = dstV; dstV = tv;
+    }
+    for (int64_t i = threadIdx.x; i < n; i += WG) {
+        a.sgid[s + i] = static_cast<uint32_t>(srcK[i]);
+        a.sslot[s + i] = srcV[i];
+    }
+}
+
+hipError_t launch_tile_sort(const Args& a, int64_t segments, hipStream_t stream) {
+    if (segments <= 0) return hipSuccess;
+    const dim3 grid(static_cast<uint32_t>(segments)), block(WG);
+    switch (a.tune.sort_cap) {
+        case 1024: hipLaunchKernelGGL(k_tile_sort<1024>, grid, block, 0, stream, a); break;
+        case 2048: hipLaunchKernelGGL(k_tile_sort<2048>, grid, block, 0, stream, a); break;
+        default: hipLaunchKernelGGL(k_tile_sort<4096>, grid, block, 0, stream, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gv

@@ -1,0 +1,119 @@
+"""C-ABI library: loads, exports every entry point of include/gv.h, and the
+host-only calls validate their arguments (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2501_04782_amd import _lib as L
+from paper_2501_04782_amd.raster import Camera
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "gv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gv_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    lib = L.load()
+    decl = declared_symbols()
+    assert len(decl) >= 19
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert sorted(L.EXPORTED) == decl
+
+
+def test_status_strings_and_version():
+    lib = L.load()
+    assert lib.gv_abi_version() == 1
+    for s in range(6):
+        assert lib.gv_status_str(s)
+    assert lib.gv_status_str(L.GV_ERR_CAPACITY) == b"intersection capacity exceeded"
+
+
+def cam(w=960, h=540):
+    return Camera(w, h, float(w), float(w), w / 2, h / 2)
+
+
+def test_workspace_sizing_and_validation():
+    lib = L.load()
+    out = ctypes.c_size_t()
+    c = cam()
+    assert lib.gv_workspace_bytes(ctypes.byref(c.c()), 1000, 2, 5000, ctypes.byref(out)) == L.GV_OK
+    small = out.value
+    assert lib.gv_workspace_bytes(ctypes.byref(c.c()), 1000, 2, 50000, ctypes.byref(out)) == L.GV_OK
+    assert out.value > small + 45000 * 60  # per-intersection storage
+    cap = ctypes.c_int64()
+    assert lib.gv_workspace_capacity(ctypes.byref(c.c()), 1000, 2, out.value, ctypes.byref(cap)) == L.GV_OK
+    assert 50000 <= cap.value < 50010
+    # invalid arguments
+    assert lib.gv_workspace_bytes(ctypes.byref(c.c()), -1, 2, 10, ctypes.byref(out)) == L.GV_ERR_INVALID_ARG
+    assert lib.gv_workspace_bytes(ctypes.byref(c.c()), 10, 0, 10, ctypes.byref(out)) == L.GV_ERR_INVALID_ARG
+    assert lib.gv_workspace_bytes(ctypes.byref(c.c()), 10, 1, -5, ctypes.byref(out)) == L.GV_ERR_INVALID_ARG
+    assert lib.gv_workspace_bytes(None, 10, 1, 5, ctypes.byref(out)) == L.GV_ERR_INVALID_ARG
+    bad = cam()
+    bad.width = 0
+    assert lib.gv_workspace_bytes(ctypes.byref(bad.c()), 10, 1, 5, ctypes.byref(out)) == L.GV_ERR_INVALID_ARG
+    bad = cam()
+    bad.near_plane = 0.0
+    assert lib.gv_workspace_bytes(ctypes.byref(bad.c()), 10, 1, 5, ctypes.byref(out)) == L.GV_ERR_INVALID_ARG
+    bad = cam()
+    bad.fx = float("nan")
+    assert lib.gv_workspace_bytes(ctypes.byref(bad.c()), 10, 1, 5, ctypes.byref(out)) == L.GV_ERR_INVALID_ARG
+
+
+def test_entry_points_reject_bad_arguments_before_touching_the_device():
+    lib = L.load()
+    c = cam(64, 48)
+    sc = L.GvScene()
+    sc.n, sc.dtype = 10, 7  # unknown dtype
+    assert lib.gv_render_fwd(ctypes.byref(sc), ctypes.byref(c.c()), ctypes.c_void_p(256), 0.0,
+                             ctypes.c_void_p(256), None, ctypes.c_void_p(256), 1 << 20, None) == L.GV_ERR_INVALID_ARG
+    sc.dtype = L.GV_F32  # null parameter pointers with n > 0
+    assert lib.gv_render_fwd(ctypes.byref(sc), ctypes.byref(c.c()), ctypes.c_void_p(256), 0.0,
+                             ctypes.c_void_p(256), None, ctypes.c_void_p(256), 1 << 20, None) == L.GV_ERR_INVALID_ARG
+    sc.n = 0  # valid empty scene but misaligned workspace
+    assert lib.gv_render_fwd(ctypes.byref(sc), ctypes.byref(c.c()), ctypes.c_void_p(256), 0.0,
+                             ctypes.c_void_p(256), None, ctypes.c_void_p(257), 1 << 20, None) == L.GV_ERR_WORKSPACE
+    # workspace too small
+    assert lib.gv_render_fwd(ctypes.byref(sc), ctypes.byref(c.c()), ctypes.c_void_p(256), 0.0,
+                             ctypes.c_void_p(256), None, ctypes.c_void_p(256), 16, None) == L.GV_ERR_WORKSPACE
+    # batch: unknown flag, missing targets for the L2 loss, zero frames
+    g = L.GvGrads()
+    for flags, frames in [(64, 2), (L.GV_FWD | L.GV_LOSS_L2, 2), (L.GV_FWD, 0), (0, 2)]:
+        st = lib.gv_render_batch(ctypes.byref(sc), ctypes.byref(c.c()), ctypes.c_void_p(256), None, frames, None,
+                                 None, flags, ctypes.c_void_p(256), None, ctypes.byref(g), None,
+                                 ctypes.c_void_p(256), 1 << 30, None)
+        assert st == L.GV_ERR_INVALID_ARG, (flags, frames)
+    # camera ODE
+    sz = ctypes.c_size_t()
+    assert lib.gv_camera_ode_workspace_bytes(100, 4, ctypes.byref(sz)) == L.GV_OK and sz.value > 396 * 4 * 136 * 4
+    assert lib.gv_camera_ode_workspace_bytes(0, 4, ctypes.byref(sz)) == L.GV_ERR_INVALID_ARG
+    assert lib.gv_camera_ode_fwd(None, None, 10, 4, None, None, 0, None) == L.GV_ERR_INVALID_ARG
+
+
+def test_tuning_table_validation():
+    lib = L.load()
+    t = L.GvTuning()
+    assert lib.gv_get_tuning(ctypes.byref(t)) == L.GV_OK
+    old = (t.batch, t.sort_cap)
+    assert t.batch in (64, 128, 256) and t.sort_cap in (1024, 2048, 4096)
+    t2 = L.GvTuning()
+    t2.batch, t2.sort_cap = 100, 4096
+    assert lib.gv_set_tuning(ctypes.byref(t2)) == L.GV_ERR_INVALID_ARG
+    t2.batch, t2.sort_cap = 128, 2048
+    assert lib.gv_set_tuning(ctypes.byref(t2)) == L.GV_OK
+    assert lib.gv_get_tuning(ctypes.byref(t)) == L.GV_OK and (t.batch, t.sort_cap) == (128, 2048)
+    t2.batch, t2.sort_cap = old
+    assert lib.gv_set_tuning(ctypes.byref(t2)) == L.GV_OK
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(L, "_LIB", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "libgv.so"))
+    with pytest.raises(RuntimeError, match="no fallback"):
+        L.load()

@@ -1,0 +1,363 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Run on an MI355X: ``python -u -m pytest tests -m gpu -x -v``.  Tolerances and
+the knife-edge rule are in parity_util.py.
+"""
+import numpy as np
+import pytest
+import torch
+
+import gv_synth
+import oracle
+from oracle import camera_ode as ode_ref
+from parity_util import (GRAD_TOL, PIXEL_TOL, compare_grads, compare_image, device_inputs, knife_edge, oracle_frame,
+                         planar_to_pixels, rel_err, workspace_for)
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2501_04782_amd import _lib as L
+    from paper_2501_04782_amd import camera as gvcam
+    from paper_2501_04782_amd import raster
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def small_workload(seed, W, H, n, F, trajectory=False, dtype="f32", cubic=False, z=(2.0, 6.0), ls=(-3.5, 0.3),
+                   bg=(0.0, 0.0, 0.0)):
+    rng = np.random.default_rng(seed)
+    scene = gv_synth.make_scene(rng, n, z=z, log_scale=ls, dtype=dtype, cubic=cubic)
+    cam = gv_synth.make_camera(W, H, float(W), bg=bg)
+    poses = gv_synth.make_trajectory(rng, F) if trajectory else gv_synth.identity_poses(F)
+    return dict(scene=scene, camera=cam, poses=poses, times=gv_synth.make_times(F), frames=F, n=n)
+
+
+def upstream_for(w, refs, seed):
+    """Random upstream gradient per frame [F][3][H][W], zero at knife-edge pixels."""
+    rng = np.random.default_rng(seed)
+    H, W = w["camera"].height, w["camera"].width
+    dl = rng.normal(0, 1, (w["frames"], 3, H, W)).astype(np.float32)
+    for f, r in enumerate(refs):
+        ke = knife_edge(r["margins"], grads=True).reshape(H, W)
+        dl[f][:, ke] = 0.0
+    return dl
+
+
+def run_clip(w, dl=None, targets=None, forward=True, backward=True):
+    scene, cam, poses, times = device_inputs(w)
+    ws = workspace_for(scene, cam, poses, times)
+    dlt = None if dl is None else torch.from_numpy(dl).cuda()
+    tg = None if targets is None else torch.from_numpy(targets).cuda()
+    out = raster.render_batch(scene, cam, poses, times, ws, targets=tg, dL_dimages=dlt, forward=forward,
+                              backward=backward)
+    torch.cuda.synchronize()
+    st = ws.status()
+    assert st["overflow"] == 0, st
+    return out, ws, (scene, cam, poses, times)
+
+
+def check_clip_against_oracle(w, label, seed=0):
+    say(f"[{label}] oracle forward")
+    refs = [oracle_frame(w, f) for f in range(w["frames"])]
+    dl = upstream_for(w, refs, seed)
+    say(f"[{label}] gpu batch fwd+bwd: F={w['frames']} N={w['n']} {w['camera'].width}x{w['camera'].height}")
+    out, ws, _ = run_clip(w, dl=dl)
+    imgs = out["images"].cpu().numpy()
+    stats = [compare_image(imgs[f], refs[f], f"{label} frame {f}") for f in range(w["frames"])]
+    say(f"[{label}] oracle backward")
+    g_ref, dposes_ref, _ = oracle.render_clip_grads(w["scene"], w["camera"], w["poses"].astype(np.float64),
+                                                    w["times"], range(w["frames"]), [None] * w["frames"],
+                                                    [planar_to_pixels(dl[f]) for f in range(w["frames"])])
+    ge = compare_grads(out["grads"], g_ref, label)
+    pe = rel_err(out["dL_dposes"].cpu().numpy(), dposes_ref)
+    assert pe <= GRAD_TOL, f"{label}: pose gradient relative error {pe:.3e}"
+    say(f"[{label}] pixels max|d|={max(s['max_abs'] for s in stats):.2e} knife-edge="
+        f"{sum(s['knife_edge'] for s in stats)}/{sum(s['pixels'] for s in stats)} grads={ge} pose={pe:.2e}")
+    return out
+
+
+# ---------------------------------------------------------------------------
+
+
+def test_project_records_match_oracle():
+    w = gv_synth.make_workload("frame128_n2k")
+    pose = np.array([0.995, 0.05, -0.06, 0.04, 0.05, -0.08, 0.2], np.float32)
+    scene, cam, _, _ = device_inputs(w)
+    ws = raster.Workspace(cam, scene.n, 1, 0)
+    rec, cnt = raster.project_fwd(scene, cam, torch.from_numpy(pose).cuda(), 0.0, ws)
+    rec, cnt = rec.cpu().numpy(), cnt.cpu().numpy()
+    ref = oracle.project(w["scene"], w["camera"], pose.astype(np.float64))
+    vis = cnt > 0
+    assert vis.sum() > 1500
+    assert np.all(ref["valid"][vis] == 1)
+    np.testing.assert_allclose(rec[vis, 0], ref["u"][vis], rtol=1e-6, atol=1e-4)
+    np.testing.assert_allclose(rec[vis, 1], ref["v"][vis], rtol=1e-6, atol=1e-4)
+    for k, name in [(2, "A00"), (3, "A01"), (4, "A11")]:
+        np.testing.assert_allclose(rec[vis, k], ref[name][vis], rtol=1e-6, atol=1e-7)
+    # the depth key is the fp32 rounding of the FP64 depth: bit-exact
+    assert np.array_equal(rec[vis, 5].astype(np.float32), ref["key"][vis].astype(np.float32))
+    np.testing.assert_allclose(rec[vis, 6], ref["opacity"][vis], rtol=1e-6)
+
+
+def test_frame128_forward_backward_per_frame_path():
+    """The plain per-frame path (render_fwd / render_bwd) on the 128x128, 2k
+    Gaussian frame with a rotated camera."""
+    w = gv_synth.make_workload("frame128_n2k")
+    w["poses"] = np.array([[0.995, 0.05, -0.06, 0.04, 0.05, -0.08, 0.2]], np.float32)
+    ref = oracle_frame(w, 0)
+    scene, cam, poses, times = device_inputs(w)
+    ws = workspace_for(scene, cam, poses, times)
+    Tf = torch.empty(128, 128, device="cuda")
+    img = raster.render_fwd(scene, cam, poses[0].contiguous(), 0.0, ws, T_final=Tf)
+    torch.cuda.synchronize()
+    s = compare_image(img.cpu().numpy(), ref, "frame128 fwd")
+    ke = knife_edge(ref["margins"])
+    np.testing.assert_allclose(Tf.cpu().numpy().reshape(-1)[~ke], ref["T_final"][~ke], atol=PIXEL_TOL)
+    dl = upstream_for(w, [ref], 5)[0]
+    g, dpose = raster.render_bwd(scene, cam, poses[0].contiguous(), 0.0, ws, img,
+                                 dL_dimage=torch.from_numpy(dl).cuda())
+    torch.cuda.synchronize()
+    gref = oracle_frame(w, 0, dL_dC=planar_to_pixels(dl))["grads"]
+    ge = compare_grads(g, gref, "frame128 bwd")
+    pe = rel_err(dpose.cpu().numpy(), gref["pose"])
+    assert pe <= GRAD_TOL, pe
+    say(f"frame128: {s} grads {ge} pose {pe:.2e}")
+
+
+@pytest.mark.parametrize("W,H", [(100, 75), (17, 33), (64, 16)])
+def test_ragged_image_sizes(W, H):
+    w = small_workload(1, W, H, 600, 2, trajectory=True, bg=(0.2, 0.1, 0.3))
+    check_clip_against_oracle(w, f"ragged {W}x{H}")
+
+
+ADVERSARIAL = ["huge", "offscreen", "near", "ties", "zero_opacity", "dense", "elongated"]
+
+
+@pytest.mark.parametrize("kind", ADVERSARIAL)
+def test_adversarial_scenes(kind):
+    rng = np.random.default_rng(100 + ADVERSARIAL.index(kind))
+    scene, cam = gv_synth.adversarial_scene(rng, 300, kind)
+    cam.bg = (0.1, 0.2, 0.3)
+    w = dict(scene=scene, camera=cam, poses=gv_synth.identity_poses(1), times=gv_synth.make_times(1), frames=1,
+             n=300)
+    check_clip_against_oracle(w, f"adversarial {kind}")
+
+
+def test_empty_and_single_gaussian():
+    for n in (0, 1):
+        w = small_workload(2, 40, 30, max(n, 1), 1, bg=(0.3, 0.5, 0.7))
+        if n == 0:
+            s = w["scene"]
+            w["scene"] = gv_synth.Scene("f32", s.means[:, :0].copy(), s.log_scales[:, :0].copy(),
+                                        s.quats[:, :0].copy(), s.opacity_logits[:0].copy(), s.colors[:, :0].copy())
+            w["n"] = 0
+            scene, cam, poses, times = device_inputs(w)
+            ws = raster.Workspace(cam, 0, 1, 16)
+            dl = torch.ones(1, 3, 30, 40, device="cuda")
+            out = raster.render_batch(scene, cam, poses, times, ws, dL_dimages=dl)
+            torch.cuda.synchronize()
+            img = out["images"][0].cpu().numpy()
+            assert np.all(img == np.array([0.3, 0.5, 0.7], np.float32)[:, None, None])
+            assert torch.all(out["dL_dposes"] == 0)
+        else:
+            w["scene"].means[:, 0] = [0.0, 0.0, 3.0]
+            w["scene"].log_scales[:, 0] = -1.5
+            check_clip_against_oracle(w, "single Gaussian")
+
+
+def test_clip_reduced_batch_matches_oracle():
+    """Batched path on a reduced clip: moving camera, several frames."""
+    w = small_workload(3, 160, 96, 3000, 4, trajectory=True, z=(2.0, 10.0), ls=(-3.2, 0.5))
+    check_clip_against_oracle(w, "clip 160x96 F=4")
+
+
+def test_batch_equals_per_frame_path():
+    w = small_workload(4, 128, 80, 2000, 3, trajectory=True)
+    rng = np.random.default_rng(9)
+    targets = rng.random((3, 3, 80, 128)).astype(np.float32)
+    out, ws, (scene, cam, poses, times) = run_clip(w, targets=targets)
+    F, H, W = 3, 80, 128
+    ws1 = raster.Workspace(cam, scene.n, 1, ws.k_capacity)
+    grads = raster.grad_buffers(scene)
+    scale = 2.0 / (3 * H * W * F)
+    for f in range(F):
+        img = raster.render_fwd(scene, cam, poses[f].contiguous(), float(times[f]), ws1)
+        raster.render_bwd(scene, cam, poses[f].contiguous(), float(times[f]), ws1, img,
+                          target=torch.from_numpy(targets[f]).cuda(), loss_scale=scale, grads=grads,
+                          accumulate=f > 0)
+        torch.cuda.synchronize()
+        assert torch.equal(img, out["images"][f]), f"frame {f} image differs"
+    for k in ("means", "log_scales", "quats", "opacity_logits", "colors"):
+        e = rel_err(grads[k].cpu().numpy(), out["grads"][k].cpu().numpy())
+        assert e < 1e-6, (k, e)
+    # the fused loss equals the mean squared error of the returned images
+    mse = float(((out["images"] - torch.from_numpy(targets).cuda()) ** 2).double().mean())
+    assert float(out["loss"].double().sum()) == pytest.approx(mse, rel=1e-5)
+
+
+def test_fused_l2_equals_explicit_upstream():
+    w = small_workload(5, 96, 64, 1500, 2, trajectory=True)
+    rng = np.random.default_rng(10)
+    targets = rng.random((2, 3, 64, 96)).astype(np.float32)
+    out, _, _ = run_clip(w, targets=targets)
+    dl = (2.0 * (out["images"] - torch.from_numpy(targets).cuda()) / out["images"].numel()).cpu().numpy()
+    out2, _, _ = run_clip(w, dl=dl)
+    for k in ("means", "log_scales", "quats", "opacity_logits", "colors"):
+        e = rel_err(out["grads"][k].cpu().numpy(), out2["grads"][k].cpu().numpy())
+        assert e < 1e-5, (k, e)
+
+
+def test_graph_replay_matches_eager():
+    w = small_workload(6, 96, 64, 1500, 3, trajectory=True)
+    rng = np.random.default_rng(11)
+    targets = torch.from_numpy(rng.random((3, 3, 64, 96)).astype(np.float32)).cuda()
+    scene, cam, poses, times = device_inputs(w)
+    ws = workspace_for(scene, cam, poses, times)
+    eager = raster.render_batch(scene, cam, poses, times, ws, targets=targets)
+    torch.cuda.synchronize()
+    ref = {k: (v.clone() if isinstance(v, torch.Tensor) else {kk: vv.clone() for kk, vv in v.items() if vv is not None})
+           for k, v in eager.items() if v is not None}
+    ws2 = workspace_for(scene, cam, poses, times)
+    g = raster.BatchGraph(scene, cam, poses, times, ws2, targets=targets)
+    junk = torch.randn(1 << 20, device="cuda")
+    for rep in range(3):
+        g.launch()
+        junk = junk * 1.0001 + 1.0  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(g.images, ref["images"]), rep
+        assert torch.equal(g.loss, ref["loss"]), rep
+        for k, v in ref["grads"].items():
+            assert torch.equal(g.grads[k], v), (rep, k)
+        assert torch.equal(g.dL_dposes, ref["dL_dposes"]), rep
+    g.close()
+
+
+def test_capacity_overflow_is_reported_and_recoverable():
+    w = small_workload(7, 96, 64, 1500, 2, trajectory=True)
+    scene, cam, poses, times = device_inputs(w)
+    ws = raster.Workspace(cam, scene.n, 1, 10)
+    with pytest.raises(L.GvError) as ei:
+        raster.render_fwd(scene, cam, poses[0].contiguous(), 0.0, ws)
+    assert ei.value.status == L.GV_ERR_CAPACITY
+    wsb = raster.Workspace(cam, scene.n, 2, 10)
+    dl = torch.ones(2, 3, 64, 96, device="cuda")
+    raster.render_batch(scene, cam, poses, times, wsb, dL_dimages=dl)
+    st = wsb.status()
+    assert st["overflow"] == 1 and st["intersections"] > 10
+    wsb = raster.Workspace(cam, scene.n, 2, st["intersections"])
+    raster.render_batch(scene, cam, poses, times, wsb, dL_dimages=dl)
+    assert wsb.status()["overflow"] == 0
+
+
+def test_determinism_bitwise():
+    w = small_workload(8, 128, 96, 3000, 2, trajectory=True)
+    rng = np.random.default_rng(12)
+    targets = rng.random((2, 3, 96, 128)).astype(np.float32)
+    a, _, _ = run_clip(w, targets=targets)
+    b, _, _ = run_clip(w, targets=targets)
+    assert torch.equal(a["images"], b["images"])
+    for k, v in a["grads"].items():
+        if v is not None:
+            assert torch.equal(v, b["grads"][k]), k
+    assert torch.equal(a["dL_dposes"], b["dL_dposes"])
+
+
+def test_bf16_cubic_means_reduced():
+    w = small_workload(13, 192, 108, 4000, 3, dtype="bf16", cubic=True, z=(2.0, 10.0), ls=(-3.0, 0.5))
+    check_clip_against_oracle(w, "bf16 cubic 192x108 F=3")
+
+
+@pytest.mark.parametrize("frames,substeps", [(1, 4), (12, 4), (100, 4)])
+def test_camera_ode_matches_oracle(frames, substeps):
+    rng = np.random.default_rng(frames)
+    theta = ode_ref.init_theta(rng, last_layer_scale=0.5).astype(np.float32)
+    q = rng.normal(0, 1, 4)
+    z0 = np.concatenate([q / np.linalg.norm(q), rng.normal(0, 0.2, 3)]).astype(np.float32)
+    ref = ode_ref.camera_ode_fwd(theta.astype(np.float64), z0.astype(np.float64), frames, substeps)
+    th, z = torch.from_numpy(theta).cuda(), torch.from_numpy(z0).cuda()
+    ws = gvcam.OdeWorkspace(frames, substeps)
+    poses = gvcam.camera_ode_fwd(th, z, frames, substeps, ws)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(poses.cpu().numpy(), ref, atol=2e-5)
+    dp = rng.normal(0, 1, (frames, 7)).astype(np.float32)
+    dth_ref, dz_ref = ode_ref.camera_ode_bwd(theta.astype(np.float64), z0.astype(np.float64), frames, substeps,
+                                             dp.astype(np.float64))
+    dth, dz = gvcam.camera_ode_bwd(th, z, frames, substeps, torch.from_numpy(dp).cuda(), ws)
+    torch.cuda.synchronize()
+    if frames > 1:
+        assert rel_err(dth.cpu().numpy(), dth_ref) <= GRAD_TOL
+    else:
+        assert float(dth.abs().max()) == 0.0
+    assert rel_err(dz.cpu().numpy(), dz_ref) <= GRAD_TOL
+
+
+def test_frame540p_n100k_full_size_sampled():
+    """960x540, 100k Gaussians, per-frame path at full size: all pixels of the
+    GPU image against the oracle on 2048 sampled pixels; gradients with an
+    upstream gradient supported on those pixels only."""
+    w = gv_synth.make_workload("frame540p_n100k", targets=False)
+    rng = np.random.default_rng(20)
+    pix = np.sort(rng.choice(960 * 540, 2048, replace=False))
+    say("[540p n100k] oracle on sampled pixels")
+    ref = oracle_frame(w, 0, pixels=pix)
+    ke = knife_edge(ref["margins"], grads=True)
+    dl_pix = rng.normal(0, 1, (pix.size, 3))
+    dl_pix[ke] = 0.0
+    scene, cam, poses, times = device_inputs(w)
+    ws = workspace_for(scene, cam, poses, times)
+    img = raster.render_fwd(scene, cam, poses[0].contiguous(), 0.0, ws)
+    dl = np.zeros((3, 540 * 960), np.float32)
+    dl[:, pix] = dl_pix.T
+    g, dpose = raster.render_bwd(scene, cam, poses[0].contiguous(), 0.0, ws, img,
+                                 dL_dimage=torch.from_numpy(dl.reshape(3, 540, 960)).cuda())
+    torch.cuda.synchronize()
+    got = planar_to_pixels(img.cpu().numpy())[pix]
+    d = np.abs(got - ref["color"]).max(axis=1)
+    kef = knife_edge(ref["margins"])
+    assert d[~kef].max() <= PIXEL_TOL, d[~kef].max()
+    gref = oracle_frame(w, 0, pixels=pix, dL_dC=dl_pix)["grads"]
+    ge = compare_grads(g, gref, "540p n100k")
+    say(f"[540p n100k] max|d|={d[~kef].max():.2e} knife-edge={kef.sum()}/{pix.size} grads={ge}")
+
+
+def test_clip540p_f50_n200k_full_size_sampled():
+    """The benchmark clip (960x540, 200k Gaussians, 50 frames, moving camera)
+    in the benchmark's launch configuration: one batched fwd+bwd; frames
+    {0, 24, 49} checked on 1024 sampled pixels each, gradients with an upstream
+    gradient supported on those pixels."""
+    w = gv_synth.make_workload("clip540p_f50_n200k", targets=False)
+    F, H, W = 50, 540, 960
+    rng = np.random.default_rng(21)
+    frames = [0, 24, 49]
+    pix = [np.sort(rng.choice(H * W, 1024, replace=False)) for _ in frames]
+    refs, dls = [], []
+    for f, p in zip(frames, pix):
+        say(f"[clip540p] oracle frame {f}")
+        r = oracle_frame(w, f, pixels=p)
+        refs.append(r)
+        d = rng.normal(0, 1, (p.size, 3))
+        d[knife_edge(r["margins"], grads=True)] = 0.0
+        dls.append(d)
+    dl = np.zeros((F, 3, H * W), np.float32)
+    for f, p, d in zip(frames, pix, dls):
+        dl[f][:, p] = d.T
+    say("[clip540p] gpu batch")
+    out, ws, _ = run_clip(w, dl=dl.reshape(F, 3, H, W))
+    imgs = out["images"].cpu().numpy()
+    for f, p, r in zip(frames, pix, refs):
+        got = planar_to_pixels(imgs[f])[p]
+        d = np.abs(got - r["color"]).max(axis=1)
+        ke = knife_edge(r["margins"])
+        assert d[~ke].max() <= PIXEL_TOL, (f, d[~ke].max())
+        say(f"[clip540p] frame {f}: max|d|={d[~ke].max():.2e} knife-edge={ke.sum()}/{p.size}")
+    say("[clip540p] oracle backward")
+    g_ref, dposes_ref, _ = oracle.render_clip_grads(w["scene"], w["camera"], w["poses"].astype(np.float64),
+                                                    w["times"], frames, pix, dls)
+    ge = compare_grads(out["grads"], g_ref, "clip540p")
+    gp = out["dL_dposes"].cpu().numpy()
+    pe = rel_err(gp[frames], dposes_ref[frames])
+    assert pe <= GRAD_TOL, pe
+    assert np.all(np.delete(gp, frames, axis=0) == 0.0)
+    say(f"[clip540p] grads={ge} pose={pe:.2e} intersections={ws.status()['intersections']}")
