@@ -1,0 +1,279 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched differentiable Gaussian rasterizer on one MI355X.
+
+One step = one forward+backward pass of the whole hot path (projection,
+binning, per-tile sort, compositing, fused L2 loss, compositing adjoint,
+projection adjoint with per-frame pose gradients) over one clip of synthetic
+input: 50 frames at 960x540, 200k Gaussians shared by all frames, a smooth
+camera trajectory (the clip540p_f50_n200k workload).  The step is a single
+HIP-graph launch; inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line.  Besides the headline frames/s it reports the plain
+per-frame GPU path on the same clip, per-stage times from HIP events, the
+roofline of the dominant kernel and the FP64 CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "fwd+bwd frames/s at 960×540, 200k Gaussians (batched vs per-frame), % HBM roof"
+HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
+# FP32 vector peak without packed-FP32 instructions (this build disables them):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
+ALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
+# Algorithmic FP32 operations per contributing (pixel, Gaussian) pair
+# (footprint 9, falloff 2, opacity/clamp 2, transmittance 2, colour 6 = 21 in
+# the forward; the adjoint re-derives those 13 and adds 46 for the colour,
+# alpha, conic and centre partials and the suffix colour).
+FLOPS_FWD_PER_PAIR = 21
+FLOPS_BWD_PER_PAIR = 59
+PARAM_BYTES = 56           # fp32: means 3, log-scales 3, quats 4, opacity 1, colour 3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(N, V, K, P, F):
+    """Compulsory HBM bytes of one fwd+bwd step over F frames (each input read
+    once, each output written once).  Per frame: forward N*56 + V*40 + K*64 +
+    P*20; backward P*20 + K*112 + N*(56+56)."""
+    per_frame_fwd = N * PARAM_BYTES + V * 40 + (K / F) * 64 + P * 20
+    per_frame_bwd = P * 20 + (K / F) * 112 + N * (PARAM_BYTES + 56)
+    return F * (per_frame_fwd + per_frame_bwd)
+
+
+def stage_bytes(stage, N, V, K, P, F):
+    """Algorithmic bytes of one launch of a stage over the whole clip."""
+    if stage == "composite_fwd":
+        # per intersection: sorted index 4 + record 32 + colour 16; per pixel:
+        # image 12 + T_final 4 + last index 4 written, target 12 read
+        return K * (4 + 32 + 16) + F * P * (12 + 4 + 4 + 12)
+    if stage == "composite_bwd":
+        # per intersection: index 4 + slot 4 + record 32 + colour 16 read,
+        # 36 B of partials written; per pixel image/target 24 + T/last 8 read
+        return K * (4 + 4 + 32 + 16 + 36) + F * P * (24 + 8)
+    if stage == "project_bwd":
+        return F * V * 36 + F * N * PARAM_BYTES + N * 56 + K * 36
+    if stage == "project":
+        return F * N * PARAM_BYTES + F * V * (32 + 8 + 4)
+    if stage == "sort":
+        return K * (8 + 4) * 2 + K * 8
+    if stage == "scatter":
+        return F * V * 48 + K * 12
+    return 0
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="clip540p_f50_n200k")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-frame", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--stage-reps", type=int, default=5)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); the clip "
+              "would shard by frames across GPUs with one gradient all-reduce, which this build does not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    ROOT = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, ROOT)
+    import gv_synth
+    from paper_2501_04782_amd import _lib, raster
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+
+    log(f"[bench] building inputs: {args.workload}")
+    w = gv_synth.make_workload(args.workload, seed=0, targets=True)
+    F, N = w["frames"], w["n"]
+    H, W = w["camera"].height, w["camera"].width
+    P = H * W
+    scene = raster.Scene.from_synth(w["scene"], dev)
+    cam = raster.Camera.of(w["camera"])
+    poses = torch.from_numpy(w["poses"]).to(dev)
+    times = torch.from_numpy(w["times"]).to(dev)
+    targets = torch.from_numpy(w["targets"]).to(dev)
+    dtype_name = "bf16-params/f32" if w["scene"].dtype == "bf16" else "f32"
+
+    # capacity from the exact tile counts of three frames, and visible counts
+    ws1 = raster.Workspace(cam, N, 1, 0, device=dev)
+    vis, kf = [], []
+    for f in sorted({0, F // 2, F - 1}):
+        _, cnt = raster.project_fwd(scene, cam, poses[f].contiguous(), float(w["times"][f]), ws1)
+        vis.append(int((cnt > 0).sum().item()))
+        kf.append(int(cnt.sum().item()))
+    cap = int(max(kf) * F * 1.25) + 4096
+    ws = raster.Workspace(cam, N, F, cap, device=dev)
+    log(f"[bench] workspace {ws.nbytes / 1e9:.2f} GB, capacity {cap}")
+
+    tuning = raster.get_tuning()
+    if not args.no_autotune:
+        log("[bench] autotuning")
+        tuning = raster.autotune(scene, cam, poses, times, ws, targets)
+    log(f"[bench] tuning {tuning}")
+
+    graph = raster.BatchGraph(scene, cam, poses, times, ws, targets=targets)
+    for _ in range(args.warmup):
+        graph.launch()
+    torch.cuda.synchronize()
+    st = ws.status()
+    if st["overflow"]:
+        raise RuntimeError(f"intersection capacity overflow: {st}")
+    K = st["intersections"]
+    V = float(np.mean(vis))
+    log(f"[bench] intersections per step {K} ({K / F:.0f} per frame), visible ~{V:.0f}")
+
+    # timed region: K graph launches, one fwd+bwd step each
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.launch()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+    fps = F * args.steps / elapsed
+    log(f"[bench] batched: {ms_step:.3f} ms/step, {fps:.1f} frames/s")
+    loss_val = float(graph.loss.double().sum())
+
+    # per-stage durations (HIP events on the launch stream, eager sequence)
+    stage_ms = {}
+    out = dict(images=graph.images, loss=graph.loss, grads=graph.grads, dL_dposes=graph.dL_dposes)
+    for r in range(args.stage_reps + 1):
+        res = raster.render_batch_timed(scene, cam, poses, times, ws, targets=targets, out=out)
+        if r == 0:
+            continue  # warm
+        for k, v in res["stage_ms"].items():
+            stage_ms[k] = stage_ms.get(k, 0.0) + v / args.stage_reps
+    log(f"[bench] stages (ms): " + ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()))
+
+    # plain per-frame path on the same clip (render_fwd reads K back each frame)
+    per_frame = None
+    if not args.no_per_frame:
+        wsf = raster.Workspace(cam, N, 1, int(max(kf) * 1.25) + 4096, device=dev)
+        grads = raster.grad_buffers(scene)
+        scale = 2.0 / (3.0 * P * F)
+        img = torch.empty(3, H, W, device=dev)
+        tms = [float(x) for x in w["times"]]
+
+        def per_frame_clip():
+            for f in range(F):
+                raster.render_fwd(scene, cam, poses[f], tms[f], wsf, image=img)
+                raster.render_bwd(scene, cam, poses[f], tms[f], wsf, img, target=targets[f], loss_scale=scale,
+                                  grads=grads, accumulate=f > 0)
+
+        per_frame_clip()
+        torch.cuda.synchronize()
+        reps = 2
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            per_frame_clip()
+        torch.cuda.synchronize()
+        pf_elapsed = time.perf_counter() - t0
+        pf_fps = F * reps / pf_elapsed
+        per_frame = dict(value=round(pf_fps, 2), unit="frames/s", ms_per_clip=round(1e3 * pf_elapsed / reps, 3),
+                         batched_speedup=round(fps / pf_fps, 3))
+        log(f"[bench] per-frame path: {pf_fps:.1f} frames/s (batched x{fps / pf_fps:.2f})")
+
+    # CPU baseline: the FP64 oracle (fwd + bwd) on a bounded pixel sample of frame 0
+    cpu = None
+    mean_contrib = None
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(1)
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+        def run(npx):
+            pix = np.sort(rng.choice(P, npx, replace=False))
+            dl = rng.normal(0, 1, (npx, 3)) * (2.0 / (3.0 * P * F))
+            t = time.perf_counter()
+            r = oracle.render_frame(w["scene"], w["camera"], w["poses"][0].astype(np.float64), 0.0, pixels=pix,
+                                    dL_dC=dl, threads=cores)
+            return time.perf_counter() - t, r
+
+        log("[bench] CPU oracle pilot")
+        t_pilot, _ = run(1024)
+        npx = int(min(P, max(1024, 1024 * args.cpu_seconds / max(t_pilot, 1e-3))))
+        log(f"[bench] CPU oracle sample: {npx} pixels (pilot {t_pilot:.2f} s)")
+        t_cpu, r = run(npx)
+        mean_contrib = float(np.mean(r["n_contrib"]))
+        cpu_fps = npx / (t_cpu * P)
+        cpu = dict(value=cpu_fps, unit="frames/s", cores=cores, kind="oracle",
+                   sample=f"{npx} random pixels of frame 0 (of {P}), forward+backward incl. projection and "
+                          f"depth sort of all {N} Gaussians, {t_cpu:.1f} s; scaled by pixel count")
+        log(f"[bench] CPU oracle: {cpu_fps:.3e} frames/s on {cores} threads")
+
+    # roofline of the dominant kernel
+    dom = max(stage_ms, key=stage_ms.get)
+    t_dom = stage_ms[dom] / 1e3
+    traffic = None
+    bytes_dom = stage_bytes(dom, N, V, K, P, F)
+    hbm_ach = bytes_dom / t_dom if bytes_dom else 0.0
+    roof = dict(bound="hbm", achieved=round(hbm_ach / 1e9, 2), peak=HBM_PEAK / 1e9, unit="GB/s",
+                frac=round(hbm_ach / HBM_PEAK, 4), traffic=traffic, kernel=dom,
+                avg_ms=round(stage_ms[dom], 4), algorithmic_bytes=int(bytes_dom))
+    if mean_contrib is not None and dom in ("composite_fwd", "composite_bwd"):
+        pairs = mean_contrib * P * F
+        flops = pairs * (FLOPS_FWD_PER_PAIR if dom == "composite_fwd" else FLOPS_BWD_PER_PAIR)
+        alu_ach = flops / t_dom
+        if alu_ach / ALU_PEAK > hbm_ach / HBM_PEAK:
+            roof = dict(bound="alu", achieved=round(alu_ach / 1e12, 3), peak=round(ALU_PEAK / 1e12, 2),
+                        unit="TFLOP/s", frac=round(alu_ach / ALU_PEAK, 4), traffic=traffic, kernel=dom,
+                        avg_ms=round(stage_ms[dom], 4), contributing_pairs=int(pairs),
+                        hbm_frac=round(hbm_ach / HBM_PEAK, 4))
+    b_alg = algorithmic_bytes(N, V, K, P, F)
+    step_hbm_frac = b_alg / (ms_step / 1e3) / HBM_PEAK
+
+    line = {
+        "metric": METRIC,
+        "value": round(fps, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "width": W, "height": H, "gaussians": N, "frames_per_step": F,
+                   "loss": "l2", "path": "batched, one HIP graph per step", "param_dtype": dtype_name},
+        "gaussians_per_s": round(fps * N, 1),
+        "hbm_roof_frac_step": round(step_hbm_frac, 4),
+        "algorithmic_bytes_per_frame": int(b_alg / F),
+        "per_frame_path": per_frame,
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "intersections_per_frame": int(K / F),
+        "tuning": tuning,
+        "loss": loss_val,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if mean_contrib is not None:
+        line["mean_contributors_per_pixel"] = round(mean_contrib, 3)
+    print(json.dumps(line), flush=True)
+    graph.close()
+
+
+if __name__ == "__main__":
+    main()

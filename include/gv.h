@@ -174,6 +174,18 @@ gv_status gv_render_batch(const gv_scene *scene, const gv_camera *cam, const flo
                           float *images, float *loss, gv_grads *grads, float *dL_dposes, void *ws,
                           size_t ws_bytes, void *stream);
 
+/* gv_render_batch with HIP events recorded on `stream` between its stages,
+ * for measurement.  Synchronises; stage_ms[GV_STAGES] (host) receives each
+ * stage's elapsed time in ms: 0 projection (+ clearing the counters),
+ * 1 prefix sums, 2 key scatter, 3 per-tile sort, 4 forward compositing,
+ * 5 loss reduction, 6 backward compositing, 7 projection adjoint (+ pose
+ * reduction).  Stages a call does not run read 0. */
+#define GV_STAGES 8
+gv_status gv_render_batch_timed(const gv_scene *scene, const gv_camera *cam, const float *poses, const float *times,
+                                int32_t frames, const float *targets, const float *dL_dimages, uint32_t flags,
+                                float *images, float *loss, gv_grads *grads, float *dL_dposes, void *ws,
+                                size_t ws_bytes, void *stream, float *stage_ms);
+
 /* Capture one gv_render_batch call (same arguments; every pointer is baked
  * in) into an executable HIP graph; launch it any number of times; destroy
  * it.  Capture happens on a private stream; nothing runs at creation. */

@@ -18,6 +18,8 @@ c_int32, c_int64, c_float, c_uint32, c_void_p, c_size_t = (ctypes.c_int32, ctype
 GV_OK, GV_ERR_INVALID_ARG, GV_ERR_WORKSPACE, GV_ERR_CAPACITY, GV_ERR_HIP, GV_ERR_UNSUPPORTED = range(6)
 GV_F32, GV_BF16 = 0, 1
 GV_FWD, GV_BWD, GV_LOSS_L2, GV_ACCUMULATE = 1, 2, 4, 8
+GV_STAGES = 8
+STAGE_NAMES = ["project", "scan", "scatter", "sort", "composite_fwd", "loss", "composite_bwd", "project_bwd"]
 
 
 class GvCamera(ctypes.Structure):
@@ -63,6 +65,10 @@ _SIGS = [
     ("gv_render_batch", c_int32, [ctypes.POINTER(GvScene), ctypes.POINTER(GvCamera), c_void_p, c_void_p, c_int32,
                                   c_void_p, c_void_p, c_uint32, c_void_p, c_void_p, ctypes.POINTER(GvGrads),
                                   c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("gv_render_batch_timed", c_int32, [ctypes.POINTER(GvScene), ctypes.POINTER(GvCamera), c_void_p, c_void_p,
+                                        c_int32, c_void_p, c_void_p, c_uint32, c_void_p, c_void_p,
+                                        ctypes.POINTER(GvGrads), c_void_p, c_void_p, c_size_t, c_void_p,
+                                        ctypes.POINTER(c_float)]),
     ("gv_batch_graph_create", c_int32, [ctypes.POINTER(GvScene), ctypes.POINTER(GvCamera), c_void_p, c_void_p,
                                         c_int32, c_void_p, c_void_p, c_uint32, c_void_p, c_void_p,
                                         ctypes.POINTER(GvGrads), c_void_p, c_void_p, c_size_t,

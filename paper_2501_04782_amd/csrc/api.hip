@@ -198,16 +198,33 @@ static unsigned long long* scan_tmp(const Args& a, const Layout& L) {
     return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(a.status) - L.status + L.scan_tmp);
 }
 
+// Optional HIP events between the stages of a launch sequence (GV_STAGES).
+struct StageTimer {
+    hipEvent_t ev[GV_STAGES + 1];
+    hipStream_t st;
+    void mark(int i) {
+        if (i >= 0 && i <= GV_STAGES) hipEventRecord(ev[i], st);
+    }
+};
+
+static inline void mark(StageTimer* tm, int i) {
+    if (tm) tm->mark(i);
+}
+
 // Projection, binning and scans; optionally reads the intersection count back.
-static gv_status enqueue_binning(const Args& a, const Layout& L, hipStream_t st, bool readback) {
+static gv_status enqueue_binning(const Args& a, const Layout& L, hipStream_t st, bool readback,
+                                 StageTimer* tm = nullptr) {
     const int64_t FN = static_cast<int64_t>(a.frames) * a.n;
     const int64_t FT = static_cast<int64_t>(a.frames) * a.tiles;
+    mark(tm, 0);
     GV_TRY(launch_fill_u32(a.status, 0u, ST_WORDS, st));
     GV_TRY(launch_fill_u32(a.tcnt, 0u, FT, st));
     GV_TRY(launch_fill_u32(a.tcur, 0u, FT, st));
     GV_TRY(launch_project(a, st));
+    mark(tm, 1);
     GV_TRY(exclusive_scan(a.gcnt, a.goff, FN, scan_tmp(a, L), a.status, 0, a.k_cap, st));
     GV_TRY(exclusive_scan(a.tcnt, a.toff, FT, scan_tmp(a, L), a.status, 1, a.k_cap, st));
+    mark(tm, 2);
     if (readback) {
         uint32_t k2[2] = {0, 0};
         GV_TRY(hipMemcpyAsync(k2, a.status + ST_K_LO, sizeof(k2), hipMemcpyDeviceToHost, st));
@@ -216,14 +233,16 @@ static gv_status enqueue_binning(const Args& a, const Layout& L, hipStream_t st,
         if (K > static_cast<uint64_t>(a.k_cap)) return GV_ERR_CAPACITY;
     }
     GV_TRY(launch_scatter(a, st));
+    mark(tm, 3);
     GV_TRY(launch_tile_sort(a, FT, st));
+    mark(tm, 4);
     return GV_OK;
 }
 
 static gv_status enqueue_batch(const gv_scene* scene, const gv_camera* cam, const float* poses, const float* times,
                                int32_t frames, const float* targets, const float* dL_dimages, uint32_t flags,
                                float* images, float* loss, gv_grads* grads, float* dL_dposes, void* ws,
-                               size_t ws_bytes, hipStream_t st) {
+                               size_t ws_bytes, hipStream_t st, StageTimer* tm = nullptr) {
     if ((flags & ~(GV_FWD | GV_BWD | GV_LOSS_L2 | GV_ACCUMULATE)) != 0u || !(flags & (GV_FWD | GV_BWD)))
         return GV_ERR_INVALID_ARG;
     if (!images) return GV_ERR_INVALID_ARG;
@@ -254,14 +273,23 @@ static gv_status enqueue_batch(const gv_scene* scene, const gv_camera* cam, cons
     a.g_poses = dL_dposes;
     a.accumulate = (flags & GV_ACCUMULATE) ? 1 : 0;
     if (flags & GV_FWD) {
-        s = enqueue_binning(a, L, st, false);
+        s = enqueue_binning(a, L, st, false, tm);
         if (s != GV_OK) return s;
         GV_TRY(launch_composite_fwd(a, st));
+        mark(tm, 5);
         if (a.loss) GV_TRY(launch_loss_finalize(a, st));
+        mark(tm, 6);
+    } else {
+        for (int i = 0; i <= 6; ++i) mark(tm, i);
     }
     if (flags & GV_BWD) {
         GV_TRY(launch_composite_bwd(a, st));
+        mark(tm, 7);
         GV_TRY(launch_project_bwd(a, st));
+        mark(tm, 8);
+    } else {
+        mark(tm, 7);
+        mark(tm, 8);
     }
     return GV_OK;
 }
@@ -361,6 +389,33 @@ gv_status gv_render_batch(const gv_scene* scene, const gv_camera* cam, const flo
                           float* loss, gv_grads* grads, float* dL_dposes, void* ws, size_t ws_bytes, void* stream) {
     return enqueue_batch(scene, cam, poses, times, frames, targets, dL_dimages, flags, images, loss, grads, dL_dposes,
                          ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+gv_status gv_render_batch_timed(const gv_scene* scene, const gv_camera* cam, const float* poses, const float* times,
+                                int32_t frames, const float* targets, const float* dL_dimages, uint32_t flags,
+                                float* images, float* loss, gv_grads* grads, float* dL_dposes, void* ws,
+                                size_t ws_bytes, void* stream, float* stage_ms) {
+    if (!stage_ms) return GV_ERR_INVALID_ARG;
+    StageTimer tm;
+    tm.st = static_cast<hipStream_t>(stream);
+    int made = 0;
+    hipError_t e = hipSuccess;
+    for (; made <= GV_STAGES && e == hipSuccess; ++made) e = hipEventCreate(&tm.ev[made]);
+    gv_status s = (e == hipSuccess) ? GV_OK : hip_status(e);
+    if (s == GV_OK)
+        s = enqueue_batch(scene, cam, poses, times, frames, targets, dL_dimages, flags, images, loss, grads, dL_dposes,
+                          ws, ws_bytes, tm.st, &tm);
+    if (s == GV_OK) {
+        e = hipEventSynchronize(tm.ev[GV_STAGES]);
+        if (e != hipSuccess) s = hip_status(e);
+    }
+    for (int i = 0; i < GV_STAGES; ++i) {
+        float ms = 0.f;
+        if (s == GV_OK) hipEventElapsedTime(&ms, tm.ev[i], tm.ev[i + 1]);
+        stage_ms[i] = ms;
+    }
+    for (int i = 0; i < made && i <= GV_STAGES; ++i) hipEventDestroy(tm.ev[i]);
+    return s;
 }
 
 gv_status gv_batch_graph_create(const gv_scene* scene, const gv_camera* cam, const float* poses, const float* times,

@@ -247,6 +247,59 @@ def render_batch(scene: Scene, camera: Camera, poses: torch.Tensor, times: Optio
     return dict(images=images, loss=loss, grads=grads, dL_dposes=dL_dposes)
 
 
+def render_batch_timed(scene: Scene, camera: Camera, poses: torch.Tensor, times: Optional[torch.Tensor],
+                       ws: Workspace, targets: Optional[torch.Tensor] = None,
+                       dL_dimages: Optional[torch.Tensor] = None, out: Optional[dict] = None) -> dict:
+    """One forward+backward of the clip with HIP events between the stages
+    (synchronous); returns {stage name: ms} and the outputs."""
+    F = int(poses.shape[0])
+    dev = poses.device
+    H, W = camera.height, camera.width
+    flags = L.GV_FWD | L.GV_BWD | (L.GV_LOSS_L2 if targets is not None else 0)
+    out = out or {}
+    images = out.get("images") if out.get("images") is not None else torch.empty(F, 3, H, W, device=dev)
+    loss = out.get("loss") if out.get("loss") is not None else (torch.empty(F, device=dev) if targets is not None
+                                                                else None)
+    grads = out.get("grads") or grad_buffers(scene)
+    dposes = out.get("dL_dposes") if out.get("dL_dposes") is not None else torch.empty(F, 7, device=dev)
+    args, _keep = _batch_args(scene, camera, poses, times, ws, targets, dL_dimages, flags, images, loss, grads, dposes)
+    ms = (ctypes.c_float * L.GV_STAGES)()
+    L.check(L.load().gv_render_batch_timed(*args, _stream(), ms), "gv_render_batch_timed")
+    return dict(stage_ms={name: float(ms[i]) for i, name in enumerate(L.STAGE_NAMES)},
+                images=images, loss=loss, grads=grads, dL_dposes=dposes)
+
+
+def autotune(scene: Scene, camera: Camera, poses: torch.Tensor, times: Optional[torch.Tensor], ws: Workspace,
+             targets: torch.Tensor, cache_path: Optional[str] = None) -> dict:
+    """Time the candidate kernel settings on this clip and install the fastest."""
+    F = int(poses.shape[0])
+    dev = poses.device
+    images = torch.empty(F, 3, camera.height, camera.width, device=dev)
+    loss = torch.empty(F, device=dev)
+    grads = grad_buffers(scene)
+    dposes = torch.empty(F, 7, device=dev)
+    args, _keep = _batch_args(scene, camera, poses, times, ws, targets, None, L.GV_FWD | L.GV_BWD | L.GV_LOSS_L2,
+                              images, loss, grads, dposes)
+    # gv_autotune takes (scene, cam, poses, times, F, targets, images, loss, grads, dposes, ws, bytes, path, out)
+    t = L.GvTuning()
+    L.check(L.load().gv_autotune(args[0], args[1], args[2], args[3], args[4], args[5], args[8], args[9], args[10],
+                                 args[11], args[12], args[13], None if cache_path is None else cache_path.encode(),
+                                 ctypes.byref(t)), "gv_autotune")
+    return dict(batch=int(t.batch), sort_cap=int(t.sort_cap))
+
+
+def get_tuning() -> dict:
+    t = L.GvTuning()
+    L.check(L.load().gv_get_tuning(ctypes.byref(t)), "gv_get_tuning")
+    return dict(batch=int(t.batch), sort_cap=int(t.sort_cap))
+
+
+def set_tuning(batch: int, sort_cap: int) -> None:
+    t = L.GvTuning()
+    t.batch, t.sort_cap = int(batch), int(sort_cap)
+    L.check(L.load().gv_set_tuning(ctypes.byref(t)), "gv_set_tuning")
+
+
 class BatchGraph:
     """A gv_render_batch call captured once into a HIP graph (all buffers fixed)."""
 

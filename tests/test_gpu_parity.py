@@ -163,7 +163,8 @@ def test_empty_and_single_gaussian():
             assert torch.all(out["dL_dposes"] == 0)
         else:
             w["scene"].means[:, 0] = [0.0, 0.0, 3.0]
-            w["scene"].log_scales[:, 0] = -1.5
+            # anisotropic, so that every parameter has a non-zero gradient
+            w["scene"].log_scales[:, 0] = [-1.5, -2.2, -1.8]
             check_clip_against_oracle(w, "single Gaussian")
 
 
