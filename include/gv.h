@@ -108,11 +108,15 @@ typedef struct {
 /* Tunables of the rasterizer kernels (chosen by gv_autotune, or set directly).
  * batch: entries staged in LDS per round of a tile's compositing loop
  * (64, 128 or 256); sort_cap: longest per-tile list sorted in one LDS pass
- * (1024, 2048 or 4096; longer lists are sorted in chunks and merged). */
+ * (1024, 2048 or 4096; longer lists are sorted in chunks and merged);
+ * compact: 1 = compositing kernels that first build per-pixel entry lists from
+ * closed-form coverage masks, 0 = every staged entry visits every pixel of its
+ * 8x8 quadrant.  Results are identical; only the speed differs. */
 typedef struct {
     int32_t batch;
     int32_t sort_cap;
-    int32_t reserved[6];
+    int32_t compact;
+    int32_t reserved[5];
 } gv_tuning;
 
 /* Bytes of workspace for up to `frames` frames of `n` Gaussians at the

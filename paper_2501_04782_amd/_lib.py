@@ -38,7 +38,7 @@ class GvGrads(ctypes.Structure):
 
 
 class GvTuning(ctypes.Structure):
-    _fields_ = [("batch", c_int32), ("sort_cap", c_int32), ("reserved", c_int32 * 6)]
+    _fields_ = [("batch", c_int32), ("sort_cap", c_int32), ("compact", c_int32), ("reserved", c_int32 * 5)]
 
 
 class GvError(RuntimeError):

@@ -22,13 +22,14 @@ hipError_t launch_loss_finalize(const Args& a, hipStream_t stream);
 hipError_t launch_composite_bwd(const Args& a, hipStream_t stream);
 hipError_t launch_project_bwd(const Args& a, hipStream_t stream);
 int64_t project_bwd_blocks(int64_t n);
+int64_t bin_blocks(int64_t n);
 int64_t scan_blocks(int64_t count);
 hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t count, unsigned long long* tmp,
                           uint32_t* status, int check, int64_t k_cap, hipStream_t stream);
 
 static thread_local int32_t g_last_hip = 0;
 static std::mutex g_tune_mu;
-static Tuning g_tune = {256, 4096, 128};
+static Tuning g_tune = {256, 4096, 128, 1};
 
 Tuning current_tuning() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -60,6 +61,7 @@ Layout make_layout(const gv_camera& cam, int64_t n, int frames, int64_t k_cap) {
     const int64_t FT = static_cast<int64_t>(frames) * L.tiles;
     L.scan_blocks = std::max(scan_blocks(FN), scan_blocks(FT));
     L.pose_blocks = project_bwd_blocks(n);
+    L.bin_blocks = L.tiles <= LDS_TILE_LIMIT ? bin_blocks(n) : 0;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -75,6 +77,7 @@ Layout make_layout(const gv_camera& cam, int64_t n, int frames, int64_t k_cap) {
     L.tcnt = take(4 * static_cast<size_t>(FT));
     L.toff = take(4 * static_cast<size_t>(FT + 1));
     L.tcur = take(4 * static_cast<size_t>(FT));
+    L.bhist = take(4 * static_cast<size_t>(FT) * static_cast<size_t>(L.bin_blocks));
     L.scan_tmp = take(8 * static_cast<size_t>(L.scan_blocks + 1));
     L.tfin = take(4 * static_cast<size_t>(frames) * L.pixels);
     L.nlast = take(4 * static_cast<size_t>(frames) * L.pixels);
@@ -176,6 +179,8 @@ static gv_status make_args(const gv_scene* s, const gv_camera* c, int frames, co
     a.tcnt = reinterpret_cast<uint32_t*>(b + L.tcnt);
     a.toff = reinterpret_cast<uint32_t*>(b + L.toff);
     a.tcur = reinterpret_cast<uint32_t*>(b + L.tcur);
+    a.bhist = L.bin_blocks > 0 ? reinterpret_cast<uint32_t*>(b + L.bhist) : nullptr;
+    a.bin_blocks = static_cast<int>(L.bin_blocks);
     a.tfin = reinterpret_cast<float*>(b + L.tfin);
     a.nlast = reinterpret_cast<uint32_t*>(b + L.nlast);
     a.loss_part = reinterpret_cast<float*>(b + L.loss_part);
@@ -474,6 +479,7 @@ gv_status gv_get_tuning(gv_tuning* out) {
     memset(out, 0, sizeof(*out));
     out->batch = t.batch;
     out->sort_cap = t.sort_cap;
+    out->compact = t.compact;
     return GV_OK;
 }
 
@@ -481,9 +487,11 @@ gv_status gv_set_tuning(const gv_tuning* t) {
     if (!t) return GV_ERR_INVALID_ARG;
     if (t->batch != 64 && t->batch != 128 && t->batch != 256) return GV_ERR_INVALID_ARG;
     if (t->sort_cap != 1024 && t->sort_cap != 2048 && t->sort_cap != 4096) return GV_ERR_INVALID_ARG;
+    if (t->compact != 0 && t->compact != 1) return GV_ERR_INVALID_ARG;
     Tuning n = current_tuning();
     n.batch = t->batch;
     n.sort_cap = t->sort_cap;
+    n.compact = t->compact;
     install_tuning(n);
     return GV_OK;
 }
@@ -504,11 +512,14 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
     gv_status result = GV_OK;
     const int batches[] = {64, 128, 256};
     const int caps[] = {2048, 4096};
+    const int compacts[] = {0, 1};
     for (int b : batches) {
-        for (int c : caps) {
+        for (int cc = 0; cc < 4; ++cc) {
+            const int c = caps[cc & 1];
             Tuning t = saved;
             t.batch = b;
             t.sort_cap = c;
+            t.compact = compacts[cc >> 1];
             install_tuning(t);
             gv_status s = enqueue_batch(scene, cam, poses, times, frames, targets, nullptr, flags, images, loss, grads,
                                         dL_dposes, ws, ws_bytes, st);
@@ -550,15 +561,16 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
         memset(chosen, 0, sizeof(*chosen));
         chosen->batch = best.batch;
         chosen->sort_cap = best.sort_cap;
+        chosen->compact = best.compact;
     }
     if (cache_path) {
         FILE* fp = fopen(cache_path, "a");
         if (fp) {
             fprintf(fp,
                     "{\"arch\": \"gfx950\", \"width\": %d, \"height\": %d, \"n\": %lld, \"frames\": %d, "
-                    "\"dtype\": %d, \"batch\": %d, \"sort_cap\": %d, \"ms\": %.4f}\n",
+                    "\"dtype\": %d, \"batch\": %d, \"sort_cap\": %d, \"compact\": %d, \"ms\": %.4f}\n",
                     cam->width, cam->height, static_cast<long long>(scene->n), frames, scene->dtype, best.batch,
-                    best.sort_cap, best_ms);
+                    best.sort_cap, best.compact, best_ms);
             fclose(fp);
         }
     }

@@ -314,8 +314,341 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Compacted variant.  The quadrant loop above issues every staged entry to all
+// 64 lanes of a wave although a small Gaussian covers only a fraction of the
+// 8x8 quadrant.  Here each batch is processed in two phases:
+//  1. entry-parallel coverage: the thread that stages entry j solves the
+//     3-sigma ellipse row by row in closed form and writes four 64-bit
+//     quadrant masks (a conservative superset of the per-pixel test);
+//     each wave then transposes its quadrant's masks (64x64 bit matrices,
+//     xor shuffles) so that lane l holds the set of entries covering pixel l;
+//  2. every lane walks only the entries in its own set, in depth order (back
+//     to front in the adjoint), with the per-pixel arithmetic of the quadrant
+//     loop (shared helpers, so values and decisions are identical).
+// The adjoint accumulates each entry's partials with LDS atomics into one
+// slot per wave (one instruction's lanes commit in lane order), and the four
+// wave slots are summed in a fixed order.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void coverage_masks(float lu, float lv, float a, float b, float c, int xlim, int ylim,
+                                               uint64_t qm[4]) {
+    qm[0] = qm[1] = qm[2] = qm[3] = 0ull;
+    const float det = static_cast<float>(static_cast<double>(a) * c - static_cast<double>(b) * b);
+    if (!(det > 0.0f) || !(a > 0.0f)) {  // degenerate conic: keep every pixel (the exact test decides)
+        for (int Y = 0; Y < TILE && Y <= ylim; ++Y) {
+            const uint32_t bits = (0xFFFFu >> (15 - min(xlim, 15)));
+            qm[(Y >> 3) * 2 + 0] |= static_cast<uint64_t>(bits & 0xFFu) << ((Y & 7) * 8);
+            qm[(Y >> 3) * 2 + 1] |= static_cast<uint64_t>(bits >> 8) << ((Y & 7) * 8);
+        }
+        return;
+    }
+    const float inva = 1.0f / a;
+    const float aq = a * SUB_Q_SLACK;
+    for (int Y = 0; Y < TILE; ++Y) {
+        if (Y > ylim) break;
+        const float dy = static_cast<float>(Y) - lv;
+        const float disc = aq - dy * dy * det;
+        if (disc < 0.0f) continue;
+        const float r = sqrtf(disc) * inva;
+        const float cen = lu - b * dy * inva;
+        const float eps = 0.01f + 1e-4f * r;
+        const float lo = fminf(fmaxf(ceilf(cen - r - eps), 0.0f), 16.0f);
+        const float hi = fmaxf(fminf(floorf(cen + r + eps), static_cast<float>(min(xlim, 15))), -1.0f);
+        const int x0 = static_cast<int>(lo), x1 = static_cast<int>(hi);
+        if (x0 > x1) continue;
+        const uint32_t bits = (0xFFFFu >> (15 - (x1 - x0))) << x0;
+        qm[(Y >> 3) * 2 + 0] |= static_cast<uint64_t>(bits & 0xFFu) << ((Y & 7) * 8);
+        qm[(Y >> 3) * 2 + 1] |= static_cast<uint64_t>(bits >> 8) << ((Y & 7) * 8);
+    }
+}
+
+// Lane l holds row l of a 64x64 bit matrix; returns column l.
+__device__ __forceinline__ uint64_t transpose64(uint64_t x, int lane) {
+    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                               0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int sft = 32 >> k;
+        const uint64_t m = masks[k];
+        const uint32_t ylo = __shfl_xor(static_cast<uint32_t>(x), sft, 64);
+        const uint32_t yhi = __shfl_xor(static_cast<uint32_t>(x >> 32), sft, 64);
+        const uint64_t y = (static_cast<uint64_t>(yhi) << 32) | ylo;
+        x = (lane & sft) ? ((x & ~m) | ((y & ~m) >> sft)) : ((x & m) | ((y & m) << sft));
+    }
+    return x;
+}
+
+// Stage the batch [b0, b0 + nb) and its quadrant masks (threads t < B).
+template <int B>
+__device__ __forceinline__ void stage_batch_masks(const Args& a, int f, uint32_t b0, uint32_t nb, double ox, double oy,
+                                                  int xlim, int ylim, Staged* sh, float* shb,
+                                                  uint64_t (*qmask)[B]) {
+    const int t = threadIdx.x;
+    if (t < B) {
+        uint64_t qm[4] = {0ull, 0ull, 0ull, 0ull};
+        if (t < static_cast<int>(nb)) {
+            Staged st;
+            float blue;
+            uint32_t m;
+            stage_entry(a, f, a.sgid[b0 + t], ox, oy, xlim, ylim, st, blue, m);
+            sh[t] = st;
+            shb[t] = blue;
+            if (m) coverage_masks(st.p0.x, st.p0.y, st.p0.z, 0.5f * st.p0.w, st.p1.x, xlim, ylim, qm);
+        }
+        for (int q = 0; q < 4; ++q) qmask[q][t] = qm[q];
+    }
+}
+
+template <int B>
+__global__ __launch_bounds__(WG) void k_composite_fwd_c(Args a) {
+    if (overflowed(a.status)) return;
+    constexpr int NW = B / 64;
+    const int f = blockIdx.y;
+    const int tile = blockIdx.x;
+    const int txi = tile % a.tiles_x, tyi = tile / a.tiles_x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lx = ((w & 1) << 3) | (lane & 7), ly = ((w >> 1) << 3) | (lane >> 3);
+    const int px = txi * TILE + lx, py = tyi * TILE + ly;
+    const bool inside = px < a.width && py < a.height;
+    const int64_t seg = static_cast<int64_t>(f) * a.tiles + tile;
+    uint32_t s, e;
+    bucket_range(a, seg, s, e);
+    const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
+    const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
+
+    __shared__ Staged sh[B];
+    __shared__ float shb[B];
+    __shared__ uint64_t qmask[4][B];
+    __shared__ float red[WG / 64];
+
+    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    uint32_t last = 0;
+    bool done = !inside;
+    const float fx = static_cast<float>(lx), fy = static_cast<float>(ly);
+
+    for (uint32_t b0 = s; b0 < e; b0 += B) {
+        if (__syncthreads_count(!done) == 0) break;
+        const uint32_t nb = min(static_cast<uint32_t>(B), e - b0);
+        stage_batch_masks<B>(a, f, b0, nb, ox, oy, xlim, ylim, sh, shb, qmask);
+        __syncthreads();
+        uint64_t wq[NW];
+#pragma unroll
+        for (int r = 0; r < NW; ++r) wq[r] = transpose64(qmask[w][r * 64 + lane], lane);
+        if (!done) {
+            uint64_t cur = wq[0];
+            int base = 0;
+            for (;;) {
+                while (cur == 0ull && base < (NW - 1) * 64) {
+#pragma unroll
+                    for (int r = 0; r + 1 < NW; ++r) wq[r] = wq[r + 1];
+                    wq[NW - 1] = 0ull;
+                    cur = wq[0];
+                    base += 64;
+                }
+                if (cur == 0ull) break;
+                const int j = base + __builtin_ctzll(cur);
+                cur &= cur - 1ull;
+                const float4 p0 = sh[j].p0;
+                const float4 p1 = sh[j].p1;
+                const float dx = fx - p0.x, dy = fy - p0.y;
+                const float q = footprint_q(dx, dy, p0, p1);
+                if (q > Q_MAX) continue;
+                const float al = fminf(ALPHA_MAX, p1.y * gauss_falloff(q));
+                if (al < ALPHA_MIN) continue;
+                const float tn = T * (1.0f - al);
+                if (tn < T_MIN) {
+                    done = true;
+                    break;
+                }
+                const float wgt = al * T;
+                c0 = __builtin_fmaf(p1.z, wgt, c0);
+                c1 = __builtin_fmaf(p1.w, wgt, c1);
+                c2 = __builtin_fmaf(shb[j], wgt, c2);
+                T = tn;
+                last = b0 + j - s + 1;
+            }
+        }
+    }
+
+    float sq = 0.0f;
+    if (inside) {
+        const int64_t P = static_cast<int64_t>(a.width) * a.height;
+        const int64_t pix = static_cast<int64_t>(py) * a.width + px;
+        c0 = __builtin_fmaf(T, a.bg[0], c0);
+        c1 = __builtin_fmaf(T, a.bg[1], c1);
+        c2 = __builtin_fmaf(T, a.bg[2], c2);
+        float* img = a.images + static_cast<int64_t>(f) * 3 * P + pix;
+        img[0] = c0;
+        img[P] = c1;
+        img[2 * P] = c2;
+        a.tfin[static_cast<int64_t>(f) * P + pix] = T;
+        a.nlast[static_cast<int64_t>(f) * P + pix] = last;
+        if (a.tfin_out) a.tfin_out[static_cast<int64_t>(f) * P + pix] = T;
+        if (a.targets && a.loss) {
+            const float* tg = a.targets + static_cast<int64_t>(f) * 3 * P + pix;
+            const float d0 = c0 - tg[0], d1 = c1 - tg[P], d2 = c2 - tg[2 * P];
+            sq = d0 * d0 + d1 * d1 + d2 * d2;
+        }
+    }
+    if (a.targets && a.loss) {
+        sq = wave_sum_to_lane63(sq);
+        if (lane == 63) red[w] = sq;
+        __syncthreads();
+        if (tid == 0) a.loss_part[seg] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
+}
+
+template <int B>
+__global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
+    if (overflowed(a.status)) return;
+    constexpr int NW = B / 64;
+    const int f = blockIdx.y;
+    const int tile = blockIdx.x;
+    const int txi = tile % a.tiles_x, tyi = tile / a.tiles_x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lx = ((w & 1) << 3) | (lane & 7), ly = ((w >> 1) << 3) | (lane >> 3);
+    const int px = txi * TILE + lx, py = tyi * TILE + ly;
+    const bool inside = px < a.width && py < a.height;
+    const int64_t seg = static_cast<int64_t>(f) * a.tiles + tile;
+    uint32_t s, e;
+    bucket_range(a, seg, s, e);
+    const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
+    const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
+
+    __shared__ Staged sh[B];
+    __shared__ float shb[B];
+    __shared__ uint64_t qmask[4][B];
+    __shared__ float acc[WG / 64][9][B];
+    __shared__ uint32_t smax;
+
+    float T = 1.0f, S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+    uint32_t last = 0;
+    if (inside) {
+        const int64_t P = static_cast<int64_t>(a.width) * a.height;
+        const int64_t pix = static_cast<int64_t>(py) * a.width + px;
+        T = a.tfin[static_cast<int64_t>(f) * P + pix];
+        last = a.nlast[static_cast<int64_t>(f) * P + pix];
+        const int64_t o3 = static_cast<int64_t>(f) * 3 * P + pix;
+        if (a.targets) {
+            g0 = (a.images[o3] - a.targets[o3]) * a.loss_scale;
+            g1 = (a.images[o3 + P] - a.targets[o3 + P]) * a.loss_scale;
+            g2 = (a.images[o3 + 2 * P] - a.targets[o3 + 2 * P]) * a.loss_scale;
+        } else {
+            g0 = a.dl_dimages[o3];
+            g1 = a.dl_dimages[o3 + P];
+            g2 = a.dl_dimages[o3 + 2 * P];
+        }
+        S0 = T * a.bg[0];
+        S1 = T * a.bg[1];
+        S2 = T * a.bg[2];
+    }
+    if (tid == 0) smax = 0;
+    __syncthreads();
+    if (last) atomicMax(&smax, last);
+    __syncthreads();
+    const uint32_t used = smax;
+    for (uint32_t i = s + used + tid; i < e; i += WG) {
+        const uint32_t slot = a.sslot[i];
+        if (slot >= a.k_cap) continue;
+        a.partA[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
+        a.partB[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
+        a.partC[slot] = 0.f;
+    }
+    const float fx = static_cast<float>(lx), fy = static_cast<float>(ly);
+
+    for (int64_t bend = static_cast<int64_t>(s) + used; bend > s; bend -= B) {
+        const uint32_t b0 = static_cast<uint32_t>(bend - B > s ? bend - B : s);
+        const uint32_t nb = static_cast<uint32_t>(bend - b0);
+        stage_batch_masks<B>(a, f, b0, nb, ox, oy, xlim, ylim, sh, shb, qmask);
+        for (int k = tid; k < (WG / 64) * 9 * B; k += WG) (&acc[0][0][0])[k] = 0.0f;
+        __syncthreads();
+        // entries at or behind this pixel's last contributor are not part of its sum
+        const int64_t lim = static_cast<int64_t>(last) - (static_cast<int64_t>(b0) - s);
+        uint64_t wq[NW];
+#pragma unroll
+        for (int r = 0; r < NW; ++r) {
+            uint64_t x = transpose64(qmask[w][r * 64 + lane], lane);
+            const int64_t keep = lim - 64 * r;
+            x = keep <= 0 ? 0ull : (keep >= 64 ? x : (x & ((1ull << keep) - 1ull)));
+            wq[r] = x;
+        }
+        {
+            uint64_t cur = wq[NW - 1];
+            int base = (NW - 1) * 64;
+            for (;;) {
+                while (cur == 0ull && base > 0) {
+#pragma unroll
+                    for (int r = NW - 1; r > 0; --r) wq[r] = wq[r - 1];
+                    wq[0] = 0ull;
+                    cur = wq[NW - 1];
+                    base -= 64;
+                }
+                if (cur == 0ull) break;
+                const int bit = 63 - __builtin_clzll(cur);
+                cur ^= 1ull << bit;
+                const int j = base + bit;
+                const float4 p0 = sh[j].p0;
+                const float4 p1 = sh[j].p1;
+                const float dx = fx - p0.x, dy = fy - p0.y;
+                const float q = footprint_q(dx, dy, p0, p1);
+                if (q > Q_MAX) continue;
+                const float G = gauss_falloff(q);
+                const float raw = p1.y * G;
+                const float al = fminf(ALPHA_MAX, raw);
+                if (al < ALPHA_MIN) continue;
+                const float inv = 1.0f / (1.0f - al);
+                const float Tj = T * inv;
+                const float wgt = al * Tj;
+                const float cb = shb[j];
+                const float dal = g0 * (p1.z * Tj - S0 * inv) + g1 * (p1.w * Tj - S1 * inv) + g2 * (cb * Tj - S2 * inv);
+                S0 = __builtin_fmaf(p1.z, wgt, S0);
+                S1 = __builtin_fmaf(p1.w, wgt, S1);
+                S2 = __builtin_fmaf(cb, wgt, S2);
+                T = Tj;
+                float* ac = &acc[w][0][j];
+                atomicAdd(ac + 6 * B, wgt * g0);
+                atomicAdd(ac + 7 * B, wgt * g1);
+                atomicAdd(ac + 8 * B, wgt * g2);
+                if (raw < ALPHA_MAX) {
+                    const float dq = -0.5f * al * dal;
+                    const float hb = 0.5f * p0.w;
+                    atomicAdd(ac + 0 * B, -2.0f * dq * (p0.z * dx + hb * dy));
+                    atomicAdd(ac + 1 * B, -2.0f * dq * (hb * dx + p1.x * dy));
+                    atomicAdd(ac + 2 * B, dq * dx * dx);
+                    atomicAdd(ac + 3 * B, 2.0f * dq * dx * dy);
+                    atomicAdd(ac + 4 * B, dq * dy * dy);
+                    atomicAdd(ac + 5 * B, dal * G);
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < static_cast<int>(nb)) {
+            float v[9];
+            for (int k = 0; k < 9; ++k) v[k] = (acc[0][k][tid] + acc[1][k][tid]) + (acc[2][k][tid] + acc[3][k][tid]);
+            const uint32_t slot = a.sslot[b0 + tid];
+            if (slot < a.k_cap) {
+                a.partA[slot] = make_float4(v[0], v[1], v[2], v[3]);
+                a.partB[slot] = make_float4(v[4], v[5], v[6], v[7]);
+                a.partC[slot] = v[8];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 hipError_t launch_composite_fwd(const Args& a, hipStream_t stream) {
     const dim3 grid(static_cast<uint32_t>(a.tiles), static_cast<uint32_t>(a.frames)), block(WG);
+    if (a.tune.compact) {
+        switch (a.tune.batch) {
+            case 64: hipLaunchKernelGGL(k_composite_fwd_c<64>, grid, block, 0, stream, a); break;
+            case 128: hipLaunchKernelGGL(k_composite_fwd_c<128>, grid, block, 0, stream, a); break;
+            default: hipLaunchKernelGGL(k_composite_fwd_c<256>, grid, block, 0, stream, a); break;
+        }
+        return hipGetLastError();
+    }
     switch (a.tune.batch) {
         case 64: hipLaunchKernelGGL(k_composite_fwd<64>, grid, block, 0, stream, a); break;
         case 128: hipLaunchKernelGGL(k_composite_fwd<128>, grid, block, 0, stream, a); break;
@@ -331,6 +664,14 @@ hipError_t launch_loss_finalize(const Args& a, hipStream_t stream) {
 
 hipError_t launch_composite_bwd(const Args& a, hipStream_t stream) {
     const dim3 grid(static_cast<uint32_t>(a.tiles), static_cast<uint32_t>(a.frames)), block(WG);
+    if (a.tune.compact) {
+        switch (a.tune.batch) {
+            case 64: hipLaunchKernelGGL(k_composite_bwd_c<64>, grid, block, 0, stream, a); break;
+            case 128: hipLaunchKernelGGL(k_composite_bwd_c<128>, grid, block, 0, stream, a); break;
+            default: hipLaunchKernelGGL(k_composite_bwd_c<256>, grid, block, 0, stream, a); break;
+        }
+        return hipGetLastError();
+    }
     switch (a.tune.batch) {
         case 64: hipLaunchKernelGGL(k_composite_bwd<64>, grid, block, 0, stream, a); break;
         case 128: hipLaunchKernelGGL(k_composite_bwd<128>, grid, block, 0, stream, a); break;

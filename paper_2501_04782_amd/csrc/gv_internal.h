@@ -28,6 +28,11 @@ constexpr float K_EXP = -0.72134752044448170368f;
 constexpr double BIN_Q_SLACK = 9.0 * (1.0 + 1e-5) + 1e-6;
 constexpr float SUB_Q_SLACK = 9.0f * (1.0f + 1e-4f) + 1e-4f;
 
+// Gaussians per workgroup of the LDS-histogram binning kernels, and the
+// largest tile grid whose histogram fits in LDS (64 KiB).
+constexpr int BIN_GROUP = 2048;
+constexpr int LDS_TILE_LIMIT = 16384;
+
 // Per (frame, Gaussian) projected record, 32 bytes (one aligned half-line).
 // (u, v) stays in fp64 so that the tile-local offsets formed at staging time
 // are exact to fp32 rounding of a small number.
@@ -49,6 +54,7 @@ struct Tuning {
     int batch;      // 64 / 128 / 256 entries per LDS round of the composite kernels
     int sort_cap;   // 1024 / 2048 / 4096
     int bwd_block;  // threads per workgroup of the projection adjoint
+    int compact;    // 1: compacted compositing kernels (coverage masks + per-lane entry lists), 0: quadrant loop
 };
 
 // Byte offsets of the workspace regions (host-computed).
@@ -59,7 +65,8 @@ struct Layout {
     int64_t k_cap;
     int64_t scan_blocks;   // for the (frames*n) scan
     int64_t pose_blocks;   // workgroups of the projection adjoint (upper bound)
-    size_t status, col4, rec, rect, gcnt, goff, tcnt, toff, tcur, scan_tmp, tfin, nlast, loss_part, pose_part,
+    int64_t bin_blocks;    // workgroups per frame of the LDS-histogram binning (0: global atomics)
+    size_t status, col4, rec, rect, gcnt, goff, tcnt, toff, tcur, bhist, scan_tmp, tfin, nlast, loss_part, pose_part,
         keys, kslot, sgid, sslot, partA, partB, partC, tkeys, tslot;
     size_t total;
 };
@@ -95,6 +102,8 @@ struct Args {
     uint32_t* tcnt;       // [F*T]
     uint32_t* toff;       // [F*T + 1]
     uint32_t* tcur;       // [F*T]
+    uint32_t* bhist;      // [F][bin_blocks][T] workgroup tile histograms, or nullptr (global-atomic binning)
+    int bin_blocks;
     float* tfin;          // [F][P]
     uint32_t* nlast;      // [F][P]
     float* loss_part;     // [F*T]

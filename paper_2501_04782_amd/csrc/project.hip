@@ -27,18 +27,14 @@ __device__ __forceinline__ bool tile_span(double lo, double hi, int n_tiles, int
     return true;
 }
 
-// One thread per (frame, Gaussian): projected record, tile rectangle, the
-// number of 16x16 tiles whose pixel-centre box meets the 3-sigma ellipse
-// (exact ellipse-box test) and the per-tile counts.  Frame 0 also writes the
-// per-Gaussian colour/opacity table shared by all frames.
-__global__ __launch_bounds__(256) void k_project(Args a) {
-    const int f = blockIdx.y;
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= a.n) return;
+// Project Gaussian g in frame f: write its record and tile rectangle and call
+// tally(tile) for every 16x16 tile whose pixel-centre box meets its 3-sigma
+// ellipse (exact ellipse-box test).  Returns the number of such tiles.  Frame
+// 0 also writes the per-Gaussian colour/opacity table shared by all frames.
+template <typename Tally>
+__device__ __forceinline__ uint32_t project_and_count(const Args& a, int f, int64_t g, const CamD& cam, double t,
+                                                      Tally tally) {
     const int64_t i = static_cast<int64_t>(f) * a.n + g;
-    const CamD cam = load_camera(a.poses + 7 * f);
-    const double t = a.times ? static_cast<double>(a.times[f]) : static_cast<double>(a.t0);
-
     if (f == 0) {
         const double eta = load_param(a.opacity_logits, a.dtype, g);
         ColorOp co;
@@ -48,7 +44,6 @@ __global__ __launch_bounds__(256) void k_project(Args a) {
         co.o = static_cast<float>(1.0 / (1.0 + exp(-eta)));
         a.col4[g] = co;
     }
-
     ProjD P;
     const bool vis = project_gaussian(a, g, cam, t, P);
     if (P.nonfinite) atomicAdd(&a.status[ST_NONFINITE], 1u);
@@ -68,14 +63,13 @@ __global__ __launch_bounds__(256) void k_project(Args a) {
         int tx0, tx1, ty0, ty1;
         if (tile_span(P.u - hx, P.u + hx, a.tiles_x, tx0, tx1) && tile_span(P.v - hy, P.v + hy, a.tiles_y, ty0, ty1)) {
             const double ca = r.a, cb = r.b, cc = r.c;
-            uint32_t* tc = a.tcnt + static_cast<int64_t>(f) * a.tiles;
             for (int ty = ty0; ty <= ty1; ++ty)
                 for (int tx = tx0; tx <= tx1; ++tx) {
                     double x0, x1, y0, y1;
                     tile_box(tx, ty, a.width, a.height, x0, x1, y0, y1);
                     if (ellipse_meets_box<double>(r.u, r.v, ca, cb, cc, x0, x1, y0, y1, BIN_Q_SLACK)) {
                         ++cnt;
-                        atomicAdd(&tc[ty * a.tiles_x + tx], 1u);
+                        tally(ty * a.tiles_x + tx);
                     }
                 }
             a.rec[i] = r;
@@ -84,17 +78,15 @@ __global__ __launch_bounds__(256) void k_project(Args a) {
         }
     }
     a.gcnt[i] = cnt;
+    return cnt;
 }
 
-// Second pass: write key = (fp32 depth bits << 32 | Gaussian index) and the
-// pre-sort slot (goff + k for the k-th tile of this Gaussian) of every
-// intersection into its tile's bucket.  Decisions repeat k_project's exactly
-// (same inputs, same test, no contraction).
-__global__ __launch_bounds__(256) void k_scatter(Args a) {
-    if (overflowed(a.status)) return;
-    const int f = blockIdx.y;
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= a.n) return;
+// Write key = (fp32 depth bits << 32 | Gaussian index) and the pre-sort slot
+// (goff + k for the k-th tile of this Gaussian) of every intersection of
+// (f, g) at position next(tile) of its tile's bucket.  The decisions repeat
+// project_and_count's exactly (same inputs, same test, no contraction).
+template <typename Next>
+__device__ __forceinline__ void scatter_one(const Args& a, int f, int64_t g, Next next) {
     const int64_t i = static_cast<int64_t>(f) * a.n + g;
     const uint32_t cnt = a.gcnt[i];
     if (cnt == 0) return;
@@ -111,11 +103,11 @@ __global__ __launch_bounds__(256) void k_scatter(Args a) {
             double x0, x1, y0, y1;
             tile_box(tx, ty, a.width, a.height, x0, x1, y0, y1);
             if (ellipse_meets_box<double>(r.u, r.v, ca, cb, cc, x0, x1, y0, y1, BIN_Q_SLACK)) {
-                const int64_t tile = tile0 + ty * a.tiles_x + tx;
-                const uint32_t pos = a.toff[tile] + atomicAdd(&a.tcur[tile], 1u);
-                // the counts of k_project bound every write; a mismatch is an
-                // internal error, reported instead of written out of bounds
-                if (pos >= a.toff[tile + 1] || k >= cnt) {
+                const int tl = ty * a.tiles_x + tx;
+                const uint32_t pos = next(tl);
+                // the counts bound every write; a mismatch is an internal
+                // error, reported instead of written out of bounds
+                if (pos >= a.toff[tile0 + tl + 1] || k >= cnt) {
                     a.status[ST_OVERFLOW] = 2u;
                     continue;
                 }
@@ -124,6 +116,74 @@ __global__ __launch_bounds__(256) void k_scatter(Args a) {
                 ++k;
             }
         }
+}
+
+// Binning with workgroup-local tile histograms in LDS: each workgroup
+// projects BIN_GROUP Gaussians of one frame, counts their intersections per
+// tile with LDS atomics, stores its histogram and adds it to the frame's tile
+// counts with one global atomic per non-empty tile.
+__global__ __launch_bounds__(256) void k_project_lds(Args a) {
+    extern __shared__ uint32_t hist[];
+    const int f = blockIdx.y;
+    for (int t = threadIdx.x; t < a.tiles; t += 256) hist[t] = 0u;
+    __syncthreads();
+    const CamD cam = load_camera(a.poses + 7 * f);
+    const double tt = a.times ? static_cast<double>(a.times[f]) : static_cast<double>(a.t0);
+    const int64_t g0 = static_cast<int64_t>(blockIdx.x) * BIN_GROUP;
+    for (int k = 0; k < BIN_GROUP / 256; ++k) {
+        const int64_t g = g0 + k * 256 + threadIdx.x;
+        if (g < a.n) project_and_count(a, f, g, cam, tt, [&](int tl) { atomicAdd(&hist[tl], 1u); });
+    }
+    __syncthreads();
+    uint32_t* bh = a.bhist + (static_cast<int64_t>(f) * a.bin_blocks + blockIdx.x) * a.tiles;
+    uint32_t* tc = a.tcnt + static_cast<int64_t>(f) * a.tiles;
+    for (int t = threadIdx.x; t < a.tiles; t += 256) {
+        const uint32_t v = hist[t];
+        bh[t] = v;
+        if (v) atomicAdd(&tc[t], v);
+    }
+}
+
+// Scatter counterpart: one global atomic per non-empty (workgroup, tile)
+// reserves the workgroup's range in the tile's bucket; positions inside it are
+// handed out by LDS atomics.
+__global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
+    if (overflowed(a.status)) return;
+    extern __shared__ uint32_t base[];
+    const int f = blockIdx.y;
+    const uint32_t* bh = a.bhist + (static_cast<int64_t>(f) * a.bin_blocks + blockIdx.x) * a.tiles;
+    const int64_t tile0 = static_cast<int64_t>(f) * a.tiles;
+    for (int t = threadIdx.x; t < a.tiles; t += 256) {
+        const uint32_t v = bh[t];
+        base[t] = v ? a.toff[tile0 + t] + atomicAdd(&a.tcur[tile0 + t], v) : 0u;
+    }
+    __syncthreads();
+    const int64_t g0 = static_cast<int64_t>(blockIdx.x) * BIN_GROUP;
+    for (int k = 0; k < BIN_GROUP / 256; ++k) {
+        const int64_t g = g0 + k * 256 + threadIdx.x;
+        if (g < a.n) scatter_one(a, f, g, [&](int tl) { return atomicAdd(&base[tl], 1u); });
+    }
+}
+
+// Fallback for tile grids too large for an LDS histogram: global atomics per
+// intersection.
+__global__ __launch_bounds__(256) void k_project(Args a) {
+    const int f = blockIdx.y;
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= a.n) return;
+    const CamD cam = load_camera(a.poses + 7 * f);
+    const double t = a.times ? static_cast<double>(a.times[f]) : static_cast<double>(a.t0);
+    uint32_t* tc = a.tcnt + static_cast<int64_t>(f) * a.tiles;
+    project_and_count(a, f, g, cam, t, [&](int tl) { atomicAdd(&tc[tl], 1u); });
+}
+
+__global__ __launch_bounds__(256) void k_scatter(Args a) {
+    if (overflowed(a.status)) return;
+    const int f = blockIdx.y;
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= a.n) return;
+    const int64_t tile0 = static_cast<int64_t>(f) * a.tiles;
+    scatter_one(a, f, g, [&](int tl) { return a.toff[tile0 + tl] + atomicAdd(&a.tcur[tile0 + tl], 1u); });
 }
 
 // Copy frame 0's projected records out for inspection: (u, v, A00, A01, A11,
@@ -163,15 +223,29 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
     return hipGetLastError();
 }
 
+int64_t bin_blocks(int64_t n) { return (n + BIN_GROUP - 1) / BIN_GROUP; }
+
 hipError_t launch_project(const Args& a, hipStream_t stream) {
     if (a.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project, dim3(static_cast<uint32_t>((a.n + 255) / 256), a.frames), dim3(256), 0, stream, a);
+    if (a.bhist) {
+        hipLaunchKernelGGL(k_project_lds, dim3(static_cast<uint32_t>(a.bin_blocks), a.frames), dim3(256),
+                           sizeof(uint32_t) * a.tiles, stream, a);
+    } else {
+        hipLaunchKernelGGL(k_project, dim3(static_cast<uint32_t>((a.n + 255) / 256), a.frames), dim3(256), 0, stream,
+                           a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_scatter(const Args& a, hipStream_t stream) {
     if (a.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter, dim3(static_cast<uint32_t>((a.n + 255) / 256), a.frames), dim3(256), 0, stream, a);
+    if (a.bhist) {
+        hipLaunchKernelGGL(k_scatter_lds, dim3(static_cast<uint32_t>(a.bin_blocks), a.frames), dim3(256),
+                           sizeof(uint32_t) * a.tiles, stream, a);
+    } else {
+        hipLaunchKernelGGL(k_scatter, dim3(static_cast<uint32_t>((a.n + 255) / 256), a.frames), dim3(256), 0, stream,
+                           a);
+    }
     return hipGetLastError();
 }
 

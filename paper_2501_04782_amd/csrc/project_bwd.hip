@@ -168,18 +168,28 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
             for (int k = 0; k < 3; ++k) put(a.g_coeffs, (c * 3 + k) * n + g, gco[c * 3 + k]);
 }
 
-// Per frame: sum the workgroups' pose partials in order, then map dL/dRc and
-// dL/dtc to the unnormalised pose quaternion and translation.
-__global__ __launch_bounds__(64) void k_pose_finalize(Args a, int64_t n_blocks) {
+// Per frame: sum the workgroups' pose partials (each of the 256 threads takes
+// a strided subset of workgroups, then a fixed-order tree over threads), then
+// map dL/dRc and dL/dtc to the unnormalised pose quaternion and translation.
+__global__ __launch_bounds__(256) void k_pose_finalize(Args a, int64_t n_blocks) {
     const int f = blockIdx.x;
-    __shared__ double acc[12];
-    if (threadIdx.x < 12) {
-        double v = 0.0;
-        for (int64_t b = 0; b < n_blocks; ++b) v += a.pose_part[(b * a.frames + f) * 12 + threadIdx.x];
-        acc[threadIdx.x] = v;
+    __shared__ double red[256][13];
+    double v[12];
+    for (int k = 0; k < 12; ++k) v[k] = 0.0;
+    for (int64_t b = threadIdx.x; b < n_blocks; b += 256) {
+        const double* p = a.pose_part + (b * a.frames + f) * 12;
+        for (int k = 0; k < 12; ++k) v[k] += p[k];
     }
+    for (int k = 0; k < 12; ++k) red[threadIdx.x][k] = v[k];
     __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int k = 0; k < 12; ++k) red[threadIdx.x][k] += red[threadIdx.x + s][k];
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
+        double acc[12];
+        for (int k = 0; k < 12; ++k) acc[k] = red[0][k];
         const CamD cam = load_camera(a.poses + 7 * f);
         double dq[4] = {0, 0, 0, 0};
         if (cam.ok) quat_grad(cam.qh, cam.qn, acc, dq);
@@ -196,7 +206,7 @@ hipError_t launch_project_bwd(const Args& a, hipStream_t stream) {
     const int64_t nb = project_bwd_blocks(a.n);
     if (nb > 0) hipLaunchKernelGGL(k_project_bwd, dim3(static_cast<uint32_t>(nb)), dim3(PB_THREADS), 0, stream, a);
     if (a.g_poses)
-        hipLaunchKernelGGL(k_pose_finalize, dim3(static_cast<uint32_t>(a.frames)), dim3(64), 0, stream, a, nb);
+        hipLaunchKernelGGL(k_pose_finalize, dim3(static_cast<uint32_t>(a.frames)), dim3(256), 0, stream, a, nb);
     return hipGetLastError();
 }
 

@@ -285,18 +285,18 @@ def autotune(scene: Scene, camera: Camera, poses: torch.Tensor, times: Optional[
     L.check(L.load().gv_autotune(args[0], args[1], args[2], args[3], args[4], args[5], args[8], args[9], args[10],
                                  args[11], args[12], args[13], None if cache_path is None else cache_path.encode(),
                                  ctypes.byref(t)), "gv_autotune")
-    return dict(batch=int(t.batch), sort_cap=int(t.sort_cap))
+    return dict(batch=int(t.batch), sort_cap=int(t.sort_cap), compact=int(t.compact))
 
 
 def get_tuning() -> dict:
     t = L.GvTuning()
     L.check(L.load().gv_get_tuning(ctypes.byref(t)), "gv_get_tuning")
-    return dict(batch=int(t.batch), sort_cap=int(t.sort_cap))
+    return dict(batch=int(t.batch), sort_cap=int(t.sort_cap), compact=int(t.compact))
 
 
-def set_tuning(batch: int, sort_cap: int) -> None:
+def set_tuning(batch: int, sort_cap: int, compact: int = 1) -> None:
     t = L.GvTuning()
-    t.batch, t.sort_cap = int(batch), int(sort_cap)
+    t.batch, t.sort_cap, t.compact = int(batch), int(sort_cap), int(compact)
     L.check(L.load().gv_set_tuning(ctypes.byref(t)), "gv_set_tuning")
 
 

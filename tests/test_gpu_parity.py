@@ -168,10 +168,30 @@ def test_empty_and_single_gaussian():
             check_clip_against_oracle(w, "single Gaussian")
 
 
-def test_clip_reduced_batch_matches_oracle():
-    """Batched path on a reduced clip: moving camera, several frames."""
+@pytest.mark.parametrize("compact,batch,sort_cap", [(1, 256, 4096), (1, 128, 2048), (1, 64, 1024),
+                                                    (0, 256, 4096), (0, 128, 2048), (0, 64, 1024)])
+def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
+    """Batched path on a reduced clip (moving camera, several frames) under
+    every setting the autotuner can choose."""
     w = small_workload(3, 160, 96, 3000, 4, trajectory=True, z=(2.0, 10.0), ls=(-3.2, 0.5))
-    check_clip_against_oracle(w, "clip 160x96 F=4")
+    old = raster.get_tuning()
+    raster.set_tuning(batch, sort_cap, compact)
+    try:
+        check_clip_against_oracle(w, f"clip 160x96 F=4 compact={compact} batch={batch} cap={sort_cap}")
+    finally:
+        raster.set_tuning(old["batch"], old["sort_cap"], old["compact"])
+
+
+def test_long_tile_buckets_use_the_merge_sort():
+    """Many large Gaussians over a small image: buckets far longer than the
+    LDS sort capacity (chunked LDS sort + global merges)."""
+    w = small_workload(14, 48, 32, 5000, 1, z=(2.0, 6.0), ls=(-1.2, 0.3))
+    old = raster.get_tuning()
+    raster.set_tuning(old["batch"], 1024, old["compact"])
+    try:
+        out = check_clip_against_oracle(w, "long buckets")
+    finally:
+        raster.set_tuning(old["batch"], old["sort_cap"], old["compact"])
 
 
 def test_batch_equals_per_frame_path():
