@@ -24,6 +24,7 @@ import time
 import numpy as np
 
 METRIC = "fwd+bwd frames/s at 960×540, 200k Gaussians (batched vs per-frame), % HBM roof"
+ODE_WORKLOAD = "clip540p_f100_n200k"
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
 # FP32 vector peak without packed-FP32 instructions (this build disables them):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
@@ -132,7 +133,35 @@ def main():
         tuning = raster.autotune(scene, cam, poses, times, ws, targets)
     log(f"[bench] tuning {tuning}")
 
-    graph = raster.BatchGraph(scene, cam, poses, times, ws, targets=targets)
+    ode_info = None
+    if args.workload == ODE_WORKLOAD:
+        # learned camera (Eq. 1): targets are renders at the ground-truth
+        # trajectory; one step integrates the ODE from (theta, z0 = frame-0
+        # pose), renders all frames, back-propagates the L2 loss and runs the
+        # ODE adjoint, captured in one graph
+        from paper_2501_04782_amd import camera
+        gt = raster.render_batch(scene, cam, poses, times, ws, forward=True, backward=False)
+        targets = gt["images"].clone()
+        rng_t = np.random.default_rng(7)
+        theta = torch.from_numpy(gv_synth.init_mlp_theta(rng_t).astype(np.float32)).to(dev)
+        z0 = poses[0].clone()
+        ode_substeps = 4
+        graph = camera.FitGraph(scene, cam, theta, z0, F, ode_substeps, times, ws, targets=targets)
+        ows = camera.OdeWorkspace(F, ode_substeps, device=dev)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        camera.camera_ode_fwd(theta, z0, F, ode_substeps, ows)
+        torch.cuda.synchronize()
+        e0.record()
+        p = camera.camera_ode_fwd(theta, z0, F, ode_substeps, ows)
+        e1.record()
+        camera.camera_ode_bwd(theta, z0, F, ode_substeps, torch.ones_like(p), ows)
+        e2.record()
+        torch.cuda.synchronize()
+        ode_info = dict(fwd_ms=round(e0.elapsed_time(e1), 4), bwd_ms=round(e1.elapsed_time(e2), 4),
+                        substeps=ode_substeps, mlp_evals=4 * ode_substeps * (F - 1))
+        log(f"[bench] camera ODE: {ode_info}")
+    else:
+        graph = raster.BatchGraph(scene, cam, poses, times, ws, targets=targets)
     for _ in range(args.warmup):
         graph.launch()
     torch.cuda.synchronize()
@@ -168,7 +197,7 @@ def main():
 
     # plain per-frame path on the same clip (render_fwd reads K back each frame)
     per_frame = None
-    if not args.no_per_frame:
+    if not args.no_per_frame and ode_info is None:
         wsf = raster.Workspace(cam, N, 1, int(max(kf) * 1.25) + 4096, device=dev)
         grads = raster.grad_buffers(scene)
         scale = 2.0 / (3.0 * P * F)
@@ -271,6 +300,9 @@ def main():
     }
     if mean_contrib is not None:
         line["mean_contributors_per_pixel"] = round(mean_contrib, 3)
+    if ode_info is not None:
+        line["camera_ode"] = ode_info
+        line["config"]["path"] = "camera ODE fwd -> batched raster fwd+bwd -> ODE adjoint, one HIP graph per step"
     print(json.dumps(line), flush=True)
     graph.close()
 

@@ -30,7 +30,7 @@ import numpy as np
 __all__ = [
     "Camera", "Scene", "WORKLOADS", "make_camera", "make_scene", "make_trajectory",
     "make_times", "make_targets", "make_workload", "round_bf16", "bf16_bits_to_f64",
-    "adversarial_scene", "identity_poses",
+    "adversarial_scene", "identity_poses", "init_mlp_theta",
 ]
 
 
@@ -310,3 +310,22 @@ def adversarial_scene(rng: np.random.Generator, n: int, kind: str, width: int = 
     scene = Scene(dtype="f32", means=_store(means, "f32"), log_scales=_store(ls, "f32"),
                   quats=_store(q, "f32"), opacity_logits=_store(eta, "f32"), colors=_store(col, "f32"))
     return scene, cam
+
+
+# --------------------------------------------------------------------------
+# camera-ODE parameters
+# --------------------------------------------------------------------------
+
+def init_mlp_theta(rng: np.random.Generator, last_layer_scale: float = 0.1, hidden: int = 64,
+                   state: int = 7) -> np.ndarray:
+    """Parameters of the 8 -> 64 -> 64 -> 7 vector-field MLP as one FP64 vector
+    (W1 [64][8], b1, W2 [64][64], b2, W3 [7][64], b3): each layer's weights and
+    bias ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)), the last layer scaled by
+    ``last_layer_scale`` (a small initial camera velocity)."""
+    def layer(fan_out, fan_in, scale=1.0):
+        b = 1.0 / np.sqrt(fan_in)
+        return rng.uniform(-b, b, (fan_out, fan_in)) * scale, rng.uniform(-b, b, fan_out) * scale
+    W1, b1 = layer(hidden, state + 1)
+    W2, b2 = layer(hidden, hidden)
+    W3, b3 = layer(state, hidden, last_layer_scale)
+    return np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3.ravel(), b3])

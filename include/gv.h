@@ -217,6 +217,19 @@ gv_status gv_camera_ode_bwd(const float *theta, const float *z0, int32_t frames,
                             const float *dL_dposes, float *dtheta, float *dz0, void *ws, size_t ws_bytes,
                             void *stream);
 
+/* One fitting step of the learned-camera form, captured into one HIP graph
+ * (launch/destroy with gv_batch_graph_launch / gv_batch_graph_destroy):
+ * gv_camera_ode_fwd (theta, z0 -> poses [F][7]), then gv_render_batch with
+ * GV_FWD | GV_BWD on those poses (GV_LOSS_L2 with targets, or an explicit
+ * dL_dimages: exactly one of the two is given), then gv_camera_ode_bwd
+ * (dL_dposes -> dtheta [5191], dz0 [7]).  Everything stays on the device
+ * (Sec. 3.4: camera and renderer are integrated to avoid transfers). */
+gv_status gv_fit_graph_create(const gv_scene *scene, const gv_camera *cam, const float *theta, const float *z0,
+                              int32_t substeps, void *ode_ws, size_t ode_ws_bytes, const float *times, int32_t frames,
+                              const float *targets, const float *dL_dimages, float *poses, float *images, float *loss,
+                              gv_grads *grads, float *dL_dposes, float *dtheta, float *dz0, void *ws, size_t ws_bytes,
+                              gv_graph **out);
+
 /* Tunables: read/set the process-wide table; gv_autotune times candidate
  * settings on the given batch problem (it runs gv_render_batch several times
  * on the caller's buffers, overwriting its outputs, and synchronises) and

@@ -157,15 +157,3 @@ def camera_ode_bwd(theta, z0, frames: int, substeps: int, dposes):
                 lam = dz
             lam = lam + pose_cotangent(states[f - 1], dposes[f - 1])
     return dtheta, lam
-
-
-def init_theta(rng: np.random.Generator, last_layer_scale: float = 0.1):
-    """theta ~ U(+-1/sqrt(fan_in)) per layer, last layer scaled (a small
-    initial velocity field)."""
-    def lin(fan_out, fan_in, scale=1.0):
-        b = 1.0 / np.sqrt(fan_in)
-        return (rng.uniform(-b, b, (fan_out, fan_in)) * scale, rng.uniform(-b, b, fan_out) * scale)
-    W1, b1 = lin(HIDDEN, STATE + 1)
-    W2, b2 = lin(HIDDEN, HIDDEN)
-    W3, b3 = lin(STATE, HIDDEN, last_layer_scale)
-    return pack(W1, b1, W2, b2, W3, b3)

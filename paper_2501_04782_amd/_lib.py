@@ -73,6 +73,10 @@ _SIGS = [
                                         c_int32, c_void_p, c_void_p, c_uint32, c_void_p, c_void_p,
                                         ctypes.POINTER(GvGrads), c_void_p, c_void_p, c_size_t,
                                         ctypes.POINTER(c_void_p)]),
+    ("gv_fit_graph_create", c_int32, [ctypes.POINTER(GvScene), ctypes.POINTER(GvCamera), c_void_p, c_void_p, c_int32,
+                                      c_void_p, c_size_t, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, ctypes.POINTER(GvGrads), c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_size_t, ctypes.POINTER(c_void_p)]),
     ("gv_batch_graph_launch", c_int32, [c_void_p, c_void_p]),
     ("gv_batch_graph_destroy", c_int32, [c_void_p]),
     ("gv_camera_ode_workspace_bytes", c_int32, [c_int32, c_int32, ctypes.POINTER(c_size_t)]),

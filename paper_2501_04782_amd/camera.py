@@ -14,7 +14,7 @@ import ctypes
 import torch
 
 from . import _lib as L
-from .raster import _need, _ptr, _stream
+from .raster import Camera, Scene, Workspace, _grads_c, _need, _ptr, _stream, grad_buffers
 
 N_THETA = 5191
 
@@ -74,3 +74,48 @@ class CameraODE(torch.autograd.Function):
         theta, z0 = ctx.saved_tensors
         dtheta, dz0 = camera_ode_bwd(theta, z0, ctx.frames, ctx.substeps, dposes.contiguous(), ctx.ws)
         return dtheta, dz0, None, None, None
+
+
+class FitGraph:
+    """One learned-camera fitting step as a single HIP graph: camera ODE forward,
+    batched raster forward+backward (fused L2 against ``targets`` or an explicit
+    ``dL_dimages``), camera ODE adjoint.  All buffers are fixed at creation."""
+
+    def __init__(self, scene: Scene, camera: Camera, theta, z0, frames: int, substeps: int, times, ws: Workspace,
+                 targets=None, dL_dimages=None):
+        dev = theta.device
+        H, W = camera.height, camera.width
+        _need(theta, (N_THETA,), torch.float32, "theta")
+        _need(z0, (7,), torch.float32, "z0")
+        self.ode_ws = OdeWorkspace(frames, substeps, device=dev)
+        self.poses = torch.empty(frames, 7, device=dev)
+        self.images = torch.empty(frames, 3, H, W, device=dev)
+        self.loss = torch.empty(frames, device=dev) if targets is not None else None
+        self.grads = grad_buffers(scene)
+        self.dL_dposes = torch.empty(frames, 7, device=dev)
+        self.dtheta = torch.empty(N_THETA, device=dev)
+        self.dz0 = torch.empty(7, device=dev)
+        self._refs = (scene, camera, theta, z0, times, ws, targets, dL_dimages)
+        self._gs = _grads_c(self.grads)
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        L.check(L.load().gv_fit_graph_create(
+            ctypes.byref(scene.c()), ctypes.byref(camera.c()), _ptr(theta), _ptr(z0), int(substeps),
+            self.ode_ws.ptr, self.ode_ws.buf.numel(), _ptr(times), int(frames), _ptr(targets), _ptr(dL_dimages),
+            _ptr(self.poses), _ptr(self.images), _ptr(self.loss), ctypes.byref(self._gs), _ptr(self.dL_dposes),
+            _ptr(self.dtheta), _ptr(self.dz0), ws.ptr, ws.nbytes, ctypes.byref(h)), "gv_fit_graph_create")
+        self._h = h
+
+    def launch(self):
+        L.check(L.load().gv_batch_graph_launch(self._h, _stream()), "gv_batch_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.load().gv_batch_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

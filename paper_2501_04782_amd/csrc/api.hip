@@ -459,6 +459,49 @@ gv_status gv_batch_graph_create(const gv_scene* scene, const gv_camera* cam, con
     return GV_OK;
 }
 
+gv_status gv_fit_graph_create(const gv_scene* scene, const gv_camera* cam, const float* theta, const float* z0,
+                              int32_t substeps, void* ode_ws, size_t ode_ws_bytes, const float* times, int32_t frames,
+                              const float* targets, const float* dL_dimages, float* poses, float* images, float* loss,
+                              gv_grads* grads, float* dL_dposes, float* dtheta, float* dz0, void* ws, size_t ws_bytes,
+                              gv_graph** out) {
+    if (!out || !theta || !z0 || !poses || !dL_dposes || !dtheta || !dz0 || !grads) return GV_ERR_INVALID_ARG;
+    if ((targets == nullptr) == (dL_dimages == nullptr)) return GV_ERR_INVALID_ARG;
+    *out = nullptr;
+    const uint32_t flags = GV_FWD | GV_BWD | (targets ? GV_LOSS_L2 : 0u);
+    hipStream_t cs;
+    GV_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        hipStreamDestroy(cs);
+        return hip_status(e);
+    }
+    gv_status s = gv_camera_ode_fwd(theta, z0, frames, substeps, poses, ode_ws, ode_ws_bytes, cs);
+    if (s == GV_OK)
+        s = enqueue_batch(scene, cam, poses, times, frames, targets, dL_dimages, flags, images, loss, grads, dL_dposes,
+                          ws, ws_bytes, cs);
+    if (s == GV_OK)
+        s = gv_camera_ode_bwd(theta, z0, frames, substeps, dL_dposes, dtheta, dz0, ode_ws, ode_ws_bytes, cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    hipStreamDestroy(cs);
+    if (s != GV_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return s;
+    }
+    if (e != hipSuccess) return hip_status(e);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return hip_status(e);
+    }
+    gv_graph* g = new gv_graph;
+    g->graph = graph;
+    g->exec = exec;
+    *out = g;
+    return GV_OK;
+}
+
 gv_status gv_batch_graph_launch(gv_graph* graph, void* stream) {
     if (!graph) return GV_ERR_INVALID_ARG;
     GV_TRY(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)));

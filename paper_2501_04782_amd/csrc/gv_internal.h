@@ -199,7 +199,7 @@ __device__ __forceinline__ CamD load_camera(const float* pose7) {
 
 // FP64 projection state of one Gaussian in one frame (EWA splatting).
 struct ProjD {
-    double mu[3], s[3], qh[4], qn, R[9], M[9];
+    double mu[3], s[3], qh[4], qn, R[9];
     double Sig[6];        // xx xy xz yy yz zz
     double m[3];
     double u, v;
@@ -244,15 +244,18 @@ __device__ __forceinline__ bool project_gaussian(const Args& a, int64_t g, const
     P.eta = raw[10];
     P.o = 1.0 / (1.0 + exp(-raw[10]));
     rot_from_quat(P.qh[0], P.qh[1], P.qh[2], P.qh[3], P.R);
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) P.M[i * 3 + j] = P.R[i * 3 + j] * P.s[j];
-    const double* M = P.M;
-    P.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
-    P.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
-    P.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
-    P.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
-    P.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
-    P.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+    {
+        // Sigma = M M^T with M = R diag(s)
+        double M[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) M[i * 3 + j] = P.R[i * 3 + j] * P.s[j];
+        P.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+        P.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+        P.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+        P.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+        P.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+        P.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+    }
     const double* Rc = cam.R;
     // m = tc + Rc mu, summed in this order (with no contraction the fp32
     // rounding of m_z, the depth sort key, is then reproducible bit for bit)

@@ -130,6 +130,7 @@ __global__ __launch_bounds__(256) void k_project_lds(Args a) {
     const CamD cam = load_camera(a.poses + 7 * f);
     const double tt = a.times ? static_cast<double>(a.times[f]) : static_cast<double>(a.t0);
     const int64_t g0 = static_cast<int64_t>(blockIdx.x) * BIN_GROUP;
+#pragma unroll 1
     for (int k = 0; k < BIN_GROUP / 256; ++k) {
         const int64_t g = g0 + k * 256 + threadIdx.x;
         if (g < a.n) project_and_count(a, f, g, cam, tt, [&](int tl) { atomicAdd(&hist[tl], 1u); });
@@ -159,6 +160,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
     }
     __syncthreads();
     const int64_t g0 = static_cast<int64_t>(blockIdx.x) * BIN_GROUP;
+#pragma unroll 1
     for (int k = 0; k < BIN_GROUP / 256; ++k) {
         const int64_t g = g0 + k * 256 + threadIdx.x;
         if (g < a.n) scatter_one(a, f, g, [&](int tl) { return atomicAdd(&base[tl], 1u); });

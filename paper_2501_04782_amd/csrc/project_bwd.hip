@@ -1,8 +1,10 @@
 // Adjoint of the EWA projection.  One thread per Gaussian loops over the
 // frames: it sums the per-(Gaussian, tile) partials left by the compositing
-// adjoint (contiguous slots of this Gaussian), re-derives the frame's
-// projection in FP64 and applies the chain rule down to the stored
-// parameters, accumulating the shared parameters over frames in registers.
+// adjoint (contiguous slots of this Gaussian, in FP64), takes the conic of the
+// forward record, re-derives the rest of the frame's projection and applies
+// the chain rule down to the stored parameters in FP32, accumulating the
+// shared parameters over frames in FP64 (in LDS, which keeps the chain rule's
+// registers free for occupancy).
 // Each frame's pose gradient (dL/dRc, dL/dtc) is reduced per workgroup in a
 // fixed order; a second kernel sums the workgroups and maps it to the 7-vector
 // pose.  Everything is deterministic (no floating-point atomics).
@@ -12,141 +14,233 @@ namespace gv {
 
 constexpr int PB_THREADS = 128;
 
+// dR_e * dR_e/dq for the e-th entry (row-major) of the rotation matrix of the
+// unit quaternion (w, x, y, z); e is a compile-time constant after unrolling.
+__device__ __forceinline__ void add_rot_partial(int e, float v, const float q[4], float g[4]) {
+    const float w = q[0], x = q[1], y = q[2], z = q[3];
+    switch (e) {
+        case 0: g[2] += -4.0f * y * v; g[3] += -4.0f * z * v; break;
+        case 1: g[0] += -2.0f * z * v; g[1] += 2.0f * y * v; g[2] += 2.0f * x * v; g[3] += -2.0f * w * v; break;
+        case 2: g[0] += 2.0f * y * v; g[1] += 2.0f * z * v; g[2] += 2.0f * w * v; g[3] += 2.0f * x * v; break;
+        case 3: g[0] += 2.0f * z * v; g[1] += 2.0f * y * v; g[2] += 2.0f * x * v; g[3] += 2.0f * w * v; break;
+        case 4: g[1] += -4.0f * x * v; g[3] += -4.0f * z * v; break;
+        case 5: g[0] += -2.0f * x * v; g[1] += -2.0f * w * v; g[2] += 2.0f * z * v; g[3] += 2.0f * y * v; break;
+        case 6: g[0] += -2.0f * y * v; g[1] += 2.0f * z * v; g[2] += -2.0f * w * v; g[3] += 2.0f * x * v; break;
+        case 7: g[0] += 2.0f * x * v; g[1] += 2.0f * w * v; g[2] += 2.0f * z * v; g[3] += 2.0f * y * v; break;
+        default: g[1] += -4.0f * x * v; g[2] += -4.0f * y * v; break;
+    }
+}
+
+// FP32 quantities of the projection of (f, g) that the adjoint needs.  The
+// conic is read from the forward record (the FP64 value rounded once: exactly
+// the one the compositing kernels used); the rest is recomputed.
+struct AdjIn {
+    float mu[3], s[3], qh[4], qn, R[9], Sig[6], m[3], T[6], A[3], o;
+};
+
+__device__ __forceinline__ void adjoint_inputs(const Args& a, int64_t g, const Record& rec, const float* Rc,
+                                               const float* tc, float t, AdjIn& P) {
+    const int64_t n = a.n;
+    float q[4];
+    for (int k = 0; k < 3; ++k) {
+        float mu = static_cast<float>(load_param(a.means, a.dtype, k * n + g));
+        if (a.mean_coeffs) {
+            const float c1 = static_cast<float>(load_param(a.mean_coeffs, a.dtype, (0 * 3 + k) * n + g));
+            const float c2 = static_cast<float>(load_param(a.mean_coeffs, a.dtype, (1 * 3 + k) * n + g));
+            const float c3 = static_cast<float>(load_param(a.mean_coeffs, a.dtype, (2 * 3 + k) * n + g));
+            mu = mu + t * (c1 + t * (c2 + t * c3));
+        }
+        P.mu[k] = mu;
+        P.s[k] = expf(static_cast<float>(load_param(a.log_scales, a.dtype, k * n + g)));
+    }
+    for (int k = 0; k < 4; ++k) q[k] = static_cast<float>(load_param(a.quats, a.dtype, k * n + g));
+    P.qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int k = 0; k < 4; ++k) P.qh[k] = q[k] / P.qn;
+    const float eta = static_cast<float>(load_param(a.opacity_logits, a.dtype, g));
+    P.o = 1.0f / (1.0f + expf(-eta));
+    {
+        const float w = P.qh[0], x = P.qh[1], y = P.qh[2], z = P.qh[3];
+        float* R = P.R;
+        R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z);       R[2] = 2.f * (x * z + w * y);
+        R[3] = 2.f * (x * y + w * z);       R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+        R[6] = 2.f * (x * z - w * y);       R[7] = 2.f * (y * z + w * x);       R[8] = 1.f - 2.f * (x * x + y * y);
+    }
+    {
+        float M[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) M[i * 3 + j] = P.R[i * 3 + j] * P.s[j];
+        P.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+        P.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+        P.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+        P.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+        P.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+        P.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+    }
+    for (int i = 0; i < 3; ++i)
+        P.m[i] = tc[i] + Rc[i * 3 + 0] * P.mu[0] + Rc[i * 3 + 1] * P.mu[1] + Rc[i * 3 + 2] * P.mu[2];
+    const float iz = 1.0f / P.m[2];
+    const float j00 = a.fx * iz, j02 = -a.fx * P.m[0] * iz * iz;
+    const float j11 = a.fy * iz, j12 = -a.fy * P.m[1] * iz * iz;
+    for (int j = 0; j < 3; ++j) {
+        P.T[j] = j00 * Rc[0 * 3 + j] + j02 * Rc[2 * 3 + j];
+        P.T[3 + j] = j11 * Rc[1 * 3 + j] + j12 * Rc[2 * 3 + j];
+    }
+    P.A[0] = rec.a;
+    P.A[1] = rec.b;
+    P.A[2] = rec.c;
+}
+
 // Chain rule for one (frame, Gaussian).  d: dL/d(u, v, A00, A01, A11, o, r, g,
 // b) with A01 the single off-diagonal conic parameter (it enters q twice).
-__device__ __forceinline__ void projection_adjoint(const Args& a, const CamD& cam, const ProjD& P, double t,
-                                                   const double d[9], double dmu[3], double dls[3], double dq[4],
-                                                   double& deta, double dcol[3], double dRc[9], double dtc[3]) {
-    const double A0 = P.A[0], A1 = P.A[1], A2 = P.A[2];
+// Adds the parameter gradients to acc[.][tid] (means 0-2, log-scales 3-5,
+// quaternion 6-9, opacity logit 10, colour 11-13, cubic coefficients 14-22)
+// and the pose gradient (dL/dRc row-major 0-8, dL/dtc 9-11) to pose[.][tid].
+template <int NT>
+__device__ __forceinline__ void projection_adjoint(const Args& a, const float* Rc, const AdjIn& P, float t,
+                                                   const float d[9], double (*acc)[NT], double (*pose)[NT],
+                                                   int tid) {
+    const float A0 = P.A[0], A1 = P.A[1], A2 = P.A[2];
     // gradient w.r.t. the symmetric conic matrix
-    const double G00 = d[2], G01 = 0.5 * d[3], G11 = d[4];
+    const float G00 = d[2], G01 = 0.5f * d[3], G11 = d[4];
     // A = cov^-1  =>  dL/dcov = -A G A
-    const double AG00 = A0 * G00 + A1 * G01, AG01 = A0 * G01 + A1 * G11;
-    const double AG10 = A1 * G00 + A2 * G01, AG11 = A1 * G01 + A2 * G11;
-    const double C00 = -(AG00 * A0 + AG01 * A1);
-    const double C01 = -0.5 * ((AG00 * A1 + AG01 * A2) + (AG10 * A0 + AG11 * A1));
-    const double C11 = -(AG10 * A1 + AG11 * A2);
-    // cov = T Sig T^T + dil I with T = J Rc (2x3)
-    const double* Tm = P.T;
-    // dSig = T^T C T (3x3 symmetric)
-    double CT[6];  // C T, 2x3
+    const float AG00 = A0 * G00 + A1 * G01, AG01 = A0 * G01 + A1 * G11;
+    const float AG10 = A1 * G00 + A2 * G01, AG11 = A1 * G01 + A2 * G11;
+    const float C00 = -(AG00 * A0 + AG01 * A1);
+    const float C01 = -0.5f * ((AG00 * A1 + AG01 * A2) + (AG10 * A0 + AG11 * A1));
+    const float C11 = -(AG10 * A1 + AG11 * A2);
+    // cov = T Sig T^T + dil I with T = J Rc (2x3); CT = C T
+    const float* Tm = P.T;
+    float CT[6];
     for (int j = 0; j < 3; ++j) {
         CT[j] = C00 * Tm[j] + C01 * Tm[3 + j];
         CT[3 + j] = C01 * Tm[j] + C11 * Tm[3 + j];
     }
-    double GS[9];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) GS[i * 3 + j] = Tm[i] * CT[j] + Tm[3 + i] * CT[3 + j];
-    // dT = 2 C T Sig
-    const double* S = P.Sig;  // xx xy xz yy yz zz
-    const double Sm[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
-    double dT[6];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 3; ++j)
-            dT[i * 3 + j] = 2.0 * (CT[i * 3 + 0] * Sm[0 * 3 + j] + CT[i * 3 + 1] * Sm[1 * 3 + j] +
-                                   CT[i * 3 + 2] * Sm[2 * 3 + j]);
+    // dT = 2 C T Sig  (Sig symmetric, stored xx xy xz yy yz zz)
+    const float* S = P.Sig;
+    float dT[6];
+    for (int i = 0; i < 2; ++i) {
+        const float c0 = CT[i * 3 + 0], c1 = CT[i * 3 + 1], c2 = CT[i * 3 + 2];
+        dT[i * 3 + 0] = 2.0f * (c0 * S[0] + c1 * S[1] + c2 * S[2]);
+        dT[i * 3 + 1] = 2.0f * (c0 * S[1] + c1 * S[3] + c2 * S[4]);
+        dT[i * 3 + 2] = 2.0f * (c0 * S[2] + c1 * S[4] + c2 * S[5]);
+    }
     // T = J Rc with J = [[j00, 0, j02], [0, j11, j12]]
-    const double* Rc = cam.R;
-    const double mx = P.m[0], my = P.m[1], mz = P.m[2];
-    const double iz = 1.0 / mz, iz2 = iz * iz, iz3 = iz2 * iz;
-    const double fx = a.fx, fy = a.fy;
-    const double j00 = fx * iz, j02 = -fx * mx * iz2, j11 = fy * iz, j12 = -fy * my * iz2;
-    double dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0;
+    const float mx = P.m[0], my = P.m[1], mz = P.m[2];
+    const float iz = 1.0f / mz, iz2 = iz * iz, iz3 = iz2 * iz;
+    const float fx = a.fx, fy = a.fy;
+    const float j00 = fx * iz, j02 = -fx * mx * iz2, j11 = fy * iz, j12 = -fy * my * iz2;
+    float dJ00 = 0.f, dJ02 = 0.f, dJ11 = 0.f, dJ12 = 0.f;
     for (int j = 0; j < 3; ++j) {
         dJ00 += dT[j] * Rc[0 * 3 + j];
         dJ02 += dT[j] * Rc[2 * 3 + j];
         dJ11 += dT[3 + j] * Rc[1 * 3 + j];
         dJ12 += dT[3 + j] * Rc[2 * 3 + j];
-        dRc[0 * 3 + j] += j00 * dT[j];
-        dRc[1 * 3 + j] += j11 * dT[3 + j];
-        dRc[2 * 3 + j] += j02 * dT[j] + j12 * dT[3 + j];
+        pose[0 * 3 + j][tid] += j00 * dT[j];
+        pose[1 * 3 + j][tid] += j11 * dT[3 + j];
+        pose[2 * 3 + j][tid] += j02 * dT[j] + j12 * dT[3 + j];
     }
     // J(m) and (u, v)(m)
-    double dm[3];
+    float dm[3];
     dm[0] = -dJ02 * fx * iz2 + d[0] * fx * iz;
     dm[1] = -dJ12 * fy * iz2 + d[1] * fy * iz;
-    dm[2] = -dJ00 * fx * iz2 + dJ02 * 2.0 * fx * mx * iz3 - dJ11 * fy * iz2 + dJ12 * 2.0 * fy * my * iz3 -
+    dm[2] = -dJ00 * fx * iz2 + dJ02 * 2.0f * fx * mx * iz3 - dJ11 * fy * iz2 + dJ12 * 2.0f * fy * my * iz3 -
             d[0] * fx * mx * iz2 - d[1] * fy * my * iz2;
     // m = Rc mu + tc
     for (int k = 0; k < 3; ++k) {
-        dmu[k] = Rc[0 * 3 + k] * dm[0] + Rc[1 * 3 + k] * dm[1] + Rc[2 * 3 + k] * dm[2];
-        dtc[k] += dm[k];
+        const float dmu = Rc[0 * 3 + k] * dm[0] + Rc[1 * 3 + k] * dm[1] + Rc[2 * 3 + k] * dm[2];
+        acc[k][tid] += dmu;
+        if (a.mean_coeffs) {
+            acc[14 + k][tid] += static_cast<double>(dmu) * t;
+            acc[17 + k][tid] += static_cast<double>(dmu) * t * t;
+            acc[20 + k][tid] += static_cast<double>(dmu) * t * t * t;
+        }
+        pose[9 + k][tid] += dm[k];
     }
     for (int i = 0; i < 3; ++i)
-        for (int k = 0; k < 3; ++k) dRc[i * 3 + k] += dm[i] * P.mu[k];
-    // Sig = M M^T, M = R diag(s)
-    double dR[9];
-    double ds[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < 3; ++k) pose[i * 3 + k][tid] += dm[i] * P.mu[k];
+    // Sig = M M^T, M = R diag(s): dM = 2 (T^T C T) M, i.e. with U = C T R,
+    // dM_ij = 2 s_j (T_0i U_0j + T_1i U_1j); then dR = dM diag(s), ds_j = sum_i dM_ij R_ij
+    float U[6];
+    for (int r = 0; r < 2; ++r)
+        for (int j = 0; j < 3; ++j)
+            U[r * 3 + j] = CT[r * 3 + 0] * P.R[0 * 3 + j] + CT[r * 3 + 1] * P.R[1 * 3 + j] +
+                           CT[r * 3 + 2] * P.R[2 * 3 + j];
+    float ds[3] = {0.f, 0.f, 0.f};
+    float gq[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const double dM = 2.0 * (GS[i * 3 + 0] * P.M[0 * 3 + j] + GS[i * 3 + 1] * P.M[1 * 3 + j] +
-                                     GS[i * 3 + 2] * P.M[2 * 3 + j]);
-            dR[i * 3 + j] = dM * P.s[j];
+            const float dM = 2.0f * P.s[j] * (Tm[i] * U[j] + Tm[3 + i] * U[3 + j]);
             ds[j] += dM * P.R[i * 3 + j];
+            add_rot_partial(i * 3 + j, dM * P.s[j], P.qh, gq);
         }
-    for (int k = 0; k < 3; ++k) dls[k] = ds[k] * P.s[k];
-    quat_grad(P.qh, P.qn, dR, dq);
-    deta = d[5] * P.o * (1.0 - P.o);
-    dcol[0] = d[6];
-    dcol[1] = d[7];
-    dcol[2] = d[8];
-    (void)t;
+    for (int k = 0; k < 3; ++k) acc[3 + k][tid] += ds[k] * P.s[k];
+    // q_hat = q / |q|
+    const float dot = P.qh[0] * gq[0] + P.qh[1] * gq[1] + P.qh[2] * gq[2] + P.qh[3] * gq[3];
+    for (int k = 0; k < 4; ++k) acc[6 + k][tid] += (gq[k] - P.qh[k] * dot) / P.qn;
+    acc[10][tid] += d[5] * P.o * (1.0f - P.o);
+    acc[11][tid] += d[6];
+    acc[12][tid] += d[7];
+    acc[13][tid] += d[8];
 }
 
 __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
     if (overflowed(a.status)) return;
     const int64_t g = static_cast<int64_t>(blockIdx.x) * PB_THREADS + threadIdx.x;
     const bool live = g < a.n;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     __shared__ double red[PB_THREADS / 64][12];
+    // per-thread gradient accumulators (FP64) live in LDS: means 3,
+    // log-scales 3, quaternion 4, opacity 1, colour 3, cubic coefficients 9
+    __shared__ double acc[23][PB_THREADS];
+    __shared__ double pacc[12][PB_THREADS];  // this frame's pose contributions (dL/dRc, dL/dtc)
+    __shared__ float camR[9], camT[3];
+    for (int k = 0; k < 23; ++k) acc[k][tid] = 0.0;
 
-    double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, geta = 0, gcol[3] = {0, 0, 0};
-    double gco[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
     for (int f = 0; f < a.frames; ++f) {
-        double pr[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        __syncthreads();
+        if (tid == 0) {
+            const CamD c = load_camera(a.poses + 7 * f);
+            for (int k = 0; k < 9; ++k) camR[k] = c.ok ? static_cast<float>(c.R[k]) : 0.0f;
+            for (int k = 0; k < 3; ++k) camT[k] = c.ok ? static_cast<float>(c.t[k]) : 0.0f;
+        }
+        __syncthreads();
+        for (int k = 0; k < 12; ++k) pacc[k][tid] = 0.0;
         const int64_t i = static_cast<int64_t>(f) * a.n + g;
         uint32_t cnt = live ? a.gcnt[i] : 0u;
         const uint32_t base = live ? a.goff[i] : 0u;
         if (static_cast<int64_t>(base) + cnt > a.k_cap) cnt = 0u;  // only after an internal error
         if (cnt) {
-            double d[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            double dd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 2
             for (uint32_t k = 0; k < cnt; ++k) {
                 const float4 pa = a.partA[base + k];
                 const float4 pb = a.partB[base + k];
                 const float pc = a.partC[base + k];
-                d[0] += pa.x; d[1] += pa.y; d[2] += pa.z; d[3] += pa.w;
-                d[4] += pb.x; d[5] += pb.y; d[6] += pb.z; d[7] += pb.w; d[8] += pc;
+                dd[0] += pa.x; dd[1] += pa.y; dd[2] += pa.z; dd[3] += pa.w;
+                dd[4] += pb.x; dd[5] += pb.y; dd[6] += pb.z; dd[7] += pb.w; dd[8] += pc;
             }
-            const CamD cam = load_camera(a.poses + 7 * f);
-            const double t = a.times ? static_cast<double>(a.times[f]) : static_cast<double>(a.t0);
-            ProjD P;
-            if (project_gaussian(a, g, cam, t, P)) {
-                double dmu[3], dls[3], dq[4], deta, dcol[3];
-                projection_adjoint(a, cam, P, t, d, dmu, dls, dq, deta, dcol, pr, pr + 9);
-                for (int k = 0; k < 3; ++k) {
-                    gmu[k] += dmu[k];
-                    gls[k] += dls[k];
-                    gcol[k] += dcol[k];
-                    gco[k] += dmu[k] * t;
-                    gco[3 + k] += dmu[k] * t * t;
-                    gco[6 + k] += dmu[k] * t * t * t;
-                }
-                for (int k = 0; k < 4; ++k) gq[k] += dq[k];
-                geta += deta;
-            }
+            float d[9];
+            for (int k = 0; k < 9; ++k) d[k] = static_cast<float>(dd[k]);
+            const float t = a.times ? a.times[f] : a.t0;
+            const Record rec = a.rec[i];
+            AdjIn P;
+            adjoint_inputs(a, g, rec, camR, camT, t, P);
+            projection_adjoint<PB_THREADS>(a, camR, P, t, d, acc, pacc, tid);
         }
         if (a.g_poses) {
             for (int k = 0; k < 12; ++k) {
-                const double v = wave_sum_f64(pr[k]);
+                const double v = wave_sum_f64(pacc[k][tid]);
                 if (lane == 0) red[w][k] = v;
             }
             __syncthreads();
-            if (threadIdx.x < 12) {
+            if (tid < 12) {
                 double v = 0.0;
-                for (int ww = 0; ww < PB_THREADS / 64; ++ww) v += red[ww][threadIdx.x];
-                a.pose_part[(static_cast<int64_t>(blockIdx.x) * a.frames + f) * 12 + threadIdx.x] = v;
+                for (int ww = 0; ww < PB_THREADS / 64; ++ww) v += red[ww][tid];
+                a.pose_part[(static_cast<int64_t>(blockIdx.x) * a.frames + f) * 12 + tid] = v;
             }
-            __syncthreads();
         }
     }
     if (!live) return;
@@ -157,15 +251,15 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
         else dst[idx] = static_cast<float>(v);
     };
     for (int k = 0; k < 3; ++k) {
-        put(a.g_means, k * n + g, gmu[k]);
-        put(a.g_log_scales, k * n + g, gls[k]);
-        put(a.g_colors, k * n + g, gcol[k]);
+        put(a.g_means, k * n + g, acc[k][tid]);
+        put(a.g_log_scales, k * n + g, acc[3 + k][tid]);
+        put(a.g_colors, k * n + g, acc[11 + k][tid]);
     }
-    for (int k = 0; k < 4; ++k) put(a.g_quats, k * n + g, gq[k]);
-    put(a.g_opacity, g, geta);
+    for (int k = 0; k < 4; ++k) put(a.g_quats, k * n + g, acc[6 + k][tid]);
+    put(a.g_opacity, g, acc[10][tid]);
     if (a.mean_coeffs)
         for (int c = 0; c < 3; ++c)
-            for (int k = 0; k < 3; ++k) put(a.g_coeffs, (c * 3 + k) * n + g, gco[c * 3 + k]);
+            for (int k = 0; k < 3; ++k) put(a.g_coeffs, (c * 3 + k) * n + g, acc[14 + c * 3 + k][tid]);
 }
 
 // Per frame: sum the workgroups' pose partials (each of the 256 threads takes

@@ -1,7 +1,8 @@
 // Per-tile depth sort.  The binning pass already grouped the intersections by
 // (frame, tile) (a counting sort on the tile digit); each tile's bucket is
 // then sorted by the 64-bit key (fp32 depth bits, Gaussian index) in LDS by
-// one workgroup.  Keys are unique within a bucket, so the order is fully
+// one workgroup: rank counting for short buckets, a bitonic network up to the
+// LDS capacity.  Keys are unique within a bucket, so the order is fully
 // determined (depth, ties by lower index) whatever order the atomics of the
 // scatter produced.  Buckets longer than the LDS capacity are sorted in LDS
 // chunks and merged in global memory (each element finds its place in the
@@ -10,12 +11,17 @@
 
 namespace gv {
 
+// Buckets up to this length are sorted by rank counting (O(n^2 / threads)
+// comparisons, no barriers); longer ones by the bitonic network.
+constexpr int RANK_SORT_MAX = 512;
+
 template <int CAP>
 __device__ __forceinline__ void bitonic_lds(uint64_t* K, uint32_t* V, int m) {
     for (int k = 2; k <= m; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
+            const int lj = __builtin_ctz(j);  // j is a power of two
             for (int p = threadIdx.x; p < (m >> 1); p += WG) {
-                const int i = 2 * j * (p / j) + (p % j);
+                const int i = ((p >> lj) << (lj + 1)) | (p & (j - 1));
                 const int l = i + j;
                 const bool asc = (i & k) == 0;
                 const uint64_t ki = K[i], kl = K[l];
@@ -59,6 +65,30 @@ __global__ __launch_bounds__(WG) void k_tile_sort(Args a) {
     if (n <= 0) return;
     __shared__ uint64_t K[CAP];
     __shared__ uint32_t V[CAP];
+    if (n <= RANK_SORT_MAX) {
+        // short bucket: every element's final position is the number of
+        // smaller keys (keys are unique); no barriers after the load
+        for (int i = threadIdx.x; i < n; i += WG) {
+            K[i] = a.keys[s + i];
+            V[i] = a.kslot[s + i];
+        }
+        __syncthreads();
+        const int nn = static_cast<int>(n);
+        for (int i = threadIdx.x; i < nn; i += WG) {
+            const uint64_t key = K[i];
+            int r0 = 0, r1 = 0;
+            int k = 0;
+            for (; k + 1 < nn; k += 2) {
+                r0 += K[k] < key ? 1 : 0;
+                r1 += K[k + 1] < key ? 1 : 0;
+            }
+            if (k < nn) r0 += K[k] < key ? 1 : 0;
+            const int rank = r0 + r1;
+            a.sgid[s + rank] = static_cast<uint32_t>(key);
+            a.sslot[s + rank] = V[i];
+        }
+        return;
+    }
     if (n <= CAP) {
         const int m = next_pow2(static_cast<int>(n));
         for (int i = threadIdx.x; i < m; i += WG) {

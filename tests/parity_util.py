@@ -31,10 +31,12 @@ GRAD_TOL = 1e-3
 MARGIN_TOL = np.array([2e-5, 1e-4, 2e-3, 1e-4])
 
 
-def knife_edge(margins: np.ndarray, grads: bool = False) -> np.ndarray:
+def knife_edge(margins: np.ndarray, grads: bool = False, widen: float = 1.0) -> np.ndarray:
+    """widen > 1 also sets aside pixels whose decisions could move when the
+    two sides' inputs differ slightly (e.g. poses integrated in FP32 vs FP64)."""
     m = margins.reshape(-1, 4)
     k = 4 if grads else 3
-    return (m[:, :k] < MARGIN_TOL[None, :k]).any(axis=1)
+    return (m[:, :k] < widen * MARGIN_TOL[None, :k]).any(axis=1)
 
 
 def rel_err(got, ref) -> float:

@@ -89,6 +89,15 @@ def test_entry_points_reject_bad_arguments_before_touching_the_device():
                                  None, flags, ctypes.c_void_p(256), None, ctypes.byref(g), None,
                                  ctypes.c_void_p(256), 1 << 30, None)
         assert st == L.GV_ERR_INVALID_ARG, (flags, frames)
+    # fit graph: exactly one of targets / dL_dimages, and the ODE buffers are required
+    h = ctypes.c_void_p()
+    for tg, dl in [(None, None), (ctypes.c_void_p(256), ctypes.c_void_p(256))]:
+        st = lib.gv_fit_graph_create(ctypes.byref(sc), ctypes.byref(c.c()), ctypes.c_void_p(256),
+                                     ctypes.c_void_p(256), 4, ctypes.c_void_p(256), 1 << 20, None, 3, tg, dl,
+                                     ctypes.c_void_p(256), ctypes.c_void_p(256), None, ctypes.byref(g),
+                                     ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256),
+                                     ctypes.c_void_p(256), 1 << 30, ctypes.byref(h))
+        assert st == L.GV_ERR_INVALID_ARG
     # camera ODE
     sz = ctypes.c_size_t()
     assert lib.gv_camera_ode_workspace_bytes(100, 4, ctypes.byref(sz)) == L.GV_OK and sz.value > 396 * 4 * 136 * 4

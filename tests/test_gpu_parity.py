@@ -34,13 +34,13 @@ def small_workload(seed, W, H, n, F, trajectory=False, dtype="f32", cubic=False,
     return dict(scene=scene, camera=cam, poses=poses, times=gv_synth.make_times(F), frames=F, n=n)
 
 
-def upstream_for(w, refs, seed):
+def upstream_for(w, refs, seed, widen=1.0):
     """Random upstream gradient per frame [F][3][H][W], zero at knife-edge pixels."""
     rng = np.random.default_rng(seed)
     H, W = w["camera"].height, w["camera"].width
     dl = rng.normal(0, 1, (w["frames"], 3, H, W)).astype(np.float32)
     for f, r in enumerate(refs):
-        ke = knife_edge(r["margins"], grads=True).reshape(H, W)
+        ke = knife_edge(r["margins"], grads=True, widen=widen).reshape(H, W)
         dl[f][:, ke] = 0.0
     return dl
 
@@ -293,7 +293,7 @@ def test_bf16_cubic_means_reduced():
 @pytest.mark.parametrize("frames,substeps", [(1, 4), (12, 4), (100, 4)])
 def test_camera_ode_matches_oracle(frames, substeps):
     rng = np.random.default_rng(frames)
-    theta = ode_ref.init_theta(rng, last_layer_scale=0.5).astype(np.float32)
+    theta = gv_synth.init_mlp_theta(rng, last_layer_scale=0.5).astype(np.float32)
     q = rng.normal(0, 1, 4)
     z0 = np.concatenate([q / np.linalg.norm(q), rng.normal(0, 0.2, 3)]).astype(np.float32)
     ref = ode_ref.camera_ode_fwd(theta.astype(np.float64), z0.astype(np.float64), frames, substeps)
@@ -312,6 +312,47 @@ def test_camera_ode_matches_oracle(frames, substeps):
     else:
         assert float(dth.abs().max()) == 0.0
     assert rel_err(dz.cpu().numpy(), dz_ref) <= GRAD_TOL
+
+
+def test_fit_graph_chains_ode_and_raster():
+    """The learned-camera fitting step (ODE forward -> batched raster fwd+bwd ->
+    ODE adjoint) as one graph equals the separate calls, and its parameter
+    gradient matches the oracle chain (FP64 ODE -> FP64 renderer adjoint ->
+    FP64 discrete adjoint) on a reduced clip."""
+    F, S = 6, 4
+    rng = np.random.default_rng(30)
+    w = small_workload(31, 96, 64, 1500, F)
+    theta = gv_synth.init_mlp_theta(rng, last_layer_scale=0.3).astype(np.float32)
+    z0 = np.array([1.0, 0.02, -0.03, 0.01, 0.05, -0.02, 0.1], np.float32)
+    poses_ref = ode_ref.camera_ode_fwd(theta.astype(np.float64), z0.astype(np.float64), F, S)
+    w["poses"] = poses_ref.astype(np.float32)
+    refs = [oracle_frame(w, f) for f in range(F)]
+    # the GPU integrates the poses in FP32: set aside pixels within 50x the usual margins
+    dl = upstream_for(w, refs, 31, widen=50.0)
+    scene, cam, _, times = device_inputs(w)
+    th, z = torch.from_numpy(theta).cuda(), torch.from_numpy(z0).cuda()
+    ws = workspace_for(scene, cam, torch.from_numpy(w["poses"]).cuda(), times)
+    fit = gvcam.FitGraph(scene, cam, th, z, F, S, times, ws, dL_dimages=torch.from_numpy(dl).cuda())
+    fit.launch()
+    fit.launch()
+    torch.cuda.synchronize()
+    # same as the separate calls
+    ows = gvcam.OdeWorkspace(F, S)
+    poses = gvcam.camera_ode_fwd(th, z, F, S, ows)
+    out = raster.render_batch(scene, cam, poses, times, ws, dL_dimages=torch.from_numpy(dl).cuda())
+    dth, dz = gvcam.camera_ode_bwd(th, z, F, S, out["dL_dposes"], ows)
+    torch.cuda.synchronize()
+    assert torch.equal(fit.poses, poses) and torch.equal(fit.images, out["images"])
+    assert torch.equal(fit.dtheta, dth) and torch.equal(fit.dz0, dz)
+    # against the FP64 chain
+    g_ref, dposes_ref, _ = oracle.render_clip_grads(w["scene"], w["camera"], poses_ref, w["times"], range(F),
+                                                    [None] * F, [planar_to_pixels(dl[f]) for f in range(F)])
+    dth_ref, dz_ref = ode_ref.camera_ode_bwd(theta.astype(np.float64), z0.astype(np.float64), F, S, dposes_ref)
+    compare_grads(fit.grads, g_ref, "fit graph")
+    e1, e2 = rel_err(fit.dtheta.cpu().numpy(), dth_ref), rel_err(fit.dz0.cpu().numpy(), dz_ref)
+    assert e1 <= GRAD_TOL and e2 <= GRAD_TOL, (e1, e2)
+    fit.close()
+    say(f"[fit graph] dtheta err {e1:.2e} dz0 err {e2:.2e}")
 
 
 def test_frame540p_n100k_full_size_sampled():

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 import torch
 
+import gv_synth
 from oracle import camera_ode as co
 
 
@@ -30,7 +31,7 @@ def test_rk4_step_on_linear_field_is_taylor_polynomial():
 
 def test_constant_field_gives_linear_trajectory():
     rng = np.random.default_rng(1)
-    W1, b1, W2, b2, W3, b3 = co.unpack(co.init_theta(rng))
+    W1, b1, W2, b2, W3, b3 = co.unpack(gv_synth.init_mlp_theta(rng))
     W1 = np.zeros_like(W1)
     W2 = np.zeros_like(W2)  # f = W3 tanh(b2) + b3, independent of z and t
     theta = co.pack(W1, b1, W2, b2, W3, b3)
@@ -46,7 +47,7 @@ def test_constant_field_gives_linear_trajectory():
 
 def test_fourth_order_convergence():
     rng = np.random.default_rng(2)
-    theta = co.init_theta(rng, last_layer_scale=3.0)
+    theta = gv_synth.init_mlp_theta(rng, last_layer_scale=3.0)
     z0 = rng.normal(0, 1, 7)
     ref = co.integrate(co.MLPField(theta), z0, 2, 512)[-1]
     errs = [np.linalg.norm(co.integrate(co.MLPField(theta), z0, 2, s)[-1] - ref) for s in (4, 8, 16)]
@@ -56,7 +57,7 @@ def test_fourth_order_convergence():
 
 def test_adjoint_matches_central_differences():
     rng = np.random.default_rng(3)
-    theta = co.init_theta(rng, last_layer_scale=1.0)
+    theta = gv_synth.init_mlp_theta(rng, last_layer_scale=1.0)
     z0 = np.array([0.95, 0.1, -0.2, 0.05, 0.3, -0.1, 0.2])
     F, S = 5, 2
     dp = rng.normal(0, 1, (F, 7))
@@ -79,7 +80,7 @@ def test_adjoint_matches_central_differences():
 
 def test_adjoint_matches_torch_autograd():
     rng = np.random.default_rng(4)
-    theta = co.init_theta(rng, last_layer_scale=0.5)
+    theta = gv_synth.init_mlp_theta(rng, last_layer_scale=0.5)
     z0 = np.array([0.9, -0.1, 0.3, 0.1, -0.2, 0.1, 0.4])
     F, S = 7, 4
     dp = rng.normal(0, 1, (F, 7))
