@@ -109,9 +109,10 @@ typedef struct {
  * batch: entries staged in LDS per round of a tile's compositing loop
  * (64, 128 or 256); sort_cap: longest per-tile list sorted in one LDS pass
  * (1024, 2048 or 4096; longer lists are sorted in chunks and merged);
- * compact: 1 = compositing kernels that first build per-pixel entry lists from
- * closed-form coverage masks, 0 = every staged entry visits every pixel of its
- * 8x8 quadrant.  Results are identical; only the speed differs. */
+ * compact: bit 0 (forward) / bit 1 (backward) select compositing kernels that
+ * first build per-pixel entry lists from closed-form coverage masks instead of
+ * letting every staged entry visit every pixel of its 8x8 quadrant.  Results
+ * are identical; only the speed differs. */
 typedef struct {
     int32_t batch;
     int32_t sort_cap;

@@ -29,7 +29,7 @@ hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t count, unsi
 
 static thread_local int32_t g_last_hip = 0;
 static std::mutex g_tune_mu;
-static Tuning g_tune = {256, 4096, 128, 1};
+static Tuning g_tune = {256, 2048, 128, 1};
 
 Tuning current_tuning() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -530,7 +530,7 @@ gv_status gv_set_tuning(const gv_tuning* t) {
     if (!t) return GV_ERR_INVALID_ARG;
     if (t->batch != 64 && t->batch != 128 && t->batch != 256) return GV_ERR_INVALID_ARG;
     if (t->sort_cap != 1024 && t->sort_cap != 2048 && t->sort_cap != 4096) return GV_ERR_INVALID_ARG;
-    if (t->compact != 0 && t->compact != 1) return GV_ERR_INVALID_ARG;
+    if (t->compact < 0 || t->compact > 3) return GV_ERR_INVALID_ARG;
     Tuning n = current_tuning();
     n.batch = t->batch;
     n.sort_cap = t->sort_cap;
@@ -555,14 +555,13 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
     gv_status result = GV_OK;
     const int batches[] = {64, 128, 256};
     const int caps[] = {2048, 4096};
-    const int compacts[] = {0, 1};
     for (int b : batches) {
-        for (int cc = 0; cc < 4; ++cc) {
+        for (int cc = 0; cc < 8; ++cc) {
             const int c = caps[cc & 1];
             Tuning t = saved;
             t.batch = b;
             t.sort_cap = c;
-            t.compact = compacts[cc >> 1];
+            t.compact = cc >> 1;  // bit 0: compacted forward, bit 1: compacted backward
             install_tuning(t);
             gv_status s = enqueue_batch(scene, cam, poses, times, frames, targets, nullptr, flags, images, loss, grads,
                                         dL_dposes, ws, ws_bytes, st);

@@ -165,6 +165,62 @@ __global__ __launch_bounds__(WG) void k_loss_finalize(Args a) {
     if (threadIdx.x == 0) a.loss[f] = overflowed(a.status) ? 0.0f : red[0] * a.loss_norm;
 }
 
+// Sum over the 64 lanes of 64 values at once: after six halving stages
+// (cross-half swaps for distances 32 and 16, DPP for 8, 4, 2, 1) lane l holds
+// the wave total of value l.  Exact in the order of its additions, which is
+// fixed.
+__device__ __forceinline__ float dpp_f(float x, int ctrl) {
+    switch (ctrl) {  // constant after inlining
+        case 0x128: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x128, 0xf, 0xf, true));
+        case 0x114: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x114, 0xf, 0xf, true));
+        case 0x104: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x104, 0xf, 0xf, true));
+        case 0x4E: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x4E, 0xf, 0xf, true));
+        default: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0xB1, 0xf, 0xf, true));
+    }
+}
+
+__device__ __forceinline__ float reduce_scatter64(float (&v)[64], int lane) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 32]), false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 16]), false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    const bool b8 = lane & 8, b4 = lane & 4, b2 = lane & 2, b1 = lane & 1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const float keep = b8 ? v[i + 8] : v[i], send = b8 ? v[i] : v[i + 8];
+        v[i] = keep + dpp_f(send, 0x128);  // row_ror:8 (partner lane ^ 8)
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float keep = b4 ? v[i + 4] : v[i], send = b4 ? v[i] : v[i + 4];
+        const float from_lo = dpp_f(send, 0x114), from_hi = dpp_f(send, 0x104);  // row_shr:4 / row_shl:4
+        v[i] = keep + (b4 ? from_lo : from_hi);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float keep = b2 ? v[i + 2] : v[i], send = b2 ? v[i] : v[i + 2];
+        v[i] = keep + dpp_f(send, 0x4E);  // quad_perm [2,3,0,1] (partner lane ^ 2)
+    }
+    {
+        const float keep = b1 ? v[1] : v[0], send = b1 ? v[0] : v[1];
+        v[0] = keep + dpp_f(send, 0xB1);  // quad_perm [1,0,3,2] (partner lane ^ 1)
+    }
+    return v[0];
+}
+
+// Adjoint of the quadrant loop.  Each wave first lists, back to front, the
+// staged entries whose ellipse meets its quadrant; it then takes them in
+// groups of RS_GROUP, keeps every lane's 9 partials of each entry in
+// registers, and sums all 9 x RS_GROUP values over the wave with one
+// reduce-scatter (lane l ends with partial l % 9 of the group's entry l / 9).
+constexpr int RS_GROUP = 7;
+
 template <int B>
 __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
     if (overflowed(a.status)) return;
@@ -186,6 +242,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
     __shared__ float shb[B];
     __shared__ uint32_t shm[B];
     __shared__ float acc[WG / 64][9][B];
+    __shared__ int16_t wl[WG / 64][B];
     __shared__ uint32_t smax;
 
     // per-pixel state: T after the current entry, colour composited behind it
@@ -237,72 +294,77 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
             shb[tid] = blue;
             shm[tid] = m;
         }
-        for (int k = tid; k < (WG / 64) * 9 * B; k += WG) (&acc[0][0][0])[k] = 0.0f;
         __syncthreads();
-        for (int j = static_cast<int>(nb) - 1; j >= 0; --j) {
-            const uint32_t m = __builtin_amdgcn_readfirstlane(shm[j]);
-            if (!((m >> w) & 1u)) continue;
-            const uint32_t rel = b0 + j - s;
-            float du = 0.f, dv = 0.f, da = 0.f, db = 0.f, dc = 0.f, dop = 0.f, dr = 0.f, dg = 0.f, dbl = 0.f;
-            bool hit = false;
-            if (rel < last) {
-                const float4 p0 = sh[j].p0;
-                const float4 p1 = sh[j].p1;
-                const float dx = fx - p0.x, dy = fy - p0.y;
-                const float q = footprint_q(dx, dy, p0, p1);
-                if (q <= Q_MAX) {
-                    const float G = gauss_falloff(q);
-                    const float raw = p1.y * G;
-                    const float al = fminf(ALPHA_MAX, raw);
-                    if (al >= ALPHA_MIN) {
-                        hit = true;
-                        const float inv = 1.0f / (1.0f - al);
-                        const float Tj = T * inv;  // transmittance in front of this entry
-                        const float wgt = al * Tj;
-                        const float cb = shb[j];
-                        dr = wgt * g0;
-                        dg = wgt * g1;
-                        dbl = wgt * g2;
-                        const float dal = g0 * (p1.z * Tj - S0 * inv) + g1 * (p1.w * Tj - S1 * inv) +
-                                          g2 * (cb * Tj - S2 * inv);
-                        S0 = __builtin_fmaf(p1.z, wgt, S0);
-                        S1 = __builtin_fmaf(p1.w, wgt, S1);
-                        S2 = __builtin_fmaf(cb, wgt, S2);
-                        T = Tj;
-                        if (raw < ALPHA_MAX) {
-                            dop = dal * G;
-                            const float dq = -0.5f * al * dal;
-                            da = dq * dx * dx;
-                            db = 2.0f * dq * dx * dy;
-                            dc = dq * dy * dy;
-                            const float hb = 0.5f * p0.w;
-                            du = -2.0f * dq * (p0.z * dx + hb * dy);
-                            dv = -2.0f * dq * (hb * dx + p1.x * dy);
+        // this wave's entries, back to front (ballot compaction; the list is
+        // written and read by this wave only)
+        int cnt = 0;
+        for (int j0 = static_cast<int>(nb) - 1; j0 >= 0; j0 -= 64) {
+            const int j = j0 - lane;
+            const bool on = j >= 0 && ((shm[j >> 0] >> w) & 1u);
+            const uint64_t bal = __ballot(on);
+            if (on) wl[w][cnt + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<int16_t>(j);
+            cnt += __popcll(bal);
+        }
+        for (int g = 0; g < cnt; g += RS_GROUP) {
+            float P[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k) P[k] = 0.0f;
+#pragma unroll
+            for (int r = 0; r < RS_GROUP; ++r) {
+                if (g + r >= cnt) break;
+                const int j = wl[w][g + r];
+                const uint32_t rel = b0 + j - s;
+                if (rel < last) {
+                    const float4 p0 = sh[j].p0;
+                    const float4 p1 = sh[j].p1;
+                    const float dx = fx - p0.x, dy = fy - p0.y;
+                    const float q = footprint_q(dx, dy, p0, p1);
+                    if (q <= Q_MAX) {
+                        const float G = gauss_falloff(q);
+                        const float raw = p1.y * G;
+                        const float al = fminf(ALPHA_MAX, raw);
+                        if (al >= ALPHA_MIN) {
+                            const float inv = 1.0f / (1.0f - al);
+                            const float Tj = T * inv;  // transmittance in front of this entry
+                            const float wgt = al * Tj;
+                            const float cb = shb[j];
+                            P[r * 9 + 6] = wgt * g0;
+                            P[r * 9 + 7] = wgt * g1;
+                            P[r * 9 + 8] = wgt * g2;
+                            const float dal = g0 * (p1.z * Tj - S0 * inv) + g1 * (p1.w * Tj - S1 * inv) +
+                                              g2 * (cb * Tj - S2 * inv);
+                            S0 = __builtin_fmaf(p1.z, wgt, S0);
+                            S1 = __builtin_fmaf(p1.w, wgt, S1);
+                            S2 = __builtin_fmaf(cb, wgt, S2);
+                            T = Tj;
+                            if (raw < ALPHA_MAX) {
+                                const float dq = -0.5f * al * dal;
+                                const float hb = 0.5f * p0.w;
+                                P[r * 9 + 0] = -2.0f * dq * (p0.z * dx + hb * dy);
+                                P[r * 9 + 1] = -2.0f * dq * (hb * dx + p1.x * dy);
+                                P[r * 9 + 2] = dq * dx * dx;
+                                P[r * 9 + 3] = 2.0f * dq * dx * dy;
+                                P[r * 9 + 4] = dq * dy * dy;
+                                P[r * 9 + 5] = dal * G;
+                            }
                         }
                     }
                 }
             }
-            if (__ballot(hit) != 0ull) {
-                du = wave_sum_to_lane63(du);
-                dv = wave_sum_to_lane63(dv);
-                da = wave_sum_to_lane63(da);
-                db = wave_sum_to_lane63(db);
-                dc = wave_sum_to_lane63(dc);
-                dop = wave_sum_to_lane63(dop);
-                dr = wave_sum_to_lane63(dr);
-                dg = wave_sum_to_lane63(dg);
-                dbl = wave_sum_to_lane63(dbl);
-                if (lane == 63) {
-                    acc[w][0][j] = du; acc[w][1][j] = dv; acc[w][2][j] = da;
-                    acc[w][3][j] = db; acc[w][4][j] = dc; acc[w][5][j] = dop;
-                    acc[w][6][j] = dr; acc[w][7][j] = dg; acc[w][8][j] = dbl;
-                }
-            }
+            const float tot = reduce_scatter64(P, lane);
+            const int r = lane / 9;
+            if (lane < 9 * RS_GROUP && g + r < cnt) acc[w][lane - 9 * r][wl[w][g + r]] = tot;
         }
         __syncthreads();
         if (tid < static_cast<int>(nb)) {
+            const uint32_t m = shm[tid];
             float v[9];
-            for (int k = 0; k < 9; ++k) v[k] = (acc[0][k][tid] + acc[1][k][tid]) + (acc[2][k][tid] + acc[3][k][tid]);
+            for (int k = 0; k < 9; ++k) {
+                float x = 0.0f;
+                for (int ww = 0; ww < WG / 64; ++ww)
+                    if ((m >> ww) & 1u) x += acc[ww][k][tid];
+                v[k] = x;
+            }
             const uint32_t slot = a.sslot[b0 + tid];
             if (slot < a.k_cap) {
                 a.partA[slot] = make_float4(v[0], v[1], v[2], v[3]);
@@ -379,11 +441,14 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x, int lane) {
     return x;
 }
 
-// Stage the batch [b0, b0 + nb) and its quadrant masks (threads t < B).
+// Stage the batch [b0, b0 + nb) and its quadrant masks (threads t < B).  The
+// compacted kernels read staged entries at lane-dependent indices, so they are
+// staged structure-of-arrays (4-byte stride: lanes reading different entries
+// fall into different banks): sv[0..8][j] = local u, local v, conic a, 2b, c,
+// opacity, r, g, b.
 template <int B>
 __device__ __forceinline__ void stage_batch_masks(const Args& a, int f, uint32_t b0, uint32_t nb, double ox, double oy,
-                                                  int xlim, int ylim, Staged* sh, float* shb,
-                                                  uint64_t (*qmask)[B]) {
+                                                  int xlim, int ylim, float (*sv)[B], uint64_t (*qmask)[B]) {
     const int t = threadIdx.x;
     if (t < B) {
         uint64_t qm[4] = {0ull, 0ull, 0ull, 0ull};
@@ -392,12 +457,23 @@ __device__ __forceinline__ void stage_batch_masks(const Args& a, int f, uint32_t
             float blue;
             uint32_t m;
             stage_entry(a, f, a.sgid[b0 + t], ox, oy, xlim, ylim, st, blue, m);
-            sh[t] = st;
-            shb[t] = blue;
+            sv[0][t] = st.p0.x; sv[1][t] = st.p0.y; sv[2][t] = st.p0.z; sv[3][t] = st.p0.w;
+            sv[4][t] = st.p1.x; sv[5][t] = st.p1.y; sv[6][t] = st.p1.z; sv[7][t] = st.p1.w;
+            sv[8][t] = blue;
             if (m) coverage_masks(st.p0.x, st.p0.y, st.p0.z, 0.5f * st.p0.w, st.p1.x, xlim, ylim, qm);
         }
         for (int q = 0; q < 4; ++q) qmask[q][t] = qm[q];
     }
+}
+
+// Lane l's set of staged entries covering its pixel, as NW 64-bit words
+// (rounds beyond the staged count are empty and not transposed).
+template <int B>
+__device__ __forceinline__ void lane_entry_sets(uint64_t (*qmask)[B], int w, int lane, uint32_t nb,
+                                                uint64_t wq[B / 64]) {
+#pragma unroll
+    for (int r = 0; r < B / 64; ++r)
+        wq[r] = (static_cast<uint32_t>(r * 64) < nb) ? transpose64(qmask[w][r * 64 + lane], lane) : 0ull;
 }
 
 template <int B>
@@ -418,8 +494,7 @@ __global__ __launch_bounds__(WG) void k_composite_fwd_c(Args a) {
     const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
     const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
 
-    __shared__ Staged sh[B];
-    __shared__ float shb[B];
+    __shared__ float sv[9][B];
     __shared__ uint64_t qmask[4][B];
     __shared__ float red[WG / 64];
 
@@ -431,11 +506,10 @@ __global__ __launch_bounds__(WG) void k_composite_fwd_c(Args a) {
     for (uint32_t b0 = s; b0 < e; b0 += B) {
         if (__syncthreads_count(!done) == 0) break;
         const uint32_t nb = min(static_cast<uint32_t>(B), e - b0);
-        stage_batch_masks<B>(a, f, b0, nb, ox, oy, xlim, ylim, sh, shb, qmask);
+        stage_batch_masks<B>(a, f, b0, nb, ox, oy, xlim, ylim, sv, qmask);
         __syncthreads();
         uint64_t wq[NW];
-#pragma unroll
-        for (int r = 0; r < NW; ++r) wq[r] = transpose64(qmask[w][r * 64 + lane], lane);
+        lane_entry_sets<B>(qmask, w, lane, nb, wq);
         if (!done) {
             uint64_t cur = wq[0];
             int base = 0;
@@ -450,8 +524,8 @@ __global__ __launch_bounds__(WG) void k_composite_fwd_c(Args a) {
                 if (cur == 0ull) break;
                 const int j = base + __builtin_ctzll(cur);
                 cur &= cur - 1ull;
-                const float4 p0 = sh[j].p0;
-                const float4 p1 = sh[j].p1;
+                const float4 p0 = make_float4(sv[0][j], sv[1][j], sv[2][j], sv[3][j]);
+                const float4 p1 = make_float4(sv[4][j], sv[5][j], 0.0f, 0.0f);
                 const float dx = fx - p0.x, dy = fy - p0.y;
                 const float q = footprint_q(dx, dy, p0, p1);
                 if (q > Q_MAX) continue;
@@ -463,9 +537,9 @@ __global__ __launch_bounds__(WG) void k_composite_fwd_c(Args a) {
                     break;
                 }
                 const float wgt = al * T;
-                c0 = __builtin_fmaf(p1.z, wgt, c0);
-                c1 = __builtin_fmaf(p1.w, wgt, c1);
-                c2 = __builtin_fmaf(shb[j], wgt, c2);
+                c0 = __builtin_fmaf(sv[6][j], wgt, c0);
+                c1 = __builtin_fmaf(sv[7][j], wgt, c1);
+                c2 = __builtin_fmaf(sv[8][j], wgt, c2);
                 T = tn;
                 last = b0 + j - s + 1;
             }
@@ -518,8 +592,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
     const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
     const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
 
-    __shared__ Staged sh[B];
-    __shared__ float shb[B];
+    __shared__ float sv[9][B];
     __shared__ uint64_t qmask[4][B];
     __shared__ float acc[WG / 64][9][B];
     __shared__ uint32_t smax;
@@ -562,18 +635,17 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
     for (int64_t bend = static_cast<int64_t>(s) + used; bend > s; bend -= B) {
         const uint32_t b0 = static_cast<uint32_t>(bend - B > s ? bend - B : s);
         const uint32_t nb = static_cast<uint32_t>(bend - b0);
-        stage_batch_masks<B>(a, f, b0, nb, ox, oy, xlim, ylim, sh, shb, qmask);
+        stage_batch_masks<B>(a, f, b0, nb, ox, oy, xlim, ylim, sv, qmask);
         for (int k = tid; k < (WG / 64) * 9 * B; k += WG) (&acc[0][0][0])[k] = 0.0f;
         __syncthreads();
         // entries at or behind this pixel's last contributor are not part of its sum
         const int64_t lim = static_cast<int64_t>(last) - (static_cast<int64_t>(b0) - s);
         uint64_t wq[NW];
+        lane_entry_sets<B>(qmask, w, lane, nb, wq);
 #pragma unroll
         for (int r = 0; r < NW; ++r) {
-            uint64_t x = transpose64(qmask[w][r * 64 + lane], lane);
             const int64_t keep = lim - 64 * r;
-            x = keep <= 0 ? 0ull : (keep >= 64 ? x : (x & ((1ull << keep) - 1ull)));
-            wq[r] = x;
+            wq[r] = keep <= 0 ? 0ull : (keep >= 64 ? wq[r] : (wq[r] & ((1ull << keep) - 1ull)));
         }
         {
             uint64_t cur = wq[NW - 1];
@@ -590,8 +662,8 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
                 const int bit = 63 - __builtin_clzll(cur);
                 cur ^= 1ull << bit;
                 const int j = base + bit;
-                const float4 p0 = sh[j].p0;
-                const float4 p1 = sh[j].p1;
+                const float4 p0 = make_float4(sv[0][j], sv[1][j], sv[2][j], sv[3][j]);
+                const float4 p1 = make_float4(sv[4][j], sv[5][j], sv[6][j], sv[7][j]);
                 const float dx = fx - p0.x, dy = fy - p0.y;
                 const float q = footprint_q(dx, dy, p0, p1);
                 if (q > Q_MAX) continue;
@@ -602,7 +674,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
                 const float inv = 1.0f / (1.0f - al);
                 const float Tj = T * inv;
                 const float wgt = al * Tj;
-                const float cb = shb[j];
+                const float cb = sv[8][j];
                 const float dal = g0 * (p1.z * Tj - S0 * inv) + g1 * (p1.w * Tj - S1 * inv) + g2 * (cb * Tj - S2 * inv);
                 S0 = __builtin_fmaf(p1.z, wgt, S0);
                 S1 = __builtin_fmaf(p1.w, wgt, S1);
@@ -641,7 +713,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
 
 hipError_t launch_composite_fwd(const Args& a, hipStream_t stream) {
     const dim3 grid(static_cast<uint32_t>(a.tiles), static_cast<uint32_t>(a.frames)), block(WG);
-    if (a.tune.compact) {
+    if (a.tune.compact & 1) {
         switch (a.tune.batch) {
             case 64: hipLaunchKernelGGL(k_composite_fwd_c<64>, grid, block, 0, stream, a); break;
             case 128: hipLaunchKernelGGL(k_composite_fwd_c<128>, grid, block, 0, stream, a); break;
@@ -664,7 +736,7 @@ hipError_t launch_loss_finalize(const Args& a, hipStream_t stream) {
 
 hipError_t launch_composite_bwd(const Args& a, hipStream_t stream) {
     const dim3 grid(static_cast<uint32_t>(a.tiles), static_cast<uint32_t>(a.frames)), block(WG);
-    if (a.tune.compact) {
+    if (a.tune.compact & 2) {
         switch (a.tune.batch) {
             case 64: hipLaunchKernelGGL(k_composite_bwd_c<64>, grid, block, 0, stream, a); break;
             case 128: hipLaunchKernelGGL(k_composite_bwd_c<128>, grid, block, 0, stream, a); break;

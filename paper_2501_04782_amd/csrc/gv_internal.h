@@ -54,7 +54,8 @@ struct Tuning {
     int batch;      // 64 / 128 / 256 entries per LDS round of the composite kernels
     int sort_cap;   // 1024 / 2048 / 4096
     int bwd_block;  // threads per workgroup of the projection adjoint
-    int compact;    // 1: compacted compositing kernels (coverage masks + per-lane entry lists), 0: quadrant loop
+    int compact;    // bit 0 / bit 1: compacted forward / backward compositing (coverage masks + per-lane entry
+                    // walks) instead of the quadrant loop
 };
 
 // Byte offsets of the workspace regions (host-computed).

@@ -110,7 +110,7 @@ def test_tuning_table_validation():
     t = L.GvTuning()
     assert lib.gv_get_tuning(ctypes.byref(t)) == L.GV_OK
     old = (t.batch, t.sort_cap)
-    assert t.batch in (64, 128, 256) and t.sort_cap in (1024, 2048, 4096) and t.compact in (0, 1)
+    assert t.batch in (64, 128, 256) and t.sort_cap in (1024, 2048, 4096) and t.compact in (0, 1, 2, 3)
     t2 = L.GvTuning()
     t2.batch, t2.sort_cap = 100, 4096
     assert lib.gv_set_tuning(ctypes.byref(t2)) == L.GV_ERR_INVALID_ARG

@@ -168,8 +168,9 @@ def test_empty_and_single_gaussian():
             check_clip_against_oracle(w, "single Gaussian")
 
 
-@pytest.mark.parametrize("compact,batch,sort_cap", [(1, 256, 4096), (1, 128, 2048), (1, 64, 1024),
-                                                    (0, 256, 4096), (0, 128, 2048), (0, 64, 1024)])
+@pytest.mark.parametrize("compact,batch,sort_cap", [(3, 256, 4096), (3, 128, 2048), (3, 64, 1024),
+                                                    (0, 256, 4096), (0, 128, 2048), (0, 64, 1024),
+                                                    (1, 128, 2048), (2, 256, 2048)])
 def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
     """Batched path on a reduced clip (moving camera, several frames) under
     every setting the autotuner can choose."""
