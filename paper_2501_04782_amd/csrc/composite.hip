@@ -306,50 +306,49 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
             cnt += __popcll(bal);
         }
         for (int g = 0; g < cnt; g += RS_GROUP) {
+            // Branch-free: an entry that does not reach the pixel (or a group
+            // slot past the list's end) takes alpha = 0, which leaves T and the
+            // colour behind it exactly unchanged (1 - 0 and its reciprocal are
+            // exact) and gives zero partials.
             float P[64];
-#pragma unroll
-            for (int k = 0; k < 64; ++k) P[k] = 0.0f;
+            P[63] = 0.0f;
 #pragma unroll
             for (int r = 0; r < RS_GROUP; ++r) {
-                if (g + r >= cnt) break;
-                const int j = wl[w][g + r];
+                const bool listed = g + r < cnt;
+                const int j = wl[w][listed ? g + r : cnt - 1];
                 const uint32_t rel = b0 + j - s;
-                if (rel < last) {
-                    const float4 p0 = sh[j].p0;
-                    const float4 p1 = sh[j].p1;
-                    const float dx = fx - p0.x, dy = fy - p0.y;
-                    const float q = footprint_q(dx, dy, p0, p1);
-                    if (q <= Q_MAX) {
-                        const float G = gauss_falloff(q);
-                        const float raw = p1.y * G;
-                        const float al = fminf(ALPHA_MAX, raw);
-                        if (al >= ALPHA_MIN) {
-                            const float inv = 1.0f / (1.0f - al);
-                            const float Tj = T * inv;  // transmittance in front of this entry
-                            const float wgt = al * Tj;
-                            const float cb = shb[j];
-                            P[r * 9 + 6] = wgt * g0;
-                            P[r * 9 + 7] = wgt * g1;
-                            P[r * 9 + 8] = wgt * g2;
-                            const float dal = g0 * (p1.z * Tj - S0 * inv) + g1 * (p1.w * Tj - S1 * inv) +
-                                              g2 * (cb * Tj - S2 * inv);
-                            S0 = __builtin_fmaf(p1.z, wgt, S0);
-                            S1 = __builtin_fmaf(p1.w, wgt, S1);
-                            S2 = __builtin_fmaf(cb, wgt, S2);
-                            T = Tj;
-                            if (raw < ALPHA_MAX) {
-                                const float dq = -0.5f * al * dal;
-                                const float hb = 0.5f * p0.w;
-                                P[r * 9 + 0] = -2.0f * dq * (p0.z * dx + hb * dy);
-                                P[r * 9 + 1] = -2.0f * dq * (hb * dx + p1.x * dy);
-                                P[r * 9 + 2] = dq * dx * dx;
-                                P[r * 9 + 3] = 2.0f * dq * dx * dy;
-                                P[r * 9 + 4] = dq * dy * dy;
-                                P[r * 9 + 5] = dal * G;
-                            }
-                        }
-                    }
-                }
+                const float4 p0 = sh[j].p0;
+                const float4 p1 = sh[j].p1;
+                const float cb = shb[j];
+                const float dx = fx - p0.x, dy = fy - p0.y;
+                const float q = footprint_q(dx, dy, p0, p1);
+                const float G = gauss_falloff(q);
+                const float raw = p1.y * G;
+                const float al0 = fminf(ALPHA_MAX, raw);
+                const bool on = listed && rel < last && q <= Q_MAX && al0 >= ALPHA_MIN;
+                const float al = on ? al0 : 0.0f;
+                const float inv = __builtin_amdgcn_rcpf(1.0f - al);
+                const float Tj = T * inv;  // transmittance in front of this entry
+                const float wgt = al * Tj;
+                P[r * 9 + 6] = wgt * g0;
+                P[r * 9 + 7] = wgt * g1;
+                P[r * 9 + 8] = wgt * g2;
+                const float dal = g0 * (p1.z * Tj - S0 * inv) + g1 * (p1.w * Tj - S1 * inv) +
+                                  g2 * (cb * Tj - S2 * inv);
+                S0 = __builtin_fmaf(p1.z, wgt, S0);
+                S1 = __builtin_fmaf(p1.w, wgt, S1);
+                S2 = __builtin_fmaf(cb, wgt, S2);
+                T = Tj;
+                // a clamped alpha has no gradient w.r.t. the opacity or footprint
+                const float dalc = on && raw < ALPHA_MAX ? dal : 0.0f;
+                const float dq = -0.5f * al * dalc;
+                const float hb = 0.5f * p0.w;
+                P[r * 9 + 0] = -2.0f * dq * (p0.z * dx + hb * dy);
+                P[r * 9 + 1] = -2.0f * dq * (hb * dx + p1.x * dy);
+                P[r * 9 + 2] = dq * dx * dx;
+                P[r * 9 + 3] = 2.0f * dq * dx * dy;
+                P[r * 9 + 4] = dq * dy * dy;
+                P[r * 9 + 5] = dalc * G;
             }
             const float tot = reduce_scatter64(P, lane);
             const int r = lane / 9;
