@@ -81,8 +81,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--tuning", default=None, help="batch,sort_cap,compact: fixed tuning (skips the autotuner)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle sample")
     ap.add_argument("--stage-reps", type=int, default=5)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (counter calibration) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -103,6 +106,17 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.rand(nbytes // 4, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "reps": 3}))
+        return
 
     log(f"[bench] building inputs: {args.workload}")
     w = gv_synth.make_workload(args.workload, seed=0, targets=True)
@@ -128,7 +142,11 @@ def main():
     log(f"[bench] workspace {ws.nbytes / 1e9:.2f} GB, capacity {cap}")
 
     tuning = raster.get_tuning()
-    if not args.no_autotune:
+    if args.tuning:
+        b, c, m = (int(x) for x in args.tuning.split(","))
+        raster.set_tuning(b, c, m)
+        tuning = raster.get_tuning()
+    elif not args.no_autotune:
         log("[bench] autotuning")
         tuning = raster.autotune(scene, cam, poses, times, ws, targets)
     log(f"[bench] tuning {tuning}")
@@ -254,7 +272,11 @@ def main():
     # roofline of the dominant kernel
     dom = max(stage_ms, key=stage_ms.get)
     t_dom = stage_ms[dom] / 1e3
-    traffic = None
+    from paper_2501_04782_amd import rocprof_summary
+    tun_s = f"{tuning['batch']},{tuning['sort_cap']},{tuning['compact']}"
+    traffic = rocprof_summary.read_traffic(
+        os.path.join(ROOT, "profiles", f"{dom}_{args.workload}_{tun_s.replace(',', '-')}_hbm_traffic.txt"),
+        dom, args.workload, tun_s)
     bytes_dom = stage_bytes(dom, N, V, K, P, F)
     hbm_ach = bytes_dom / t_dom if bytes_dom else 0.0
     roof = dict(bound="hbm", achieved=round(hbm_ach / 1e9, 2), peak=HBM_PEAK / 1e9, unit="GB/s",

@@ -88,9 +88,7 @@ Layout make_layout(const gv_camera& cam, int64_t n, int frames, int64_t k_cap) {
     L.kslot = take(4 * K);
     L.sgid = take(4 * K);
     L.sslot = take(4 * K);
-    L.partA = take(16 * K);
-    L.partB = take(16 * K);
-    L.partC = take(4 * K);
+    L.part = take(4 * PART * K);
     L.tkeys = take(8 * K);
     L.tslot = take(4 * K);
     L.total = off;
@@ -189,9 +187,7 @@ static gv_status make_args(const gv_scene* s, const gv_camera* c, int frames, co
     a.kslot = reinterpret_cast<uint32_t*>(b + L.kslot);
     a.sgid = reinterpret_cast<uint32_t*>(b + L.sgid);
     a.sslot = reinterpret_cast<uint32_t*>(b + L.sslot);
-    a.partA = reinterpret_cast<float4*>(b + L.partA);
-    a.partB = reinterpret_cast<float4*>(b + L.partB);
-    a.partC = reinterpret_cast<float*>(b + L.partC);
+    a.part = reinterpret_cast<float*>(b + L.part);
     a.tkeys = reinterpret_cast<uint64_t*>(b + L.tkeys);
     a.tslot = reinterpret_cast<uint32_t*>(b + L.tslot);
     a.k_cap = L.k_cap;

@@ -166,14 +166,13 @@ __global__ __launch_bounds__(WG) void k_loss_finalize(Args a) {
 }
 
 // Sum over the 64 lanes of 64 values at once: after six halving stages
-// (cross-half swaps for distances 32 and 16, DPP for 8, 4, 2, 1) lane l holds
+// (cross-half swaps for 32 and 16 lanes, DPP within rows for the rest) lane l holds
 // the wave total of value l.  Exact in the order of its additions, which is
 // fixed.
 __device__ __forceinline__ float dpp_f(float x, int ctrl) {
     switch (ctrl) {  // constant after inlining
         case 0x128: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x128, 0xf, 0xf, true));
-        case 0x114: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x114, 0xf, 0xf, true));
-        case 0x104: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x104, 0xf, 0xf, true));
+        case 0x141: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x141, 0xf, 0xf, true));
         case 0x4E: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x4E, 0xf, 0xf, true));
         default: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0xB1, 0xf, 0xf, true));
     }
@@ -198,9 +197,11 @@ __device__ __forceinline__ float reduce_scatter64(float (&v)[64], int lane) {
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
+        // row_half_mirror pairs lane p with 7 - p within each 8 lanes: always
+        // across bit 2, and with the later xor-2 / xor-1 stages it still merges
+        // all 8 lanes
         const float keep = b4 ? v[i + 4] : v[i], send = b4 ? v[i] : v[i + 4];
-        const float from_lo = dpp_f(send, 0x114), from_hi = dpp_f(send, 0x104);  // row_shr:4 / row_shl:4
-        v[i] = keep + (b4 ? from_lo : from_hi);
+        v[i] = keep + dpp_f(send, 0x141);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -244,6 +245,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
     __shared__ float acc[WG / 64][9][B];
     __shared__ int16_t wl[WG / 64][B];
     __shared__ uint32_t smax;
+    __shared__ uint32_t wlast[WG / 64];
 
     // per-pixel state: T after the current entry, colour composited behind it
     float T = 1.0f, S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
@@ -268,6 +270,11 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
         S2 = T * a.bg[2];
     }
     if (tid == 0) smax = 0;
+    // entries at or past a wave's last contributor need no work in that wave
+    uint32_t wmax = last;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) wmax = max(wmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(wmax), d)));
+    if (lane == 0) wlast[w] = wmax;
     __syncthreads();
     if (last) atomicMax(&smax, last);
     __syncthreads();
@@ -276,9 +283,8 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
     for (uint32_t i = s + used + tid; i < e; i += WG) {
         const uint32_t slot = a.sslot[i];
         if (slot >= a.k_cap) continue;
-        a.partA[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
-        a.partB[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
-        a.partC[slot] = 0.f;
+        const float z[PART] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        store_partials(a.part, slot, z);
     }
     const float fx = static_cast<float>(lx), fy = static_cast<float>(ly);
 
@@ -300,7 +306,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
         int cnt = 0;
         for (int j0 = static_cast<int>(nb) - 1; j0 >= 0; j0 -= 64) {
             const int j = j0 - lane;
-            const bool on = j >= 0 && ((shm[j >> 0] >> w) & 1u);
+            const bool on = j >= 0 && ((shm[j] >> w) & 1u) && b0 + j - s < wmax;
             const uint64_t bal = __ballot(on);
             if (on) wl[w][cnt + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<int16_t>(j);
             cnt += __popcll(bal);
@@ -333,21 +339,27 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
                 P[r * 9 + 6] = wgt * g0;
                 P[r * 9 + 7] = wgt * g1;
                 P[r * 9 + 8] = wgt * g2;
-                const float dal = g0 * (p1.z * Tj - S0 * inv) + g1 * (p1.w * Tj - S1 * inv) +
-                                  g2 * (cb * Tj - S2 * inv);
+                // dL/dalpha = sum_c g_c (c_c T_j - S_c / (1 - alpha))
+                const float e0 = __builtin_fmaf(p1.z, Tj, -(S0 * inv));
+                const float e1 = __builtin_fmaf(p1.w, Tj, -(S1 * inv));
+                const float e2 = __builtin_fmaf(cb, Tj, -(S2 * inv));
+                const float dal = __builtin_fmaf(g2, e2, __builtin_fmaf(g1, e1, g0 * e0));
                 S0 = __builtin_fmaf(p1.z, wgt, S0);
                 S1 = __builtin_fmaf(p1.w, wgt, S1);
                 S2 = __builtin_fmaf(cb, wgt, S2);
                 T = Tj;
-                // a clamped alpha has no gradient w.r.t. the opacity or footprint
+                // a clamped alpha has no gradient w.r.t. the opacity or footprint;
+                // with D = alpha dL/dalpha, dL/dq = -D/2, and the footprint
+                // partials are moments of D over the pixel offsets, to which
+                // the conic is applied once per entry after the reduction
                 const float dalc = on && raw < ALPHA_MAX ? dal : 0.0f;
-                const float dq = -0.5f * al * dalc;
-                const float hb = 0.5f * p0.w;
-                P[r * 9 + 0] = -2.0f * dq * (p0.z * dx + hb * dy);
-                P[r * 9 + 1] = -2.0f * dq * (hb * dx + p1.x * dy);
-                P[r * 9 + 2] = dq * dx * dx;
-                P[r * 9 + 3] = 2.0f * dq * dx * dy;
-                P[r * 9 + 4] = dq * dy * dy;
+                const float D = al * dalc;
+                const float X = D * dx, Y = D * dy;
+                P[r * 9 + 0] = X;
+                P[r * 9 + 1] = Y;
+                P[r * 9 + 2] = X * dx;
+                P[r * 9 + 3] = X * dy;
+                P[r * 9 + 4] = Y * dy;
                 P[r * 9 + 5] = dalc * G;
             }
             const float tot = reduce_scatter64(P, lane);
@@ -357,18 +369,26 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
         __syncthreads();
         if (tid < static_cast<int>(nb)) {
             const uint32_t m = shm[tid];
+            const uint32_t rel = b0 + tid - s;
             float v[9];
             for (int k = 0; k < 9; ++k) {
                 float x = 0.0f;
                 for (int ww = 0; ww < WG / 64; ++ww)
-                    if ((m >> ww) & 1u) x += acc[ww][k][tid];
+                    if (((m >> ww) & 1u) && rel < wlast[ww]) x += acc[ww][k][tid];
                 v[k] = x;
             }
+            // moments -> (du, dv, dA00, dA01, dA11); conic (a, b, c) with b the off-diagonal
+            const Staged st = sh[tid];
+            const float ca = st.p0.z, cb2 = st.p0.w, cc = st.p1.x;
+            const float X = v[0], Y = v[1];
+            v[0] = ca * X + 0.5f * cb2 * Y;
+            v[1] = 0.5f * cb2 * X + cc * Y;
+            v[2] = -0.5f * v[2];
+            v[3] = -v[3];
+            v[4] = -0.5f * v[4];
             const uint32_t slot = a.sslot[b0 + tid];
             if (slot < a.k_cap) {
-                a.partA[slot] = make_float4(v[0], v[1], v[2], v[3]);
-                a.partB[slot] = make_float4(v[4], v[5], v[6], v[7]);
-                a.partC[slot] = v[8];
+                store_partials(a.part, slot, v);
             }
         }
         __syncthreads();
@@ -625,9 +645,8 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
     for (uint32_t i = s + used + tid; i < e; i += WG) {
         const uint32_t slot = a.sslot[i];
         if (slot >= a.k_cap) continue;
-        a.partA[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
-        a.partB[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
-        a.partC[slot] = 0.f;
+        const float z[PART] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        store_partials(a.part, slot, z);
     }
     const float fx = static_cast<float>(lx), fy = static_cast<float>(ly);
 
@@ -701,9 +720,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
             for (int k = 0; k < 9; ++k) v[k] = (acc[0][k][tid] + acc[1][k][tid]) + (acc[2][k][tid] + acc[3][k][tid]);
             const uint32_t slot = a.sslot[b0 + tid];
             if (slot < a.k_cap) {
-                a.partA[slot] = make_float4(v[0], v[1], v[2], v[3]);
-                a.partB[slot] = make_float4(v[4], v[5], v[6], v[7]);
-                a.partC[slot] = v[8];
+                store_partials(a.part, slot, v);
             }
         }
         __syncthreads();

@@ -36,6 +36,16 @@ constexpr int LDS_TILE_LIMIT = 16384;
 // Per (frame, Gaussian) projected record, 32 bytes (one aligned half-line).
 // (u, v) stays in fp64 so that the tile-local offsets formed at staging time
 // are exact to fp32 rounding of a small number.
+// Partials of one (Gaussian, tile) pair, stored contiguously per pre-sort
+// slot so that a Gaussian's tiles share cache lines.
+constexpr int PART = 9;
+
+__device__ __forceinline__ void store_partials(float* part, uint32_t slot, const float (&v)[PART]) {
+    float* p = part + static_cast<int64_t>(slot) * PART;
+#pragma unroll
+    for (int k = 0; k < PART; ++k) p[k] = v[k];
+}
+
 struct __align__(32) Record {
     double u, v;
     float a, b, c;   // conic A = [[a, b], [b, c]]
@@ -68,7 +78,7 @@ struct Layout {
     int64_t pose_blocks;   // workgroups of the projection adjoint (upper bound)
     int64_t bin_blocks;    // workgroups per frame of the LDS-histogram binning (0: global atomics)
     size_t status, col4, rec, rect, gcnt, goff, tcnt, toff, tcur, bhist, scan_tmp, tfin, nlast, loss_part, pose_part,
-        keys, kslot, sgid, sslot, partA, partB, partC, tkeys, tslot;
+        keys, kslot, sgid, sslot, part, tkeys, tslot;
     size_t total;
 };
 
@@ -113,9 +123,7 @@ struct Args {
     uint32_t* kslot;      // [K]
     uint32_t* sgid;       // [K]
     uint32_t* sslot;      // [K]
-    float4* partA;        // [K] (du, dv, dA00, dA01)
-    float4* partB;        // [K] (dA11, do, dr, dg)
-    float* partC;         // [K] db
+    float* part;          // [K][PART] (du, dv, dA00, dA01, dA11, do, dr, dg, db) per pre-sort slot
     uint64_t* tkeys;      // [K] merge scratch of the sort
     uint32_t* tslot;      // [K]
     int64_t k_cap;

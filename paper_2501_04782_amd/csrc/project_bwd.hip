@@ -216,11 +216,9 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
             double dd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll 2
             for (uint32_t k = 0; k < cnt; ++k) {
-                const float4 pa = a.partA[base + k];
-                const float4 pb = a.partB[base + k];
-                const float pc = a.partC[base + k];
-                dd[0] += pa.x; dd[1] += pa.y; dd[2] += pa.z; dd[3] += pa.w;
-                dd[4] += pb.x; dd[5] += pb.y; dd[6] += pb.z; dd[7] += pb.w; dd[8] += pc;
+                const float* pp = a.part + static_cast<int64_t>(base + k) * PART;
+#pragma unroll
+                for (int m = 0; m < PART; ++m) dd[m] += pp[m];
             }
             float d[9];
             for (int k = 0; k < 9; ++k) d[k] = static_cast<float>(dd[k]);
