@@ -56,6 +56,9 @@ __device__ __forceinline__ void stage_entry(const Args& a, int f, uint32_t gid, 
     mask = m;
 }
 
+// Entries per unrolled group of the quadrant forward loop.
+constexpr int FWD_GROUP = 8;
+
 template <int B>
 __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
     if (overflowed(a.status)) return;
@@ -73,10 +76,17 @@ __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
     const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
     const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
 
-    __shared__ Staged sh[B];
-    __shared__ float shb[B];
+    // sh[B] is an inert entry (opacity 0) that pads the wave lists to whole groups
+    __shared__ Staged sh[B + 1];
+    __shared__ float shb[B + 1];
     __shared__ uint32_t shm[B];
     __shared__ float red[WG / 64];
+    __shared__ __align__(16) uint16_t wl[WG / 64][B + FWD_GROUP];
+    if (tid == 0) {
+        sh[B].p0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        sh[B].p1 = make_float4(0.f, 0.f, 0.f, 0.f);
+        shb[B] = 0.f;
+    }
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
     uint32_t last = 0;
@@ -96,29 +106,55 @@ __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
             shm[tid] = m;
         }
         __syncthreads();
-        if (!done) {
-            for (uint32_t j = 0; j < nb; ++j) {
-                const uint32_t m = __builtin_amdgcn_readfirstlane(shm[j]);
-                if (!((m >> w) & 1u)) continue;
-                const float4 p0 = sh[j].p0;
-                const float4 p1 = sh[j].p1;
+        if (__ballot(!done) == 0) continue;  // wave-uniform; the barriers are outside
+        // this wave's entries, front to back (ballot compaction)
+        int cnt = 0;
+        for (int j0 = 0; j0 < static_cast<int>(nb); j0 += 64) {
+            const int j = j0 + lane;
+            const bool on = j < static_cast<int>(nb) && ((shm[j] >> w) & 1u);
+            const uint64_t bal = __ballot(on);
+            if (on) wl[w][cnt + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<uint16_t>(j);
+            cnt += __popcll(bal);
+        }
+        if (lane < FWD_GROUP) wl[w][cnt + lane] = static_cast<uint16_t>(B);
+        __builtin_amdgcn_wave_barrier();
+        // Branch-free groups: an entry that misses the pixel, or reaches it
+        // after it terminated, adds a zero weight and leaves T unchanged.
+        for (int g = 0; g < cnt; g += FWD_GROUP) {
+            static_assert(FWD_GROUP == 8, "one 16-byte read of the wave list per group");
+            const uint4 jj = *reinterpret_cast<const uint4*>(&wl[w][g]);
+            const uint32_t jw[4] = {jj.x, jj.y, jj.z, jj.w};
+            float4 P0[FWD_GROUP], P1[FWD_GROUP];
+            float CB[FWD_GROUP];
+#pragma unroll
+            for (int r = 0; r < FWD_GROUP; ++r) {
+                const int j = (jw[r >> 1] >> (16 * (r & 1))) & 0xffff;
+                P0[r] = sh[j].p0;
+                P1[r] = sh[j].p1;
+                CB[r] = shb[j];
+            }
+#pragma unroll
+            for (int r = 0; r < FWD_GROUP; ++r) {
+                const int j = (jw[r >> 1] >> (16 * (r & 1))) & 0xffff;
+                const float4 p0 = P0[r];
+                const float4 p1 = P1[r];
+                const float cb = CB[r];
                 const float dx = fx - p0.x, dy = fy - p0.y;
                 const float q = footprint_q(dx, dy, p0, p1);
-                if (q > Q_MAX) continue;
                 const float al = fminf(ALPHA_MAX, p1.y * gauss_falloff(q));
-                if (al < ALPHA_MIN) continue;
+                const bool hit = !done && q <= Q_MAX && al >= ALPHA_MIN;
                 const float tn = T * (1.0f - al);
-                if (tn < T_MIN) {
-                    done = true;
-                    break;
-                }
-                const float wgt = al * T;
+                const bool stop = hit && tn < T_MIN;  // stop before this entry
+                const bool take = hit && !stop;
+                done = done || stop;
+                const float wgt = take ? al * T : 0.0f;
                 c0 = __builtin_fmaf(p1.z, wgt, c0);
                 c1 = __builtin_fmaf(p1.w, wgt, c1);
-                c2 = __builtin_fmaf(shb[j], wgt, c2);
-                T = tn;
-                last = b0 + j - s + 1;
+                c2 = __builtin_fmaf(cb, wgt, c2);
+                T = take ? tn : T;
+                last = take ? b0 + j - s + 1 : last;
             }
+            if (__ballot(!done) == 0) break;
         }
     }
 
@@ -239,16 +275,24 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
     const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
     const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
 
-    __shared__ Staged sh[B];
-    __shared__ float shb[B];
+    // sh[B] is an inert entry (opacity 0) that pads the wave lists to whole groups
+    __shared__ Staged sh[B + 1];
+    __shared__ float shb[B + 1];
     __shared__ uint32_t shm[B];
     __shared__ float acc[WG / 64][9][B];
-    __shared__ int16_t wl[WG / 64][B];
+    __shared__ uint16_t wl[WG / 64][B + RS_GROUP];
+    if (tid == 0) {
+        sh[B].p0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        sh[B].p1 = make_float4(0.f, 0.f, 0.f, 0.f);
+        shb[B] = 0.f;
+    }
     __shared__ uint32_t smax;
     __shared__ uint32_t wlast[WG / 64];
 
-    // per-pixel state: T after the current entry, colour composited behind it
-    float T = 1.0f, S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+    // per-pixel state: T after the current entry and GS = sum_c g_c S_c, the
+    // colour composited behind it (S_c, background included) weighted by the
+    // upstream gradient; only this weighted sum enters dL/dalpha
+    float T = 1.0f, GS = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
     uint32_t last = 0;
     if (inside) {
         const int64_t P = static_cast<int64_t>(a.width) * a.height;
@@ -265,9 +309,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
             g1 = a.dl_dimages[o3 + P];
             g2 = a.dl_dimages[o3 + 2 * P];
         }
-        S0 = T * a.bg[0];
-        S1 = T * a.bg[1];
-        S2 = T * a.bg[2];
+        GS = T * (g0 * a.bg[0] + g1 * a.bg[1] + g2 * a.bg[2]);
     }
     if (tid == 0) smax = 0;
     // entries at or past a wave's last contributor need no work in that wave
@@ -308,30 +350,42 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
             const int j = j0 - lane;
             const bool on = j >= 0 && ((shm[j] >> w) & 1u) && b0 + j - s < wmax;
             const uint64_t bal = __ballot(on);
-            if (on) wl[w][cnt + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<int16_t>(j);
+            if (on) wl[w][cnt + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<uint16_t>(j);
             cnt += __popcll(bal);
         }
+        if (lane < RS_GROUP) wl[w][cnt + lane] = static_cast<uint16_t>(B);
+        __builtin_amdgcn_wave_barrier();
         for (int g = 0; g < cnt; g += RS_GROUP) {
-            // Branch-free: an entry that does not reach the pixel (or a group
-            // slot past the list's end) takes alpha = 0, which leaves T and the
-            // colour behind it exactly unchanged (1 - 0 and its reciprocal are
-            // exact) and gives zero partials.
+            // Branch-free: an entry that does not reach the pixel (or the inert
+            // padding entry) takes alpha = 0, which leaves T and the colour
+            // behind it exactly unchanged (1 - 0 and its reciprocal are exact)
+            // and gives zero partials.
             float P[64];
             P[63] = 0.0f;
+            int J[RS_GROUP];
+            float4 P0[RS_GROUP], P1[RS_GROUP];
+            float CB[RS_GROUP];
+#pragma unroll
+            for (int r = 0; r < RS_GROUP; ++r) J[r] = wl[w][g + r];
 #pragma unroll
             for (int r = 0; r < RS_GROUP; ++r) {
-                const bool listed = g + r < cnt;
-                const int j = wl[w][listed ? g + r : cnt - 1];
+                P0[r] = sh[J[r]].p0;
+                P1[r] = sh[J[r]].p1;
+                CB[r] = shb[J[r]];
+            }
+#pragma unroll
+            for (int r = 0; r < RS_GROUP; ++r) {
+                const int j = J[r];
                 const uint32_t rel = b0 + j - s;
-                const float4 p0 = sh[j].p0;
-                const float4 p1 = sh[j].p1;
-                const float cb = shb[j];
+                const float4 p0 = P0[r];
+                const float4 p1 = P1[r];
+                const float cb = CB[r];
                 const float dx = fx - p0.x, dy = fy - p0.y;
                 const float q = footprint_q(dx, dy, p0, p1);
                 const float G = gauss_falloff(q);
                 const float raw = p1.y * G;
                 const float al0 = fminf(ALPHA_MAX, raw);
-                const bool on = listed && rel < last && q <= Q_MAX && al0 >= ALPHA_MIN;
+                const bool on = rel < last && q <= Q_MAX && al0 >= ALPHA_MIN;
                 const float al = on ? al0 : 0.0f;
                 const float inv = __builtin_amdgcn_rcpf(1.0f - al);
                 const float Tj = T * inv;  // transmittance in front of this entry
@@ -340,13 +394,10 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
                 P[r * 9 + 7] = wgt * g1;
                 P[r * 9 + 8] = wgt * g2;
                 // dL/dalpha = sum_c g_c (c_c T_j - S_c / (1 - alpha))
-                const float e0 = __builtin_fmaf(p1.z, Tj, -(S0 * inv));
-                const float e1 = __builtin_fmaf(p1.w, Tj, -(S1 * inv));
-                const float e2 = __builtin_fmaf(cb, Tj, -(S2 * inv));
-                const float dal = __builtin_fmaf(g2, e2, __builtin_fmaf(g1, e1, g0 * e0));
-                S0 = __builtin_fmaf(p1.z, wgt, S0);
-                S1 = __builtin_fmaf(p1.w, wgt, S1);
-                S2 = __builtin_fmaf(cb, wgt, S2);
+                //           = (T gc - GS) / (1 - alpha), gc = sum_c g_c c_c
+                const float gc = __builtin_fmaf(g2, cb, __builtin_fmaf(g1, p1.w, g0 * p1.z));
+                const float dal = inv * __builtin_fmaf(T, gc, -GS);
+                GS = __builtin_fmaf(gc, wgt, GS);
                 T = Tj;
                 // a clamped alpha has no gradient w.r.t. the opacity or footprint;
                 // with D = alpha dL/dalpha, dL/dq = -D/2, and the footprint
