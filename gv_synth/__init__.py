@@ -83,8 +83,14 @@ class Scene:
     """Gaussian parameters in storage precision, planar [C][N].
 
     ``dtype`` is "f32" (float32 arrays) or "bf16" (uint16 bit patterns).
-    ``mean_coeffs`` is None or [3 coeff][3 xyz][N] holding a1..a3 of the cubic
-    mean mu(t) = mu0 + a1 t + a2 t^2 + a3 t^3.
+    Optional time dependence (all None for a static scene):
+
+    * ``mean_coeffs`` [3 coeff][3 xyz][N]: a1..a3 of the cubic mean
+      mu(t) = mu0 + a1 t + a2 t^2 + a3 t^3;
+    * ``ctrl`` [M][3 xyz][N]: control points of the clamped cubic B-spline
+      mean (then ``means`` holds the centre the points were drawn around);
+    * ``scale_coeffs`` [3 coeff][3][N] and ``quat_coeffs`` [3 coeff][4][N]:
+      b1..b3 and r1..r3 of the cubic log-scales and quaternion.
     """
     dtype: str
     means: np.ndarray
@@ -93,6 +99,11 @@ class Scene:
     opacity_logits: np.ndarray
     colors: np.ndarray
     mean_coeffs: Optional[np.ndarray] = None
+    ctrl: Optional[np.ndarray] = None
+    scale_coeffs: Optional[np.ndarray] = None
+    quat_coeffs: Optional[np.ndarray] = None
+
+    OPTIONAL = ("mean_coeffs", "ctrl", "scale_coeffs", "quat_coeffs")
 
     @property
     def n(self) -> int:
@@ -100,8 +111,7 @@ class Scene:
 
     def fields(self):
         names = ["means", "log_scales", "quats", "opacity_logits", "colors"]
-        if self.mean_coeffs is not None:
-            names.append("mean_coeffs")
+        names += [k for k in self.OPTIONAL if getattr(self, k) is not None]
         return names
 
     def as_f64(self) -> dict:
@@ -110,7 +120,8 @@ class Scene:
         for k in self.fields():
             a = getattr(self, k)
             out[k] = bf16_bits_to_f64(a) if self.dtype == "bf16" else np.asarray(a, np.float32).astype(np.float64)
-        out["mean_coeffs"] = out.get("mean_coeffs")
+        for k in self.OPTIONAL:
+            out[k] = out.get(k)
         return out
 
 
@@ -139,6 +150,11 @@ WORKLOADS = {
     "clip1080p_f32_n500k_bf16": dict(width=1920, height=1080, n=500_000, frames=32, focal=1920.0,
                                      z=(2.0, 10.0), log_scale=(-4.5, 0.5), trajectory=None,
                                      dtype="bf16", cubic=True),
+    # the benchmark clip with Eq. 2-3 dynamics: B-spline means (8 control
+    # points) and cubic log-scales and quaternions
+    "clip540p_f50_n200k_dyn": dict(width=960, height=540, n=200_000, frames=50, focal=960.0,
+                                   z=(2.0, 10.0), log_scale=(-4.5, 0.5), trajectory="smooth",
+                                   dtype="f32", cubic=False, n_ctrl=8, poly_cov=True),
 }
 
 
@@ -158,10 +174,13 @@ def _store(x: np.ndarray, dtype: str) -> np.ndarray:
 
 def make_scene(rng: np.random.Generator, n: int, z=(2.0, 6.0), log_scale=(-3.5, 0.3),
                dtype: str = "f32", cubic: bool = False, xy=(-1.0, 1.0),
-               coeff_std: float = 0.05) -> Scene:
+               coeff_std: float = 0.05, n_ctrl: int = 0, poly_cov: bool = False,
+               ctrl_std: float = 0.05) -> Scene:
     """Draw N Gaussians: means x,y ~ U[xy], z ~ U[z]; log-scales ~ N(mu, sd);
     quaternions ~ N(0, I4) normalised; opacity logits ~ N(0, 1); RGB ~ U[0,1];
-    optional cubic mean coefficients ~ N(0, coeff_std)."""
+    optional cubic mean coefficients ~ N(0, coeff_std).  Then, in this order:
+    n_ctrl > 0 control points P_i = mean + N(0, ctrl_std) per axis, and with
+    poly_cov the cubic log-scale and quaternion coefficients ~ N(0, coeff_std)."""
     means = np.empty((3, n))
     means[0] = rng.uniform(xy[0], xy[1], n)
     means[1] = rng.uniform(xy[0], xy[1], n)
@@ -172,10 +191,14 @@ def make_scene(rng: np.random.Generator, n: int, z=(2.0, 6.0), log_scale=(-3.5, 
     opacity_logits = rng.normal(0.0, 1.0, n)
     colors = rng.uniform(0.0, 1.0, (3, n))
     coeffs = rng.normal(0.0, coeff_std, (3, 3, n)) if cubic else None
+    ctrl = means[None] + rng.normal(0.0, ctrl_std, (n_ctrl, 3, n)) if n_ctrl > 0 else None
+    sc = rng.normal(0.0, coeff_std, (3, 3, n)) if poly_cov else None
+    qc = rng.normal(0.0, coeff_std, (3, 4, n)) if poly_cov else None
+    opt = lambda a: None if a is None else _store(a, dtype)  # noqa: E731
     return Scene(dtype=dtype, means=_store(means, dtype), log_scales=_store(log_scales, dtype),
                  quats=_store(q, dtype), opacity_logits=_store(opacity_logits, dtype),
-                 colors=_store(colors, dtype),
-                 mean_coeffs=None if coeffs is None else _store(coeffs, dtype))
+                 colors=_store(colors, dtype), mean_coeffs=opt(coeffs), ctrl=opt(ctrl),
+                 scale_coeffs=opt(sc), quat_coeffs=opt(qc))
 
 
 def identity_poses(frames: int) -> np.ndarray:
@@ -250,7 +273,8 @@ def make_workload(name: str, seed: int = 0, targets: bool = True, n: Optional[in
     n = w["n"] if n is None else n
     F = w["frames"] if frames is None else frames
     rng = np.random.default_rng(seed)
-    scene = make_scene(rng, n, z=w["z"], log_scale=w["log_scale"], dtype=w["dtype"], cubic=w["cubic"])
+    scene = make_scene(rng, n, z=w["z"], log_scale=w["log_scale"], dtype=w["dtype"], cubic=w["cubic"],
+                       n_ctrl=w.get("n_ctrl", 0), poly_cov=w.get("poly_cov", False))
     cam = make_camera(w["width"], w["height"], w["focal"])
     poses = make_trajectory(rng, F) if w["trajectory"] == "smooth" else identity_poses(F)
     times = make_times(F)

@@ -39,12 +39,16 @@ class _Frame(ctypes.Structure):
         ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
         ("near_plane", ctypes.c_double), ("dilation", ctypes.c_double),
         ("bg", ctypes.c_double * 3), ("pose", ctypes.c_double * 7), ("t", ctypes.c_double),
+        ("n_ctrl", ctypes.c_int32), ("ctrl", _dp), ("scale_coeffs", _dp), ("quat_coeffs", _dp),
     ]
 
 
 class _Grads(ctypes.Structure):
     _fields_ = [("means", _dp), ("log_scales", _dp), ("quats", _dp), ("opacity_logits", _dp),
-                ("colors", _dp), ("mean_coeffs", _dp), ("pose", _dp)]
+                ("colors", _dp), ("mean_coeffs", _dp), ("pose", _dp),
+                ("ctrl", _dp), ("scale_coeffs", _dp), ("quat_coeffs", _dp)]
+
+OPTIONAL = ("mean_coeffs", "ctrl", "scale_coeffs", "quat_coeffs")
 
 
 def _load():
@@ -59,6 +63,11 @@ def _load():
         lib.gvo_render.argtypes = [ctypes.POINTER(_Frame), ctypes.c_int64, _i64p, _dp, _dp, _i64p, _dp,
                                    _dp, ctypes.POINTER(_Grads), ctypes.c_int]
         lib.gvo_render.restype = ctypes.c_int
+        lib.gvo_bspline_basis.argtypes = [ctypes.c_int32, ctypes.c_double, _dp]
+        lib.gvo_bspline_basis.restype = ctypes.c_int
+        lib.gvo_abi_version.restype = ctypes.c_int
+        if lib.gvo_abi_version() != 2:
+            raise RuntimeError("liboracle.so is stale: rebuild it (python -m oracle.build)")
         _lib = lib
     return _lib
 
@@ -76,8 +85,19 @@ def scene_f64(scene) -> dict:
     out = {}
     for k in ("means", "log_scales", "quats", "opacity_logits", "colors"):
         out[k] = np.ascontiguousarray(np.asarray(d[k], dtype=np.float64))
-    mc = d.get("mean_coeffs")
-    out["mean_coeffs"] = None if mc is None else np.ascontiguousarray(np.asarray(mc, dtype=np.float64))
+    for k in OPTIONAL:
+        v = d.get(k)
+        out[k] = None if v is None else np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+    if out["ctrl"] is not None and out["mean_coeffs"] is not None:
+        raise ValueError("a scene has either B-spline control points or cubic mean coefficients")
+    return out
+
+
+def bspline_basis(n_ctrl: int, t: float) -> np.ndarray:
+    """N_{i,3}(t), i < n_ctrl, of the clamped cubic B-spline of Eq. 2."""
+    out = np.zeros(n_ctrl)
+    if _load().gvo_bspline_basis(int(n_ctrl), float(t), _ptr(out)) != 0:
+        raise ValueError(f"bspline_basis: need 4 <= n_ctrl <= 64 and 0 <= t <= 1 (got {n_ctrl}, {t})")
     return out
 
 
@@ -87,6 +107,8 @@ def _frame(s: dict, cam, pose7, t: float):
     fr.means, fr.log_scales, fr.quats = _ptr(s["means"]), _ptr(s["log_scales"]), _ptr(s["quats"])
     fr.opacity_logits, fr.colors = _ptr(s["opacity_logits"]), _ptr(s["colors"])
     fr.mean_coeffs = _ptr(s["mean_coeffs"])
+    fr.n_ctrl = 0 if s["ctrl"] is None else int(s["ctrl"].shape[0])
+    fr.ctrl, fr.scale_coeffs, fr.quat_coeffs = _ptr(s["ctrl"]), _ptr(s["scale_coeffs"]), _ptr(s["quat_coeffs"])
     fr.width, fr.height = int(cam.width), int(cam.height)
     fr.fx, fr.fy, fr.cx, fr.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
     fr.near_plane, fr.dilation = float(cam.near_plane), float(cam.dilation)
@@ -117,7 +139,8 @@ def zero_grads(scene) -> dict:
     n = s["opacity_logits"].shape[0]
     g = dict(means=np.zeros((3, n)), log_scales=np.zeros((3, n)), quats=np.zeros((4, n)),
              opacity_logits=np.zeros(n), colors=np.zeros((3, n)), pose=np.zeros(7))
-    g["mean_coeffs"] = None if s["mean_coeffs"] is None else np.zeros((3, 3, n))
+    for k in OPTIONAL:
+        g[k] = None if s[k] is None else np.zeros_like(s[k])
     return g
 
 
@@ -151,8 +174,9 @@ def render_frame(scene, cam, pose7, t: float = 0.0, pixels: Optional[np.ndarray]
         if grads is None:
             grads = zero_grads(s)
         gstruct = _Grads(_ptr(grads["means"]), _ptr(grads["log_scales"]), _ptr(grads["quats"]),
-                         _ptr(grads["opacity_logits"]), _ptr(grads["colors"]), _ptr(grads["mean_coeffs"]),
-                         _ptr(grads["pose"]))
+                         _ptr(grads["opacity_logits"]), _ptr(grads["colors"]), _ptr(grads.get("mean_coeffs")),
+                         _ptr(grads["pose"]), _ptr(grads.get("ctrl")), _ptr(grads.get("scale_coeffs")),
+                         _ptr(grads.get("quat_coeffs")))
     rc = _load().gvo_render(ctypes.byref(fr), npx, pix_p, _ptr(color), _ptr(T), nc.ctypes.data_as(_i64p),
                             _ptr(mg), _ptr(dl), ctypes.byref(gstruct) if gstruct is not None else None,
                             int(threads))

@@ -12,8 +12,15 @@
  * the one of 3D Gaussian Splatting, which the paper cites).  The plain,
  * tile-free definition is written out, per pixel, with no binning:
  *
- *   1. mu(t) = mu0 + a1 t + a2 t^2 + a3 t^3 when cubic coefficients are given
- *      (the polynomial motion basis of Sec. 3.2, Fig. 3 / Tab. 2).
+ *   1. Time evaluation (Sec. 3.2, Eq. 2-3).  Either
+ *      mu(t) = mu0 + a1 t + a2 t^2 + a3 t^3 when cubic coefficients are given
+ *      (the polynomial motion basis of Fig. 3 / Tab. 2), or, when M control
+ *      points P_0..P_{M-1} are given, the clamped cubic B-spline
+ *      mu(t) = sum_i N_{i,3}(t) P_i of Eq. 2 (knots: four at 0, four at 1,
+ *      the M-4 interior ones evenly spaced; N_{i,p} by the Cox-de Boor
+ *      recursion).  Log-scales and quaternions may be cubic polynomials in t
+ *      (Eq. 3): l(t) = l0 + b1 t + b2 t^2 + b3 t^3, q(t) likewise before
+ *      normalisation.
  *   2. s = exp(log_scale), qhat = q/|q|, R = R(qhat) (w first),
  *      o = 1/(1+exp(-eta)), Sigma = R diag(s)^2 R^T          (Sec. 3.1)
  *   3. camera: world->camera rotation Rc = R(qc/|qc|), translation tc;
@@ -34,8 +41,9 @@
  * the chain rule is taken through step 4..1 in closed matrix form.  Skip and
  * stop decisions and the alpha clamp are piecewise constants (their
  * derivative is zero).  Gradients are with respect to the stored parameters:
- * means (or mu0 and a1..a3), log-scales, unnormalised quaternions, opacity
- * logits, colours, and the 7-vector pose (qc unnormalised, tc).
+ * means (or mu0 and a1..a3, or the control points), log-scales (and b1..b3),
+ * unnormalised quaternions (and r1..r3), opacity logits, colours, and the
+ * 7-vector pose (qc unnormalised, tc).
  *
  * Per pixel the oracle also reports how close each discrete decision came to
  * its threshold (relative margins), so that comparisons against an FP32
@@ -51,7 +59,7 @@
 
 typedef struct {
     int64_t n;
-    const double *means;          /* [3][n] (mu0 when cubic) */
+    const double *means;          /* [3][n] (mu0 when cubic; unused with control points) */
     const double *log_scales;     /* [3][n] */
     const double *quats;          /* [4][n] w,x,y,z */
     const double *opacity_logits; /* [n] */
@@ -61,11 +69,16 @@ typedef struct {
     double fx, fy, cx, cy, near_plane, dilation;
     double bg[3];
     double pose[7];               /* world->camera qw qx qy qz tx ty tz */
-    double t;                     /* frame time for the cubic mean */
+    double t;                     /* frame time in [0, 1] */
+    int32_t n_ctrl;               /* M >= 4 control points of the B-spline mean, or 0 */
+    const double *ctrl;           /* NULL or [M][3][n] */
+    const double *scale_coeffs;   /* NULL or [3 coeff][3][n]: b1..b3 of the log-scales */
+    const double *quat_coeffs;    /* NULL or [3 coeff][4][n]: r1..r3 of the quaternion */
 } gvo_frame;
 
 typedef struct {
     double *means, *log_scales, *quats, *opacity_logits, *colors, *mean_coeffs, *pose;
+    double *ctrl, *scale_coeffs, *quat_coeffs;
 } gvo_grads;
 
 typedef struct {
@@ -134,6 +147,43 @@ static void rot_grad_to_quat(const double qhat[4], double qnorm, const double dR
     for (int k = 0; k < 4; ++k) dq[k] = (dqh[k] - qhat[k] * dot) / qnorm;
 }
 
+/* Clamped cubic B-spline basis of Eq. 2 on [0, 1] with M >= 4 control
+ * points: knot u_j = 0 for j <= 3, 1 for j >= M, (j - 3)/(M - 3) between.
+ * Cox-de Boor: N_{j,0}(t) = 1 on [u_j, u_{j+1}) (the last non-empty span is
+ * closed at t = 1), N_{j,p} = (t - u_j)/(u_{j+p} - u_j) N_{j,p-1}
+ * + (u_{j+p+1} - t)/(u_{j+p+1} - u_{j+1}) N_{j+1,p-1}, a term with a zero
+ * denominator being 0.  out[i] = N_{i,3}(t), i < M. */
+#define SPLINE_MAX_CTRL 64
+static double knot(int j, int M)
+{
+    if (j <= 3) return 0.0;
+    if (j >= M) return 1.0;
+    return (double)(j - 3) / (double)(M - 3);
+}
+
+int gvo_bspline_basis(int32_t M, double t, double *out)
+{
+    if (M < 4 || M > SPLINE_MAX_CTRL || !(t >= 0.0 && t <= 1.0)) return -1;
+    double N[SPLINE_MAX_CTRL + 3];
+    const int nk = M + 4;
+    for (int j = 0; j < nk - 1; ++j) {
+        double a = knot(j, M), b = knot(j + 1, M);
+        N[j] = (a <= t && t < b) ? 1.0 : 0.0;
+        if (t == 1.0 && j == M - 1) N[j] = 1.0; /* close the last span */
+    }
+    for (int p = 1; p <= 3; ++p)
+        for (int j = 0; j < nk - 1 - p; ++j) {
+            double v = 0.0;
+            double d1 = knot(j + p, M) - knot(j, M);
+            double d2 = knot(j + p + 1, M) - knot(j + 1, M);
+            if (d1 > 0.0) v += (t - knot(j, M)) / d1 * N[j];
+            if (d2 > 0.0) v += (knot(j + p + 1, M) - t) / d2 * N[j + 1];
+            N[j] = v;
+        }
+    for (int i = 0; i < M; ++i) out[i] = N[i];
+    return 0;
+}
+
 static int all_finite(const double *v, int k)
 {
     for (int i = 0; i < k; ++i)
@@ -157,27 +207,58 @@ static void setup_camera(const gvo_frame *fr, cam_t *c, int *ok)
 static void project_one(const gvo_frame *fr, const cam_t *c, int64_t g, proj_t *P)
 {
     const int64_t n = fr->n;
+    const double t = fr->t;
     double raw[14];
     memset(P, 0, sizeof(*P));
-    for (int k = 0; k < 3; ++k) raw[k] = fr->means[k * n + g];
+    for (int k = 0; k < 3; ++k) raw[k] = fr->n_ctrl > 0 ? 0.0 : fr->means[k * n + g];
     for (int k = 0; k < 3; ++k) raw[3 + k] = fr->log_scales[k * n + g];
     for (int k = 0; k < 4; ++k) raw[6 + k] = fr->quats[k * n + g];
     raw[10] = fr->opacity_logits[g];
     for (int k = 0; k < 3; ++k) raw[11 + k] = fr->colors[k * n + g];
     if (!all_finite(raw, 14)) return;
 
-    /* 1. mean at time t */
-    for (int k = 0; k < 3; ++k) {
-        double mu = raw[k];
-        if (fr->mean_coeffs) {
-            double a1 = fr->mean_coeffs[(0 * 3 + k) * n + g];
-            double a2 = fr->mean_coeffs[(1 * 3 + k) * n + g];
-            double a3 = fr->mean_coeffs[(2 * 3 + k) * n + g];
-            if (!isfinite(a1) || !isfinite(a2) || !isfinite(a3)) return;
-            mu = mu + a1 * fr->t + a2 * fr->t * fr->t + a3 * fr->t * fr->t * fr->t;
+    /* 1. time evaluation: mean, log-scales and quaternion at t */
+    if (fr->n_ctrl > 0) {
+        double B[SPLINE_MAX_CTRL];
+        if (gvo_bspline_basis(fr->n_ctrl, t, B)) return;
+        for (int k = 0; k < 3; ++k) {
+            double mu = 0.0;
+            for (int i = 0; i < fr->n_ctrl; ++i) {
+                double c = fr->ctrl[((int64_t)i * 3 + k) * n + g];
+                if (!isfinite(c)) return;
+                mu += B[i] * c;
+            }
+            P->mu[k] = mu;
         }
-        P->mu[k] = mu;
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            double mu = raw[k];
+            if (fr->mean_coeffs) {
+                double a1 = fr->mean_coeffs[(0 * 3 + k) * n + g];
+                double a2 = fr->mean_coeffs[(1 * 3 + k) * n + g];
+                double a3 = fr->mean_coeffs[(2 * 3 + k) * n + g];
+                if (!isfinite(a1) || !isfinite(a2) || !isfinite(a3)) return;
+                mu = mu + a1 * t + a2 * t * t + a3 * t * t * t;
+            }
+            P->mu[k] = mu;
+        }
     }
+    if (fr->scale_coeffs)
+        for (int k = 0; k < 3; ++k) {
+            double b1 = fr->scale_coeffs[(0 * 3 + k) * n + g];
+            double b2 = fr->scale_coeffs[(1 * 3 + k) * n + g];
+            double b3 = fr->scale_coeffs[(2 * 3 + k) * n + g];
+            if (!isfinite(b1) || !isfinite(b2) || !isfinite(b3)) return;
+            raw[3 + k] = raw[3 + k] + b1 * t + b2 * t * t + b3 * t * t * t;
+        }
+    if (fr->quat_coeffs)
+        for (int k = 0; k < 4; ++k) {
+            double r1 = fr->quat_coeffs[(0 * 4 + k) * n + g];
+            double r2 = fr->quat_coeffs[(1 * 4 + k) * n + g];
+            double r3 = fr->quat_coeffs[(2 * 4 + k) * n + g];
+            if (!isfinite(r1) || !isfinite(r2) || !isfinite(r3)) return;
+            raw[6 + k] = raw[6 + k] + r1 * t + r2 * t * t + r3 * t * t * t;
+        }
     /* 2. activations and world covariance */
     P->qnorm = sqrt(raw[6] * raw[6] + raw[7] * raw[7] + raw[8] * raw[8] + raw[9] * raw[9]);
     if (!(P->qnorm > 0.0)) return;
@@ -434,18 +515,41 @@ static void project_adjoint(const gvo_frame *fr, const cam_t *c, int64_t g, cons
         }
     double dq[4];
     rot_grad_to_quat(P->qhat, P->qnorm, dR, dq);
-    /* write (accumulate) */
+    /* write (accumulate); the time evaluation of step 1 is linear in every
+     * coefficient, so each gets the gradient of its value times its basis
+     * function (N_i(t) or t^k) */
+    const double t = fr->t;
+    double B[SPLINE_MAX_CTRL];
+    if (fr->n_ctrl > 0) gvo_bspline_basis(fr->n_ctrl, t, B);
     for (int k = 0; k < 3; ++k) {
-        gr->means[k * n + g] += dmu[k];
-        if (gr->mean_coeffs && fr->mean_coeffs) {
-            gr->mean_coeffs[(0 * 3 + k) * n + g] += dmu[k] * fr->t;
-            gr->mean_coeffs[(1 * 3 + k) * n + g] += dmu[k] * fr->t * fr->t;
-            gr->mean_coeffs[(2 * 3 + k) * n + g] += dmu[k] * fr->t * fr->t * fr->t;
+        if (fr->n_ctrl > 0) {
+            if (gr->ctrl)
+                for (int i = 0; i < fr->n_ctrl; ++i) gr->ctrl[((int64_t)i * 3 + k) * n + g] += B[i] * dmu[k];
+        } else {
+            gr->means[k * n + g] += dmu[k];
         }
-        gr->log_scales[k * n + g] += ds[k] * P->s[k];
+        if (gr->mean_coeffs && fr->mean_coeffs) {
+            gr->mean_coeffs[(0 * 3 + k) * n + g] += dmu[k] * t;
+            gr->mean_coeffs[(1 * 3 + k) * n + g] += dmu[k] * t * t;
+            gr->mean_coeffs[(2 * 3 + k) * n + g] += dmu[k] * t * t * t;
+        }
+        double dl = ds[k] * P->s[k];
+        gr->log_scales[k * n + g] += dl;
+        if (gr->scale_coeffs && fr->scale_coeffs) {
+            gr->scale_coeffs[(0 * 3 + k) * n + g] += dl * t;
+            gr->scale_coeffs[(1 * 3 + k) * n + g] += dl * t * t;
+            gr->scale_coeffs[(2 * 3 + k) * n + g] += dl * t * t * t;
+        }
         gr->colors[k * n + g] += d[6 + k];
     }
-    for (int k = 0; k < 4; ++k) gr->quats[k * n + g] += dq[k];
+    for (int k = 0; k < 4; ++k) {
+        gr->quats[k * n + g] += dq[k];
+        if (gr->quat_coeffs && fr->quat_coeffs) {
+            gr->quat_coeffs[(0 * 4 + k) * n + g] += dq[k] * t;
+            gr->quat_coeffs[(1 * 4 + k) * n + g] += dq[k] * t * t;
+            gr->quat_coeffs[(2 * 4 + k) * n + g] += dq[k] * t * t * t;
+        }
+    }
     gr->opacity_logits[g] += d[5] * P->o * (1.0 - P->o);
 }
 
@@ -571,4 +675,4 @@ int gvo_render(const gvo_frame *fr, int64_t n_pix, const int64_t *pix, double *c
     return err;
 }
 
-int gvo_abi_version(void) { return 1; }
+int gvo_abi_version(void) { return 2; }
