@@ -81,7 +81,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--tuning", default=None, help="batch,sort_cap,compact: fixed tuning (skips the autotuner)")
+    ap.add_argument("--tuning", default=None,
+                    help="batch,sort_cap,compact[,bwd_batch]: fixed tuning (skips the autotuner)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle sample")
     ap.add_argument("--stage-reps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -143,8 +144,7 @@ def main():
 
     tuning = raster.get_tuning()
     if args.tuning:
-        b, c, m = (int(x) for x in args.tuning.split(","))
-        raster.set_tuning(b, c, m)
+        raster.set_tuning(*(int(x) for x in args.tuning.split(",")))
         tuning = raster.get_tuning()
     elif not args.no_autotune:
         log("[bench] autotuning")
@@ -273,7 +273,7 @@ def main():
     dom = max(stage_ms, key=stage_ms.get)
     t_dom = stage_ms[dom] / 1e3
     from paper_2501_04782_amd import rocprof_summary
-    tun_s = f"{tuning['batch']},{tuning['sort_cap']},{tuning['compact']}"
+    tun_s = f"{tuning['batch']},{tuning['sort_cap']},{tuning['compact']},{tuning['bwd_batch']}"
     traffic = rocprof_summary.read_traffic(
         os.path.join(ROOT, "profiles", f"{dom}_{args.workload}_{tun_s.replace(',', '-')}_hbm_traffic.txt"),
         dom, args.workload, tun_s)

@@ -72,10 +72,23 @@ typedef struct {
  * (Sec. 3.1 and Eq. 3): means [3][N] (mu0 when mean_coeffs is set),
  * log-scales [3][N] (s = exp), quaternions [4][N] (w, x, y, z; normalised
  * inside), opacity logits [N] (o = sigmoid), RGB colours [3][N] (constant in
- * time, Eq. 3).  mean_coeffs is NULL or [3 coeff][3 xyz][N]: the cubic mean
- * mu(t) = mu0 + a1 t + a2 t^2 + a3 t^3 (polynomial motion basis, Sec. 3.2).
- * dtype GV_F32: float arrays; GV_BF16: bfloat16 bit patterns (uint16),
- * widened to FP32/FP64 on load. */
+ * time, Eq. 3).  dtype GV_F32: float arrays; GV_BF16: bfloat16 bit patterns
+ * (uint16), widened to FP32/FP64 on load.
+ *
+ * Optional time dependence, evaluated at each frame's time t (Sec. 3.2):
+ * - mean_coeffs [3 coeff][3 xyz][N]: the cubic mean
+ *   mu(t) = mu0 + a1 t + a2 t^2 + a3 t^3 (the polynomial motion basis);
+ * - n_ctrl = M (4 .. GV_MAX_CTRL) and ctrl [M][3 xyz][N]: the clamped cubic
+ *   B-spline mean of Eq. 2, mu(t) = sum_i N_{i,3}(t) P_i, with four knots at
+ *   0, four at 1 and M - 4 evenly spaced between; `means` is then ignored
+ *   (may be NULL) and every frame time must lie in [0, 1] (a Gaussian is
+ *   dropped in a frame whose time does not);
+ * - scale_coeffs [3 coeff][3][N] and quat_coeffs [3 coeff][4][N]: cubic
+ *   polynomials for the log-scales and the quaternion (Eq. 3),
+ *   l(t) = l0 + b1 t + b2 t^2 + b3 t^3 and q(t) = q0 + r1 t + r2 t^2 + r3 t^3
+ *   (normalised after evaluation).
+ * mean_coeffs and ctrl exclude each other.  NULL / 0 = absent. */
+#define GV_MAX_CTRL 64
 typedef struct {
     int64_t n;              /* number of Gaussians, 0 .. 2^31-1 */
     int32_t dtype;          /* gv_dtype */
@@ -85,11 +98,16 @@ typedef struct {
     const void *opacity_logits;
     const void *colors;
     const void *mean_coeffs; /* may be NULL */
+    int32_t n_ctrl;          /* 0, or 4 .. GV_MAX_CTRL */
+    const void *ctrl;        /* NULL, or [n_ctrl][3][N] */
+    const void *scale_coeffs;/* may be NULL */
+    const void *quat_coeffs; /* may be NULL */
 } gv_scene;
 
 /* FP32 gradient outputs, same layouts as gv_scene (always FP32, even for bf16
- * parameters).  mean_coeffs may be NULL when the scene has none; any other
- * NULL member skips that output. */
+ * parameters).  A NULL member skips that output; members for parameters the
+ * scene does not have are ignored.  With control points, `means` receives
+ * nothing (the gradient goes to `ctrl`). */
 typedef struct {
     float *means;
     float *log_scales;
@@ -97,6 +115,9 @@ typedef struct {
     float *opacity_logits;
     float *colors;
     float *mean_coeffs;
+    float *ctrl;
+    float *scale_coeffs;
+    float *quat_coeffs;
 } gv_grads;
 
 /* Flags for gv_render_batch / gv_render_bwd. */
@@ -111,13 +132,15 @@ typedef struct {
  * (1024, 2048 or 4096; longer lists are sorted in chunks and merged);
  * compact: bit 0 (forward) / bit 1 (backward) select compositing kernels that
  * first build per-pixel entry lists from closed-form coverage masks instead of
- * letting every staged entry visit every pixel of its 8x8 quadrant.  Results
- * are identical; only the speed differs. */
+ * letting every staged entry visit every pixel of its 8x8 quadrant;
+ * bwd_batch: the backward's LDS batch (0 = same as batch).  Results are
+ * identical; only the speed differs. */
 typedef struct {
     int32_t batch;
     int32_t sort_cap;
     int32_t compact;
-    int32_t reserved[5];
+    int32_t bwd_batch;
+    int32_t reserved[4];
 } gv_tuning;
 
 /* Bytes of workspace for up to `frames` frames of `n` Gaussians at the
@@ -251,6 +274,7 @@ gv_status gv_device_status(const void *ws, uint32_t out[4]);
 
 const char *gv_status_str(gv_status s);
 int32_t gv_last_hip_error(void);
+/* Version of this interface: 2 (B-spline / polynomial dynamics, bwd_batch). */
 int32_t gv_abi_version(void);
 
 #ifdef __cplusplus

@@ -221,9 +221,12 @@ static void project_one(const gvo_frame *fr, const cam_t *c, int64_t g, proj_t *
     if (fr->n_ctrl > 0) {
         double B[SPLINE_MAX_CTRL];
         if (gvo_bspline_basis(fr->n_ctrl, t, B)) return;
+        /* local support: a control point with zero weight at t takes no part
+         * (not even through a non-finite value) */
         for (int k = 0; k < 3; ++k) {
             double mu = 0.0;
             for (int i = 0; i < fr->n_ctrl; ++i) {
+                if (B[i] == 0.0) continue;
                 double c = fr->ctrl[((int64_t)i * 3 + k) * n + g];
                 if (!isfinite(c)) return;
                 mu += B[i] * c;

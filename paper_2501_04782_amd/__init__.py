@@ -3,12 +3,12 @@ hot path): gfx950 HIP kernels behind the C ABI of include/gv.h, with a thin
 torch binding.  Importing the package does not touch the GPU; the first call
 loads libgv.so and raises if it has not been built."""
 from . import _lib
-from .raster import (BatchGraph, Camera, RasterizeClip, RasterizeFrame, Scene, Workspace, autotune, estimate_capacity,
-                     get_tuning, grad_buffers, project_fwd, render_batch, render_batch_timed, render_bwd, render_fwd,
-                     set_tuning)
+from .raster import (BatchGraph, Camera, RasterizeClip, RasterizeDynamicClip, RasterizeFrame, Scene, Workspace,
+                     autotune, estimate_capacity, get_tuning, grad_buffers, project_fwd, render_batch,
+                     render_batch_timed, render_bwd, render_fwd, set_tuning)
 
-__all__ = ["BatchGraph", "Camera", "RasterizeClip", "RasterizeFrame", "Scene", "Workspace", "autotune",
-           "estimate_capacity", "get_tuning", "grad_buffers", "project_fwd", "render_batch", "render_batch_timed",
+__all__ = ["BatchGraph", "Camera", "RasterizeClip", "RasterizeDynamicClip", "RasterizeFrame", "Scene", "Workspace",
+           "autotune", "estimate_capacity", "get_tuning", "grad_buffers", "project_fwd", "render_batch", "render_batch_timed",
            "render_bwd", "render_fwd", "set_tuning", "load_library"]
 
 

@@ -27,18 +27,25 @@ class GvCamera(ctypes.Structure):
                 ("cy", c_float), ("near_plane", c_float), ("dilation", c_float), ("bg", c_float * 3)]
 
 
+ABI_VERSION = 2
+GV_MAX_CTRL = 64
+
+
 class GvScene(ctypes.Structure):
     _fields_ = [("n", c_int64), ("dtype", c_int32), ("means", c_void_p), ("log_scales", c_void_p),
-                ("quats", c_void_p), ("opacity_logits", c_void_p), ("colors", c_void_p), ("mean_coeffs", c_void_p)]
+                ("quats", c_void_p), ("opacity_logits", c_void_p), ("colors", c_void_p), ("mean_coeffs", c_void_p),
+                ("n_ctrl", c_int32), ("ctrl", c_void_p), ("scale_coeffs", c_void_p), ("quat_coeffs", c_void_p)]
 
 
 class GvGrads(ctypes.Structure):
     _fields_ = [("means", c_void_p), ("log_scales", c_void_p), ("quats", c_void_p), ("opacity_logits", c_void_p),
-                ("colors", c_void_p), ("mean_coeffs", c_void_p)]
+                ("colors", c_void_p), ("mean_coeffs", c_void_p), ("ctrl", c_void_p), ("scale_coeffs", c_void_p),
+                ("quat_coeffs", c_void_p)]
 
 
 class GvTuning(ctypes.Structure):
-    _fields_ = [("batch", c_int32), ("sort_cap", c_int32), ("compact", c_int32), ("reserved", c_int32 * 5)]
+    _fields_ = [("batch", c_int32), ("sort_cap", c_int32), ("compact", c_int32), ("bwd_batch", c_int32),
+                ("reserved", c_int32 * 4)]
 
 
 class GvError(RuntimeError):
@@ -111,6 +118,9 @@ def load() -> ctypes.CDLL:
             fn = getattr(lib, name)
             fn.restype = res
             fn.argtypes = args
+        if lib.gv_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} implements ABI {lib.gv_abi_version()}, this binding ABI {ABI_VERSION}: "
+                               "rebuild it")
         _LIB = lib
     return _LIB
 

@@ -29,7 +29,7 @@ hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t count, unsi
 
 static thread_local int32_t g_last_hip = 0;
 static std::mutex g_tune_mu;
-static Tuning g_tune = {256, 2048, 128, 1};
+static Tuning g_tune = {256, 2048, 128, 0};
 
 Tuning current_tuning() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -122,8 +122,23 @@ static bool scene_ok(const gv_scene* s) {
     if (!s) return false;
     if (s->n < 0 || s->n > K_LIMIT) return false;
     if (s->dtype != GV_F32 && s->dtype != GV_BF16) return false;
-    if (s->n > 0 && (!s->means || !s->log_scales || !s->quats || !s->opacity_logits || !s->colors)) return false;
+    if (s->n_ctrl != 0 && (s->n_ctrl < 4 || s->n_ctrl > GV_MAX_CTRL || !s->ctrl || s->mean_coeffs)) return false;
+    if (s->n_ctrl == 0 && s->ctrl) return false;
+    const bool means_ok = s->means || s->n_ctrl > 0;
+    if (s->n > 0 && (!means_ok || !s->log_scales || !s->quats || !s->opacity_logits || !s->colors)) return false;
     return true;
+}
+
+static void set_grads(Args& a, const gv_grads* g) {
+    a.g_means = g->means;
+    a.g_log_scales = g->log_scales;
+    a.g_quats = g->quats;
+    a.g_opacity = g->opacity_logits;
+    a.g_colors = g->colors;
+    a.g_coeffs = g->mean_coeffs;
+    a.g_ctrl = g->ctrl;
+    a.g_scale_coeffs = g->scale_coeffs;
+    a.g_quat_coeffs = g->quat_coeffs;
 }
 
 static gv_status hip_status(hipError_t e) {
@@ -155,6 +170,10 @@ static gv_status make_args(const gv_scene* s, const gv_camera* c, int frames, co
     a.opacity_logits = s->opacity_logits;
     a.colors = s->colors;
     a.mean_coeffs = s->mean_coeffs;
+    a.n_ctrl = s->n_ctrl;
+    a.ctrl = s->ctrl;
+    a.scale_coeffs = s->scale_coeffs;
+    a.quat_coeffs = s->quat_coeffs;
     a.width = c->width;
     a.height = c->height;
     a.tiles_x = L.tiles_x;
@@ -263,14 +282,7 @@ static gv_status enqueue_batch(const gv_scene* scene, const gv_camera* cam, cons
         a.loss_scale = static_cast<float>(2.0 / denom);
     }
     a.dl_dimages = (flags & GV_LOSS_L2) ? nullptr : dL_dimages;
-    if (grads) {
-        a.g_means = grads->means;
-        a.g_log_scales = grads->log_scales;
-        a.g_quats = grads->quats;
-        a.g_opacity = grads->opacity_logits;
-        a.g_colors = grads->colors;
-        a.g_coeffs = grads->mean_coeffs;
-    }
+    if (grads) set_grads(a, grads);
     a.g_poses = dL_dposes;
     a.accumulate = (flags & GV_ACCUMULATE) ? 1 : 0;
     if (flags & GV_FWD) {
@@ -372,12 +384,7 @@ gv_status gv_render_bwd(const gv_scene* scene, const gv_camera* cam, const float
     } else {
         a.dl_dimages = dL_dimage;
     }
-    a.g_means = grads->means;
-    a.g_log_scales = grads->log_scales;
-    a.g_quats = grads->quats;
-    a.g_opacity = grads->opacity_logits;
-    a.g_colors = grads->colors;
-    a.g_coeffs = grads->mean_coeffs;
+    set_grads(a, grads);
     a.g_poses = dL_dpose7;
     a.accumulate = (flags & GV_ACCUMULATE) ? 1 : 0;
     GV_TRY(launch_composite_bwd(a, st));
@@ -519,16 +526,21 @@ gv_status gv_get_tuning(gv_tuning* out) {
     out->batch = t.batch;
     out->sort_cap = t.sort_cap;
     out->compact = t.compact;
+    out->bwd_batch = t.bwd_batch;
     return GV_OK;
 }
 
+static bool batch_ok(int b) { return b == 64 || b == 128 || b == 256; }
+
 gv_status gv_set_tuning(const gv_tuning* t) {
     if (!t) return GV_ERR_INVALID_ARG;
-    if (t->batch != 64 && t->batch != 128 && t->batch != 256) return GV_ERR_INVALID_ARG;
+    if (!batch_ok(t->batch)) return GV_ERR_INVALID_ARG;
+    if (t->bwd_batch != 0 && !batch_ok(t->bwd_batch)) return GV_ERR_INVALID_ARG;
     if (t->sort_cap != 1024 && t->sort_cap != 2048 && t->sort_cap != 4096) return GV_ERR_INVALID_ARG;
     if (t->compact < 0 || t->compact > 3) return GV_ERR_INVALID_ARG;
     Tuning n = current_tuning();
     n.batch = t->batch;
+    n.bwd_batch = t->bwd_batch ? t->bwd_batch : t->batch;
     n.sort_cap = t->sort_cap;
     n.compact = t->compact;
     install_tuning(n);
@@ -542,26 +554,33 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
     const uint32_t flags = GV_FWD | GV_BWD | GV_LOSS_L2;
     hipStream_t st;
     GV_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    hipEvent_t e0, e1;
-    GV_TRY(hipEventCreate(&e0));
-    GV_TRY(hipEventCreate(&e1));
+    StageTimer tm;
+    tm.st = st;
+    int made = 0;
+    hipError_t he = hipSuccess;
+    for (; made <= GV_STAGES && he == hipSuccess; ++made) he = hipEventCreate(&tm.ev[made]);
     const Tuning saved = current_tuning();
-    Tuning best = saved;
-    float best_ms = INFINITY;
-    gv_status result = GV_OK;
-    const int batches[] = {64, 128, 256};
-    const int caps[] = {2048, 4096};
-    for (int b : batches) {
-        for (int cc = 0; cc < 8; ++cc) {
-            const int c = caps[cc & 1];
-            Tuning t = saved;
-            t.batch = b;
-            t.sort_cap = c;
-            t.compact = cc >> 1;  // bit 0: compacted forward, bit 1: compacted backward
-            install_tuning(t);
-            gv_status s = enqueue_batch(scene, cam, poses, times, frames, targets, nullptr, flags, images, loss, grads,
-                                        dL_dposes, ws, ws_bytes, st);
-            if (s == GV_OK && hipStreamSynchronize(st) != hipSuccess) s = GV_ERR_HIP;
+    gv_status result = (he == hipSuccess) ? GV_OK : hip_status(he);
+    // The stages are independent (the forward's outputs do not depend on its
+    // kernel variant), so every stage keeps its own fastest setting: six runs
+    // cover the forward and backward kernels (batch x quadrant / compacted)
+    // and each sort capacity twice.
+    struct Cand { int batch, compact, cap; };
+    const Cand cands[6] = {{64, 0, 1024}, {128, 0, 2048}, {256, 0, 4096},
+                           {64, 3, 2048}, {128, 3, 4096}, {256, 3, 1024}};
+    float fwd_ms[6], bwd_ms[6], sort_ms[6], total_ms[6];
+    constexpr int REPS = 2;
+    for (int c = 0; c < 6 && result == GV_OK; ++c) {
+        Tuning t = saved;
+        t.batch = t.bwd_batch = cands[c].batch;
+        t.compact = cands[c].compact;
+        t.sort_cap = cands[c].cap;
+        install_tuning(t);
+        fwd_ms[c] = bwd_ms[c] = sort_ms[c] = total_ms[c] = 0.f;
+        for (int r = 0; r <= REPS && result == GV_OK; ++r) {  // run 0 warms up
+            gv_status s = enqueue_batch(scene, cam, poses, times, frames, targets, nullptr, flags, images, loss,
+                                        grads, dL_dposes, ws, ws_bytes, st, &tm);
+            if (s == GV_OK && hipEventSynchronize(tm.ev[GV_STAGES]) != hipSuccess) s = GV_ERR_HIP;
             uint32_t w[1] = {0};
             if (s == GV_OK && hipMemcpy(w, ws, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess) s = GV_ERR_HIP;
             if (s == GV_OK && w[0]) s = GV_ERR_CAPACITY;
@@ -569,30 +588,30 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
                 result = s;
                 break;
             }
-            constexpr int REPS = 3;
-            hipEventRecord(e0, st);
-            for (int r = 0; r < REPS && s == GV_OK; ++r)
-                s = enqueue_batch(scene, cam, poses, times, frames, targets, nullptr, flags, images, loss, grads,
-                                  dL_dposes, ws, ws_bytes, st);
-            hipEventRecord(e1, st);
-            hipEventSynchronize(e1);
-            float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
-            ms /= REPS;
-            if (s != GV_OK) {
-                result = s;
-                break;
-            }
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = t;
-            }
+            if (r == 0) continue;
+            float ms[GV_STAGES];
+            for (int i = 0; i < GV_STAGES; ++i) hipEventElapsedTime(&ms[i], tm.ev[i], tm.ev[i + 1]);
+            fwd_ms[c] += ms[4] / REPS;
+            bwd_ms[c] += ms[6] / REPS;
+            sort_ms[c] += ms[3] / REPS;
+            for (int i = 0; i < GV_STAGES; ++i) total_ms[c] += ms[i] / REPS;
         }
-        if (result != GV_OK) break;
+    }
+    Tuning best = saved;
+    if (result == GV_OK) {
+        int bf = 0, bb = 0, bs = 0;
+        for (int c = 1; c < 6; ++c) {
+            if (fwd_ms[c] < fwd_ms[bf]) bf = c;
+            if (bwd_ms[c] < bwd_ms[bb]) bb = c;
+            if (sort_ms[c] < sort_ms[bs]) bs = c;
+        }
+        best.batch = cands[bf].batch;
+        best.bwd_batch = cands[bb].batch;
+        best.compact = (cands[bf].compact & 1) | (cands[bb].compact & 2);
+        best.sort_cap = cands[bs].cap;
     }
     install_tuning(result == GV_OK ? best : saved);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    for (int i = 0; i < made && i <= GV_STAGES; ++i) hipEventDestroy(tm.ev[i]);
     hipStreamDestroy(st);
     if (result != GV_OK) return result;
     if (chosen) {
@@ -600,15 +619,16 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
         chosen->batch = best.batch;
         chosen->sort_cap = best.sort_cap;
         chosen->compact = best.compact;
+        chosen->bwd_batch = best.bwd_batch;
     }
     if (cache_path) {
         FILE* fp = fopen(cache_path, "a");
         if (fp) {
             fprintf(fp,
                     "{\"arch\": \"gfx950\", \"width\": %d, \"height\": %d, \"n\": %lld, \"frames\": %d, "
-                    "\"dtype\": %d, \"batch\": %d, \"sort_cap\": %d, \"compact\": %d, \"ms\": %.4f}\n",
+                    "\"dtype\": %d, \"batch\": %d, \"bwd_batch\": %d, \"sort_cap\": %d, \"compact\": %d}\n",
                     cam->width, cam->height, static_cast<long long>(scene->n), frames, scene->dtype, best.batch,
-                    best.sort_cap, best.compact, best_ms);
+                    best.bwd_batch, best.sort_cap, best.compact);
             fclose(fp);
         }
     }
@@ -641,6 +661,6 @@ const char* gv_status_str(gv_status s) {
 
 int32_t gv_last_hip_error(void) { return g_last_hip; }
 
-int32_t gv_abi_version(void) { return 1; }
+int32_t gv_abi_version(void) { return 2; }
 
 }  // extern "C"

@@ -804,14 +804,14 @@ hipError_t launch_loss_finalize(const Args& a, hipStream_t stream) {
 hipError_t launch_composite_bwd(const Args& a, hipStream_t stream) {
     const dim3 grid(static_cast<uint32_t>(a.tiles), static_cast<uint32_t>(a.frames)), block(WG);
     if (a.tune.compact & 2) {
-        switch (a.tune.batch) {
+        switch (a.tune.bwd_batch) {
             case 64: hipLaunchKernelGGL(k_composite_bwd_c<64>, grid, block, 0, stream, a); break;
             case 128: hipLaunchKernelGGL(k_composite_bwd_c<128>, grid, block, 0, stream, a); break;
             default: hipLaunchKernelGGL(k_composite_bwd_c<256>, grid, block, 0, stream, a); break;
         }
         return hipGetLastError();
     }
-    switch (a.tune.batch) {
+    switch (a.tune.bwd_batch) {
         case 64: hipLaunchKernelGGL(k_composite_bwd<64>, grid, block, 0, stream, a); break;
         case 128: hipLaunchKernelGGL(k_composite_bwd<128>, grid, block, 0, stream, a); break;
         default: hipLaunchKernelGGL(k_composite_bwd<256>, grid, block, 0, stream, a); break;

@@ -61,9 +61,9 @@ struct __align__(16) ColorOp {
 enum : int { ST_OVERFLOW = 0, ST_NONFINITE = 1, ST_K_LO = 2, ST_K_HI = 3, ST_WORDS = 16 };
 
 struct Tuning {
-    int batch;      // 64 / 128 / 256 entries per LDS round of the composite kernels
+    int batch;      // 64 / 128 / 256 entries per LDS round of the forward compositing kernel
     int sort_cap;   // 1024 / 2048 / 4096
-    int bwd_block;  // threads per workgroup of the projection adjoint
+    int bwd_batch;  // the same for the backward compositing kernel
     int compact;    // bit 0 / bit 1: compacted forward / backward compositing (coverage masks + per-lane entry
                     // walks) instead of the quadrant loop
 };
@@ -95,6 +95,10 @@ struct Args {
     const void* opacity_logits;
     const void* colors;
     const void* mean_coeffs;
+    int n_ctrl;                // B-spline control points (0 = none)
+    const void* ctrl;          // [n_ctrl][3][N]
+    const void* scale_coeffs;  // [3][3][N] or nullptr
+    const void* quat_coeffs;   // [3][4][N] or nullptr
     // camera
     int width, height, tiles_x, tiles_y, tiles;
     float fx, fy, cx, cy, near_plane, dilation, bg[3];
@@ -142,6 +146,9 @@ struct Args {
     float* g_opacity;
     float* g_colors;
     float* g_coeffs;
+    float* g_ctrl;
+    float* g_scale_coeffs;
+    float* g_quat_coeffs;
     float* g_poses;           // [F][7]
     int accumulate;
     Tuning tune;
@@ -206,6 +213,59 @@ __device__ __forceinline__ CamD load_camera(const float* pose7) {
     return c;
 }
 
+// Clamped cubic B-spline of Eq. 2 with M control points: knot u_j = 0 for
+// j <= 3, 1 for j >= M, (j - 3) / (M - 3) between.
+__device__ __forceinline__ double spline_knot(int j, int M) {
+    if (j <= 3) return 0.0;
+    if (j >= M) return 1.0;
+    return static_cast<double>(j - 3) / static_cast<double>(M - 3);
+}
+
+// The four basis functions N_{b..b+3, 3}(t) that can be non-zero at t in
+// [0, 1]; returns b (the first control point they weight).  Runs the
+// Cox-de Boor recurrence only over the triangle of non-zero terms, each in
+// the form ((t - u_i) / d) * N + ((u - t) / d') * N': the terms left out are
+// exact zeros, so the values equal those of the full recurrence bit for bit.
+template <typename R>
+__device__ __forceinline__ int spline_basis(int M, R t, R N[4]) {
+    int j = M - 1;  // knot span u_j <= t < u_{j+1}; t = 1 closes the last one
+    if (t < R(1)) {
+        j = 3 + static_cast<int>(t * static_cast<R>(M - 3));
+        j = j < 3 ? 3 : (j > M - 1 ? M - 1 : j);
+        while (j > 3 && t < static_cast<R>(spline_knot(j, M))) --j;
+        while (j < M - 1 && t >= static_cast<R>(spline_knot(j + 1, M))) ++j;
+    }
+    R B[4] = {R(1), R(0), R(0), R(0)};  // B[r] = N_{j-p+r, p}
+#pragma unroll
+    for (int p = 1; p <= 3; ++p) {
+        R nb[4] = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+        for (int r = 0; r <= p; ++r) {
+            const int i = j - p + r;
+            R v = R(0);
+            bool any = false;
+            if (r >= 1) {  // (t - u_i) / (u_{i+p} - u_i) * N_{i, p-1}
+                const R ui = static_cast<R>(spline_knot(i, M));
+                const R d1 = static_cast<R>(spline_knot(i + p, M)) - ui;
+                v = (t - ui) / d1 * B[r - 1];
+                any = true;
+            }
+            if (r <= p - 1) {  // (u_{i+p+1} - t) / (u_{i+p+1} - u_{i+1}) * N_{i+1, p-1}
+                const R ue = static_cast<R>(spline_knot(i + p + 1, M));
+                const R d2 = ue - static_cast<R>(spline_knot(i + 1, M));
+                const R w = (ue - t) / d2 * B[r];
+                v = any ? v + w : w;
+            }
+            nb[r] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) B[r] = nb[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) N[r] = B[r];
+    return j - 3;
+}
+
 // FP64 projection state of one Gaussian in one frame (EWA splatting).
 struct ProjD {
     double mu[3], s[3], qh[4], qn, R[9];
@@ -225,27 +285,62 @@ struct ProjD {
 __device__ __forceinline__ bool project_gaussian(const Args& a, int64_t g, const CamD& cam, double t, ProjD& P) {
     const int64_t n = a.n;
     double raw[14];
-    for (int k = 0; k < 3; ++k) raw[k] = load_param(a.means, a.dtype, k * n + g);
+    for (int k = 0; k < 3; ++k) raw[k] = a.n_ctrl > 0 ? 0.0 : load_param(a.means, a.dtype, k * n + g);
     for (int k = 0; k < 3; ++k) raw[3 + k] = load_param(a.log_scales, a.dtype, k * n + g);
     for (int k = 0; k < 4; ++k) raw[6 + k] = load_param(a.quats, a.dtype, k * n + g);
     raw[10] = load_param(a.opacity_logits, a.dtype, g);
     for (int k = 0; k < 3; ++k) raw[11 + k] = load_param(a.colors, a.dtype, k * n + g);
     bool fin = true;
     for (int k = 0; k < 14; ++k) fin = fin && isfinite(raw[k]);
-    for (int k = 0; k < 3; ++k) {
-        double mu = raw[k];
-        if (a.mean_coeffs) {
-            const double c1 = load_param(a.mean_coeffs, a.dtype, (0 * 3 + k) * n + g);
-            const double c2 = load_param(a.mean_coeffs, a.dtype, (1 * 3 + k) * n + g);
-            const double c3 = load_param(a.mean_coeffs, a.dtype, (2 * 3 + k) * n + g);
-            fin = fin && isfinite(c1) && isfinite(c2) && isfinite(c3);
-            // same left-to-right order as mu0 + a1 t + a2 t t + a3 t t t
-            mu = mu + c1 * t + c2 * t * t + c3 * t * t * t;
+    bool in_domain = true;
+    if (a.n_ctrl > 0) {
+        // B-spline mean (Eq. 2): sum over the span's four control points in
+        // index order (the other basis functions are exact zeros)
+        in_domain = t >= 0.0 && t <= 1.0;
+        double N[4];
+        const int b = spline_basis<double>(a.n_ctrl, in_domain ? t : 0.0, N);
+        for (int k = 0; k < 3; ++k) {
+            double mu = 0.0;
+            for (int r = 0; r < 4; ++r) {
+                if (N[r] == 0.0) continue;  // local support: zero weight, no part in mu
+                const double c = load_param(a.ctrl, a.dtype, (static_cast<int64_t>(b + r) * 3 + k) * n + g);
+                fin = fin && isfinite(c);
+                mu = mu + N[r] * c;
+            }
+            P.mu[k] = mu;
         }
-        P.mu[k] = mu;
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            double mu = raw[k];
+            if (a.mean_coeffs) {
+                const double c1 = load_param(a.mean_coeffs, a.dtype, (0 * 3 + k) * n + g);
+                const double c2 = load_param(a.mean_coeffs, a.dtype, (1 * 3 + k) * n + g);
+                const double c3 = load_param(a.mean_coeffs, a.dtype, (2 * 3 + k) * n + g);
+                fin = fin && isfinite(c1) && isfinite(c2) && isfinite(c3);
+                // same left-to-right order as mu0 + a1 t + a2 t t + a3 t t t
+                mu = mu + c1 * t + c2 * t * t + c3 * t * t * t;
+            }
+            P.mu[k] = mu;
+        }
     }
+    if (a.scale_coeffs)
+        for (int k = 0; k < 3; ++k) {
+            const double b1 = load_param(a.scale_coeffs, a.dtype, (0 * 3 + k) * n + g);
+            const double b2 = load_param(a.scale_coeffs, a.dtype, (1 * 3 + k) * n + g);
+            const double b3 = load_param(a.scale_coeffs, a.dtype, (2 * 3 + k) * n + g);
+            fin = fin && isfinite(b1) && isfinite(b2) && isfinite(b3);
+            raw[3 + k] = raw[3 + k] + b1 * t + b2 * t * t + b3 * t * t * t;
+        }
+    if (a.quat_coeffs)
+        for (int k = 0; k < 4; ++k) {
+            const double r1 = load_param(a.quat_coeffs, a.dtype, (0 * 4 + k) * n + g);
+            const double r2 = load_param(a.quat_coeffs, a.dtype, (1 * 4 + k) * n + g);
+            const double r3 = load_param(a.quat_coeffs, a.dtype, (2 * 4 + k) * n + g);
+            fin = fin && isfinite(r1) && isfinite(r2) && isfinite(r3);
+            raw[6 + k] = raw[6 + k] + r1 * t + r2 * t * t + r3 * t * t * t;
+        }
     P.nonfinite = !fin;
-    if (!fin || !cam.ok) return false;
+    if (!fin || !cam.ok || !in_domain) return false;
     P.qn = sqrt(raw[6] * raw[6] + raw[7] * raw[7] + raw[8] * raw[8] + raw[9] * raw[9]);
     if (!(P.qn > 0.0)) return false;
     for (int k = 0; k < 4; ++k) P.qh[k] = raw[6 + k] / P.qn;

@@ -36,24 +36,51 @@ __device__ __forceinline__ void add_rot_partial(int e, float v, const float q[4]
 // the one the compositing kernels used); the rest is recomputed.
 struct AdjIn {
     float mu[3], s[3], qh[4], qn, R[9], Sig[6], m[3], T[6], A[3], o;
+    float N[4];  // B-spline weights of control points span .. span + 3
+    int span;
 };
 
+// Cubic polynomial in t without a constant term: c1 t + c2 t^2 + c3 t^3.
+__device__ __forceinline__ float cubic_in_t(const Args& a, const void* coeffs, int rows, int k, int64_t g, float t) {
+    const int64_t n = a.n;
+    const float c1 = static_cast<float>(load_param(coeffs, a.dtype, (0 * rows + k) * n + g));
+    const float c2 = static_cast<float>(load_param(coeffs, a.dtype, (1 * rows + k) * n + g));
+    const float c3 = static_cast<float>(load_param(coeffs, a.dtype, (2 * rows + k) * n + g));
+    return t * (c1 + t * (c2 + t * c3));
+}
+
+template <bool DYN>
 __device__ __forceinline__ void adjoint_inputs(const Args& a, int64_t g, const Record& rec, const float* Rc,
                                                const float* tc, float t, AdjIn& P) {
     const int64_t n = a.n;
     float q[4];
-    for (int k = 0; k < 3; ++k) {
-        float mu = static_cast<float>(load_param(a.means, a.dtype, k * n + g));
-        if (a.mean_coeffs) {
-            const float c1 = static_cast<float>(load_param(a.mean_coeffs, a.dtype, (0 * 3 + k) * n + g));
-            const float c2 = static_cast<float>(load_param(a.mean_coeffs, a.dtype, (1 * 3 + k) * n + g));
-            const float c3 = static_cast<float>(load_param(a.mean_coeffs, a.dtype, (2 * 3 + k) * n + g));
-            mu = mu + t * (c1 + t * (c2 + t * c3));
+    P.span = 0;
+    if (DYN && a.n_ctrl > 0) {
+        P.span = spline_basis<float>(a.n_ctrl, fminf(fmaxf(t, 0.0f), 1.0f), P.N);
+        for (int k = 0; k < 3; ++k) {
+            float mu = 0.0f;
+            for (int r = 0; r < 4; ++r)
+                if (P.N[r] != 0.0f)
+                    mu += P.N[r] * static_cast<float>(
+                                       load_param(a.ctrl, a.dtype, (static_cast<int64_t>(P.span + r) * 3 + k) * n + g));
+            P.mu[k] = mu;
         }
-        P.mu[k] = mu;
-        P.s[k] = expf(static_cast<float>(load_param(a.log_scales, a.dtype, k * n + g)));
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            float mu = static_cast<float>(load_param(a.means, a.dtype, k * n + g));
+            if (a.mean_coeffs) mu = mu + cubic_in_t(a, a.mean_coeffs, 3, k, g, t);
+            P.mu[k] = mu;
+        }
     }
-    for (int k = 0; k < 4; ++k) q[k] = static_cast<float>(load_param(a.quats, a.dtype, k * n + g));
+    for (int k = 0; k < 3; ++k) {
+        float ls = static_cast<float>(load_param(a.log_scales, a.dtype, k * n + g));
+        if (DYN && a.scale_coeffs) ls = ls + cubic_in_t(a, a.scale_coeffs, 3, k, g, t);
+        P.s[k] = expf(ls);
+    }
+    for (int k = 0; k < 4; ++k) {
+        q[k] = static_cast<float>(load_param(a.quats, a.dtype, k * n + g));
+        if (DYN && a.quat_coeffs) q[k] = q[k] + cubic_in_t(a, a.quat_coeffs, 4, k, g, t);
+    }
     P.qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     for (int k = 0; k < 4; ++k) P.qh[k] = q[k] / P.qn;
     const float eta = static_cast<float>(load_param(a.opacity_logits, a.dtype, g));
@@ -92,13 +119,12 @@ __device__ __forceinline__ void adjoint_inputs(const Args& a, int64_t g, const R
 
 // Chain rule for one (frame, Gaussian).  d: dL/d(u, v, A00, A01, A11, o, r, g,
 // b) with A01 the single off-diagonal conic parameter (it enters q twice).
-// Adds the parameter gradients to acc[.][tid] (means 0-2, log-scales 3-5,
-// quaternion 6-9, opacity logit 10, colour 11-13, cubic coefficients 14-22)
-// and the pose gradient (dL/dRc row-major 0-8, dL/dtc 9-11) to pose[.][tid].
+// Writes the gradients w.r.t. the frame's parameter values to gout (mean 0-2,
+// log-scales 3-5, quaternion 6-9, opacity logit 10, colour 11-13) and adds
+// the pose gradient (dL/dRc row-major 0-8, dL/dtc 9-11) to pose[.][tid].
 template <int NT>
-__device__ __forceinline__ void projection_adjoint(const Args& a, const float* Rc, const AdjIn& P, float t,
-                                                   const float d[9], double (*acc)[NT], double (*pose)[NT],
-                                                   int tid) {
+__device__ __forceinline__ void projection_adjoint(const Args& a, const float* Rc, const AdjIn& P,
+                                                   const float d[9], float gout[14], double (*pose)[NT], int tid) {
     const float A0 = P.A[0], A1 = P.A[1], A2 = P.A[2];
     // gradient w.r.t. the symmetric conic matrix
     const float G00 = d[2], G01 = 0.5f * d[3], G11 = d[4];
@@ -147,13 +173,7 @@ __device__ __forceinline__ void projection_adjoint(const Args& a, const float* R
             d[0] * fx * mx * iz2 - d[1] * fy * my * iz2;
     // m = Rc mu + tc
     for (int k = 0; k < 3; ++k) {
-        const float dmu = Rc[0 * 3 + k] * dm[0] + Rc[1 * 3 + k] * dm[1] + Rc[2 * 3 + k] * dm[2];
-        acc[k][tid] += dmu;
-        if (a.mean_coeffs) {
-            acc[14 + k][tid] += static_cast<double>(dmu) * t;
-            acc[17 + k][tid] += static_cast<double>(dmu) * t * t;
-            acc[20 + k][tid] += static_cast<double>(dmu) * t * t * t;
-        }
+        gout[k] = Rc[0 * 3 + k] * dm[0] + Rc[1 * 3 + k] * dm[1] + Rc[2 * 3 + k] * dm[2];
         pose[9 + k][tid] += dm[k];
     }
     for (int i = 0; i < 3; ++i)
@@ -175,28 +195,58 @@ __device__ __forceinline__ void projection_adjoint(const Args& a, const float* R
             ds[j] += dM * P.R[i * 3 + j];
             add_rot_partial(i * 3 + j, dM * P.s[j], P.qh, gq);
         }
-    for (int k = 0; k < 3; ++k) acc[3 + k][tid] += ds[k] * P.s[k];
+    for (int k = 0; k < 3; ++k) gout[3 + k] = ds[k] * P.s[k];
     // q_hat = q / |q|
     const float dot = P.qh[0] * gq[0] + P.qh[1] * gq[1] + P.qh[2] * gq[2] + P.qh[3] * gq[3];
-    for (int k = 0; k < 4; ++k) acc[6 + k][tid] += (gq[k] - P.qh[k] * dot) / P.qn;
-    acc[10][tid] += d[5] * P.o * (1.0f - P.o);
-    acc[11][tid] += d[6];
-    acc[12][tid] += d[7];
-    acc[13][tid] += d[8];
+    for (int k = 0; k < 4; ++k) gout[6 + k] = (gq[k] - P.qh[k] * dot) / P.qn;
+    gout[10] = d[5] * P.o * (1.0f - P.o);
+    gout[11] = d[6];
+    gout[12] = d[7];
+    gout[13] = d[8];
 }
 
+// Accumulator slots (FP64, in LDS) of the projection adjoint kernel.  The
+// static layout holds the 14 per-frame parameter gradients (mean 0-2,
+// log-scales 3-5, quaternion 6-9, opacity 10, colour 11-13) and the cubic mean
+// coefficients 14-22.  The dynamic layout (B-spline means and/or polynomial
+// log-scales and quaternions, Eq. 2-3) holds the 14 at 0-13, a window of four
+// control points 14-25 (point span + r, axis k at 14 + 3 r + k), the
+// log-scale coefficients 26-34 and the quaternion coefficients 35-46.
+template <bool DYN>
+struct AccLayout {
+    static constexpr int N = DYN ? 47 : 23;
+    static constexpr int CUBIC = 14, WIN = 14, SCALE = 26, QUAT = 35;
+};
+
+template <bool DYN>
 __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
     if (overflowed(a.status)) return;
+    using LA = AccLayout<DYN>;
     const int64_t g = static_cast<int64_t>(blockIdx.x) * PB_THREADS + threadIdx.x;
     const bool live = g < a.n;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t n = a.n;
     __shared__ double red[PB_THREADS / 64][12];
-    // per-thread gradient accumulators (FP64) live in LDS: means 3,
-    // log-scales 3, quaternion 4, opacity 1, colour 3, cubic coefficients 9
-    __shared__ double acc[23][PB_THREADS];
+    // per-thread gradient accumulators (FP64) live in LDS, see AccLayout
+    __shared__ double acc[LA::N][PB_THREADS];
     __shared__ double pacc[12][PB_THREADS];  // this frame's pose contributions (dL/dRc, dL/dtc)
     __shared__ float camR[9], camT[3];
-    for (int k = 0; k < 23; ++k) acc[k][tid] = 0.0;
+    for (int k = 0; k < LA::N; ++k) acc[k][tid] = 0.0;
+    // control-point window: gradients of points win .. win + 3, flushed to
+    // memory (added) when a frame falls in another knot span
+    int win = -1;
+    const bool spline = DYN && a.n_ctrl > 0 && a.g_ctrl != nullptr;
+    auto flush_window = [&]() {
+        if (win < 0) return;
+        for (int r = 0; r < 4; ++r)
+            for (int k = 0; k < 3; ++k) {
+                float* dst = a.g_ctrl + (static_cast<int64_t>(win + r) * 3 + k) * n + g;
+                *dst += static_cast<float>(acc[LA::WIN + 3 * r + k][tid]);
+                acc[LA::WIN + 3 * r + k][tid] = 0.0;
+            }
+    };
+    if (spline && live && !a.accumulate)
+        for (int64_t i = 0; i < static_cast<int64_t>(a.n_ctrl) * 3; ++i) a.g_ctrl[i * n + g] = 0.0f;
 
 #pragma unroll 1
     for (int f = 0; f < a.frames; ++f) {
@@ -225,8 +275,39 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
             const float t = a.times ? a.times[f] : a.t0;
             const Record rec = a.rec[i];
             AdjIn P;
-            adjoint_inputs(a, g, rec, camR, camT, t, P);
-            projection_adjoint<PB_THREADS>(a, camR, P, t, d, acc, pacc, tid);
+            adjoint_inputs<DYN>(a, g, rec, camR, camT, t, P);
+            float go[14];
+            projection_adjoint<PB_THREADS>(a, camR, P, d, go, pacc, tid);
+            for (int k = 0; k < 14; ++k) acc[k][tid] += go[k];
+            const double t1 = t, t2 = t1 * t1, t3 = t2 * t1;
+            if (!DYN && a.mean_coeffs)
+                for (int k = 0; k < 3; ++k) {
+                    acc[LA::CUBIC + k][tid] += go[k] * t1;
+                    acc[LA::CUBIC + 3 + k][tid] += go[k] * t2;
+                    acc[LA::CUBIC + 6 + k][tid] += go[k] * t3;
+                }
+            if (DYN) {
+                if (spline) {
+                    if (P.span != win) {
+                        flush_window();
+                        win = P.span;
+                    }
+                    for (int r = 0; r < 4; ++r)
+                        for (int k = 0; k < 3; ++k) acc[LA::WIN + 3 * r + k][tid] += P.N[r] * go[k];
+                }
+                if (a.scale_coeffs)
+                    for (int k = 0; k < 3; ++k) {
+                        acc[LA::SCALE + k][tid] += go[3 + k] * t1;
+                        acc[LA::SCALE + 3 + k][tid] += go[3 + k] * t2;
+                        acc[LA::SCALE + 6 + k][tid] += go[3 + k] * t3;
+                    }
+                if (a.quat_coeffs)
+                    for (int k = 0; k < 4; ++k) {
+                        acc[LA::QUAT + k][tid] += go[6 + k] * t1;
+                        acc[LA::QUAT + 4 + k][tid] += go[6 + k] * t2;
+                        acc[LA::QUAT + 8 + k][tid] += go[6 + k] * t3;
+                    }
+            }
         }
         if (a.g_poses) {
             for (int k = 0; k < 12; ++k) {
@@ -242,22 +323,28 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
         }
     }
     if (!live) return;
-    const int64_t n = a.n;
+    if (spline) flush_window();
     auto put = [&](float* dst, int64_t idx, double v) {
         if (!dst) return;
         if (a.accumulate) dst[idx] += static_cast<float>(v);
         else dst[idx] = static_cast<float>(v);
     };
     for (int k = 0; k < 3; ++k) {
-        put(a.g_means, k * n + g, acc[k][tid]);
+        if (a.n_ctrl == 0) put(a.g_means, k * n + g, acc[k][tid]);
         put(a.g_log_scales, k * n + g, acc[3 + k][tid]);
         put(a.g_colors, k * n + g, acc[11 + k][tid]);
     }
     for (int k = 0; k < 4; ++k) put(a.g_quats, k * n + g, acc[6 + k][tid]);
     put(a.g_opacity, g, acc[10][tid]);
-    if (a.mean_coeffs)
+    if (!DYN && a.mean_coeffs)
         for (int c = 0; c < 3; ++c)
-            for (int k = 0; k < 3; ++k) put(a.g_coeffs, (c * 3 + k) * n + g, acc[14 + c * 3 + k][tid]);
+            for (int k = 0; k < 3; ++k) put(a.g_coeffs, (c * 3 + k) * n + g, acc[LA::CUBIC + c * 3 + k][tid]);
+    if (DYN && a.scale_coeffs)
+        for (int c = 0; c < 3; ++c)
+            for (int k = 0; k < 3; ++k) put(a.g_scale_coeffs, (c * 3 + k) * n + g, acc[LA::SCALE + c * 3 + k][tid]);
+    if (DYN && a.quat_coeffs)
+        for (int c = 0; c < 3; ++c)
+            for (int k = 0; k < 4; ++k) put(a.g_quat_coeffs, (c * 4 + k) * n + g, acc[LA::QUAT + c * 4 + k][tid]);
 }
 
 // Per frame: sum the workgroups' pose partials (each of the 256 threads takes
@@ -296,7 +383,11 @@ int64_t project_bwd_blocks(int64_t n) { return (n + PB_THREADS - 1) / PB_THREADS
 
 hipError_t launch_project_bwd(const Args& a, hipStream_t stream) {
     const int64_t nb = project_bwd_blocks(a.n);
-    if (nb > 0) hipLaunchKernelGGL(k_project_bwd, dim3(static_cast<uint32_t>(nb)), dim3(PB_THREADS), 0, stream, a);
+    const bool dyn = a.n_ctrl > 0 || a.scale_coeffs || a.quat_coeffs;
+    if (nb > 0 && dyn)
+        hipLaunchKernelGGL(k_project_bwd<true>, dim3(static_cast<uint32_t>(nb)), dim3(PB_THREADS), 0, stream, a);
+    else if (nb > 0)
+        hipLaunchKernelGGL(k_project_bwd<false>, dim3(static_cast<uint32_t>(nb)), dim3(PB_THREADS), 0, stream, a);
     if (a.g_poses)
         hipLaunchKernelGGL(k_pose_finalize, dim3(static_cast<uint32_t>(a.frames)), dim3(256), 0, stream, a, nb);
     return hipGetLastError();

@@ -73,21 +73,48 @@ class Scene:
 
     FIELDS = ("means", "log_scales", "quats", "opacity_logits", "colors")
     ROWS = dict(means=3, log_scales=3, quats=4, opacity_logits=None, colors=3)
+    OPTIONAL = ("mean_coeffs", "ctrl", "scale_coeffs", "quat_coeffs")
 
-    def __init__(self, means, log_scales, quats, opacity_logits, colors, mean_coeffs=None):
+    def __init__(self, means, log_scales, quats, opacity_logits, colors, mean_coeffs=None, ctrl=None,
+                 scale_coeffs=None, quat_coeffs=None):
+        """Time dependence (Sec. 3.2, Eq. 2-3), all optional: ``mean_coeffs``
+        [3][3][N] cubic mean; ``ctrl`` [M][3][N] B-spline control points (then
+        ``means`` is not read); ``scale_coeffs`` [3][3][N] and ``quat_coeffs``
+        [3][4][N] cubic log-scales and quaternion."""
         self.means, self.log_scales, self.quats = means, log_scales, quats
         self.opacity_logits, self.colors, self.mean_coeffs = opacity_logits, colors, mean_coeffs
-        dt = means.dtype
+        self.ctrl, self.scale_coeffs, self.quat_coeffs = ctrl, scale_coeffs, quat_coeffs
+        dt = log_scales.dtype
         if dt not in (torch.float32, torch.bfloat16):
             raise ValueError("parameters must be float32 or bfloat16")
         n = opacity_logits.shape[-1]
         for f in self.FIELDS:
             rows = self.ROWS[f]
+            if f == "means" and means is None and ctrl is not None:
+                continue
             _need(getattr(self, f), (n,) if rows is None else (rows, n), dt, f)
         if mean_coeffs is not None:
             _need(mean_coeffs, (3, 3, n), dt, "mean_coeffs")
+        if ctrl is not None:
+            if mean_coeffs is not None:
+                raise ValueError("a scene has either B-spline control points or cubic mean coefficients")
+            if ctrl.dim() != 3 or not (4 <= ctrl.shape[0] <= L.GV_MAX_CTRL):
+                raise ValueError(f"ctrl must be [M][3][N] with 4 <= M <= {L.GV_MAX_CTRL}")
+            _need(ctrl, (ctrl.shape[0], 3, n), dt, "ctrl")
+        if scale_coeffs is not None:
+            _need(scale_coeffs, (3, 3, n), dt, "scale_coeffs")
+        if quat_coeffs is not None:
+            _need(quat_coeffs, (3, 4, n), dt, "quat_coeffs")
         self.dtype = L.GV_BF16 if dt == torch.bfloat16 else L.GV_F32
         self.n = int(n)
+
+    @property
+    def device(self):
+        return self.log_scales.device
+
+    @property
+    def n_ctrl(self) -> int:
+        return 0 if self.ctrl is None else int(self.ctrl.shape[0])
 
     @classmethod
     def from_synth(cls, s, device="cuda") -> "Scene":
@@ -98,31 +125,38 @@ class Scene:
             if s.dtype == "bf16":
                 return torch.from_numpy(np.ascontiguousarray(a).view(np.int16)).to(device).view(torch.bfloat16)
             return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
-        return cls(t(s.means), t(s.log_scales), t(s.quats), t(s.opacity_logits), t(s.colors), t(s.mean_coeffs))
+        return cls(t(s.means), t(s.log_scales), t(s.quats), t(s.opacity_logits), t(s.colors), t(s.mean_coeffs),
+                   t(getattr(s, "ctrl", None)), t(getattr(s, "scale_coeffs", None)),
+                   t(getattr(s, "quat_coeffs", None)))
 
     def c(self) -> L.GvScene:
         g = L.GvScene()
         g.n, g.dtype = self.n, self.dtype
-        g.means, g.log_scales, g.quats = self.means.data_ptr(), self.log_scales.data_ptr(), self.quats.data_ptr()
-        g.opacity_logits, g.colors = self.opacity_logits.data_ptr(), self.colors.data_ptr()
-        g.mean_coeffs = None if self.mean_coeffs is None else self.mean_coeffs.data_ptr()
+        ptr = lambda x: None if x is None else x.data_ptr()  # noqa: E731
+        g.means, g.log_scales, g.quats = ptr(self.means), ptr(self.log_scales), ptr(self.quats)
+        g.opacity_logits, g.colors = ptr(self.opacity_logits), ptr(self.colors)
+        g.mean_coeffs = ptr(self.mean_coeffs)
+        g.n_ctrl, g.ctrl = self.n_ctrl, ptr(self.ctrl)
+        g.scale_coeffs, g.quat_coeffs = ptr(self.scale_coeffs), ptr(self.quat_coeffs)
         return g
 
 
 def grad_buffers(scene: Scene) -> dict:
     """FP32 gradient outputs shaped like the scene's parameters."""
-    dev = scene.means.device
+    dev = scene.device
     n = scene.n
     g = dict(means=torch.zeros(3, n, device=dev), log_scales=torch.zeros(3, n, device=dev),
              quats=torch.zeros(4, n, device=dev), opacity_logits=torch.zeros(n, device=dev),
              colors=torch.zeros(3, n, device=dev))
-    g["mean_coeffs"] = None if scene.mean_coeffs is None else torch.zeros(3, 3, n, device=dev)
+    for k in Scene.OPTIONAL:
+        v = getattr(scene, k)
+        g[k] = None if v is None else torch.zeros(v.shape, device=dev)
     return g
 
 
 def _grads_c(g: dict) -> L.GvGrads:
     s = L.GvGrads()
-    for k in ("means", "log_scales", "quats", "opacity_logits", "colors", "mean_coeffs"):
+    for k in ("means", "log_scales", "quats", "opacity_logits", "colors") + Scene.OPTIONAL:
         t = g.get(k)
         if t is not None:
             _need(t, t.shape, torch.float32, f"grad {k}")
@@ -291,12 +325,13 @@ def autotune(scene: Scene, camera: Camera, poses: torch.Tensor, times: Optional[
 def get_tuning() -> dict:
     t = L.GvTuning()
     L.check(L.load().gv_get_tuning(ctypes.byref(t)), "gv_get_tuning")
-    return dict(batch=int(t.batch), sort_cap=int(t.sort_cap), compact=int(t.compact))
+    return dict(batch=int(t.batch), sort_cap=int(t.sort_cap), compact=int(t.compact), bwd_batch=int(t.bwd_batch))
 
 
-def set_tuning(batch: int, sort_cap: int, compact: int = 1) -> None:
+def set_tuning(batch: int, sort_cap: int, compact: int = 0, bwd_batch: int = 0) -> None:
+    """Install a tuning (bwd_batch 0 = same as batch)."""
     t = L.GvTuning()
-    t.batch, t.sort_cap, t.compact = int(batch), int(sort_cap), int(compact)
+    t.batch, t.sort_cap, t.compact, t.bwd_batch = int(batch), int(sort_cap), int(compact), int(bwd_batch)
     L.check(L.load().gv_set_tuning(ctypes.byref(t)), "gv_set_tuning")
 
 
@@ -397,3 +432,32 @@ class RasterizeClip(torch.autograd.Function):
         g = out["grads"]
         return (g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["colors"], g["mean_coeffs"],
                 out["dL_dposes"], None, None, None)
+
+
+class RasterizeDynamicClip(torch.autograd.Function):
+    """Like RasterizeClip for Gaussians with the dynamics of Eq. 2-3: B-spline
+    means (control points [M][3][N]) and cubic log-scales and quaternions
+    (coefficients [3][3][N], [3][4][N]); frame times must lie in [0, 1]."""
+
+    @staticmethod
+    def forward(ctx, ctrl, log_scales, quats, opacity_logits, colors, scale_coeffs, quat_coeffs, poses, times,
+                camera, ws):
+        scene = Scene(None, log_scales, quats, opacity_logits, colors, ctrl=ctrl, scale_coeffs=scale_coeffs,
+                      quat_coeffs=quat_coeffs)
+        out = render_batch(scene, camera, poses, times, ws, forward=True, backward=False)
+        ctx.save_for_backward(ctrl, log_scales, quats, opacity_logits, colors, scale_coeffs, quat_coeffs, poses,
+                              times, out["images"])
+        ctx.camera, ctx.ws = camera, ws
+        return out["images"]
+
+    @staticmethod
+    def backward(ctx, dimages):
+        ctrl, log_scales, quats, opacity_logits, colors, scale_coeffs, quat_coeffs, poses, times, images = \
+            ctx.saved_tensors
+        scene = Scene(None, log_scales, quats, opacity_logits, colors, ctrl=ctrl, scale_coeffs=scale_coeffs,
+                      quat_coeffs=quat_coeffs)
+        out = render_batch(scene, ctx.camera, poses, times, ctx.ws, dL_dimages=dimages.contiguous(), forward=False,
+                           backward=True, images=images)
+        g = out["grads"]
+        return (g["ctrl"], g["log_scales"], g["quats"], g["opacity_logits"], g["colors"], g["scale_coeffs"],
+                g["quat_coeffs"], out["dL_dposes"], None, None, None)

@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 def test_status_strings_and_version():
     lib = L.load()
-    assert lib.gv_abi_version() == 1
+    assert lib.gv_abi_version() == 2
     for s in range(6):
         assert lib.gv_status_str(s)
     assert lib.gv_status_str(L.GV_ERR_CAPACITY) == b"intersection capacity exceeded"
@@ -109,17 +109,52 @@ def test_tuning_table_validation():
     lib = L.load()
     t = L.GvTuning()
     assert lib.gv_get_tuning(ctypes.byref(t)) == L.GV_OK
-    old = (t.batch, t.sort_cap)
+    old = (t.batch, t.sort_cap, t.compact, t.bwd_batch)
     assert t.batch in (64, 128, 256) and t.sort_cap in (1024, 2048, 4096) and t.compact in (0, 1, 2, 3)
+    assert t.bwd_batch in (64, 128, 256)
     t2 = L.GvTuning()
     t2.batch, t2.sort_cap = 100, 4096
     assert lib.gv_set_tuning(ctypes.byref(t2)) == L.GV_ERR_INVALID_ARG
-    t2.batch, t2.sort_cap = 128, 2048
+    t2.batch, t2.sort_cap, t2.bwd_batch = 128, 2048, 96
+    assert lib.gv_set_tuning(ctypes.byref(t2)) == L.GV_ERR_INVALID_ARG
+    t2.bwd_batch = 0  # same as batch
     assert lib.gv_set_tuning(ctypes.byref(t2)) == L.GV_OK
-    assert lib.gv_get_tuning(ctypes.byref(t)) == L.GV_OK and (t.batch, t.sort_cap) == (128, 2048)
-    t2.batch, t2.sort_cap = old
-    t2.compact = 1
+    assert lib.gv_get_tuning(ctypes.byref(t)) == L.GV_OK
+    assert (t.batch, t.sort_cap, t.bwd_batch) == (128, 2048, 128)
+    t2.batch, t2.sort_cap, t2.compact, t2.bwd_batch = old
     assert lib.gv_set_tuning(ctypes.byref(t2)) == L.GV_OK
+    assert lib.gv_get_tuning(ctypes.byref(t)) == L.GV_OK and (t.batch, t.sort_cap, t.compact, t.bwd_batch) == old
+
+
+def test_dynamic_scene_validation():
+    """B-spline / polynomial scene fields are checked before anything is
+    enqueued (no GPU needed: the calls fail on the host)."""
+    lib = L.load()
+    cam = L.GvCamera(64, 48, 64.0, 64.0, 32.0, 24.0, 0.01, 0.3)
+    fake = 0x1000  # never dereferenced: validation fails first
+    sz = ctypes.c_size_t()
+    assert lib.gv_workspace_bytes(ctypes.byref(cam), 10, 1, 1000, ctypes.byref(sz)) == L.GV_OK
+
+    def scene(**kw):
+        s = L.GvScene()
+        s.n, s.dtype = 10, L.GV_F32
+        s.means = s.log_scales = s.quats = s.opacity_logits = s.colors = fake
+        for k, v in kw.items():
+            setattr(s, k, v)
+        return s
+
+    pose = fake
+    bad = [scene(n_ctrl=3, ctrl=fake), scene(n_ctrl=L.GV_MAX_CTRL + 1, ctrl=fake), scene(n_ctrl=5, ctrl=None),
+           scene(n_ctrl=0, ctrl=fake), scene(n_ctrl=5, ctrl=fake, mean_coeffs=fake)]
+    for s in bad:
+        st = lib.gv_project_fwd(ctypes.byref(s), ctypes.byref(cam), pose, 0.0, fake, fake, None, 0, None)
+        assert st == L.GV_ERR_INVALID_ARG
+    # a well-formed dynamic scene passes validation and stops at the missing workspace
+    good = [scene(n_ctrl=5, ctrl=fake, means=None), scene(n_ctrl=4, ctrl=fake, scale_coeffs=fake, quat_coeffs=fake),
+            scene(scale_coeffs=fake)]
+    for s in good:
+        st = lib.gv_project_fwd(ctypes.byref(s), ctypes.byref(cam), pose, 0.0, fake, fake, None, 0, None)
+        assert st == L.GV_ERR_WORKSPACE
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

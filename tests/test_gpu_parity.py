@@ -180,7 +180,7 @@ def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
     try:
         check_clip_against_oracle(w, f"clip 160x96 F=4 compact={compact} batch={batch} cap={sort_cap}")
     finally:
-        raster.set_tuning(old["batch"], old["sort_cap"], old["compact"])
+        raster.set_tuning(old["batch"], old["sort_cap"], old["compact"], old["bwd_batch"])
 
 
 def test_long_tile_buckets_use_the_merge_sort():
@@ -188,11 +188,11 @@ def test_long_tile_buckets_use_the_merge_sort():
     LDS sort capacity (chunked LDS sort + global merges)."""
     w = small_workload(14, 48, 32, 5000, 1, z=(2.0, 6.0), ls=(-1.2, 0.3))
     old = raster.get_tuning()
-    raster.set_tuning(old["batch"], 1024, old["compact"])
+    raster.set_tuning(old["batch"], 1024, old["compact"], old["bwd_batch"])
     try:
         out = check_clip_against_oracle(w, "long buckets")
     finally:
-        raster.set_tuning(old["batch"], old["sort_cap"], old["compact"])
+        raster.set_tuning(old["batch"], old["sort_cap"], old["compact"], old["bwd_batch"])
 
 
 def test_batch_equals_per_frame_path():
