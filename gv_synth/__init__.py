@@ -91,6 +91,9 @@ class Scene:
       mean (then ``means`` holds the centre the points were drawn around);
     * ``scale_coeffs`` [3 coeff][3][N] and ``quat_coeffs`` [3 coeff][4][N]:
       b1..b3 and r1..r3 of the cubic log-scales and quaternion.
+
+    ``sh`` [(D+1)^2 - 1][3][N] holds spherical-harmonics coefficients of
+    degrees 1..D for a view-dependent colour (``colors`` is the l = 0 term).
     """
     dtype: str
     means: np.ndarray
@@ -102,8 +105,9 @@ class Scene:
     ctrl: Optional[np.ndarray] = None
     scale_coeffs: Optional[np.ndarray] = None
     quat_coeffs: Optional[np.ndarray] = None
+    sh: Optional[np.ndarray] = None
 
-    OPTIONAL = ("mean_coeffs", "ctrl", "scale_coeffs", "quat_coeffs")
+    OPTIONAL = ("mean_coeffs", "ctrl", "scale_coeffs", "quat_coeffs", "sh")
 
     @property
     def n(self) -> int:
@@ -155,6 +159,10 @@ WORKLOADS = {
     "clip540p_f50_n200k_dyn": dict(width=960, height=540, n=200_000, frames=50, focal=960.0,
                                    z=(2.0, 10.0), log_scale=(-4.5, 0.5), trajectory="smooth",
                                    dtype="f32", cubic=False, n_ctrl=8, poly_cov=True),
+    # the benchmark clip with view-dependent colour: SH of degree 3
+    "clip540p_f50_n200k_sh3": dict(width=960, height=540, n=200_000, frames=50, focal=960.0,
+                                   z=(2.0, 10.0), log_scale=(-4.5, 0.5), trajectory="smooth",
+                                   dtype="f32", cubic=False, sh_degree=3),
 }
 
 
@@ -175,12 +183,13 @@ def _store(x: np.ndarray, dtype: str) -> np.ndarray:
 def make_scene(rng: np.random.Generator, n: int, z=(2.0, 6.0), log_scale=(-3.5, 0.3),
                dtype: str = "f32", cubic: bool = False, xy=(-1.0, 1.0),
                coeff_std: float = 0.05, n_ctrl: int = 0, poly_cov: bool = False,
-               ctrl_std: float = 0.05) -> Scene:
+               ctrl_std: float = 0.05, sh_degree: int = 0, sh_std: float = 0.1) -> Scene:
     """Draw N Gaussians: means x,y ~ U[xy], z ~ U[z]; log-scales ~ N(mu, sd);
     quaternions ~ N(0, I4) normalised; opacity logits ~ N(0, 1); RGB ~ U[0,1];
     optional cubic mean coefficients ~ N(0, coeff_std).  Then, in this order:
     n_ctrl > 0 control points P_i = mean + N(0, ctrl_std) per axis, and with
-    poly_cov the cubic log-scale and quaternion coefficients ~ N(0, coeff_std)."""
+    poly_cov the cubic log-scale and quaternion coefficients ~ N(0, coeff_std),
+    and with sh_degree D > 0 the SH coefficients of degrees 1..D ~ N(0, sh_std)."""
     means = np.empty((3, n))
     means[0] = rng.uniform(xy[0], xy[1], n)
     means[1] = rng.uniform(xy[0], xy[1], n)
@@ -194,11 +203,12 @@ def make_scene(rng: np.random.Generator, n: int, z=(2.0, 6.0), log_scale=(-3.5, 
     ctrl = means[None] + rng.normal(0.0, ctrl_std, (n_ctrl, 3, n)) if n_ctrl > 0 else None
     sc = rng.normal(0.0, coeff_std, (3, 3, n)) if poly_cov else None
     qc = rng.normal(0.0, coeff_std, (3, 4, n)) if poly_cov else None
+    sh = rng.normal(0.0, sh_std, ((sh_degree + 1) ** 2 - 1, 3, n)) if sh_degree > 0 else None
     opt = lambda a: None if a is None else _store(a, dtype)  # noqa: E731
     return Scene(dtype=dtype, means=_store(means, dtype), log_scales=_store(log_scales, dtype),
                  quats=_store(q, dtype), opacity_logits=_store(opacity_logits, dtype),
                  colors=_store(colors, dtype), mean_coeffs=opt(coeffs), ctrl=opt(ctrl),
-                 scale_coeffs=opt(sc), quat_coeffs=opt(qc))
+                 scale_coeffs=opt(sc), quat_coeffs=opt(qc), sh=opt(sh))
 
 
 def identity_poses(frames: int) -> np.ndarray:
@@ -274,7 +284,8 @@ def make_workload(name: str, seed: int = 0, targets: bool = True, n: Optional[in
     F = w["frames"] if frames is None else frames
     rng = np.random.default_rng(seed)
     scene = make_scene(rng, n, z=w["z"], log_scale=w["log_scale"], dtype=w["dtype"], cubic=w["cubic"],
-                       n_ctrl=w.get("n_ctrl", 0), poly_cov=w.get("poly_cov", False))
+                       n_ctrl=w.get("n_ctrl", 0), poly_cov=w.get("poly_cov", False),
+                       sh_degree=w.get("sh_degree", 0))
     cam = make_camera(w["width"], w["height"], w["focal"])
     poses = make_trajectory(rng, F) if w["trajectory"] == "smooth" else identity_poses(F)
     times = make_times(F)

@@ -40,15 +40,16 @@ class _Frame(ctypes.Structure):
         ("near_plane", ctypes.c_double), ("dilation", ctypes.c_double),
         ("bg", ctypes.c_double * 3), ("pose", ctypes.c_double * 7), ("t", ctypes.c_double),
         ("n_ctrl", ctypes.c_int32), ("ctrl", _dp), ("scale_coeffs", _dp), ("quat_coeffs", _dp),
+        ("sh_degree", ctypes.c_int32), ("sh", _dp),
     ]
 
 
 class _Grads(ctypes.Structure):
     _fields_ = [("means", _dp), ("log_scales", _dp), ("quats", _dp), ("opacity_logits", _dp),
                 ("colors", _dp), ("mean_coeffs", _dp), ("pose", _dp),
-                ("ctrl", _dp), ("scale_coeffs", _dp), ("quat_coeffs", _dp)]
+                ("ctrl", _dp), ("scale_coeffs", _dp), ("quat_coeffs", _dp), ("sh", _dp)]
 
-OPTIONAL = ("mean_coeffs", "ctrl", "scale_coeffs", "quat_coeffs")
+OPTIONAL = ("mean_coeffs", "ctrl", "scale_coeffs", "quat_coeffs", "sh")
 
 
 def _load():
@@ -65,8 +66,10 @@ def _load():
         lib.gvo_render.restype = ctypes.c_int
         lib.gvo_bspline_basis.argtypes = [ctypes.c_int32, ctypes.c_double, _dp]
         lib.gvo_bspline_basis.restype = ctypes.c_int
+        lib.gvo_sh_basis.argtypes = [ctypes.c_int32, _dp, _dp, _dp]
+        lib.gvo_sh_basis.restype = ctypes.c_int
         lib.gvo_abi_version.restype = ctypes.c_int
-        if lib.gvo_abi_version() != 2:
+        if lib.gvo_abi_version() != 3:
             raise RuntimeError("liboracle.so is stale: rebuild it (python -m oracle.build)")
         _lib = lib
     return _lib
@@ -101,6 +104,28 @@ def bspline_basis(n_ctrl: int, t: float) -> np.ndarray:
     return out
 
 
+def sh_basis(degree: int, d, grad: bool = False):
+    """Real SH Y_lm(d), 1 <= l <= degree, (l, m) ascending; with grad=True
+    also the partials of each polynomial w.r.t. (x, y, z)."""
+    d = np.ascontiguousarray(np.asarray(d, dtype=np.float64).reshape(3))
+    nb = (degree + 1) ** 2 - 1
+    out = np.zeros(max(nb, 1))
+    g = np.zeros((max(nb, 1), 3))
+    if _load().gvo_sh_basis(int(degree), _ptr(d), _ptr(out), _ptr(g)) != 0:
+        raise ValueError(f"sh_basis: degree must be 0..3 (got {degree})")
+    return (out[:nb], g[:nb]) if grad else out[:nb]
+
+
+def sh_degree_of(sh) -> int:
+    if sh is None:
+        return 0
+    nb = int(np.asarray(sh).shape[0])
+    deg = {3: 1, 8: 2, 15: 3}.get(nb)
+    if deg is None:
+        raise ValueError(f"sh must hold 3, 8 or 15 coefficient rows (degree 1..3), got {nb}")
+    return deg
+
+
 def _frame(s: dict, cam, pose7, t: float):
     fr = _Frame()
     fr.n = int(s["opacity_logits"].shape[0])
@@ -109,6 +134,7 @@ def _frame(s: dict, cam, pose7, t: float):
     fr.mean_coeffs = _ptr(s["mean_coeffs"])
     fr.n_ctrl = 0 if s["ctrl"] is None else int(s["ctrl"].shape[0])
     fr.ctrl, fr.scale_coeffs, fr.quat_coeffs = _ptr(s["ctrl"]), _ptr(s["scale_coeffs"]), _ptr(s["quat_coeffs"])
+    fr.sh_degree, fr.sh = sh_degree_of(s["sh"]), _ptr(s["sh"])
     fr.width, fr.height = int(cam.width), int(cam.height)
     fr.fx, fr.fy, fr.cx, fr.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
     fr.near_plane, fr.dilation = float(cam.near_plane), float(cam.dilation)
@@ -176,7 +202,7 @@ def render_frame(scene, cam, pose7, t: float = 0.0, pixels: Optional[np.ndarray]
         gstruct = _Grads(_ptr(grads["means"]), _ptr(grads["log_scales"]), _ptr(grads["quats"]),
                          _ptr(grads["opacity_logits"]), _ptr(grads["colors"]), _ptr(grads.get("mean_coeffs")),
                          _ptr(grads["pose"]), _ptr(grads.get("ctrl")), _ptr(grads.get("scale_coeffs")),
-                         _ptr(grads.get("quat_coeffs")))
+                         _ptr(grads.get("quat_coeffs")), _ptr(grads.get("sh")))
     rc = _load().gvo_render(ctypes.byref(fr), npx, pix_p, _ptr(color), _ptr(T), nc.ctypes.data_as(_i64p),
                             _ptr(mg), _ptr(dl), ctypes.byref(gstruct) if gstruct is not None else None,
                             int(threads))

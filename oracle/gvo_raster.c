@@ -23,6 +23,10 @@
  *      normalisation.
  *   2. s = exp(log_scale), qhat = q/|q|, R = R(qhat) (w first),
  *      o = 1/(1+exp(-eta)), Sigma = R diag(s)^2 R^T          (Sec. 3.1)
+ *      colour: the stored RGB plus, with spherical-harmonics coefficients of
+ *      degree D (1..3, Sec. 3.1), sum over 1 <= l <= D, -l <= m <= l of
+ *      k_lm Y_lm(d), d the unit vector from the camera centre to the mean
+ *      (the RGB term plays the part of the l = 0 function).
  *   3. camera: world->camera rotation Rc = R(qc/|qc|), translation tc;
  *      m = Rc mu + tc; the Gaussian is dropped if m_z <= near_plane.
  *   4. (u,v) = (fx m_x/m_z + cx, fy m_y/m_z + cy);  J = d(u,v)/dm;
@@ -74,11 +78,13 @@ typedef struct {
     const double *ctrl;           /* NULL or [M][3][n] */
     const double *scale_coeffs;   /* NULL or [3 coeff][3][n]: b1..b3 of the log-scales */
     const double *quat_coeffs;    /* NULL or [3 coeff][4][n]: r1..r3 of the quaternion */
+    int32_t sh_degree;            /* 0 (RGB only) .. 3 */
+    const double *sh;             /* NULL or [(D+1)^2 - 1][3][n]: k_lm for l >= 1, (l, m) ascending */
 } gvo_frame;
 
 typedef struct {
     double *means, *log_scales, *quats, *opacity_logits, *colors, *mean_coeffs, *pose;
-    double *ctrl, *scale_coeffs, *quat_coeffs;
+    double *ctrl, *scale_coeffs, *quat_coeffs, *sh;
 } gvo_grads;
 
 typedef struct {
@@ -89,10 +95,14 @@ typedef struct {
     double cov[2][2], A[2][2];
     double u, v, o;
     float key;
+    double col[3];                /* colour seen from this frame's camera */
+    double dir[3], vnorm;         /* unit direction camera centre -> mean, and the distance */
+    double Y[15];                 /* real SH basis at dir, l = 1..3 */
 } proj_t;
 
 typedef struct {
     double Rc[3][3], qc_hat[4], qc_norm, tc[3];
+    double C[3];                  /* camera centre in the world, -Rc^T tc */
 } cam_t;
 
 /* ------------------------------------------------------------------ */
@@ -184,6 +194,58 @@ int gvo_bspline_basis(int32_t M, double t, double *out)
     return 0;
 }
 
+/* Real spherical harmonics Y_lm, 1 <= l <= 3, at the unit vector (x, y, z),
+ * out[l*l + l + m - 1]: the l-th degree harmonic polynomials with the
+ * orthonormal normalisation sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) (times
+ * sqrt 2 for m != 0) and the Condon-Shortley sign (-1)^m for m > 0, which the
+ * real forms carry as a sign on the odd-m terms.  grad (optional) receives
+ * the partial derivatives of each polynomial w.r.t. x, y, z. */
+int gvo_sh_basis(int32_t degree, const double d[3], double *out, double *grad)
+{
+    if (degree < 0 || degree > 3) return -1;
+    const double x = d[0], y = d[1], z = d[2];
+    const double pi = 3.14159265358979323846;
+    const double c1 = sqrt(3.0 / (4.0 * pi));
+    const double c2a = sqrt(15.0 / (4.0 * pi)), c2b = sqrt(5.0 / (16.0 * pi)), c2c = sqrt(15.0 / (16.0 * pi));
+    const double c3a = -sqrt(35.0 / (32.0 * pi)), c3b = sqrt(105.0 / (4.0 * pi));
+    const double c3c = -sqrt(21.0 / (32.0 * pi)), c3d = sqrt(7.0 / (16.0 * pi));
+    const double c3e = sqrt(105.0 / (16.0 * pi));
+    double Y[15], G[15][3];
+    /* l = 1 */
+    Y[0] = -c1 * y;                    G[0][0] = 0;        G[0][1] = -c1;      G[0][2] = 0;
+    Y[1] = c1 * z;                     G[1][0] = 0;        G[1][1] = 0;        G[1][2] = c1;
+    Y[2] = -c1 * x;                    G[2][0] = -c1;      G[2][1] = 0;        G[2][2] = 0;
+    /* l = 2 */
+    Y[3] = c2a * x * y;                G[3][0] = c2a * y;  G[3][1] = c2a * x;  G[3][2] = 0;
+    Y[4] = -c2a * y * z;               G[4][0] = 0;        G[4][1] = -c2a * z; G[4][2] = -c2a * y;
+    Y[5] = c2b * (2 * z * z - x * x - y * y);
+    G[5][0] = -2 * c2b * x;  G[5][1] = -2 * c2b * y;  G[5][2] = 4 * c2b * z;
+    Y[6] = -c2a * x * z;               G[6][0] = -c2a * z; G[6][1] = 0;        G[6][2] = -c2a * x;
+    Y[7] = c2c * (x * x - y * y);      G[7][0] = 2 * c2c * x; G[7][1] = -2 * c2c * y; G[7][2] = 0;
+    /* l = 3 */
+    Y[8] = c3a * y * (3 * x * x - y * y);
+    G[8][0] = c3a * 6 * x * y;  G[8][1] = c3a * (3 * x * x - 3 * y * y);  G[8][2] = 0;
+    Y[9] = c3b * x * y * z;
+    G[9][0] = c3b * y * z;  G[9][1] = c3b * x * z;  G[9][2] = c3b * x * y;
+    Y[10] = c3c * y * (4 * z * z - x * x - y * y);
+    G[10][0] = c3c * (-2 * x * y);  G[10][1] = c3c * (4 * z * z - x * x - 3 * y * y);  G[10][2] = c3c * 8 * y * z;
+    Y[11] = c3d * z * (2 * z * z - 3 * x * x - 3 * y * y);
+    G[11][0] = c3d * (-6 * x * z);  G[11][1] = c3d * (-6 * y * z);  G[11][2] = c3d * (6 * z * z - 3 * x * x - 3 * y * y);
+    Y[12] = c3c * x * (4 * z * z - x * x - y * y);
+    G[12][0] = c3c * (4 * z * z - 3 * x * x - y * y);  G[12][1] = c3c * (-2 * x * y);  G[12][2] = c3c * 8 * x * z;
+    Y[13] = c3e * z * (x * x - y * y);
+    G[13][0] = c3e * 2 * x * z;  G[13][1] = c3e * (-2 * y * z);  G[13][2] = c3e * (x * x - y * y);
+    Y[14] = c3a * x * (x * x - 3 * y * y);
+    G[14][0] = c3a * (3 * x * x - 3 * y * y);  G[14][1] = c3a * (-6 * x * y);  G[14][2] = 0;
+    const int nb = (degree + 1) * (degree + 1) - 1;
+    for (int k = 0; k < nb; ++k) {
+        out[k] = Y[k];
+        if (grad)
+            for (int j = 0; j < 3; ++j) grad[k * 3 + j] = G[k][j];
+    }
+    return 0;
+}
+
 static int all_finite(const double *v, int k)
 {
     for (int i = 0; i < k; ++i)
@@ -201,6 +263,11 @@ static void setup_camera(const gvo_frame *fr, cam_t *c, int *ok)
     for (int k = 0; k < 4; ++k) c->qc_hat[k] = fr->pose[k] / qn;
     quat_to_rot(c->qc_hat, c->Rc);
     for (int k = 0; k < 3; ++k) c->tc[k] = fr->pose[4 + k];
+    for (int i = 0; i < 3; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < 3; ++j) acc -= c->Rc[j][i] * c->tc[j];
+        c->C[i] = acc;
+    }
 }
 
 /* Steps 1-4 for Gaussian g. */
@@ -262,6 +329,27 @@ static void project_one(const gvo_frame *fr, const cam_t *c, int64_t g, proj_t *
             if (!isfinite(r1) || !isfinite(r2) || !isfinite(r3)) return;
             raw[6 + k] = raw[6 + k] + r1 * t + r2 * t * t + r3 * t * t * t;
         }
+    /* colour, view-dependent with SH coefficients */
+    for (int ch = 0; ch < 3; ++ch) P->col[ch] = raw[11 + ch];
+    if (fr->sh_degree > 0) {
+        double v[3], vn = 0.0;
+        for (int k = 0; k < 3; ++k) { v[k] = P->mu[k] - c->C[k]; vn += v[k] * v[k]; }
+        vn = sqrt(vn);
+        if (!(vn > 0.0)) return;
+        P->vnorm = vn;
+        for (int k = 0; k < 3; ++k) P->dir[k] = v[k] / vn;
+        gvo_sh_basis(fr->sh_degree, P->dir, P->Y, NULL);
+        const int nb = (fr->sh_degree + 1) * (fr->sh_degree + 1) - 1;
+        for (int ch = 0; ch < 3; ++ch) {
+            double acc = P->col[ch];
+            for (int k = 0; k < nb; ++k) {
+                double kc = fr->sh[((int64_t)k * 3 + ch) * n + g];
+                if (!isfinite(kc)) return;
+                acc += P->Y[k] * kc;
+            }
+            P->col[ch] = acc;
+        }
+    }
     /* 2. activations and world covariance */
     P->qnorm = sqrt(raw[6] * raw[6] + raw[7] * raw[7] + raw[8] * raw[8] + raw[9] * raw[9]);
     if (!(P->qnorm > 0.0)) return;
@@ -390,8 +478,7 @@ static int composite_pixel(const gvo_frame *fr, const proj_t *P, const int64_t *
         upd(&margins[2], fabs(Tn - T_MIN) / T_MIN);
         if (Tn < T_MIN) break;
         upd(&margins[3], fabs(a - ALPHA_MAX) / ALPHA_MAX);
-        const int64_t n = fr->n;
-        for (int ch = 0; ch < 3; ++ch) C[ch] += fr->colors[ch * n + g] * alpha * T;
+        for (int ch = 0; ch < 3; ++ch) C[ch] += p->col[ch] * alpha * T;
         if (L) {
             contrib_t c = {g, alpha, T, G, dx, dy, a >= ALPHA_MAX};
             if (clist_push(L, c)) return -1;
@@ -412,7 +499,6 @@ static int composite_pixel(const gvo_frame *fr, const proj_t *P, const int64_t *
 static void composite_pixel_adjoint(const gvo_frame *fr, const proj_t *P, const clist_t *L,
                                     double T_final, const double dC[3], double *acc)
 {
-    const int64_t n = fr->n;
     double S[3];
     for (int ch = 0; ch < 3; ++ch) S[ch] = T_final * fr->bg[ch];
     for (int64_t k = L->len - 1; k >= 0; --k) {
@@ -421,7 +507,7 @@ static void composite_pixel_adjoint(const gvo_frame *fr, const proj_t *P, const 
         const proj_t *p = &P[g];
         double *d = acc + g * 9;
         double c[3], dalpha = 0.0;
-        for (int ch = 0; ch < 3; ++ch) c[ch] = fr->colors[ch * n + g];
+        for (int ch = 0; ch < 3; ++ch) c[ch] = p->col[ch];
         for (int ch = 0; ch < 3; ++ch) {
             d[6 + ch] += e->alpha * e->T * dC[ch];
             dalpha += dC[ch] * (c[ch] * e->T - S[ch] / (1.0 - e->alpha));
@@ -518,6 +604,31 @@ static void project_adjoint(const gvo_frame *fr, const cam_t *c, int64_t g, cons
         }
     double dq[4];
     rot_grad_to_quat(P->qhat, P->qnorm, dR, dq);
+    /* view-dependent colour: d[6..8] is dL/d(colour); the direction
+     * v / |v|, v = mu - C, passes a gradient to the mean and, through the
+     * camera centre C = -Rc^T tc, to the pose */
+    if (fr->sh_degree > 0) {
+        const int nb = (fr->sh_degree + 1) * (fr->sh_degree + 1) - 1;
+        double Yb[15], Gb[45], ddir[3] = {0, 0, 0};
+        gvo_sh_basis(fr->sh_degree, P->dir, Yb, Gb);
+        for (int k = 0; k < nb; ++k)
+            for (int ch = 0; ch < 3; ++ch) {
+                double kc = fr->sh[((int64_t)k * 3 + ch) * n + g];
+                if (gr->sh) gr->sh[((int64_t)k * 3 + ch) * n + g] += Yb[k] * d[6 + ch];
+                for (int j = 0; j < 3; ++j) ddir[j] += d[6 + ch] * kc * Gb[k * 3 + j];
+            }
+        double dot = P->dir[0] * ddir[0] + P->dir[1] * ddir[1] + P->dir[2] * ddir[2];
+        double dv[3];
+        for (int j = 0; j < 3; ++j) dv[j] = (ddir[j] - P->dir[j] * dot) / P->vnorm;
+        for (int j = 0; j < 3; ++j) dmu[j] += dv[j];
+        /* dL/dC = -dv; C_i = -sum_j Rc[j][i] tc[j] */
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int i = 0; i < 3; ++i) acc += c->Rc[j][i] * dv[i];
+            dtc[j] += acc;
+            for (int i = 0; i < 3; ++i) dRc[j][i] += c->tc[j] * dv[i];
+        }
+    }
     /* write (accumulate); the time evaluation of step 1 is linear in every
      * coefficient, so each gets the gradient of its value times its basis
      * function (N_i(t) or t^k) */
@@ -678,4 +789,4 @@ int gvo_render(const gvo_frame *fr, int64_t n_pix, const int64_t *pix, double *c
     return err;
 }
 
-int gvo_abi_version(void) { return 2; }
+int gvo_abi_version(void) { return 3; }
