@@ -87,8 +87,16 @@ typedef struct {
  *   polynomials for the log-scales and the quaternion (Eq. 3),
  *   l(t) = l0 + b1 t + b2 t^2 + b3 t^3 and q(t) = q0 + r1 t + r2 t^2 + r3 t^3
  *   (normalised after evaluation).
- * mean_coeffs and ctrl exclude each other.  NULL / 0 = absent. */
+ * mean_coeffs and ctrl exclude each other.  NULL / 0 = absent.
+ *
+ * Optional view-dependent colour (Sec. 3.1: colour as spherical harmonics of
+ * degree d_c): sh_degree D in 1..3 and sh [(D+1)^2 - 1][3 rgb][N], the real
+ * SH coefficients k_lm of degrees 1..D in (l, m) ascending order; the colour
+ * seen from a frame's camera is colors + sum_lm k_lm Y_lm(d), d the unit
+ * vector from the camera centre (-Rc^T tc) to the mean; `colors` is the
+ * degree-0 term (raw RGB, no offset, no clamp). */
 #define GV_MAX_CTRL 64
+#define GV_MAX_SH_DEGREE 3
 typedef struct {
     int64_t n;              /* number of Gaussians, 0 .. 2^31-1 */
     int32_t dtype;          /* gv_dtype */
@@ -102,6 +110,8 @@ typedef struct {
     const void *ctrl;        /* NULL, or [n_ctrl][3][N] */
     const void *scale_coeffs;/* may be NULL */
     const void *quat_coeffs; /* may be NULL */
+    int32_t sh_degree;       /* 0 (RGB only) .. GV_MAX_SH_DEGREE */
+    const void *sh;          /* NULL, or [(sh_degree+1)^2 - 1][3][N] */
 } gv_scene;
 
 /* FP32 gradient outputs, same layouts as gv_scene (always FP32, even for bf16
@@ -118,6 +128,7 @@ typedef struct {
     float *ctrl;
     float *scale_coeffs;
     float *quat_coeffs;
+    float *sh;
 } gv_grads;
 
 /* Flags for gv_render_batch / gv_render_bwd. */
@@ -274,7 +285,8 @@ gv_status gv_device_status(const void *ws, uint32_t out[4]);
 
 const char *gv_status_str(gv_status s);
 int32_t gv_last_hip_error(void);
-/* Version of this interface: 2 (B-spline / polynomial dynamics, bwd_batch). */
+/* Version of this interface: 3 (2: B-spline / polynomial dynamics and
+ * bwd_batch; 3: spherical-harmonics colour). */
 int32_t gv_abi_version(void);
 
 #ifdef __cplusplus

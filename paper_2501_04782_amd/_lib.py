@@ -27,20 +27,22 @@ class GvCamera(ctypes.Structure):
                 ("cy", c_float), ("near_plane", c_float), ("dilation", c_float), ("bg", c_float * 3)]
 
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 GV_MAX_CTRL = 64
+GV_MAX_SH_DEGREE = 3
 
 
 class GvScene(ctypes.Structure):
     _fields_ = [("n", c_int64), ("dtype", c_int32), ("means", c_void_p), ("log_scales", c_void_p),
                 ("quats", c_void_p), ("opacity_logits", c_void_p), ("colors", c_void_p), ("mean_coeffs", c_void_p),
-                ("n_ctrl", c_int32), ("ctrl", c_void_p), ("scale_coeffs", c_void_p), ("quat_coeffs", c_void_p)]
+                ("n_ctrl", c_int32), ("ctrl", c_void_p), ("scale_coeffs", c_void_p), ("quat_coeffs", c_void_p),
+                ("sh_degree", c_int32), ("sh", c_void_p)]
 
 
 class GvGrads(ctypes.Structure):
     _fields_ = [("means", c_void_p), ("log_scales", c_void_p), ("quats", c_void_p), ("opacity_logits", c_void_p),
                 ("colors", c_void_p), ("mean_coeffs", c_void_p), ("ctrl", c_void_p), ("scale_coeffs", c_void_p),
-                ("quat_coeffs", c_void_p)]
+                ("quat_coeffs", c_void_p), ("sh", c_void_p)]
 
 
 class GvTuning(ctypes.Structure):

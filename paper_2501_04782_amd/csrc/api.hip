@@ -69,7 +69,7 @@ Layout make_layout(const gv_camera& cam, int64_t n, int frames, int64_t k_cap) {
         return o;
     };
     L.status = take(ST_WORDS * sizeof(uint32_t));
-    L.col4 = take(sizeof(ColorOp) * static_cast<size_t>(n));
+    L.col4 = take(sizeof(ColorOp) * static_cast<size_t>(FN));  // per frame: view-dependent colour
     L.rec = take(sizeof(Record) * static_cast<size_t>(FN));
     L.rect = take(sizeof(uint2) * static_cast<size_t>(FN));
     L.gcnt = take(4 * static_cast<size_t>(FN));
@@ -124,6 +124,7 @@ static bool scene_ok(const gv_scene* s) {
     if (s->dtype != GV_F32 && s->dtype != GV_BF16) return false;
     if (s->n_ctrl != 0 && (s->n_ctrl < 4 || s->n_ctrl > GV_MAX_CTRL || !s->ctrl || s->mean_coeffs)) return false;
     if (s->n_ctrl == 0 && s->ctrl) return false;
+    if (s->sh_degree < 0 || s->sh_degree > GV_MAX_SH_DEGREE || (s->sh_degree > 0) != (s->sh != nullptr)) return false;
     const bool means_ok = s->means || s->n_ctrl > 0;
     if (s->n > 0 && (!means_ok || !s->log_scales || !s->quats || !s->opacity_logits || !s->colors)) return false;
     return true;
@@ -139,6 +140,7 @@ static void set_grads(Args& a, const gv_grads* g) {
     a.g_ctrl = g->ctrl;
     a.g_scale_coeffs = g->scale_coeffs;
     a.g_quat_coeffs = g->quat_coeffs;
+    a.g_sh = g->sh;
 }
 
 static gv_status hip_status(hipError_t e) {
@@ -174,6 +176,8 @@ static gv_status make_args(const gv_scene* s, const gv_camera* c, int frames, co
     a.ctrl = s->ctrl;
     a.scale_coeffs = s->scale_coeffs;
     a.quat_coeffs = s->quat_coeffs;
+    a.sh_degree = s->sh_degree;
+    a.sh = s->sh;
     a.width = c->width;
     a.height = c->height;
     a.tiles_x = L.tiles_x;
@@ -189,6 +193,7 @@ static gv_status make_args(const gv_scene* s, const gv_camera* c, int frames, co
     char* b = static_cast<char*>(ws);
     a.status = reinterpret_cast<uint32_t*>(b + L.status);
     a.col4 = reinterpret_cast<ColorOp*>(b + L.col4);
+    a.col_stride = s->sh_degree > 0 ? s->n : 0;
     a.rec = reinterpret_cast<Record*>(b + L.rec);
     a.rect = reinterpret_cast<uint2*>(b + L.rect);
     a.gcnt = reinterpret_cast<uint32_t*>(b + L.gcnt);
@@ -661,6 +666,6 @@ const char* gv_status_str(gv_status s) {
 
 int32_t gv_last_hip_error(void) { return g_last_hip; }
 
-int32_t gv_abi_version(void) { return 2; }
+int32_t gv_abi_version(void) { return 3; }
 
 }  // extern "C"

@@ -38,7 +38,7 @@ __device__ __forceinline__ void stage_entry(const Args& a, int f, uint32_t gid, 
         return;
     }
     const Record r = a.rec[static_cast<int64_t>(f) * a.n + gid];
-    const ColorOp co = a.col4[gid];
+    const ColorOp co = a.col4[static_cast<int64_t>(f) * a.col_stride + gid];
     const float lu = static_cast<float>(r.u - ox);
     const float lv = static_cast<float>(r.v - oy);
     st.p0 = make_float4(lu, lv, r.a, 2.0f * r.b);

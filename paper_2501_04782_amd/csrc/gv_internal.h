@@ -99,6 +99,8 @@ struct Args {
     const void* ctrl;          // [n_ctrl][3][N]
     const void* scale_coeffs;  // [3][3][N] or nullptr
     const void* quat_coeffs;   // [3][4][N] or nullptr
+    int sh_degree;             // 0 .. 3
+    const void* sh;            // [(D+1)^2 - 1][3][N] or nullptr
     // camera
     int width, height, tiles_x, tiles_y, tiles;
     float fx, fy, cx, cy, near_plane, dilation, bg[3];
@@ -109,7 +111,8 @@ struct Args {
     float t0;
     // workspace
     uint32_t* status;
-    ColorOp* col4;
+    ColorOp* col4;        // [F][N] (colour seen from each frame's camera) when view-dependent, else [N]
+    int64_t col_stride;   // N with view-dependent colour, else 0: frame f reads col4[f * col_stride + g]
     Record* rec;          // [F][N]
     uint2* rect;          // [F][N]: (x0 | x1 << 16, y0 | y1 << 16) in tiles
     uint32_t* gcnt;       // [F*N]
@@ -149,6 +152,7 @@ struct Args {
     float* g_ctrl;
     float* g_scale_coeffs;
     float* g_quat_coeffs;
+    float* g_sh;
     float* g_poses;           // [F][7]
     int accumulate;
     Tuning tune;
@@ -266,6 +270,62 @@ __device__ __forceinline__ int spline_basis(int M, R t, R N[4]) {
     return j - 3;
 }
 
+// Real spherical harmonics of degrees 1..3 at the unit vector (x, y, z), in
+// (l, m) ascending order: the harmonic polynomials of degree l normalised to
+// unit L2 norm on the sphere, with the (-1)^m sign for m > 0.  If G is given,
+// G[k][j] = d Y_k / d(x, y, z)_j of the polynomial.
+template <typename R>
+__device__ __forceinline__ void sh_eval(int degree, R x, R y, R z, R Y[15], R (*G)[3]) {
+    const R k1 = R(0.48860251190291992);                                   // sqrt(3 / 4pi)
+    const R k2a = R(1.0925484305920792), k2b = R(0.31539156525252005);    // sqrt(15 / 4pi), sqrt(5 / 16pi)
+    const R k2c = R(0.54627421529603959);                                  // sqrt(15 / 16pi)
+    const R k3a = R(-0.59004358992664352), k3b = R(2.8906114426405538);   // -sqrt(35 / 32pi), sqrt(105 / 4pi)
+    const R k3c = R(-0.45704579946446572), k3d = R(0.3731763325901154);   // -sqrt(21 / 32pi), sqrt(7 / 16pi)
+    const R k3e = R(1.4453057213202769);                                   // sqrt(105 / 16pi)
+    const R xx = x * x, yy = y * y, zz = z * z;
+    Y[0] = -k1 * y;
+    Y[1] = k1 * z;
+    Y[2] = -k1 * x;
+    if (G) {
+        G[0][0] = R(0); G[0][1] = -k1; G[0][2] = R(0);
+        G[1][0] = R(0); G[1][1] = R(0); G[1][2] = k1;
+        G[2][0] = -k1; G[2][1] = R(0); G[2][2] = R(0);
+    }
+    if (degree < 2) return;
+    Y[3] = k2a * x * y;
+    Y[4] = -k2a * y * z;
+    Y[5] = k2b * (R(2) * zz - xx - yy);
+    Y[6] = -k2a * x * z;
+    Y[7] = k2c * (xx - yy);
+    if (G) {
+        G[3][0] = k2a * y; G[3][1] = k2a * x; G[3][2] = R(0);
+        G[4][0] = R(0); G[4][1] = -k2a * z; G[4][2] = -k2a * y;
+        G[5][0] = R(-2) * k2b * x; G[5][1] = R(-2) * k2b * y; G[5][2] = R(4) * k2b * z;
+        G[6][0] = -k2a * z; G[6][1] = R(0); G[6][2] = -k2a * x;
+        G[7][0] = R(2) * k2c * x; G[7][1] = R(-2) * k2c * y; G[7][2] = R(0);
+    }
+    if (degree < 3) return;
+    Y[8] = k3a * y * (R(3) * xx - yy);
+    Y[9] = k3b * x * y * z;
+    Y[10] = k3c * y * (R(4) * zz - xx - yy);
+    Y[11] = k3d * z * (R(2) * zz - R(3) * xx - R(3) * yy);
+    Y[12] = k3c * x * (R(4) * zz - xx - yy);
+    Y[13] = k3e * z * (xx - yy);
+    Y[14] = k3a * x * (xx - R(3) * yy);
+    if (G) {
+        G[8][0] = k3a * R(6) * x * y; G[8][1] = k3a * R(3) * (xx - yy); G[8][2] = R(0);
+        G[9][0] = k3b * y * z; G[9][1] = k3b * x * z; G[9][2] = k3b * x * y;
+        G[10][0] = k3c * R(-2) * x * y; G[10][1] = k3c * (R(4) * zz - xx - R(3) * yy); G[10][2] = k3c * R(8) * y * z;
+        G[11][0] = k3d * R(-6) * x * z; G[11][1] = k3d * R(-6) * y * z;
+        G[11][2] = k3d * (R(6) * zz - R(3) * xx - R(3) * yy);
+        G[12][0] = k3c * (R(4) * zz - R(3) * xx - yy); G[12][1] = k3c * R(-2) * x * y; G[12][2] = k3c * R(8) * x * z;
+        G[13][0] = k3e * R(2) * x * z; G[13][1] = k3e * R(-2) * y * z; G[13][2] = k3e * (xx - yy);
+        G[14][0] = k3a * R(3) * (xx - yy); G[14][1] = k3a * R(-6) * x * y; G[14][2] = R(0);
+    }
+}
+
+__device__ __forceinline__ int sh_count(int degree) { return (degree + 1) * (degree + 1) - 1; }
+
 // FP64 projection state of one Gaussian in one frame (EWA splatting).
 struct ProjD {
     double mu[3], s[3], qh[4], qn, R[9];
@@ -277,6 +337,7 @@ struct ProjD {
     double A[3];          // conic 00 01 11
     double o;
     double eta;
+    double col[3];        // colour seen from this frame's camera (view-dependent with SH)
     bool nonfinite;
 };
 
@@ -339,6 +400,27 @@ __device__ __forceinline__ bool project_gaussian(const Args& a, int64_t g, const
             fin = fin && isfinite(r1) && isfinite(r2) && isfinite(r3);
             raw[6 + k] = raw[6 + k] + r1 * t + r2 * t * t + r3 * t * t * t;
         }
+    for (int c = 0; c < 3; ++c) P.col[c] = raw[11 + c];
+    if (a.sh_degree > 0) {
+        // view-dependent colour: SH at the unit direction camera centre -> mean
+        double v[3];
+        for (int i = 0; i < 3; ++i)
+            v[i] = P.mu[i] + (cam.R[0 * 3 + i] * cam.t[0] + cam.R[1 * 3 + i] * cam.t[1] + cam.R[2 * 3 + i] * cam.t[2]);
+        const double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        const double iv = vn > 0.0 ? 1.0 / vn : 0.0;
+        double Y[15];
+        sh_eval<double>(a.sh_degree, v[0] * iv, v[1] * iv, v[2] * iv, Y, nullptr);
+        const int nb = sh_count(a.sh_degree);
+        for (int c = 0; c < 3; ++c) {
+            double acc = P.col[c];
+            for (int k = 0; k < nb; ++k) {
+                const double kc = load_param(a.sh, a.dtype, (static_cast<int64_t>(k) * 3 + c) * n + g);
+                fin = fin && isfinite(kc);
+                acc = acc + Y[k] * kc;
+            }
+            P.col[c] = acc;
+        }
+    }
     P.nonfinite = !fin;
     if (!fin || !cam.ok || !in_domain) return false;
     P.qn = sqrt(raw[6] * raw[6] + raw[7] * raw[7] + raw[8] * raw[8] + raw[9] * raw[9]);

@@ -35,7 +35,7 @@ template <typename Tally>
 __device__ __forceinline__ uint32_t project_and_count(const Args& a, int f, int64_t g, const CamD& cam, double t,
                                                       Tally tally) {
     const int64_t i = static_cast<int64_t>(f) * a.n + g;
-    if (f == 0) {
+    if (f == 0 && a.sh_degree == 0) {
         const double eta = load_param(a.opacity_logits, a.dtype, g);
         ColorOp co;
         co.r = static_cast<float>(load_param(a.colors, a.dtype, g));
@@ -46,6 +46,14 @@ __device__ __forceinline__ uint32_t project_and_count(const Args& a, int f, int6
     }
     ProjD P;
     const bool vis = project_gaussian(a, g, cam, t, P);
+    if (vis && a.sh_degree > 0) {
+        ColorOp co;
+        co.r = static_cast<float>(P.col[0]);
+        co.g = static_cast<float>(P.col[1]);
+        co.b = static_cast<float>(P.col[2]);
+        co.o = static_cast<float>(P.o);
+        a.col4[i] = co;
+    }
     if (P.nonfinite) atomicAdd(&a.status[ST_NONFINITE], 1u);
     uint32_t cnt = 0;
     // o < 1/255 can never pass the per-pixel alpha test (alpha <= o).
@@ -204,7 +212,7 @@ __global__ __launch_bounds__(256) void k_export_records(Args a, float* __restric
         o[3] = r.b;
         o[4] = r.c;
         o[5] = r.depth;
-        o[6] = a.col4[g].o;
+        o[6] = a.col4[g].o;  // frame 0
     } else {
         for (int k = 0; k < 7; ++k) o[k] = 0.0f;
     }

@@ -218,7 +218,41 @@ struct AccLayout {
     static constexpr int CUBIC = 14, WIN = 14, SCALE = 26, QUAT = 35;
 };
 
-template <bool DYN>
+// View-dependent colour (SH, Sec. 3.1): given dL/d(colour) of one frame,
+// add Y_k(d) dL/dc to the coefficient accumulators and return, through the
+// unit direction d = v / |v|, v = mu - C, dL/dv (it adds to dL/dmu, and
+// -dL/dv is the gradient of the camera centre C = -Rc^T tc).
+template <int NT>
+__device__ __forceinline__ void sh_adjoint(const Args& a, int64_t g, const AdjIn& P, const float* camC,
+                                           const float dc[3], float (*acc_sh)[NT], int tid, float dv[3]) {
+    const int64_t n = a.n;
+    float v[3];
+    for (int i = 0; i < 3; ++i) v[i] = P.mu[i] - camC[i];
+    const float vn = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const float iv = vn > 0.0f ? 1.0f / vn : 0.0f;
+    const float d[3] = {v[0] * iv, v[1] * iv, v[2] * iv};
+    float Y[15], G[15][3];
+    sh_eval<float>(3, d[0], d[1], d[2], Y, G);  // all degrees (static indexing); unused ones are skipped
+    const int nb = sh_count(a.sh_degree);
+    float dd[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 15; ++k) {  // static indices keep Y and G in registers
+        if (k < nb) {
+            float w = 0.f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                acc_sh[k * 3 + c][tid] += Y[k] * dc[c];
+                w += dc[c] * static_cast<float>(load_param(a.sh, a.dtype, (static_cast<int64_t>(k) * 3 + c) * n + g));
+            }
+#pragma unroll
+            for (int j = 0; j < 3; ++j) dd[j] += w * G[k][j];
+        }
+    }
+    const float dot = d[0] * dd[0] + d[1] * dd[1] + d[2] * dd[2];
+    for (int j = 0; j < 3; ++j) dv[j] = (dd[j] - d[j] * dot) * iv;
+}
+
+template <bool DYN, bool SH>
 __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
     if (overflowed(a.status)) return;
     using LA = AccLayout<DYN>;
@@ -230,8 +264,12 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
     // per-thread gradient accumulators (FP64) live in LDS, see AccLayout
     __shared__ double acc[LA::N][PB_THREADS];
     __shared__ double pacc[12][PB_THREADS];  // this frame's pose contributions (dL/dRc, dL/dtc)
-    __shared__ float camR[9], camT[3];
+    __shared__ float camR[9], camT[3], camC[3];
+    // SH coefficient gradients (FP32: at most a few hundred frames are summed)
+    __shared__ float acc_sh[SH ? 45 : 1][PB_THREADS];
     for (int k = 0; k < LA::N; ++k) acc[k][tid] = 0.0;
+    if (SH)
+        for (int k = 0; k < 3 * sh_count(a.sh_degree); ++k) acc_sh[k][tid] = 0.0f;
     // control-point window: gradients of points win .. win + 3, flushed to
     // memory (added) when a frame falls in another knot span
     int win = -1;
@@ -255,6 +293,10 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
             const CamD c = load_camera(a.poses + 7 * f);
             for (int k = 0; k < 9; ++k) camR[k] = c.ok ? static_cast<float>(c.R[k]) : 0.0f;
             for (int k = 0; k < 3; ++k) camT[k] = c.ok ? static_cast<float>(c.t[k]) : 0.0f;
+            for (int i = 0; i < 3; ++i)
+                camC[i] = c.ok ? static_cast<float>(-(c.R[0 * 3 + i] * c.t[0] + c.R[1 * 3 + i] * c.t[1] +
+                                                     c.R[2 * 3 + i] * c.t[2]))
+                               : 0.0f;
         }
         __syncthreads();
         for (int k = 0; k < 12; ++k) pacc[k][tid] = 0.0;
@@ -278,6 +320,17 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
             adjoint_inputs<DYN>(a, g, rec, camR, camT, t, P);
             float go[14];
             projection_adjoint<PB_THREADS>(a, camR, P, d, go, pacc, tid);
+            if (SH) {
+                float dv[3];
+                const float dc[3] = {go[11], go[12], go[13]};
+                sh_adjoint<PB_THREADS>(a, g, P, camC, dc, acc_sh, tid, dv);
+                for (int j = 0; j < 3; ++j) {
+                    go[j] += dv[j];
+                    // C = -Rc^T tc, dL/dC = -dv: dL/dtc = Rc dv, dL/dRc[j][i] = tc[j] dv[i]
+                    pacc[9 + j][tid] += camR[j * 3 + 0] * dv[0] + camR[j * 3 + 1] * dv[1] + camR[j * 3 + 2] * dv[2];
+                    for (int i = 0; i < 3; ++i) pacc[j * 3 + i][tid] += camT[j] * dv[i];
+                }
+            }
             for (int k = 0; k < 14; ++k) acc[k][tid] += go[k];
             const double t1 = t, t2 = t1 * t1, t3 = t2 * t1;
             if (!DYN && a.mean_coeffs)
@@ -345,6 +398,8 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
     if (DYN && a.quat_coeffs)
         for (int c = 0; c < 3; ++c)
             for (int k = 0; k < 4; ++k) put(a.g_quat_coeffs, (c * 4 + k) * n + g, acc[LA::QUAT + c * 4 + k][tid]);
+    if (SH)
+        for (int k = 0; k < 3 * sh_count(a.sh_degree); ++k) put(a.g_sh, static_cast<int64_t>(k) * n + g, acc_sh[k][tid]);
 }
 
 // Per frame: sum the workgroups' pose partials (each of the 256 threads takes
@@ -384,10 +439,14 @@ int64_t project_bwd_blocks(int64_t n) { return (n + PB_THREADS - 1) / PB_THREADS
 hipError_t launch_project_bwd(const Args& a, hipStream_t stream) {
     const int64_t nb = project_bwd_blocks(a.n);
     const bool dyn = a.n_ctrl > 0 || a.scale_coeffs || a.quat_coeffs;
-    if (nb > 0 && dyn)
-        hipLaunchKernelGGL(k_project_bwd<true>, dim3(static_cast<uint32_t>(nb)), dim3(PB_THREADS), 0, stream, a);
-    else if (nb > 0)
-        hipLaunchKernelGGL(k_project_bwd<false>, dim3(static_cast<uint32_t>(nb)), dim3(PB_THREADS), 0, stream, a);
+    const bool sh = a.sh_degree > 0;
+    const dim3 grid(static_cast<uint32_t>(nb > 0 ? nb : 1)), block(PB_THREADS);
+    if (nb > 0) {
+        if (dyn && sh) hipLaunchKernelGGL((k_project_bwd<true, true>), grid, block, 0, stream, a);
+        else if (dyn) hipLaunchKernelGGL((k_project_bwd<true, false>), grid, block, 0, stream, a);
+        else if (sh) hipLaunchKernelGGL((k_project_bwd<false, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((k_project_bwd<false, false>), grid, block, 0, stream, a);
+    }
     if (a.g_poses)
         hipLaunchKernelGGL(k_pose_finalize, dim3(static_cast<uint32_t>(a.frames)), dim3(256), 0, stream, a, nb);
     return hipGetLastError();

@@ -73,17 +73,20 @@ class Scene:
 
     FIELDS = ("means", "log_scales", "quats", "opacity_logits", "colors")
     ROWS = dict(means=3, log_scales=3, quats=4, opacity_logits=None, colors=3)
-    OPTIONAL = ("mean_coeffs", "ctrl", "scale_coeffs", "quat_coeffs")
+    OPTIONAL = ("mean_coeffs", "ctrl", "scale_coeffs", "quat_coeffs", "sh")
+    SH_DEGREE = {3: 1, 8: 2, 15: 3}
 
     def __init__(self, means, log_scales, quats, opacity_logits, colors, mean_coeffs=None, ctrl=None,
-                 scale_coeffs=None, quat_coeffs=None):
+                 scale_coeffs=None, quat_coeffs=None, sh=None):
         """Time dependence (Sec. 3.2, Eq. 2-3), all optional: ``mean_coeffs``
         [3][3][N] cubic mean; ``ctrl`` [M][3][N] B-spline control points (then
         ``means`` is not read); ``scale_coeffs`` [3][3][N] and ``quat_coeffs``
-        [3][4][N] cubic log-scales and quaternion."""
+        [3][4][N] cubic log-scales and quaternion.  View-dependent colour
+        (Sec. 3.1): ``sh`` [(D+1)^2-1][3][N], SH coefficients of degrees 1..D
+        (``colors`` is the degree-0 term)."""
         self.means, self.log_scales, self.quats = means, log_scales, quats
         self.opacity_logits, self.colors, self.mean_coeffs = opacity_logits, colors, mean_coeffs
-        self.ctrl, self.scale_coeffs, self.quat_coeffs = ctrl, scale_coeffs, quat_coeffs
+        self.ctrl, self.scale_coeffs, self.quat_coeffs, self.sh = ctrl, scale_coeffs, quat_coeffs, sh
         dt = log_scales.dtype
         if dt not in (torch.float32, torch.bfloat16):
             raise ValueError("parameters must be float32 or bfloat16")
@@ -105,6 +108,12 @@ class Scene:
             _need(scale_coeffs, (3, 3, n), dt, "scale_coeffs")
         if quat_coeffs is not None:
             _need(quat_coeffs, (3, 4, n), dt, "quat_coeffs")
+        self.sh_degree = 0
+        if sh is not None:
+            if sh.dim() != 3 or int(sh.shape[0]) not in self.SH_DEGREE:
+                raise ValueError("sh must be [(D+1)^2-1][3][N] with D in 1..3")
+            _need(sh, (sh.shape[0], 3, n), dt, "sh")
+            self.sh_degree = self.SH_DEGREE[int(sh.shape[0])]
         self.dtype = L.GV_BF16 if dt == torch.bfloat16 else L.GV_F32
         self.n = int(n)
 
@@ -127,7 +136,7 @@ class Scene:
             return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
         return cls(t(s.means), t(s.log_scales), t(s.quats), t(s.opacity_logits), t(s.colors), t(s.mean_coeffs),
                    t(getattr(s, "ctrl", None)), t(getattr(s, "scale_coeffs", None)),
-                   t(getattr(s, "quat_coeffs", None)))
+                   t(getattr(s, "quat_coeffs", None)), t(getattr(s, "sh", None)))
 
     def c(self) -> L.GvScene:
         g = L.GvScene()
@@ -138,6 +147,7 @@ class Scene:
         g.mean_coeffs = ptr(self.mean_coeffs)
         g.n_ctrl, g.ctrl = self.n_ctrl, ptr(self.ctrl)
         g.scale_coeffs, g.quat_coeffs = ptr(self.scale_coeffs), ptr(self.quat_coeffs)
+        g.sh_degree, g.sh = self.sh_degree, ptr(self.sh)
         return g
 
 
@@ -412,26 +422,27 @@ class RasterizeFrame(torch.autograd.Function):
 
 class RasterizeClip(torch.autograd.Function):
     """images [F][3][H][W] of a clip with per-frame poses; gradients of the
-    shared parameters are summed over frames, pose gradients are per frame."""
+    shared parameters are summed over frames, pose gradients are per frame.
+    mean_coeffs (cubic means) and sh (view-dependent colour) may be None."""
 
     @staticmethod
-    def forward(ctx, means, log_scales, quats, opacity_logits, colors, mean_coeffs, poses, times, camera, ws):
-        scene = Scene(means, log_scales, quats, opacity_logits, colors, mean_coeffs)
+    def forward(ctx, means, log_scales, quats, opacity_logits, colors, mean_coeffs, sh, poses, times, camera, ws):
+        scene = Scene(means, log_scales, quats, opacity_logits, colors, mean_coeffs, sh=sh)
         out = render_batch(scene, camera, poses, times, ws, forward=True, backward=False)
-        ctx.save_for_backward(means, log_scales, quats, opacity_logits, colors, mean_coeffs, poses, times,
+        ctx.save_for_backward(means, log_scales, quats, opacity_logits, colors, mean_coeffs, sh, poses, times,
                               out["images"])
         ctx.camera, ctx.ws = camera, ws
         return out["images"]
 
     @staticmethod
     def backward(ctx, dimages):
-        means, log_scales, quats, opacity_logits, colors, mean_coeffs, poses, times, images = ctx.saved_tensors
-        scene = Scene(means, log_scales, quats, opacity_logits, colors, mean_coeffs)
+        means, log_scales, quats, opacity_logits, colors, mean_coeffs, sh, poses, times, images = ctx.saved_tensors
+        scene = Scene(means, log_scales, quats, opacity_logits, colors, mean_coeffs, sh=sh)
         out = render_batch(scene, ctx.camera, poses, times, ctx.ws, dL_dimages=dimages.contiguous(), forward=False,
                            backward=True, images=images)
         g = out["grads"]
         return (g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["colors"], g["mean_coeffs"],
-                out["dL_dposes"], None, None, None)
+                g["sh"], out["dL_dposes"], None, None, None)
 
 
 class RasterizeDynamicClip(torch.autograd.Function):

@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 def test_status_strings_and_version():
     lib = L.load()
-    assert lib.gv_abi_version() == 2
+    assert lib.gv_abi_version() == 3
     for s in range(6):
         assert lib.gv_status_str(s)
     assert lib.gv_status_str(L.GV_ERR_CAPACITY) == b"intersection capacity exceeded"
@@ -127,7 +127,7 @@ def test_tuning_table_validation():
 
 
 def test_dynamic_scene_validation():
-    """B-spline / polynomial scene fields are checked before anything is
+    """B-spline / polynomial / SH scene fields are checked before anything is
     enqueued (no GPU needed: the calls fail on the host)."""
     lib = L.load()
     cam = L.GvCamera(64, 48, 64.0, 64.0, 32.0, 24.0, 0.01, 0.3)
@@ -145,13 +145,15 @@ def test_dynamic_scene_validation():
 
     pose = fake
     bad = [scene(n_ctrl=3, ctrl=fake), scene(n_ctrl=L.GV_MAX_CTRL + 1, ctrl=fake), scene(n_ctrl=5, ctrl=None),
-           scene(n_ctrl=0, ctrl=fake), scene(n_ctrl=5, ctrl=fake, mean_coeffs=fake)]
+           scene(n_ctrl=0, ctrl=fake), scene(n_ctrl=5, ctrl=fake, mean_coeffs=fake),
+           scene(sh_degree=4, sh=fake), scene(sh_degree=2, sh=None), scene(sh_degree=0, sh=fake),
+           scene(sh_degree=-1, sh=fake)]
     for s in bad:
         st = lib.gv_project_fwd(ctypes.byref(s), ctypes.byref(cam), pose, 0.0, fake, fake, None, 0, None)
         assert st == L.GV_ERR_INVALID_ARG
     # a well-formed dynamic scene passes validation and stops at the missing workspace
     good = [scene(n_ctrl=5, ctrl=fake, means=None), scene(n_ctrl=4, ctrl=fake, scale_coeffs=fake, quat_coeffs=fake),
-            scene(scale_coeffs=fake)]
+            scene(scale_coeffs=fake), scene(sh_degree=3, sh=fake), scene(sh_degree=1, sh=fake, n_ctrl=6, ctrl=fake)]
     for s in good:
         st = lib.gv_project_fwd(ctypes.byref(s), ctypes.byref(cam), pose, 0.0, fake, fake, None, 0, None)
         assert st == L.GV_ERR_WORKSPACE
