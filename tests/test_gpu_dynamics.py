@@ -34,6 +34,7 @@ def test_dynamic_projection_depth_keys_bit_exact():
     scene, cam, _, _ = device_inputs(w)
     ws = raster.Workspace(cam, scene.n, 1, 0)
     for t in (0.0, 0.25, 0.37, 0.75, 1.0):
+        t = float(np.float32(t))  # the C ABI takes the frame time as a float: give the oracle the same value
         rec, cnt = raster.project_fwd(scene, cam, torch.from_numpy(pose).cuda(), t, ws)
         rec, cnt = rec.cpu().numpy(), cnt.cpu().numpy()
         ref = oracle.project(w["scene"], w["camera"], pose.astype(np.float64), t)
