@@ -342,11 +342,14 @@ struct ProjD {
 };
 
 // Returns true if the Gaussian is in front of the near plane with a valid
-// footprint.  P.nonfinite marks non-finite inputs.
+// footprint.  P.nonfinite marks non-finite inputs.  EXT compiles in the
+// optional B-spline / polynomial dynamics and the SH colour (the static
+// instantiation keeps the register budget of the common case).
+template <bool EXT>
 __device__ __forceinline__ bool project_gaussian(const Args& a, int64_t g, const CamD& cam, double t, ProjD& P) {
     const int64_t n = a.n;
     double raw[14];
-    for (int k = 0; k < 3; ++k) raw[k] = a.n_ctrl > 0 ? 0.0 : load_param(a.means, a.dtype, k * n + g);
+    for (int k = 0; k < 3; ++k) raw[k] = EXT && a.n_ctrl > 0 ? 0.0 : load_param(a.means, a.dtype, k * n + g);
     for (int k = 0; k < 3; ++k) raw[3 + k] = load_param(a.log_scales, a.dtype, k * n + g);
     for (int k = 0; k < 4; ++k) raw[6 + k] = load_param(a.quats, a.dtype, k * n + g);
     raw[10] = load_param(a.opacity_logits, a.dtype, g);
@@ -354,7 +357,7 @@ __device__ __forceinline__ bool project_gaussian(const Args& a, int64_t g, const
     bool fin = true;
     for (int k = 0; k < 14; ++k) fin = fin && isfinite(raw[k]);
     bool in_domain = true;
-    if (a.n_ctrl > 0) {
+    if (EXT && a.n_ctrl > 0) {
         // B-spline mean (Eq. 2): sum over the span's four control points in
         // index order (the other basis functions are exact zeros)
         in_domain = t >= 0.0 && t <= 1.0;
@@ -384,7 +387,7 @@ __device__ __forceinline__ bool project_gaussian(const Args& a, int64_t g, const
             P.mu[k] = mu;
         }
     }
-    if (a.scale_coeffs)
+    if (EXT && a.scale_coeffs)
         for (int k = 0; k < 3; ++k) {
             const double b1 = load_param(a.scale_coeffs, a.dtype, (0 * 3 + k) * n + g);
             const double b2 = load_param(a.scale_coeffs, a.dtype, (1 * 3 + k) * n + g);
@@ -392,7 +395,7 @@ __device__ __forceinline__ bool project_gaussian(const Args& a, int64_t g, const
             fin = fin && isfinite(b1) && isfinite(b2) && isfinite(b3);
             raw[3 + k] = raw[3 + k] + b1 * t + b2 * t * t + b3 * t * t * t;
         }
-    if (a.quat_coeffs)
+    if (EXT && a.quat_coeffs)
         for (int k = 0; k < 4; ++k) {
             const double r1 = load_param(a.quat_coeffs, a.dtype, (0 * 4 + k) * n + g);
             const double r2 = load_param(a.quat_coeffs, a.dtype, (1 * 4 + k) * n + g);
@@ -401,7 +404,7 @@ __device__ __forceinline__ bool project_gaussian(const Args& a, int64_t g, const
             raw[6 + k] = raw[6 + k] + r1 * t + r2 * t * t + r3 * t * t * t;
         }
     for (int c = 0; c < 3; ++c) P.col[c] = raw[11 + c];
-    if (a.sh_degree > 0) {
+    if (EXT && a.sh_degree > 0) {
         // view-dependent colour: SH at the unit direction camera centre -> mean
         double v[3];
         for (int i = 0; i < 3; ++i)

@@ -31,7 +31,7 @@ __device__ __forceinline__ bool tile_span(double lo, double hi, int n_tiles, int
 // tally(tile) for every 16x16 tile whose pixel-centre box meets its 3-sigma
 // ellipse (exact ellipse-box test).  Returns the number of such tiles.  Frame
 // 0 also writes the per-Gaussian colour/opacity table shared by all frames.
-template <typename Tally>
+template <bool EXT, typename Tally>
 __device__ __forceinline__ uint32_t project_and_count(const Args& a, int f, int64_t g, const CamD& cam, double t,
                                                       Tally tally) {
     const int64_t i = static_cast<int64_t>(f) * a.n + g;
@@ -45,8 +45,8 @@ __device__ __forceinline__ uint32_t project_and_count(const Args& a, int f, int6
         a.col4[g] = co;
     }
     ProjD P;
-    const bool vis = project_gaussian(a, g, cam, t, P);
-    if (vis && a.sh_degree > 0) {
+    const bool vis = project_gaussian<EXT>(a, g, cam, t, P);
+    if (EXT && vis && a.sh_degree > 0) {
         ColorOp co;
         co.r = static_cast<float>(P.col[0]);
         co.g = static_cast<float>(P.col[1]);
@@ -130,6 +130,7 @@ __device__ __forceinline__ void scatter_one(const Args& a, int f, int64_t g, Nex
 // projects BIN_GROUP Gaussians of one frame, counts their intersections per
 // tile with LDS atomics, stores its histogram and adds it to the frame's tile
 // counts with one global atomic per non-empty tile.
+template <bool EXT>
 __global__ __launch_bounds__(256) void k_project_lds(Args a) {
     extern __shared__ uint32_t hist[];
     const int f = blockIdx.y;
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(256) void k_project_lds(Args a) {
 #pragma unroll 1
     for (int k = 0; k < BIN_GROUP / 256; ++k) {
         const int64_t g = g0 + k * 256 + threadIdx.x;
-        if (g < a.n) project_and_count(a, f, g, cam, tt, [&](int tl) { atomicAdd(&hist[tl], 1u); });
+        if (g < a.n) project_and_count<EXT>(a, f, g, cam, tt, [&](int tl) { atomicAdd(&hist[tl], 1u); });
     }
     __syncthreads();
     uint32_t* bh = a.bhist + (static_cast<int64_t>(f) * a.bin_blocks + blockIdx.x) * a.tiles;
@@ -177,6 +178,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
 
 // Fallback for tile grids too large for an LDS histogram: global atomics per
 // intersection.
+template <bool EXT>
 __global__ __launch_bounds__(256) void k_project(Args a) {
     const int f = blockIdx.y;
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(256) void k_project(Args a) {
     const CamD cam = load_camera(a.poses + 7 * f);
     const double t = a.times ? static_cast<double>(a.times[f]) : static_cast<double>(a.t0);
     uint32_t* tc = a.tcnt + static_cast<int64_t>(f) * a.tiles;
-    project_and_count(a, f, g, cam, t, [&](int tl) { atomicAdd(&tc[tl], 1u); });
+    project_and_count<EXT>(a, f, g, cam, t, [&](int tl) { atomicAdd(&tc[tl], 1u); });
 }
 
 __global__ __launch_bounds__(256) void k_scatter(Args a) {
@@ -237,12 +239,17 @@ int64_t bin_blocks(int64_t n) { return (n + BIN_GROUP - 1) / BIN_GROUP; }
 
 hipError_t launch_project(const Args& a, hipStream_t stream) {
     if (a.n <= 0) return hipSuccess;
+    const bool ext = a.n_ctrl > 0 || a.scale_coeffs || a.quat_coeffs || a.sh_degree > 0;
+    const dim3 block(256);
     if (a.bhist) {
-        hipLaunchKernelGGL(k_project_lds, dim3(static_cast<uint32_t>(a.bin_blocks), a.frames), dim3(256),
-                           sizeof(uint32_t) * a.tiles, stream, a);
+        const dim3 grid(static_cast<uint32_t>(a.bin_blocks), a.frames);
+        const size_t lds = sizeof(uint32_t) * a.tiles;
+        if (ext) hipLaunchKernelGGL(k_project_lds<true>, grid, block, lds, stream, a);
+        else hipLaunchKernelGGL(k_project_lds<false>, grid, block, lds, stream, a);
     } else {
-        hipLaunchKernelGGL(k_project, dim3(static_cast<uint32_t>((a.n + 255) / 256), a.frames), dim3(256), 0, stream,
-                           a);
+        const dim3 grid(static_cast<uint32_t>((a.n + 255) / 256), a.frames);
+        if (ext) hipLaunchKernelGGL(k_project<true>, grid, block, 0, stream, a);
+        else hipLaunchKernelGGL(k_project<false>, grid, block, 0, stream, a);
     }
     return hipGetLastError();
 }

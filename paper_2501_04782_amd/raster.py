@@ -329,7 +329,7 @@ def autotune(scene: Scene, camera: Camera, poses: torch.Tensor, times: Optional[
     L.check(L.load().gv_autotune(args[0], args[1], args[2], args[3], args[4], args[5], args[8], args[9], args[10],
                                  args[11], args[12], args[13], None if cache_path is None else cache_path.encode(),
                                  ctypes.byref(t)), "gv_autotune")
-    return dict(batch=int(t.batch), sort_cap=int(t.sort_cap), compact=int(t.compact))
+    return dict(batch=int(t.batch), sort_cap=int(t.sort_cap), compact=int(t.compact), bwd_batch=int(t.bwd_batch))
 
 
 def get_tuning() -> dict:
