@@ -42,12 +42,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(N, V, K, P, F):
+def algorithmic_bytes(N, V, K, P, F, p=PARAM_BYTES, pg=PARAM_BYTES):
     """Compulsory HBM bytes of one fwd+bwd step over F frames (each input read
-    once, each output written once).  Per frame: forward N*56 + V*40 + K*64 +
-    P*20; backward P*20 + K*112 + N*(56+56)."""
-    per_frame_fwd = N * PARAM_BYTES + V * 40 + (K / F) * 64 + P * 20
-    per_frame_bwd = P * 20 + (K / F) * 112 + N * (PARAM_BYTES + 56)
+    once, each output written once), with p stored parameter bytes and pg FP32
+    gradient bytes per Gaussian (56 and 56 for the static fp32 scene).  Per
+    frame: forward N*p + V*40 + K*64 + P*20; backward P*20 + K*112 + N*(p + pg)."""
+    per_frame_fwd = N * p + V * 40 + (K / F) * 64 + P * 20
+    per_frame_bwd = P * 20 + (K / F) * 112 + N * (p + pg)
     return F * (per_frame_fwd + per_frame_bwd)
 
 
@@ -130,6 +131,10 @@ def main():
     times = torch.from_numpy(w["times"]).to(dev)
     targets = torch.from_numpy(w["targets"]).to(dev)
     dtype_name = "bf16-params/f32" if w["scene"].dtype == "bf16" else "f32"
+    # stored parameter bytes per Gaussian (static fields plus any dynamics / SH coefficients)
+    read_fields = [k for k in w["scene"].fields() if not (k == "means" and w["scene"].ctrl is not None)]
+    param_bytes = sum(getattr(w["scene"], k).nbytes for k in read_fields) / N
+    grad_bytes = 4 * sum(getattr(w["scene"], k).size for k in read_fields) / N
 
     # capacity from the exact tile counts of three frames, and visible counts
     ws1 = raster.Workspace(cam, N, 1, 0, device=dev)
@@ -273,10 +278,9 @@ def main():
     dom = max(stage_ms, key=stage_ms.get)
     t_dom = stage_ms[dom] / 1e3
     from paper_2501_04782_amd import rocprof_summary
-    tun_s = f"{tuning['batch']},{tuning['sort_cap']},{tuning['compact']},{tuning['bwd_batch']}"
+    key = rocprof_summary.stage_key(dom, tuning)
     traffic = rocprof_summary.read_traffic(
-        os.path.join(ROOT, "profiles", f"{dom}_{args.workload}_{tun_s.replace(',', '-')}_hbm_traffic.txt"),
-        dom, args.workload, tun_s)
+        os.path.join(ROOT, "profiles", f"{dom}_{args.workload}_{key}_hbm_traffic.txt"), dom, args.workload, key)
     bytes_dom = stage_bytes(dom, N, V, K, P, F)
     hbm_ach = bytes_dom / t_dom if bytes_dom else 0.0
     roof = dict(bound="hbm", achieved=round(hbm_ach / 1e9, 2), peak=HBM_PEAK / 1e9, unit="GB/s",
@@ -291,7 +295,7 @@ def main():
                         unit="TFLOP/s", frac=round(alu_ach / ALU_PEAK, 4), traffic=traffic, kernel=dom,
                         avg_ms=round(stage_ms[dom], 4), contributing_pairs=int(pairs),
                         hbm_frac=round(hbm_ach / HBM_PEAK, 4))
-    b_alg = algorithmic_bytes(N, V, K, P, F)
+    b_alg = algorithmic_bytes(N, V, K, P, F, param_bytes, grad_bytes)
     step_hbm_frac = b_alg / (ms_step / 1e3) / HBM_PEAK
 
     line = {

@@ -123,6 +123,17 @@ def cmd_traffic(a):
     print("```")
 
 
+def stage_key(stage: str, tuning: dict) -> str:
+    """The part of the tuning that changes a stage's kernel (file-name safe)."""
+    if stage == "composite_fwd":
+        return f"b{tuning['batch']}-c{tuning['compact'] & 1}"
+    if stage == "composite_bwd":
+        return f"b{tuning['bwd_batch']}-c{(tuning['compact'] >> 1) & 1}"
+    if stage == "sort":
+        return f"cap{tuning['sort_cap']}"
+    return "any"
+
+
 def read_traffic(path: str, stage: str, workload: str, tuning: str):
     """Scaled HBM bytes per launch from a traffic summary, or None when the
     file is absent or was taken from other sources, tuning or workload."""
@@ -159,7 +170,7 @@ def main():
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--stage", required=True, choices=sorted(STAGE_SOURCES))
     t.add_argument("--workload", required=True)
-    t.add_argument("--tuning", required=True)
+    t.add_argument("--tuning", required=True, help="the stage key (stage_key) the counters were taken with")
     t.add_argument("--command", required=True)
     a = ap.parse_args()
     cmd_stats(a) if a.cmd == "stats" else cmd_traffic(a)
