@@ -47,7 +47,7 @@ class _Frame(ctypes.Structure):
 class _Grads(ctypes.Structure):
     _fields_ = [("means", _dp), ("log_scales", _dp), ("quats", _dp), ("opacity_logits", _dp),
                 ("colors", _dp), ("mean_coeffs", _dp), ("pose", _dp),
-                ("ctrl", _dp), ("scale_coeffs", _dp), ("quat_coeffs", _dp), ("sh", _dp)]
+                ("ctrl", _dp), ("scale_coeffs", _dp), ("quat_coeffs", _dp), ("sh", _dp), ("intrinsics", _dp)]
 
 OPTIONAL = ("mean_coeffs", "ctrl", "scale_coeffs", "quat_coeffs", "sh")
 
@@ -69,7 +69,7 @@ def _load():
         lib.gvo_sh_basis.argtypes = [ctypes.c_int32, _dp, _dp, _dp]
         lib.gvo_sh_basis.restype = ctypes.c_int
         lib.gvo_abi_version.restype = ctypes.c_int
-        if lib.gvo_abi_version() != 3:
+        if lib.gvo_abi_version() != 4:
             raise RuntimeError("liboracle.so is stale: rebuild it (python -m oracle.build)")
         _lib = lib
     return _lib
@@ -164,7 +164,7 @@ def zero_grads(scene) -> dict:
     s = scene_f64(scene)
     n = s["opacity_logits"].shape[0]
     g = dict(means=np.zeros((3, n)), log_scales=np.zeros((3, n)), quats=np.zeros((4, n)),
-             opacity_logits=np.zeros(n), colors=np.zeros((3, n)), pose=np.zeros(7))
+             opacity_logits=np.zeros(n), colors=np.zeros((3, n)), pose=np.zeros(7), intrinsics=np.zeros(4))
     for k in OPTIONAL:
         g[k] = None if s[k] is None else np.zeros_like(s[k])
     return g
@@ -202,7 +202,7 @@ def render_frame(scene, cam, pose7, t: float = 0.0, pixels: Optional[np.ndarray]
         gstruct = _Grads(_ptr(grads["means"]), _ptr(grads["log_scales"]), _ptr(grads["quats"]),
                          _ptr(grads["opacity_logits"]), _ptr(grads["colors"]), _ptr(grads.get("mean_coeffs")),
                          _ptr(grads["pose"]), _ptr(grads.get("ctrl")), _ptr(grads.get("scale_coeffs")),
-                         _ptr(grads.get("quat_coeffs")), _ptr(grads.get("sh")))
+                         _ptr(grads.get("quat_coeffs")), _ptr(grads.get("sh")), _ptr(grads.get("intrinsics")))
     rc = _load().gvo_render(ctypes.byref(fr), npx, pix_p, _ptr(color), _ptr(T), nc.ctypes.data_as(_i64p),
                             _ptr(mg), _ptr(dl), ctypes.byref(gstruct) if gstruct is not None else None,
                             int(threads))

@@ -46,8 +46,9 @@
  * stop decisions and the alpha clamp are piecewise constants (their
  * derivative is zero).  Gradients are with respect to the stored parameters:
  * means (or mu0 and a1..a3, or the control points), log-scales (and b1..b3),
- * unnormalised quaternions (and r1..r3), opacity logits, colours, and the
- * 7-vector pose (qc unnormalised, tc).
+ * unnormalised quaternions (and r1..r3), opacity logits, colours (and SH
+ * coefficients), the 7-vector pose (qc unnormalised, tc) and the intrinsics
+ * (fx, fy, cx, cy).
  *
  * Per pixel the oracle also reports how close each discrete decision came to
  * its threshold (relative margins), so that comparisons against an FP32
@@ -85,6 +86,7 @@ typedef struct {
 typedef struct {
     double *means, *log_scales, *quats, *opacity_logits, *colors, *mean_coeffs, *pose;
     double *ctrl, *scale_coeffs, *quat_coeffs, *sh;
+    double *intrinsics;           /* NULL or [4]: fx, fy, cx, cy (shared by all frames, Sec. 3.4) */
 } gvo_grads;
 
 typedef struct {
@@ -573,6 +575,14 @@ static void project_adjoint(const gvo_frame *fr, const cam_t *c, int64_t g, cons
     /* J(m) and (u, v)(m) */
     double mx = P->m[0], my = P->m[1], mz = P->m[2];
     double fx = fr->fx, fy = fr->fy;
+    /* intrinsics: u = fx mx/mz + cx, v = fy my/mz + cy, J00 = fx/mz,
+     * J02 = -fx mx/mz^2, J11 = fy/mz, J12 = -fy my/mz^2 */
+    if (gr->intrinsics) {
+        gr->intrinsics[0] += d[0] * mx / mz + dJ[0][0] / mz - dJ[0][2] * mx / (mz * mz);
+        gr->intrinsics[1] += d[1] * my / mz + dJ[1][1] / mz - dJ[1][2] * my / (mz * mz);
+        gr->intrinsics[2] += d[0];
+        gr->intrinsics[3] += d[1];
+    }
     double dm[3];
     dm[0] = dJ[0][2] * (-fx / (mz * mz)) + d[0] * fx / mz;
     dm[1] = dJ[1][2] * (-fy / (mz * mz)) + d[1] * fy / mz;
@@ -789,4 +799,4 @@ int gvo_render(const gvo_frame *fr, int64_t n_pix, const int64_t *pix, double *c
     return err;
 }
 
-int gvo_abi_version(void) { return 3; }
+int gvo_abi_version(void) { return 4; }

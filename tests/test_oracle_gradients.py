@@ -7,6 +7,8 @@ Pixels whose discrete decisions sit within 1e-3 (relative) of a threshold get
 zero upstream gradient, so no finite-difference step can flip a decision that
 matters.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -68,6 +70,13 @@ def test_adjoint_matches_central_differences(cubic):
         pm[k] -= h
         fd = (loss(s, cam, pp, t, dl) - loss(s, cam, pm, t, dl)) / (2 * h)
         assert g["pose"][k] == pytest.approx(fd, rel=2e-5, abs=1e-6), ("pose", k)
+    for k, name in enumerate(("fx", "fy", "cx", "cy")):
+        h = 1e-5 * max(1.0, abs(getattr(cam, name)))
+        cp, cm = dataclasses.replace(cam), dataclasses.replace(cam)
+        setattr(cp, name, getattr(cam, name) + h)
+        setattr(cm, name, getattr(cam, name) - h)
+        fd = (loss(s, cp, pose, t, dl) - loss(s, cm, pose, t, dl)) / (2 * h)
+        assert g["intrinsics"][k] == pytest.approx(fd, rel=2e-5, abs=1e-7), ("intrinsics", name)
 
 
 # ---------------------------------------------------------------------------
@@ -97,11 +106,15 @@ def torch_render(P, cam, t):
     Rc = _rot(pq)
     m = Rc @ mu + P["pose"][4:, None]                               # [3][N]
     zinv = 1.0 / m[2]
-    u = cam.fx * m[0] * zinv + cam.cx
-    v = cam.fy * m[1] * zinv + cam.cy
+    if "intrinsics" in P:
+        fx, fy, cx, cy = P["intrinsics"][0], P["intrinsics"][1], P["intrinsics"][2], P["intrinsics"][3]
+    else:
+        fx, fy, cx, cy = cam.fx, cam.fy, cam.cx, cam.cy
+    u = fx * m[0] * zinv + cx
+    v = fy * m[1] * zinv + cy
     zero = torch.zeros_like(zinv)
-    J = torch.stack([torch.stack([cam.fx * zinv, zero, -cam.fx * m[0] * zinv ** 2]),
-                     torch.stack([zero, cam.fy * zinv, -cam.fy * m[1] * zinv ** 2])]).permute(2, 0, 1)
+    J = torch.stack([torch.stack([fx * zinv, zero, -fx * m[0] * zinv ** 2]),
+                     torch.stack([zero, fy * zinv, -fy * m[1] * zinv ** 2])]).permute(2, 0, 1)
     Tm = J @ Rc
     cov = Tm @ Sig @ Tm.transpose(1, 2) + cam.dilation * torch.eye(2, dtype=torch.float64)
     inv = torch.linalg.inv(cov)
@@ -138,6 +151,7 @@ def test_adjoint_matches_torch_autograd(seed, cubic):
     if cubic:
         P["mean_coeffs"] = torch.tensor(s["mean_coeffs"], dtype=torch.float64, requires_grad=True)
     P["pose"] = torch.tensor(pose, dtype=torch.float64, requires_grad=True)
+    P["intrinsics"] = torch.tensor([cam.fx, cam.fy, cam.cx, cam.cy], dtype=torch.float64, requires_grad=True)
     img = torch_render(P, cam, t)
     ref = oracle.render_frame(s, cam, pose, t)["color"]
     np.testing.assert_allclose(img.detach().numpy(), ref, atol=1e-12)
