@@ -568,11 +568,13 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
     gv_status result = (he == hipSuccess) ? GV_OK : hip_status(he);
     // The stages are independent (the forward's outputs do not depend on its
     // kernel variant), so every stage keeps its own fastest setting: six runs
-    // cover the forward and backward kernels (batch x quadrant / compacted)
-    // and each sort capacity twice.
+    // cover the forward kernel (batch x quadrant / compacted), the quadrant
+    // backward (batch) and each sort capacity twice.  The compacted backward
+    // (LDS atomics per lane) measured ten times slower than the quadrant
+    // backward on every clip tried, so it is left to explicit gv_set_tuning.
     struct Cand { int batch, compact, cap; };
     const Cand cands[6] = {{64, 0, 1024}, {128, 0, 2048}, {256, 0, 4096},
-                           {64, 3, 2048}, {128, 3, 4096}, {256, 3, 1024}};
+                           {64, 1, 2048}, {128, 1, 4096}, {256, 1, 1024}};
     float fwd_ms[6], bwd_ms[6], sort_ms[6], total_ms[6];
     constexpr int REPS = 2;
     for (int c = 0; c < 6 && result == GV_OK; ++c) {
