@@ -129,6 +129,7 @@ typedef struct {
     float *scale_coeffs;
     float *quat_coeffs;
     float *sh;
+    float *intrinsics;  /* [4]: dL/d(fx, fy, cx, cy), shared by all frames (Sec. 3.4) */
 } gv_grads;
 
 /* Flags for gv_render_batch / gv_render_bwd. */
@@ -283,10 +284,31 @@ gv_status gv_autotune(const gv_scene *scene, const gv_camera *cam, const float *
  * low/high 32 bits of the intersection count of the last projection. */
 gv_status gv_device_status(const void *ws, uint32_t out[4]);
 
+/* Fused Adan step (Sec. 4.1 trains with Adan: learning rate 0.01, decayed
+ * by 0.99995 per step; the schedule is the caller's, who passes this step's
+ * lr).  Per element, with g the gradient and (m, v, n, g_prev) the state:
+ *   step 0:  m = g, v = 0, n = g^2
+ *   step k:  m = (1-b1) m + b1 g;  v = (1-b2) v + b2 (g - g_prev) (step 1:
+ *            v = g - g_prev);  n = (1-b3) n + b3 (g + (1-b2)(g - g_prev))^2
+ *   theta = (theta - lr / sqrt(n + eps) * (m + (1-b2) v)) / (1 + wd * lr)
+ * and g_prev = g.  Up to GV_ADAN_MAX_TENSORS tensors in one launch: the
+ * pointer and count arrays are HOST arrays of n_tensors entries; params[t]
+ * (FP32, updated in place), grads[t] (FP32) and states[t] ([4][counts[t]]
+ * FP32, contents ignored at step 0) are device arrays.  Enqueued on `stream`;
+ * GV_ERR_INVALID_ARG for a bad count, pointer or hyper-parameter. */
+#define GV_ADAN_MAX_TENSORS 16
+typedef struct {
+    float lr, beta1, beta2, beta3, eps, weight_decay;
+    int32_t step;     /* 0-based iteration */
+    int32_t reserved;
+} gv_adan_params;
+gv_status gv_adan_step(int32_t n_tensors, float *const *params, const float *const *grads, float *const *states,
+                       const int64_t *counts, const gv_adan_params *hp, void *stream);
+
 const char *gv_status_str(gv_status s);
 int32_t gv_last_hip_error(void);
-/* Version of this interface: 3 (2: B-spline / polynomial dynamics and
- * bwd_batch; 3: spherical-harmonics colour). */
+/* Version of this interface: 4 (2: B-spline / polynomial dynamics and
+ * bwd_batch; 3: spherical-harmonics colour; 4: intrinsics gradient, Adan). */
 int32_t gv_abi_version(void);
 
 #ifdef __cplusplus

@@ -27,9 +27,10 @@ class GvCamera(ctypes.Structure):
                 ("cy", c_float), ("near_plane", c_float), ("dilation", c_float), ("bg", c_float * 3)]
 
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 GV_MAX_CTRL = 64
 GV_MAX_SH_DEGREE = 3
+GV_ADAN_MAX_TENSORS = 16
 
 
 class GvScene(ctypes.Structure):
@@ -42,12 +43,17 @@ class GvScene(ctypes.Structure):
 class GvGrads(ctypes.Structure):
     _fields_ = [("means", c_void_p), ("log_scales", c_void_p), ("quats", c_void_p), ("opacity_logits", c_void_p),
                 ("colors", c_void_p), ("mean_coeffs", c_void_p), ("ctrl", c_void_p), ("scale_coeffs", c_void_p),
-                ("quat_coeffs", c_void_p), ("sh", c_void_p)]
+                ("quat_coeffs", c_void_p), ("sh", c_void_p), ("intrinsics", c_void_p)]
 
 
 class GvTuning(ctypes.Structure):
     _fields_ = [("batch", c_int32), ("sort_cap", c_int32), ("compact", c_int32), ("bwd_batch", c_int32),
                 ("reserved", c_int32 * 4)]
+
+
+class GvAdanParams(ctypes.Structure):
+    _fields_ = [("lr", c_float), ("beta1", c_float), ("beta2", c_float), ("beta3", c_float), ("eps", c_float),
+                ("weight_decay", c_float), ("step", c_int32), ("reserved", c_int32)]
 
 
 class GvError(RuntimeError):
@@ -98,6 +104,8 @@ _SIGS = [
                               c_void_p, c_void_p, c_void_p, ctypes.POINTER(GvGrads), c_void_p, c_void_p, c_size_t,
                               ctypes.c_char_p, ctypes.POINTER(GvTuning)]),
     ("gv_device_status", c_int32, [c_void_p, ctypes.POINTER(c_uint32)]),
+    ("gv_adan_step", c_int32, [c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                               ctypes.POINTER(c_int64), ctypes.POINTER(GvAdanParams), c_void_p]),
     ("gv_status_str", ctypes.c_char_p, [c_int32]),
     ("gv_last_hip_error", c_int32, []),
     ("gv_abi_version", c_int32, []),

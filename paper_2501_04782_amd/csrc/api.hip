@@ -83,6 +83,7 @@ Layout make_layout(const gv_camera& cam, int64_t n, int frames, int64_t k_cap) {
     L.nlast = take(4 * static_cast<size_t>(frames) * L.pixels);
     L.loss_part = take(4 * static_cast<size_t>(FT));
     L.pose_part = take(8 * 12 * static_cast<size_t>(L.pose_blocks) * frames);
+    L.intr_part = take(8 * 4 * static_cast<size_t>(L.pose_blocks));
     const size_t K = static_cast<size_t>(k_cap);
     L.keys = take(8 * K);
     L.kslot = take(4 * K);
@@ -141,6 +142,7 @@ static void set_grads(Args& a, const gv_grads* g) {
     a.g_scale_coeffs = g->scale_coeffs;
     a.g_quat_coeffs = g->quat_coeffs;
     a.g_sh = g->sh;
+    a.g_intr = g->intrinsics;
 }
 
 static gv_status hip_status(hipError_t e) {
@@ -207,6 +209,7 @@ static gv_status make_args(const gv_scene* s, const gv_camera* c, int frames, co
     a.nlast = reinterpret_cast<uint32_t*>(b + L.nlast);
     a.loss_part = reinterpret_cast<float*>(b + L.loss_part);
     a.pose_part = reinterpret_cast<double*>(b + L.pose_part);
+    a.intr_part = reinterpret_cast<double*>(b + L.intr_part);
     a.keys = reinterpret_cast<uint64_t*>(b + L.keys);
     a.kslot = reinterpret_cast<uint32_t*>(b + L.kslot);
     a.sgid = reinterpret_cast<uint32_t*>(b + L.sgid);
@@ -668,6 +671,6 @@ const char* gv_status_str(gv_status s) {
 
 int32_t gv_last_hip_error(void) { return g_last_hip; }
 
-int32_t gv_abi_version(void) { return 3; }
+int32_t gv_abi_version(void) { return 4; }
 
 }  // extern "C"

@@ -124,7 +124,8 @@ __device__ __forceinline__ void adjoint_inputs(const Args& a, int64_t g, const R
 // the pose gradient (dL/dRc row-major 0-8, dL/dtc 9-11) to pose[.][tid].
 template <int NT>
 __device__ __forceinline__ void projection_adjoint(const Args& a, const float* Rc, const AdjIn& P,
-                                                   const float d[9], float gout[14], double (*pose)[NT], int tid) {
+                                                   const float d[9], float gout[14], double (*pose)[NT], int tid,
+                                                   float gintr[4]) {
     const float A0 = P.A[0], A1 = P.A[1], A2 = P.A[2];
     // gradient w.r.t. the symmetric conic matrix
     const float G00 = d[2], G01 = 0.5f * d[3], G11 = d[4];
@@ -165,6 +166,12 @@ __device__ __forceinline__ void projection_adjoint(const Args& a, const float* R
         pose[1 * 3 + j][tid] += j11 * dT[3 + j];
         pose[2 * 3 + j][tid] += j02 * dT[j] + j12 * dT[3 + j];
     }
+    // intrinsics: u = fx mx/mz + cx, v = fy my/mz + cy, J00 = fx/mz,
+    // J02 = -fx mx/mz^2, J11 = fy/mz, J12 = -fy my/mz^2
+    gintr[0] = d[0] * mx * iz + dJ00 * iz - dJ02 * mx * iz2;
+    gintr[1] = d[1] * my * iz + dJ11 * iz - dJ12 * my * iz2;
+    gintr[2] = d[0];
+    gintr[3] = d[1];
     // J(m) and (u, v)(m)
     float dm[3];
     dm[0] = -dJ02 * fx * iz2 + d[0] * fx * iz;
@@ -265,6 +272,8 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
     __shared__ double acc[LA::N][PB_THREADS];
     __shared__ double pacc[12][PB_THREADS];  // this frame's pose contributions (dL/dRc, dL/dtc)
     __shared__ float camR[9], camT[3], camC[3];
+    __shared__ double iacc[4][PB_THREADS];  // intrinsics gradient, summed over frames
+    for (int k = 0; k < 4; ++k) iacc[k][tid] = 0.0;
     // SH coefficient gradients (FP32: at most a few hundred frames are summed)
     __shared__ float acc_sh[SH ? 45 : 1][PB_THREADS];
     for (int k = 0; k < LA::N; ++k) acc[k][tid] = 0.0;
@@ -318,8 +327,10 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
             const Record rec = a.rec[i];
             AdjIn P;
             adjoint_inputs<DYN>(a, g, rec, camR, camT, t, P);
-            float go[14];
-            projection_adjoint<PB_THREADS>(a, camR, P, d, go, pacc, tid);
+            float go[14], gi[4];
+            projection_adjoint<PB_THREADS>(a, camR, P, d, go, pacc, tid, gi);
+            if (a.g_intr)
+                for (int k = 0; k < 4; ++k) iacc[k][tid] += gi[k];
             if (SH) {
                 float dv[3];
                 const float dc[3] = {go[11], go[12], go[13]};
@@ -373,6 +384,19 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
                 for (int ww = 0; ww < PB_THREADS / 64; ++ww) v += red[ww][tid];
                 a.pose_part[(static_cast<int64_t>(blockIdx.x) * a.frames + f) * 12 + tid] = v;
             }
+        }
+    }
+    if (a.g_intr) {  // uniform: every thread takes part in the block reduction
+        __syncthreads();
+        for (int k = 0; k < 4; ++k) {
+            const double v = wave_sum_f64(iacc[k][tid]);
+            if (lane == 0) red[w][k] = v;
+        }
+        __syncthreads();
+        if (tid < 4) {
+            double v = 0.0;
+            for (int ww = 0; ww < PB_THREADS / 64; ++ww) v += red[ww][tid];
+            a.intr_part[static_cast<int64_t>(blockIdx.x) * 4 + tid] = v;
         }
     }
     if (!live) return;
@@ -434,6 +458,26 @@ __global__ __launch_bounds__(256) void k_pose_finalize(Args a, int64_t n_blocks)
     }
 }
 
+// Intrinsics gradient: fixed-order sum of the workgroups' partials.
+__global__ __launch_bounds__(256) void k_intr_finalize(Args a, int64_t n_blocks) {
+    __shared__ double red[256][4];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t b = threadIdx.x; b < n_blocks; b += 256)
+        for (int k = 0; k < 4; ++k) v[k] += a.intr_part[b * 4 + k];
+    for (int k = 0; k < 4; ++k) red[threadIdx.x][k] = v[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int k = 0; k < 4; ++k) red[threadIdx.x][k] += red[threadIdx.x + s][k];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) {
+        const float g = overflowed(a.status) ? 0.0f : static_cast<float>(red[0][threadIdx.x]);
+        if (a.accumulate) a.g_intr[threadIdx.x] += g;
+        else a.g_intr[threadIdx.x] = g;
+    }
+}
+
 int64_t project_bwd_blocks(int64_t n) { return (n + PB_THREADS - 1) / PB_THREADS; }
 
 hipError_t launch_project_bwd(const Args& a, hipStream_t stream) {
@@ -449,6 +493,10 @@ hipError_t launch_project_bwd(const Args& a, hipStream_t stream) {
     }
     if (a.g_poses)
         hipLaunchKernelGGL(k_pose_finalize, dim3(static_cast<uint32_t>(a.frames)), dim3(256), 0, stream, a, nb);
+    if (a.g_intr) {
+        if (nb > 0) hipLaunchKernelGGL(k_intr_finalize, dim3(1), dim3(256), 0, stream, a, nb);
+        else hipLaunchKernelGGL(k_intr_finalize, dim3(1), dim3(256), 0, stream, a, int64_t(0));
+    }
     return hipGetLastError();
 }
 

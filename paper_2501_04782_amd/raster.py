@@ -161,12 +161,13 @@ def grad_buffers(scene: Scene) -> dict:
     for k in Scene.OPTIONAL:
         v = getattr(scene, k)
         g[k] = None if v is None else torch.zeros(v.shape, device=dev)
+    g["intrinsics"] = torch.zeros(4, device=dev)  # dL/d(fx, fy, cx, cy)
     return g
 
 
 def _grads_c(g: dict) -> L.GvGrads:
     s = L.GvGrads()
-    for k in ("means", "log_scales", "quats", "opacity_logits", "colors") + Scene.OPTIONAL:
+    for k in ("means", "log_scales", "quats", "opacity_logits", "colors") + Scene.OPTIONAL + ("intrinsics",):
         t = g.get(k)
         if t is not None:
             _need(t, t.shape, torch.float32, f"grad {k}")

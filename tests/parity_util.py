@@ -82,7 +82,7 @@ def compare_image(gpu_img: np.ndarray, ref: dict, label: str):
 def compare_grads(gpu: dict, ref: dict, label: str, names=None):
     out = {}
     names = names or [k for k in ("means", "log_scales", "quats", "opacity_logits", "colors", "mean_coeffs", "ctrl",
-                                  "scale_coeffs", "quat_coeffs", "sh")
+                                  "scale_coeffs", "quat_coeffs", "sh", "intrinsics")
                       if ref.get(k) is not None and not (k == "means" and ref.get("ctrl") is not None)]
     for k in names:
         g = gpu[k].detach().cpu().numpy() if isinstance(gpu[k], torch.Tensor) else gpu[k]

@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 def test_status_strings_and_version():
     lib = L.load()
-    assert lib.gv_abi_version() == 3
+    assert lib.gv_abi_version() == 4
     for s in range(6):
         assert lib.gv_status_str(s)
     assert lib.gv_status_str(L.GV_ERR_CAPACITY) == b"intersection capacity exceeded"
@@ -164,3 +164,23 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "libgv.so"))
     with pytest.raises(RuntimeError, match="no fallback"):
         L.load()
+
+
+def test_adan_argument_validation():
+    """gv_adan_step checks its arguments on the host (no GPU needed)."""
+    lib = L.load()
+    fake = 0x1000
+    P = (ctypes.c_void_p * 2)(fake, fake)
+    C = (ctypes.c_int64 * 2)(10, 5)
+    ok = L.GvAdanParams(0.01, 0.02, 0.08, 0.01, 1e-8, 0.0, 0, 0)
+    assert lib.gv_adan_step(0, P, P, P, C, ctypes.byref(ok), None) == L.GV_ERR_INVALID_ARG
+    assert lib.gv_adan_step(L.GV_ADAN_MAX_TENSORS + 1, P, P, P, C, ctypes.byref(ok), None) == L.GV_ERR_INVALID_ARG
+    for field, value in (("step", -1), ("beta1", 1.5), ("beta3", -0.1), ("eps", 0.0), ("lr", float("nan")),
+                         ("weight_decay", -1.0)):
+        hp = L.GvAdanParams(0.01, 0.02, 0.08, 0.01, 1e-8, 0.0, 0, 0)
+        setattr(hp, field, value)
+        assert lib.gv_adan_step(2, P, P, P, C, ctypes.byref(hp), None) == L.GV_ERR_INVALID_ARG, field
+    Z = (ctypes.c_int64 * 2)(0, 0)
+    assert lib.gv_adan_step(2, P, P, P, Z, ctypes.byref(ok), None) == L.GV_OK  # nothing to do, nothing launched
+    N = (ctypes.c_void_p * 2)(fake, None)
+    assert lib.gv_adan_step(2, P, N, P, C, ctypes.byref(ok), None) == L.GV_ERR_INVALID_ARG
