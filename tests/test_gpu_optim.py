@@ -23,8 +23,10 @@ def test_adan_matches_oracle_over_steps():
     opt = Adan(params, lr=0.01, gamma=0.99, weight_decay=0.02)
     ref_theta = [t.astype(np.float32).astype(np.float64) for t in theta]
     ref_state = [adan_ref.init_state(s) for s in shapes]
+    gmax = [0.0] * len(shapes)
     for k in range(8):
         grads = [rng.normal(0, 1, s) * (10.0 ** rng.uniform(-3, 1, s)) for s in shapes]
+        gmax = [max(m, float(np.abs(g).max())) for m, g in zip(gmax, grads)]
         g32 = [g.astype(np.float32) for g in grads]
         opt.step([torch.from_numpy(g).cuda() for g in g32])
         lr = float(np.float32(0.01 * 0.99 ** k))
@@ -34,13 +36,16 @@ def test_adan_matches_oracle_over_steps():
                                          b2=float(np.float32(0.08)), b3=float(np.float32(0.01)),
                                          eps=float(np.float32(1e-8)))
     torch.cuda.synchronize()
+    # FP32 bar: each recurrence rounds terms as large as the largest gradient
+    # (squared for n) once per step, 2^-24 relative, over 8 steps; the
+    # parameter moves by at most lr per step (|m + (1-b2) v| / sqrt(n) stays O(1))
     for i in range(len(shapes)):
         got = params[i].cpu().numpy().astype(np.float64)
         np.testing.assert_allclose(got, ref_theta[i], rtol=2e-6, atol=2e-6)
         st = opt.states[i].cpu().numpy().astype(np.float64)
         for j, name in enumerate(("m", "v", "n", "g_prev")):
-            np.testing.assert_allclose(st[j], ref_state[i][name], rtol=1e-5, atol=1e-9 if name != "n" else 1e-12,
-                                       err_msg=name)
+            scale = gmax[i] ** 2 if name == "n" else gmax[i]
+            np.testing.assert_allclose(st[j], ref_state[i][name], rtol=1e-5, atol=1e-6 * scale, err_msg=name)
 
 
 def test_intrinsics_gradient_in_clip():
