@@ -69,7 +69,9 @@ def _load():
         lib.gvo_sh_basis.argtypes = [ctypes.c_int32, _dp, _dp, _dp]
         lib.gvo_sh_basis.restype = ctypes.c_int
         lib.gvo_abi_version.restype = ctypes.c_int
-        if lib.gvo_abi_version() != 4:
+        lib.gvo_contributors.argtypes = [ctypes.POINTER(_Frame), ctypes.POINTER(ctypes.c_uint8), ctypes.c_int]
+        lib.gvo_contributors.restype = ctypes.c_int
+        if lib.gvo_abi_version() != 5:
             raise RuntimeError("liboracle.so is stale: rebuild it (python -m oracle.build)")
         _lib = lib
     return _lib
@@ -212,6 +214,25 @@ def render_frame(scene, cam, pose7, t: float = 0.0, pixels: Optional[np.ndarray]
     if dl is not None:
         out["grads"] = grads
     return out
+
+
+def contributors(scene, cam, pose7, t: float = 0.0, threads: int = 0) -> np.ndarray:
+    """Bool per Gaussian: contributes to at least one pixel of the frame."""
+    s = scene_f64(scene)
+    fr = _frame(s, cam, pose7, t)
+    out = np.zeros(fr.n, np.uint8)
+    rc = _load().gvo_contributors(ctypes.byref(fr), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(threads))
+    if rc != 0:
+        raise RuntimeError(f"gvo_contributors failed with code {rc}")
+    return out.astype(bool)
+
+
+def visibility_counts(scene, cam, poses, times, threads: int = 0) -> np.ndarray:
+    """Per Gaussian, the number of frames of the clip it contributes to."""
+    counts = np.zeros(scene_f64(scene)["opacity_logits"].shape[0], np.int64)
+    for f in range(len(poses)):
+        counts += contributors(scene, cam, np.asarray(poses[f], np.float64), float(times[f]), threads)
+    return counts
 
 
 def render_image(scene, cam, pose7, t: float = 0.0, threads: int = 0) -> dict:

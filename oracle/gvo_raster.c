@@ -799,4 +799,69 @@ int gvo_render(const gvo_frame *fr, int64_t n_pix, const int64_t *pix, double *c
     return err;
 }
 
-int gvo_abi_version(void) { return 4; }
+/* Flags (0/1) of the Gaussians that contribute to at least one pixel of the
+ * frame (alpha >= 1/255 inside the 3-sigma cut, before the pixel stopped):
+ * the "appears in this frame" test behind warping unseen Gaussians (Sec. 4.1).
+ * Returns 0, -1 when out of memory, -2 for an invalid pose. */
+int gvo_contributors(const gvo_frame *fr, uint8_t *flags, int n_threads)
+{
+    cam_t cam;
+    int ok;
+    setup_camera(fr, &cam, &ok);
+    const int64_t n = fr->n;
+    memset(flags, 0, (size_t)(n > 0 ? n : 0));
+    if (!ok) return -2;
+    proj_t *P = (proj_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(proj_t));
+    int64_t *order = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!P || !order) { free(P); free(order); return -1; }
+    int64_t nv = 0;
+    for (int64_t g = 0; g < n; ++g) {
+        project_one(fr, &cam, g, &P[g]);
+        if (P[g].valid) order[nv++] = g;
+    }
+    g_sort_proj = P;
+    qsort(order, (size_t)nv, sizeof(int64_t), cmp_order);
+    int nt = 1;
+#ifdef _OPENMP
+    nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#endif
+    uint8_t *local = (uint8_t *)calloc((size_t)nt * (size_t)(n > 0 ? n : 1), 1);
+    int err = local ? 0 : -1;
+    const int64_t npix = (int64_t)fr->width * fr->height;
+    if (!err) {
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+        {
+            int tid = 0;
+#ifdef _OPENMP
+            tid = omp_get_thread_num();
+#endif
+            clist_t L = {0, 0, 0};
+            uint8_t *mine = local + (size_t)tid * (size_t)n;
+#ifdef _OPENMP
+#pragma omp for schedule(static, 8)
+#endif
+            for (int64_t i = 0; i < npix; ++i) {
+                double mg[4], C[3], T;
+                int64_t nc;
+                L.len = 0;
+                if (composite_pixel(fr, P, order, nv, (double)(i % fr->width) + 0.5, (double)(i / fr->width) + 0.5,
+                                    C, &T, &nc, mg, &L)) {
+                    err = -1;
+                    continue;
+                }
+                for (int64_t k = 0; k < L.len; ++k) mine[L.v[k].g] = 1;
+            }
+            free(L.v);
+        }
+        for (int t = 0; t < nt; ++t)
+            for (int64_t g = 0; g < n; ++g) flags[g] |= local[(size_t)t * (size_t)n + g];
+    }
+    free(local);
+    free(P);
+    free(order);
+    return err;
+}
+
+int gvo_abi_version(void) { return 5; }
