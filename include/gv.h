@@ -284,6 +284,27 @@ gv_status gv_autotune(const gv_scene *scene, const gv_camera *cam, const float *
  * low/high 32 bits of the intersection count of the last projection. */
 gv_status gv_device_status(const void *ws, uint32_t out[4]);
 
+/* Per-Gaussian visibility counts (Sec. 4.1: Gaussians that appear in no
+ * frame are periodically moved): renders the frames like gv_render_batch with
+ * GV_FWD (images [F][3][H][W] are written) and sets counts[g] (device, [N])
+ * to the number of frames in which Gaussian g contributes to at least one
+ * pixel (alpha >= 1/255 inside its 3-sigma ellipse, before the pixel's
+ * termination).  Same workspace and argument rules as gv_render_batch. */
+gv_status gv_visibility_counts(const gv_scene *scene, const gv_camera *cam, const float *poses, const float *times,
+                               int32_t frames, float *images, uint32_t *counts, void *ws, size_t ws_bytes,
+                               void *stream);
+
+/* Gaussian pyramid of target frames for the spatial hierarchy (Sec. 3.3):
+ * level 0 is `images` ([planes][H][W] FP32, e.g. planes = 3F); level l+1 is
+ * level l convolved with the separable binomial filter [1 4 6 4 1]/16
+ * (borders mirrored without repeating the edge sample) and decimated to its
+ * even rows and columns, size ceil(H/2) x ceil(W/2).  `out` (device) receives
+ * levels 1 .. levels-1 one after the other, each [planes][H_l][W_l];
+ * gv_pyramid_floats gives its length.  levels 1..16. */
+gv_status gv_pyramid_floats(int64_t planes, int32_t height, int32_t width, int32_t levels, int64_t *out_count);
+gv_status gv_gaussian_pyramid(const float *images, int64_t planes, int32_t height, int32_t width, int32_t levels,
+                              float *out, void *stream);
+
 /* Fused Adan step (Sec. 4.1 trains with Adan: learning rate 0.01, decayed
  * by 0.99995 per step; the schedule is the caller's, who passes this step's
  * lr).  Per element, with g the gradient and (m, v, n, g_prev) the state:
@@ -307,8 +328,9 @@ gv_status gv_adan_step(int32_t n_tensors, float *const *params, const float *con
 
 const char *gv_status_str(gv_status s);
 int32_t gv_last_hip_error(void);
-/* Version of this interface: 4 (2: B-spline / polynomial dynamics and
- * bwd_batch; 3: spherical-harmonics colour; 4: intrinsics gradient, Adan). */
+/* Version of this interface: 5 (2: B-spline / polynomial dynamics and
+ * bwd_batch; 3: spherical-harmonics colour; 4: intrinsics gradient, Adan;
+ * 5: visibility counts, Gaussian pyramid). */
 int32_t gv_abi_version(void);
 
 #ifdef __cplusplus

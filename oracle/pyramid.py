@@ -25,6 +25,17 @@ def _mirror(i: int, n: int) -> int:
     return i
 
 
+def reduce_at(img: np.ndarray, y: int, x: int):
+    """Output pixel (y, x) of one REDUCE step on [..., H, W]."""
+    img = np.asarray(img, np.float64)
+    H, W = img.shape[-2:]
+    acc = 0.0
+    for dy in range(-2, 3):
+        for dx in range(-2, 3):
+            acc = acc + KERNEL[dy + 2] * KERNEL[dx + 2] * img[..., _mirror(2 * y + dy, H), _mirror(2 * x + dx, W)]
+    return acc
+
+
 def reduce_level(img: np.ndarray) -> np.ndarray:
     """One REDUCE step on [..., H, W], written out as plain loops over the
     output pixels and the 5 x 5 taps."""
@@ -34,11 +45,7 @@ def reduce_level(img: np.ndarray) -> np.ndarray:
     out = np.zeros(img.shape[:-2] + (Ho, Wo))
     for y in range(Ho):
         for x in range(Wo):
-            acc = 0.0
-            for dy in range(-2, 3):
-                for dx in range(-2, 3):
-                    acc = acc + KERNEL[dy + 2] * KERNEL[dx + 2] * img[..., _mirror(2 * y + dy, H), _mirror(2 * x + dx, W)]
-            out[..., y, x] = acc
+            out[..., y, x] = reduce_at(img, y, x)
     return out
 
 

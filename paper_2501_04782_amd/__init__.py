@@ -4,11 +4,11 @@ torch binding.  Importing the package does not touch the GPU; the first call
 loads libgv.so and raises if it has not been built."""
 from . import _lib
 from .raster import (BatchGraph, Camera, RasterizeClip, RasterizeDynamicClip, RasterizeFrame, Scene, Workspace,
-                     autotune, estimate_capacity, get_tuning, grad_buffers, project_fwd, render_batch,
-                     render_batch_timed, render_bwd, render_fwd, set_tuning)
+                     autotune, estimate_capacity, gaussian_pyramid, get_tuning, grad_buffers, project_fwd,
+                     render_batch, render_batch_timed, render_bwd, render_fwd, set_tuning, visibility_counts)
 
 __all__ = ["BatchGraph", "Camera", "RasterizeClip", "RasterizeDynamicClip", "RasterizeFrame", "Scene", "Workspace",
-           "autotune", "estimate_capacity", "get_tuning", "grad_buffers", "project_fwd", "render_batch", "render_batch_timed",
+           "autotune", "estimate_capacity", "gaussian_pyramid", "visibility_counts", "get_tuning", "grad_buffers", "project_fwd", "render_batch", "render_batch_timed",
            "render_bwd", "render_fwd", "set_tuning", "load_library"]
 
 

@@ -27,7 +27,7 @@ class GvCamera(ctypes.Structure):
                 ("cy", c_float), ("near_plane", c_float), ("dilation", c_float), ("bg", c_float * 3)]
 
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 GV_MAX_CTRL = 64
 GV_MAX_SH_DEGREE = 3
 GV_ADAN_MAX_TENSORS = 16
@@ -104,6 +104,10 @@ _SIGS = [
                               c_void_p, c_void_p, c_void_p, ctypes.POINTER(GvGrads), c_void_p, c_void_p, c_size_t,
                               ctypes.c_char_p, ctypes.POINTER(GvTuning)]),
     ("gv_device_status", c_int32, [c_void_p, ctypes.POINTER(c_uint32)]),
+    ("gv_visibility_counts", c_int32, [ctypes.POINTER(GvScene), ctypes.POINTER(GvCamera), c_void_p, c_void_p,
+                                       c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("gv_pyramid_floats", c_int32, [c_int64, c_int32, c_int32, c_int32, ctypes.POINTER(c_int64)]),
+    ("gv_gaussian_pyramid", c_int32, [c_void_p, c_int64, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     ("gv_adan_step", c_int32, [c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
                                ctypes.POINTER(c_int64), ctypes.POINTER(GvAdanParams), c_void_p]),
     ("gv_status_str", ctypes.c_char_p, [c_int32]),

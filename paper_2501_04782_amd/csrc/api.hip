@@ -18,6 +18,7 @@ hipError_t launch_scatter(const Args& a, hipStream_t stream);
 hipError_t launch_export_records(const Args& a, float* records, int32_t* counts, hipStream_t stream);
 hipError_t launch_tile_sort(const Args& a, int64_t segments, hipStream_t stream);
 hipError_t launch_composite_fwd(const Args& a, hipStream_t stream);
+hipError_t launch_vis_count(const Args& a, uint32_t* counts, hipStream_t stream);
 hipError_t launch_loss_finalize(const Args& a, hipStream_t stream);
 hipError_t launch_composite_bwd(const Args& a, hipStream_t stream);
 hipError_t launch_project_bwd(const Args& a, hipStream_t stream);
@@ -84,6 +85,7 @@ Layout make_layout(const gv_camera& cam, int64_t n, int frames, int64_t k_cap) {
     L.loss_part = take(4 * static_cast<size_t>(FT));
     L.pose_part = take(8 * 12 * static_cast<size_t>(L.pose_blocks) * frames);
     L.intr_part = take(8 * 4 * static_cast<size_t>(L.pose_blocks));
+    L.vis = take((static_cast<size_t>(FN) + 3) / 4 * 4);
     const size_t K = static_cast<size_t>(k_cap);
     L.keys = take(8 * K);
     L.kslot = take(4 * K);
@@ -407,6 +409,26 @@ gv_status gv_render_batch(const gv_scene* scene, const gv_camera* cam, const flo
                          ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
+gv_status gv_visibility_counts(const gv_scene* scene, const gv_camera* cam, const float* poses, const float* times,
+                               int32_t frames, float* images, uint32_t* counts, void* ws, size_t ws_bytes,
+                               void* stream) {
+    if (!counts || !images) return GV_ERR_INVALID_ARG;
+    Args a;
+    Layout L;
+    gv_status s = make_args(scene, cam, frames, poses, times, ws, ws_bytes, a, L);
+    if (s != GV_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    a.images = images;
+    a.vis = reinterpret_cast<uint8_t*>(static_cast<char*>(ws) + L.vis);
+    const int64_t FN = static_cast<int64_t>(frames) * a.n;
+    GV_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(a.vis), 0u, (FN + 3) / 4, st));
+    s = enqueue_binning(a, L, st, false, nullptr);
+    if (s != GV_OK) return s;
+    GV_TRY(launch_composite_fwd(a, st));
+    GV_TRY(launch_vis_count(a, counts, st));
+    return GV_OK;
+}
+
 gv_status gv_render_batch_timed(const gv_scene* scene, const gv_camera* cam, const float* poses, const float* times,
                                 int32_t frames, const float* targets, const float* dL_dimages, uint32_t flags,
                                 float* images, float* loss, gv_grads* grads, float* dL_dposes, void* ws,
@@ -671,6 +693,6 @@ const char* gv_status_str(gv_status s) {
 
 int32_t gv_last_hip_error(void) { return g_last_hip; }
 
-int32_t gv_abi_version(void) { return 4; }
+int32_t gv_abi_version(void) { return 5; }
 
 }  // extern "C"

@@ -59,7 +59,9 @@ __device__ __forceinline__ void stage_entry(const Args& a, int f, uint32_t gid, 
 // Entries per unrolled group of the quadrant forward loop.
 constexpr int FWD_GROUP = 8;
 
-template <int B>
+// VIS: also flag every (frame, Gaussian) that contributes to a pixel of the
+// tile (vis[f * N + g] = 1), for the per-Gaussian visibility counts.
+template <int B, bool VIS>
 __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
     if (overflowed(a.status)) return;
     const int f = blockIdx.y;
@@ -82,6 +84,7 @@ __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
     __shared__ uint32_t shm[B];
     __shared__ float red[WG / 64];
     __shared__ __align__(16) uint16_t wl[WG / 64][B + FWD_GROUP];
+    __shared__ uint32_t shg[VIS ? B : 1];
     if (tid == 0) {
         sh[B].p0 = make_float4(0.f, 0.f, 0.f, 0.f);
         sh[B].p1 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -100,10 +103,12 @@ __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
             Staged st;
             float blue;
             uint32_t m;
-            stage_entry(a, f, a.sgid[b0 + tid], ox, oy, xlim, ylim, st, blue, m);
+            const uint32_t gid = a.sgid[b0 + tid];
+            stage_entry(a, f, gid, ox, oy, xlim, ylim, st, blue, m);
             sh[tid] = st;
             shb[tid] = blue;
             shm[tid] = m;
+            if (VIS) shg[tid] = gid;
         }
         __syncthreads();
         if (__ballot(!done) == 0) continue;  // wave-uniform; the barriers are outside
@@ -153,6 +158,10 @@ __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
                 c2 = __builtin_fmaf(cb, wgt, c2);
                 T = take ? tn : T;
                 last = take ? b0 + j - s + 1 : last;
+                if (VIS && __ballot(take) != 0 && lane == 0) {
+                    const uint32_t gid = shg[j];
+                    if (gid < static_cast<uint64_t>(a.n)) a.vis[static_cast<int64_t>(f) * a.n + gid] = 1;
+                }
             }
             if (__ballot(!done) == 0) break;
         }
@@ -780,7 +789,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
 
 hipError_t launch_composite_fwd(const Args& a, hipStream_t stream) {
     const dim3 grid(static_cast<uint32_t>(a.tiles), static_cast<uint32_t>(a.frames)), block(WG);
-    if (a.tune.compact & 1) {
+    if ((a.tune.compact & 1) && !a.vis) {
         switch (a.tune.batch) {
             case 64: hipLaunchKernelGGL(k_composite_fwd_c<64>, grid, block, 0, stream, a); break;
             case 128: hipLaunchKernelGGL(k_composite_fwd_c<128>, grid, block, 0, stream, a); break;
@@ -788,11 +797,34 @@ hipError_t launch_composite_fwd(const Args& a, hipStream_t stream) {
         }
         return hipGetLastError();
     }
-    switch (a.tune.batch) {
-        case 64: hipLaunchKernelGGL(k_composite_fwd<64>, grid, block, 0, stream, a); break;
-        case 128: hipLaunchKernelGGL(k_composite_fwd<128>, grid, block, 0, stream, a); break;
-        default: hipLaunchKernelGGL(k_composite_fwd<256>, grid, block, 0, stream, a); break;
+    if (a.vis) {  // visibility flags: the quadrant kernel
+        switch (a.tune.batch) {
+            case 64: hipLaunchKernelGGL((k_composite_fwd<64, true>), grid, block, 0, stream, a); break;
+            case 128: hipLaunchKernelGGL((k_composite_fwd<128, true>), grid, block, 0, stream, a); break;
+            default: hipLaunchKernelGGL((k_composite_fwd<256, true>), grid, block, 0, stream, a); break;
+        }
+        return hipGetLastError();
     }
+    switch (a.tune.batch) {
+        case 64: hipLaunchKernelGGL((k_composite_fwd<64, false>), grid, block, 0, stream, a); break;
+        case 128: hipLaunchKernelGGL((k_composite_fwd<128, false>), grid, block, 0, stream, a); break;
+        default: hipLaunchKernelGGL((k_composite_fwd<256, false>), grid, block, 0, stream, a); break;
+    }
+    return hipGetLastError();
+}
+
+// counts[g] = number of frames whose flag vis[f * N + g] is set.
+__global__ __launch_bounds__(256) void k_vis_count(Args a, uint32_t* __restrict__ counts) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (g >= a.n) return;
+    uint32_t c = 0;
+    for (int f = 0; f < a.frames; ++f) c += a.vis[static_cast<int64_t>(f) * a.n + g];
+    counts[g] = overflowed(a.status) ? 0u : c;
+}
+
+hipError_t launch_vis_count(const Args& a, uint32_t* counts, hipStream_t stream) {
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_vis_count, dim3(static_cast<uint32_t>((a.n + 255) / 256)), dim3(256), 0, stream, a, counts);
     return hipGetLastError();
 }
 

@@ -78,7 +78,7 @@ struct Layout {
     int64_t pose_blocks;   // workgroups of the projection adjoint (upper bound)
     int64_t bin_blocks;    // workgroups per frame of the LDS-histogram binning (0: global atomics)
     size_t status, col4, rec, rect, gcnt, goff, tcnt, toff, tcur, bhist, scan_tmp, tfin, nlast, loss_part, pose_part,
-        intr_part,
+        intr_part, vis,
         keys, kslot, sgid, sslot, part, tkeys, tslot;
     size_t total;
 };
@@ -128,6 +128,7 @@ struct Args {
     float* loss_part;     // [F*T]
     double* pose_part;    // [blocks][F][12]
     double* intr_part;    // [blocks][4] intrinsics-gradient partials of the projection adjoint
+    uint8_t* vis;         // [F][N] contribution flags, or nullptr (not requested)
     uint64_t* keys;       // [K]
     uint32_t* kslot;      // [K]
     uint32_t* sgid;       // [K]

@@ -473,3 +473,40 @@ class RasterizeDynamicClip(torch.autograd.Function):
         g = out["grads"]
         return (g["ctrl"], g["log_scales"], g["quats"], g["opacity_logits"], g["colors"], g["scale_coeffs"],
                 g["quat_coeffs"], out["dL_dposes"], None, None, None)
+
+
+def visibility_counts(scene: Scene, camera: Camera, poses: torch.Tensor, times: Optional[torch.Tensor],
+                      ws: Workspace, images: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Per Gaussian, the number of frames in which it contributes to at least
+    one pixel (int32 [N]); the frames are rendered into ``images``."""
+    F = int(poses.shape[0])
+    dev = poses.device
+    if images is None:
+        images = torch.empty(F, 3, camera.height, camera.width, device=dev)
+    counts = torch.empty(scene.n, dtype=torch.int32, device=dev)
+    sc, cam = scene.c(), camera.c()
+    L.check(L.load().gv_visibility_counts(ctypes.byref(sc), ctypes.byref(cam), poses.data_ptr(),
+                                          None if times is None else times.data_ptr(), F, images.data_ptr(),
+                                          counts.data_ptr(), ws.ptr, ws.nbytes, _stream()), "gv_visibility_counts")
+    return counts
+
+
+def gaussian_pyramid(images: torch.Tensor, levels: int):
+    """[images, level 1, ..., level levels-1] of [..., H, W] FP32 frames
+    (binomial 5-tap blur + decimation by 2, mirrored borders)."""
+    if images.dtype != torch.float32 or not images.is_contiguous() or not images.is_cuda:
+        raise ValueError("images must be a contiguous float32 device tensor")
+    lead = images.shape[:-2]
+    H, W = int(images.shape[-2]), int(images.shape[-1])
+    planes = int(np.prod(lead)) if len(lead) else 1
+    n = ctypes.c_int64()
+    L.check(L.load().gv_pyramid_floats(planes, H, W, levels, ctypes.byref(n)), "gv_pyramid_floats")
+    out = torch.empty(max(int(n.value), 1), device=images.device)
+    L.check(L.load().gv_gaussian_pyramid(images.data_ptr(), planes, H, W, levels, out.data_ptr(), _stream()),
+            "gv_gaussian_pyramid")
+    res, off, h, w = [images], 0, H, W
+    for _ in range(1, levels):
+        h, w = (h + 1) // 2, (w + 1) // 2
+        res.append(out[off:off + planes * h * w].view(*lead, h, w))
+        off += planes * h * w
+    return res

@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 def test_status_strings_and_version():
     lib = L.load()
-    assert lib.gv_abi_version() == 4
+    assert lib.gv_abi_version() == 5
     for s in range(6):
         assert lib.gv_status_str(s)
     assert lib.gv_status_str(L.GV_ERR_CAPACITY) == b"intersection capacity exceeded"
@@ -184,3 +184,15 @@ def test_adan_argument_validation():
     assert lib.gv_adan_step(2, P, P, P, Z, ctypes.byref(ok), None) == L.GV_OK  # nothing to do, nothing launched
     N = (ctypes.c_void_p * 2)(fake, None)
     assert lib.gv_adan_step(2, P, N, P, C, ctypes.byref(ok), None) == L.GV_ERR_INVALID_ARG
+
+
+def test_pyramid_sizes_and_validation():
+    lib = L.load()
+    n = ctypes.c_int64()
+    assert lib.gv_pyramid_floats(6, 540, 960, 4, ctypes.byref(n)) == L.GV_OK
+    assert n.value == 6 * (270 * 480 + 135 * 240 + 68 * 120)
+    assert lib.gv_pyramid_floats(1, 7, 5, 1, ctypes.byref(n)) == L.GV_OK and n.value == 0
+    assert lib.gv_pyramid_floats(0, 7, 5, 2, ctypes.byref(n)) == L.GV_ERR_INVALID_ARG
+    assert lib.gv_pyramid_floats(1, 7, 5, 17, ctypes.byref(n)) == L.GV_ERR_INVALID_ARG
+    assert lib.gv_gaussian_pyramid(None, 1, 8, 8, 2, 0x1000, None) == L.GV_ERR_INVALID_ARG
+    assert lib.gv_gaussian_pyramid(0x1000, 1, 8, 8, 2, None, None) == L.GV_ERR_INVALID_ARG
