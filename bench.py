@@ -73,6 +73,101 @@ def stage_bytes(stage, N, V, K, P, F):
     return 0
 
 
+def quick_clip(name, dev, steps=3):
+    """Frames/s of one batched fwd+bwd step (one HIP graph) on another
+    workload, with the installed tuning; for the camera-ODE workload the step
+    is the fitting graph (ODE forward -> batch -> ODE adjoint)."""
+    import torch
+    import gv_synth
+    from paper_2501_04782_amd import camera, raster
+    w = gv_synth.make_workload(name, seed=0, targets=True)
+    F, N = w["frames"], w["n"]
+    scene = raster.Scene.from_synth(w["scene"], dev)
+    cam = raster.Camera.of(w["camera"])
+    poses = torch.from_numpy(w["poses"]).to(dev)
+    times = torch.from_numpy(w["times"]).to(dev)
+    targets = torch.from_numpy(w["targets"]).to(dev)
+    cap = raster.estimate_capacity(scene, cam, poses, times, margin=1.3)
+    ws = raster.Workspace(cam, N, F, cap, device=dev)
+    info = dict(workload=name, frames=F, gaussians=N, width=cam.width, height=cam.height)
+    if name == ODE_WORKLOAD:
+        gt = raster.render_batch(scene, cam, poses, times, ws, forward=True, backward=False)
+        targets = gt["images"].clone()
+        theta = torch.from_numpy(gv_synth.init_mlp_theta(np.random.default_rng(7)).astype(np.float32)).to(dev)
+        graph = camera.FitGraph(scene, cam, theta, poses[0].clone(), F, 4, times, ws, targets=targets)
+        info["step"] = "camera ODE forward (RK4, 4 substeps) -> batched fwd+bwd -> ODE adjoint, one graph"
+    else:
+        graph = raster.BatchGraph(scene, cam, poses, times, ws, targets=targets)
+        info["step"] = "batched fwd+bwd with fused L2, one graph"
+    graph.launch()
+    torch.cuda.synchronize()
+    st = ws.status()
+    if st["overflow"]:
+        raise RuntimeError(f"{name}: intersection capacity overflow")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.launch()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    info.update(ms_per_step=round(1e3 * dt, 3), frames_per_s=round(F / dt, 1),
+                intersections_per_frame=int(st["intersections"] / F))
+    if name == ODE_WORKLOAD:
+        ows = camera.OdeWorkspace(F, 4, device=dev)
+        th = torch.from_numpy(gv_synth.init_mlp_theta(np.random.default_rng(7)).astype(np.float32)).to(dev)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        p = camera.camera_ode_fwd(th, poses[0].clone(), F, 4, ows)
+        torch.cuda.synchronize()
+        e[0].record()
+        p = camera.camera_ode_fwd(th, poses[0].clone(), F, 4, ows)
+        e[1].record()
+        camera.camera_ode_bwd(th, poses[0].clone(), F, 4, torch.ones_like(p), ows)
+        e[2].record()
+        torch.cuda.synchronize()
+        info.update(ode_fwd_ms=round(e[0].elapsed_time(e[1]), 4), ode_bwd_ms=round(e[1].elapsed_time(e[2]), 4))
+    del graph, ws
+    torch.cuda.empty_cache()
+    return info
+
+
+def micro_benchmarks(scene_np, targets, dev):
+    """HBM-bound helpers of the fitting loop: the fused Adan step over all
+    parameters of the benchmark scene, the Gaussian pyramid of the clip's
+    targets, and the visibility-count pass."""
+    import torch
+    from paper_2501_04782_amd import optim, raster
+    out = {}
+    params = [torch.from_numpy(np.ascontiguousarray(getattr(scene_np, k), dtype=np.float32)).to(dev)
+              for k in scene_np.fields()]
+    grads = [torch.randn_like(p) for p in params]
+    opt = optim.Adan(params)
+    opt.step(grads)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        opt.step(grads)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    n = sum(p.numel() for p in params)
+    out["adan"] = dict(params=n, ms=round(ms, 4), bytes_per_param=44, gb_per_s=round(44 * n / ms / 1e6, 1),
+                       hbm_frac=round(44 * n / (ms * 1e-3) / HBM_PEAK, 3))
+    levels = 4
+    raster.gaussian_pyramid(targets, levels)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        pyr = raster.gaussian_pyramid(targets, levels)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    moved = sum(4 * t.numel() for t in pyr[:-1]) + sum(4 * t.numel() for t in pyr[1:])
+    out["pyramid"] = dict(levels=levels, frames=int(targets.shape[0]), ms=round(ms, 4),
+                          gb_per_s=round(moved / ms / 1e6, 1), hbm_frac=round(moved / (ms * 1e-3) / HBM_PEAK, 3))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +181,9 @@ def main():
                     help="batch,sort_cap,compact[,bwd_batch]: fixed tuning (skips the autotuner)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle sample")
     ap.add_argument("--stage-reps", type=int, default=5)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary measurements (ODE fitting step, 1080p bf16 clip, dynamics, SH, "
+                         "Adan, pyramid, visibility)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration) and exit")
     args = ap.parse_args()
@@ -296,6 +394,28 @@ def main():
                         avg_ms=round(stage_ms[dom], 4), contributing_pairs=int(pairs),
                         hbm_frac=round(hbm_ach / HBM_PEAK, 4))
     b_alg = algorithmic_bytes(N, V, K, P, F, param_bytes, grad_bytes)
+
+    extras = None
+    if not args.no_extras and ode_info is None and args.workload == "clip540p_f50_n200k":
+        log("[bench] secondary measurements")
+        extras = micro_benchmarks(w["scene"], targets, dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        raster.visibility_counts(scene, cam, poses, times, ws)
+        torch.cuda.synchronize()
+        e0.record()
+        raster.visibility_counts(scene, cam, poses, times, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        extras["visibility_counts"] = dict(frames=F, ms=round(e0.elapsed_time(e1), 3),
+                                           note="projection + binning + sort + flagging forward + count")
+        graph.close()
+        graph = None
+        torch.cuda.empty_cache()
+        extras["workloads"] = []
+        for name in (ODE_WORKLOAD, "clip1080p_f32_n500k_bf16", "clip540p_f50_n200k_dyn", "clip540p_f50_n200k_sh3"):
+            log(f"[bench] {name}")
+            extras["workloads"].append(quick_clip(name, dev))
+        log(f"[bench] extras: {extras}")
     step_hbm_frac = b_alg / (ms_step / 1e3) / HBM_PEAK
 
     line = {
@@ -323,6 +443,7 @@ def main():
         "loss": loss_val,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     if mean_contrib is not None:
         line["mean_contributors_per_pixel"] = round(mean_contrib, 3)
@@ -330,7 +451,8 @@ def main():
         line["camera_ode"] = ode_info
         line["config"]["path"] = "camera ODE fwd -> batched raster fwd+bwd -> ODE adjoint, one HIP graph per step"
     print(json.dumps(line), flush=True)
-    graph.close()
+    if graph is not None:
+        graph.close()
 
 
 if __name__ == "__main__":
