@@ -45,7 +45,7 @@ void install_tuning(const Tuning& t) {
 static inline size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 constexpr int64_t K_LIMIT = 0x7fffffffLL;        // positions are u32; keep one bit spare
-constexpr size_t PER_ENTRY_BYTES = 8 + 4 + 4 + 4 + 16 + 16 + 4 + 8 + 4;
+constexpr size_t PER_ENTRY_BYTES = 16 + 4 + 4 + 36 + 16;  // kv, sgid, sslot, part, tkv
 
 Layout make_layout(const gv_camera& cam, int64_t n, int frames, int64_t k_cap) {
     Layout L{};
@@ -87,13 +87,11 @@ Layout make_layout(const gv_camera& cam, int64_t n, int frames, int64_t k_cap) {
     L.intr_part = take(8 * 4 * static_cast<size_t>(L.pose_blocks));
     L.vis = take((static_cast<size_t>(FN) + 3) / 4 * 4);
     const size_t K = static_cast<size_t>(k_cap);
-    L.keys = take(8 * K);
-    L.kslot = take(4 * K);
+    L.kv = take(sizeof(KeySlot) * K);
     L.sgid = take(4 * K);
     L.sslot = take(4 * K);
     L.part = take(4 * PART * K);
-    L.tkeys = take(8 * K);
-    L.tslot = take(4 * K);
+    L.tkv = take(sizeof(KeySlot) * K);
     L.total = off;
     return L;
 }
@@ -212,13 +210,11 @@ static gv_status make_args(const gv_scene* s, const gv_camera* c, int frames, co
     a.loss_part = reinterpret_cast<float*>(b + L.loss_part);
     a.pose_part = reinterpret_cast<double*>(b + L.pose_part);
     a.intr_part = reinterpret_cast<double*>(b + L.intr_part);
-    a.keys = reinterpret_cast<uint64_t*>(b + L.keys);
-    a.kslot = reinterpret_cast<uint32_t*>(b + L.kslot);
+    a.kv = reinterpret_cast<KeySlot*>(b + L.kv);
     a.sgid = reinterpret_cast<uint32_t*>(b + L.sgid);
     a.sslot = reinterpret_cast<uint32_t*>(b + L.sslot);
     a.part = reinterpret_cast<float*>(b + L.part);
-    a.tkeys = reinterpret_cast<uint64_t*>(b + L.tkeys);
-    a.tslot = reinterpret_cast<uint32_t*>(b + L.tslot);
+    a.tkv = reinterpret_cast<KeySlot*>(b + L.tkv);
     a.k_cap = L.k_cap;
     a.tune = current_tuning();
     return GV_OK;

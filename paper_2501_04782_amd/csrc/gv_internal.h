@@ -46,6 +46,15 @@ __device__ __forceinline__ void store_partials(float* part, uint32_t slot, const
     for (int k = 0; k < PART; ++k) p[k] = v[k];
 }
 
+// A binned intersection: 64-bit sort key (fp32 depth bits << 32 | Gaussian
+// index) and the pre-sort slot of its partial gradients, written by the
+// scatter as one 16-byte store.
+struct __align__(16) KeySlot {
+    uint64_t key;
+    uint32_t slot;
+    uint32_t pad;
+};
+
 struct __align__(32) Record {
     double u, v;
     float a, b, c;   // conic A = [[a, b], [b, c]]
@@ -79,7 +88,7 @@ struct Layout {
     int64_t bin_blocks;    // workgroups per frame of the LDS-histogram binning (0: global atomics)
     size_t status, col4, rec, rect, gcnt, goff, tcnt, toff, tcur, bhist, scan_tmp, tfin, nlast, loss_part, pose_part,
         intr_part, vis,
-        keys, kslot, sgid, sslot, part, tkeys, tslot;
+        kv, sgid, sslot, part, tkv;
     size_t total;
 };
 
@@ -129,13 +138,11 @@ struct Args {
     double* pose_part;    // [blocks][F][12]
     double* intr_part;    // [blocks][4] intrinsics-gradient partials of the projection adjoint
     uint8_t* vis;         // [F][N] contribution flags, or nullptr (not requested)
-    uint64_t* keys;       // [K]
-    uint32_t* kslot;      // [K]
+    KeySlot* kv;          // [K] binned (depth | index) keys with their pre-sort slots
     uint32_t* sgid;       // [K]
     uint32_t* sslot;      // [K]
     float* part;          // [K][PART] (du, dv, dA00, dA01, dA11, do, dr, dg, db) per pre-sort slot
-    uint64_t* tkeys;      // [K] merge scratch of the sort
-    uint32_t* tslot;      // [K]
+    KeySlot* tkv;         // [K] merge scratch of the sort
     int64_t k_cap;
     // image-space inputs/outputs
     float* images;            // [F][3][H][W]

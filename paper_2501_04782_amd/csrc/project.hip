@@ -119,8 +119,11 @@ __device__ __forceinline__ void scatter_one(const Args& a, int f, int64_t g, Nex
                     a.status[ST_OVERFLOW] = 2u;
                     continue;
                 }
-                a.keys[pos] = key;
-                a.kslot[pos] = base + k;
+                KeySlot ks;
+                ks.key = key;
+                ks.slot = base + k;
+                ks.pad = 0u;
+                a.kv[pos] = ks;
                 ++k;
             }
         }

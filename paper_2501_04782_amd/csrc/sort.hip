@@ -44,12 +44,12 @@ __device__ __forceinline__ int next_pow2(int x) {
     return m;
 }
 
-// Number of elements of the sorted run R[0, len) strictly smaller than key.
-__device__ __forceinline__ int64_t lower_rank(const uint64_t* R, int64_t len, uint64_t key) {
+// Number of elements of the sorted run R[0, len) whose key is strictly smaller.
+__device__ __forceinline__ int64_t lower_rank(const KeySlot* R, int64_t len, uint64_t key) {
     int64_t lo = 0, hi = len;
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
-        if (R[mid] < key) lo = mid + 1;
+        if (R[mid].key < key) lo = mid + 1;
         else hi = mid;
     }
     return lo;
@@ -69,8 +69,9 @@ __global__ __launch_bounds__(WG) void k_tile_sort(Args a) {
         // short bucket: every element's final position is the number of
         // smaller keys (keys are unique); no barriers after the load
         for (int i = threadIdx.x; i < n; i += WG) {
-            K[i] = a.keys[s + i];
-            V[i] = a.kslot[s + i];
+            const KeySlot ks = a.kv[s + i];
+            K[i] = ks.key;
+            V[i] = ks.slot;
         }
         __syncthreads();
         const int nn = static_cast<int>(n);
@@ -92,8 +93,9 @@ __global__ __launch_bounds__(WG) void k_tile_sort(Args a) {
     if (n <= CAP) {
         const int m = next_pow2(static_cast<int>(n));
         for (int i = threadIdx.x; i < m; i += WG) {
-            K[i] = i < n ? a.keys[s + i] : ~0ull;
-            V[i] = i < n ? a.kslot[s + i] : 0u;
+            const KeySlot ks = i < n ? a.kv[s + i] : KeySlot{~0ull, 0u, 0u};
+            K[i] = ks.key;
+            V[i] = ks.slot;
         }
         __syncthreads();
         bitonic_lds<CAP>(K, V, m);
@@ -104,23 +106,19 @@ __global__ __launch_bounds__(WG) void k_tile_sort(Args a) {
         return;
     }
     // Long bucket: sorted runs of CAP in place, then pairwise merges.
-    uint64_t* srcK = a.keys + s;
-    uint32_t* srcV = a.kslot + s;
-    uint64_t* dstK = a.tkeys + s;
-    uint32_t* dstV = a.tslot + s;
+    KeySlot* src = a.kv + s;
+    KeySlot* dst = a.tkv + s;
     for (int64_t c0 = 0; c0 < n; c0 += CAP) {
         const int len = static_cast<int>(n - c0 < CAP ? n - c0 : CAP);
         const int m = next_pow2(len);
         for (int i = threadIdx.x; i < m; i += WG) {
-            K[i] = i < len ? srcK[c0 + i] : ~0ull;
-            V[i] = i < len ? srcV[c0 + i] : 0u;
+            const KeySlot ks = i < len ? src[c0 + i] : KeySlot{~0ull, 0u, 0u};
+            K[i] = ks.key;
+            V[i] = ks.slot;
         }
         __syncthreads();
         bitonic_lds<CAP>(K, V, m);
-        for (int i = threadIdx.x; i < len; i += WG) {
-            srcK[c0 + i] = K[i];
-            srcV[c0 + i] = V[i];
-        }
+        for (int i = threadIdx.x; i < len; i += WG) src[c0 + i] = KeySlot{K[i], V[i], 0u};
         __syncthreads();
     }
     for (int64_t w = CAP; w < n; w <<= 1) {
@@ -128,21 +126,22 @@ __global__ __launch_bounds__(WG) void k_tile_sort(Args a) {
             const int64_t mid = lo + w < n ? lo + w : n;
             const int64_t hi = lo + 2 * w < n ? lo + 2 * w : n;
             for (int64_t i = lo + threadIdx.x; i < hi; i += WG) {
-                const uint64_t key = srcK[i];
+                const KeySlot e = src[i];
                 int64_t pos;
-                if (i < mid) pos = lo + (i - lo) + lower_rank(srcK + mid, hi - mid, key);
-                else pos = lo + (i - mid) + lower_rank(srcK + lo, mid - lo, key);
-                dstK[pos] = key;
-                dstV[pos] = srcV[i];
+                if (i < mid) pos = lo + (i - lo) + lower_rank(src + mid, hi - mid, e.key);
+                else pos = lo + (i - mid) + lower_rank(src + lo, mid - lo, e.key);
+                dst[pos] = e;
             }
         }
         __syncthreads();
-        uint64_t* tk = srcK; srcK = dstK; dstK = tk;
-        uint32_t* tv = srcV; srcV = dstV; dstV = tv;
+        KeySlot* t = src;
+        src = dst;
+        dst = t;
     }
     for (int64_t i = threadIdx.x; i < n; i += WG) {
-        a.sgid[s + i] = static_cast<uint32_t>(srcK[i]);
-        a.sslot[s + i] = srcV[i];
+        const KeySlot e = src[i];
+        a.sgid[s + i] = static_cast<uint32_t>(e.key);
+        a.sslot[s + i] = e.slot;
     }
 }
 
