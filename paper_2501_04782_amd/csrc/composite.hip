@@ -214,15 +214,6 @@ __global__ __launch_bounds__(WG) void k_loss_finalize(Args a) {
 // (cross-half swaps for 32 and 16 lanes, DPP within rows for the rest) lane l holds
 // the wave total of value l.  Exact in the order of its additions, which is
 // fixed.
-__device__ __forceinline__ float dpp_f(float x, int ctrl) {
-    switch (ctrl) {  // constant after inlining
-        case 0x128: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x128, 0xf, 0xf, true));
-        case 0x141: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x141, 0xf, 0xf, true));
-        case 0x4E: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x4E, 0xf, 0xf, true));
-        default: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0xB1, 0xf, 0xf, true));
-    }
-}
-
 __device__ __forceinline__ float reduce_scatter64(float (&v)[64], int lane) {
 #pragma unroll
     for (int i = 0; i < 32; ++i) {

@@ -547,6 +547,51 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
+// Value of lane (lane ^ 8) (row rotate by 8), lane 7 - (lane mod 8) (row
+// half-mirror), lane ^ 2 or lane ^ 1 (quad permutations): the DPP moves the
+// reductions below use.
+__device__ __forceinline__ float dpp_f(float x, int ctrl) {
+    switch (ctrl) {  // constant after inlining
+        case 0x128: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x128, 0xf, 0xf, true));
+        case 0x141: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x141, 0xf, 0xf, true));
+        case 0x4E: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x4E, 0xf, 0xf, true));
+        default: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0xB1, 0xf, 0xf, true));
+    }
+}
+
+// Sum of 16 values over the 64 lanes: four halving stages (cross-half swaps
+// for 32 and 16 lanes, DPP for 8 and 4) and two quad additions.  Afterwards
+// the four lanes of quad q hold the wave total of value
+// 8 b5 + 4 b4 + 2 b3 + b2 (b_i the lane's address bits).
+__device__ __forceinline__ float reduce_scatter16(float (&v)[16], int lane) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 8]), false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 4]), false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    const bool b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float keep = b3 ? v[i + 2] : v[i], send = b3 ? v[i] : v[i + 2];
+        v[i] = keep + dpp_f(send, 0x128);
+    }
+    {
+        const float keep = b2 ? v[1] : v[0], send = b2 ? v[0] : v[1];
+        v[0] = keep + dpp_f(send, 0x141);
+    }
+    float x = v[0] + dpp_f(v[0], 0x4E);
+    return x + dpp_f(x, 0xB1);
+}
+
+__device__ __forceinline__ int reduce_scatter16_index(int lane) {
+    return ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+}
+
 // Entry range [s, e) of bucket `seg`, clamped to the intersection capacity.
 __device__ __forceinline__ void bucket_range(const Args& a, int64_t seg, uint32_t& s, uint32_t& e) {
     const uint32_t cap = static_cast<uint32_t>(a.k_cap);

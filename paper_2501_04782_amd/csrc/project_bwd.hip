@@ -121,10 +121,9 @@ __device__ __forceinline__ void adjoint_inputs(const Args& a, int64_t g, const R
 // b) with A01 the single off-diagonal conic parameter (it enters q twice).
 // Writes the gradients w.r.t. the frame's parameter values to gout (mean 0-2,
 // log-scales 3-5, quaternion 6-9, opacity logit 10, colour 11-13) and adds
-// the pose gradient (dL/dRc row-major 0-8, dL/dtc 9-11) to pose[.][tid].
-template <int NT>
+// the pose gradient (dL/dRc row-major 0-8, dL/dtc 9-11) to pose.
 __device__ __forceinline__ void projection_adjoint(const Args& a, const float* Rc, const AdjIn& P,
-                                                   const float d[9], float gout[14], double (*pose)[NT], int tid,
+                                                   const float d[9], float gout[14], float (&pose)[12],
                                                    float gintr[4]) {
     const float A0 = P.A[0], A1 = P.A[1], A2 = P.A[2];
     // gradient w.r.t. the symmetric conic matrix
@@ -162,9 +161,9 @@ __device__ __forceinline__ void projection_adjoint(const Args& a, const float* R
         dJ02 += dT[j] * Rc[2 * 3 + j];
         dJ11 += dT[3 + j] * Rc[1 * 3 + j];
         dJ12 += dT[3 + j] * Rc[2 * 3 + j];
-        pose[0 * 3 + j][tid] += j00 * dT[j];
-        pose[1 * 3 + j][tid] += j11 * dT[3 + j];
-        pose[2 * 3 + j][tid] += j02 * dT[j] + j12 * dT[3 + j];
+        pose[0 * 3 + j] += j00 * dT[j];
+        pose[1 * 3 + j] += j11 * dT[3 + j];
+        pose[2 * 3 + j] += j02 * dT[j] + j12 * dT[3 + j];
     }
     // intrinsics: u = fx mx/mz + cx, v = fy my/mz + cy, J00 = fx/mz,
     // J02 = -fx mx/mz^2, J11 = fy/mz, J12 = -fy my/mz^2
@@ -181,10 +180,10 @@ __device__ __forceinline__ void projection_adjoint(const Args& a, const float* R
     // m = Rc mu + tc
     for (int k = 0; k < 3; ++k) {
         gout[k] = Rc[0 * 3 + k] * dm[0] + Rc[1 * 3 + k] * dm[1] + Rc[2 * 3 + k] * dm[2];
-        pose[9 + k][tid] += dm[k];
+        pose[9 + k] += dm[k];
     }
     for (int i = 0; i < 3; ++i)
-        for (int k = 0; k < 3; ++k) pose[i * 3 + k][tid] += dm[i] * P.mu[k];
+        for (int k = 0; k < 3; ++k) pose[i * 3 + k] += dm[i] * P.mu[k];
     // Sig = M M^T, M = R diag(s): dM = 2 (T^T C T) M, i.e. with U = C T R,
     // dM_ij = 2 s_j (T_0i U_0j + T_1i U_1j); then dR = dM diag(s), ds_j = sum_i dM_ij R_ij
     float U[6];
@@ -267,11 +266,14 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
     const bool live = g < a.n;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t n = a.n;
-    __shared__ double red[PB_THREADS / 64][12];
+    __shared__ double red[PB_THREADS / 64][4];
     // per-thread gradient accumulators (FP64) live in LDS, see AccLayout
     __shared__ double acc[LA::N][PB_THREADS];
-    __shared__ double pacc[12][PB_THREADS];  // this frame's pose contributions (dL/dRc, dL/dtc)
-    __shared__ float camR[9], camT[3], camC[3];
+    // cameras of a chunk of frames (R 0-8, t 9-11, centre 12-14) and the
+    // per-wave pose sums of each of its frames
+    constexpr int FC = 32;
+    __shared__ float cam[FC][15];
+    __shared__ float wpose[FC][PB_THREADS / 64][12];
     __shared__ double iacc[4][PB_THREADS];  // intrinsics gradient, summed over frames
     for (int k = 0; k < 4; ++k) iacc[k][tid] = 0.0;
     // SH coefficient gradients (FP32: at most a few hundred frames are summed)
@@ -295,94 +297,120 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
     if (spline && live && !a.accumulate)
         for (int64_t i = 0; i < static_cast<int64_t>(a.n_ctrl) * 3; ++i) a.g_ctrl[i * n + g] = 0.0f;
 
+    // the next frame's count, slot offset and record are loaded one frame ahead
+    uint32_t cnt_n = 0u, base_n = 0u;
+    Record rec_n = {};
+    auto fetch = [&](int f) {
+        const int64_t i = static_cast<int64_t>(f) * a.n + g;
+        cnt_n = live ? a.gcnt[i] : 0u;
+        base_n = live ? a.goff[i] : 0u;
+        if (cnt_n) rec_n = a.rec[i];
+    };
+    fetch(0);
 #pragma unroll 1
-    for (int f = 0; f < a.frames; ++f) {
-        __syncthreads();
-        if (tid == 0) {
-            const CamD c = load_camera(a.poses + 7 * f);
-            for (int k = 0; k < 9; ++k) camR[k] = c.ok ? static_cast<float>(c.R[k]) : 0.0f;
-            for (int k = 0; k < 3; ++k) camT[k] = c.ok ? static_cast<float>(c.t[k]) : 0.0f;
+    for (int f0 = 0; f0 < a.frames; f0 += FC) {
+        const int nf = a.frames - f0 < FC ? a.frames - f0 : FC;
+        __syncthreads();  // the previous chunk's cameras and pose sums are consumed
+        if (tid < nf) {
+            const CamD c = load_camera(a.poses + 7 * (f0 + tid));
+            for (int k = 0; k < 9; ++k) cam[tid][k] = c.ok ? static_cast<float>(c.R[k]) : 0.0f;
+            for (int k = 0; k < 3; ++k) cam[tid][9 + k] = c.ok ? static_cast<float>(c.t[k]) : 0.0f;
             for (int i = 0; i < 3; ++i)
-                camC[i] = c.ok ? static_cast<float>(-(c.R[0 * 3 + i] * c.t[0] + c.R[1 * 3 + i] * c.t[1] +
-                                                     c.R[2 * 3 + i] * c.t[2]))
-                               : 0.0f;
+                cam[tid][12 + i] = c.ok ? static_cast<float>(-(c.R[0 * 3 + i] * c.t[0] + c.R[1 * 3 + i] * c.t[1] +
+                                                               c.R[2 * 3 + i] * c.t[2]))
+                                        : 0.0f;
         }
         __syncthreads();
-        for (int k = 0; k < 12; ++k) pacc[k][tid] = 0.0;
-        const int64_t i = static_cast<int64_t>(f) * a.n + g;
-        uint32_t cnt = live ? a.gcnt[i] : 0u;
-        const uint32_t base = live ? a.goff[i] : 0u;
-        if (static_cast<int64_t>(base) + cnt > a.k_cap) cnt = 0u;  // only after an internal error
-        if (cnt) {
-            double dd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+        for (int fi = 0; fi < nf; ++fi) {
+            const int f = f0 + fi;
+            uint32_t cnt = cnt_n;
+            const uint32_t base = base_n;
+            const Record rec = rec_n;
+            if (f + 1 < a.frames) fetch(f + 1);
+            if (static_cast<int64_t>(base) + cnt > a.k_cap) cnt = 0u;  // only after an internal error
+            const float* camR = cam[fi];
+            const float* camT = cam[fi] + 9;
+            const float* camC = cam[fi] + 12;
+            float pose[12];
+            for (int k = 0; k < 12; ++k) pose[k] = 0.0f;
+            if (cnt) {
+                double dd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll 2
-            for (uint32_t k = 0; k < cnt; ++k) {
-                const float* pp = a.part + static_cast<int64_t>(base + k) * PART;
+                for (uint32_t k = 0; k < cnt; ++k) {
+                    const float* pp = a.part + static_cast<int64_t>(base + k) * PART;
 #pragma unroll
-                for (int m = 0; m < PART; ++m) dd[m] += pp[m];
-            }
-            float d[9];
-            for (int k = 0; k < 9; ++k) d[k] = static_cast<float>(dd[k]);
-            const float t = a.times ? a.times[f] : a.t0;
-            const Record rec = a.rec[i];
-            AdjIn P;
-            adjoint_inputs<DYN>(a, g, rec, camR, camT, t, P);
-            float go[14], gi[4];
-            projection_adjoint<PB_THREADS>(a, camR, P, d, go, pacc, tid, gi);
-            if (a.g_intr)
-                for (int k = 0; k < 4; ++k) iacc[k][tid] += gi[k];
-            if (SH) {
-                float dv[3];
-                const float dc[3] = {go[11], go[12], go[13]};
-                sh_adjoint<PB_THREADS>(a, g, P, camC, dc, acc_sh, tid, dv);
-                for (int j = 0; j < 3; ++j) {
-                    go[j] += dv[j];
-                    // C = -Rc^T tc, dL/dC = -dv: dL/dtc = Rc dv, dL/dRc[j][i] = tc[j] dv[i]
-                    pacc[9 + j][tid] += camR[j * 3 + 0] * dv[0] + camR[j * 3 + 1] * dv[1] + camR[j * 3 + 2] * dv[2];
-                    for (int i = 0; i < 3; ++i) pacc[j * 3 + i][tid] += camT[j] * dv[i];
+                    for (int m = 0; m < PART; ++m) dd[m] += pp[m];
                 }
-            }
-            for (int k = 0; k < 14; ++k) acc[k][tid] += go[k];
-            const double t1 = t, t2 = t1 * t1, t3 = t2 * t1;
-            if (!DYN && a.mean_coeffs)
-                for (int k = 0; k < 3; ++k) {
-                    acc[LA::CUBIC + k][tid] += go[k] * t1;
-                    acc[LA::CUBIC + 3 + k][tid] += go[k] * t2;
-                    acc[LA::CUBIC + 6 + k][tid] += go[k] * t3;
-                }
-            if (DYN) {
-                if (spline) {
-                    if (P.span != win) {
-                        flush_window();
-                        win = P.span;
+                float d[9];
+                for (int k = 0; k < 9; ++k) d[k] = static_cast<float>(dd[k]);
+                const float t = a.times ? a.times[f] : a.t0;
+                AdjIn P;
+                adjoint_inputs<DYN>(a, g, rec, camR, camT, t, P);
+                float go[14], gi[4];
+                projection_adjoint(a, camR, P, d, go, pose, gi);
+                if (a.g_intr)
+                    for (int k = 0; k < 4; ++k) iacc[k][tid] += gi[k];
+                if (SH) {
+                    float dv[3];
+                    const float dc[3] = {go[11], go[12], go[13]};
+                    sh_adjoint<PB_THREADS>(a, g, P, camC, dc, acc_sh, tid, dv);
+                    for (int j = 0; j < 3; ++j) {
+                        go[j] += dv[j];
+                        // C = -Rc^T tc, dL/dC = -dv: dL/dtc = Rc dv, dL/dRc[j][i] = tc[j] dv[i]
+                        pose[9 + j] += camR[j * 3 + 0] * dv[0] + camR[j * 3 + 1] * dv[1] + camR[j * 3 + 2] * dv[2];
+                        for (int i = 0; i < 3; ++i) pose[j * 3 + i] += camT[j] * dv[i];
                     }
-                    for (int r = 0; r < 4; ++r)
-                        for (int k = 0; k < 3; ++k) acc[LA::WIN + 3 * r + k][tid] += P.N[r] * go[k];
                 }
-                if (a.scale_coeffs)
+                for (int k = 0; k < 14; ++k) acc[k][tid] += go[k];
+                const double t1 = t, t2 = t1 * t1, t3 = t2 * t1;
+                if (!DYN && a.mean_coeffs)
                     for (int k = 0; k < 3; ++k) {
-                        acc[LA::SCALE + k][tid] += go[3 + k] * t1;
-                        acc[LA::SCALE + 3 + k][tid] += go[3 + k] * t2;
-                        acc[LA::SCALE + 6 + k][tid] += go[3 + k] * t3;
+                        acc[LA::CUBIC + k][tid] += go[k] * t1;
+                        acc[LA::CUBIC + 3 + k][tid] += go[k] * t2;
+                        acc[LA::CUBIC + 6 + k][tid] += go[k] * t3;
                     }
-                if (a.quat_coeffs)
-                    for (int k = 0; k < 4; ++k) {
-                        acc[LA::QUAT + k][tid] += go[6 + k] * t1;
-                        acc[LA::QUAT + 4 + k][tid] += go[6 + k] * t2;
-                        acc[LA::QUAT + 8 + k][tid] += go[6 + k] * t3;
+                if (DYN) {
+                    if (spline) {
+                        if (P.span != win) {
+                            flush_window();
+                            win = P.span;
+                        }
+                        for (int r = 0; r < 4; ++r)
+                            for (int k = 0; k < 3; ++k) acc[LA::WIN + 3 * r + k][tid] += P.N[r] * go[k];
                     }
+                    if (a.scale_coeffs)
+                        for (int k = 0; k < 3; ++k) {
+                            acc[LA::SCALE + k][tid] += go[3 + k] * t1;
+                            acc[LA::SCALE + 3 + k][tid] += go[3 + k] * t2;
+                            acc[LA::SCALE + 6 + k][tid] += go[3 + k] * t3;
+                        }
+                    if (a.quat_coeffs)
+                        for (int k = 0; k < 4; ++k) {
+                            acc[LA::QUAT + k][tid] += go[6 + k] * t1;
+                            acc[LA::QUAT + 4 + k][tid] += go[6 + k] * t2;
+                            acc[LA::QUAT + 8 + k][tid] += go[6 + k] * t3;
+                        }
+                }
+            }
+            if (a.g_poses) {  // wave sums of this frame's pose contributions
+                float v[16];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) v[k] = pose[k];
+#pragma unroll
+                for (int k = 12; k < 16; ++k) v[k] = 0.0f;
+                const float x = reduce_scatter16(v, lane);
+                const int idx = reduce_scatter16_index(lane);
+                if ((lane & 3) == 0 && idx < 12) wpose[fi][w][idx] = x;
             }
         }
         if (a.g_poses) {
-            for (int k = 0; k < 12; ++k) {
-                const double v = wave_sum_f64(pacc[k][tid]);
-                if (lane == 0) red[w][k] = v;
-            }
             __syncthreads();
-            if (tid < 12) {
+            for (int q = tid; q < nf * 12; q += PB_THREADS) {
+                const int fi = q / 12, k = q - fi * 12;
                 double v = 0.0;
-                for (int ww = 0; ww < PB_THREADS / 64; ++ww) v += red[ww][tid];
-                a.pose_part[(static_cast<int64_t>(blockIdx.x) * a.frames + f) * 12 + tid] = v;
+                for (int ww = 0; ww < PB_THREADS / 64; ++ww) v += static_cast<double>(wpose[fi][ww][k]);
+                a.pose_part[(static_cast<int64_t>(blockIdx.x) * a.frames + f0 + fi) * 12 + k] = v;
             }
         }
     }

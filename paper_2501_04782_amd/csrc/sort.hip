@@ -74,19 +74,35 @@ __global__ __launch_bounds__(WG) void k_tile_sort(Args a) {
             V[i] = ks.slot;
         }
         __syncthreads();
+        // each thread ranks element tid and, for buckets longer than WG,
+        // element tid + WG, in one pass over the keys
         const int nn = static_cast<int>(n);
-        for (int i = threadIdx.x; i < nn; i += WG) {
-            const uint64_t key = K[i];
-            int r0 = 0, r1 = 0;
+        const int i0 = threadIdx.x, i1 = threadIdx.x + WG;
+        const uint64_t k0 = i0 < nn ? K[i0] : ~0ull, k1 = i1 < nn ? K[i1] : ~0ull;
+        int r0 = 0, r1 = 0;
+        if (nn > WG) {
+            for (int k = 0; k < nn; ++k) {
+                const uint64_t x = K[k];
+                r0 += x < k0 ? 1 : 0;
+                r1 += x < k1 ? 1 : 0;
+            }
+        } else if (i0 < nn) {
+            int q0 = 0, q1 = 0;
             int k = 0;
             for (; k + 1 < nn; k += 2) {
-                r0 += K[k] < key ? 1 : 0;
-                r1 += K[k + 1] < key ? 1 : 0;
+                q0 += K[k] < k0 ? 1 : 0;
+                q1 += K[k + 1] < k0 ? 1 : 0;
             }
-            if (k < nn) r0 += K[k] < key ? 1 : 0;
-            const int rank = r0 + r1;
-            a.sgid[s + rank] = static_cast<uint32_t>(key);
-            a.sslot[s + rank] = V[i];
+            if (k < nn) q0 += K[k] < k0 ? 1 : 0;
+            r0 = q0 + q1;
+        }
+        if (i0 < nn) {
+            a.sgid[s + r0] = static_cast<uint32_t>(k0);
+            a.sslot[s + r0] = V[i0];
+        }
+        if (i1 < nn) {
+            a.sgid[s + r1] = static_cast<uint32_t>(k1);
+            a.sslot[s + r1] = V[i1];
         }
         return;
     }
