@@ -258,22 +258,36 @@ __device__ __forceinline__ void sh_adjoint(const Args& a, int64_t g, const AdjIn
     for (int j = 0; j < 3; ++j) dv[j] = (dd[j] - d[j] * dot) * iv;
 }
 
+// SPLIT waves share each Gaussian: wave h of a workgroup takes the h-th
+// contiguous part of the frames for the workgroup's 128 / SPLIT Gaussians, and
+// the parts' accumulators are added in a fixed order at the end (more waves
+// in flight for this latency-bound kernel).  The dynamic variant keeps one
+// wave per Gaussian: its control-point window adds to memory as it moves.
+template <bool DYN>
+constexpr int pb_split() { return DYN ? 1 : 2; }
+
 template <bool DYN, bool SH>
 __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
     if (overflowed(a.status)) return;
     using LA = AccLayout<DYN>;
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * PB_THREADS + threadIdx.x;
-    const bool live = g < a.n;
+    constexpr int SPLIT = pb_split<DYN>();
+    constexpr int GPB = PB_THREADS / SPLIT;  // Gaussians per workgroup
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int h = tid / GPB;                 // which part of the frames
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * GPB + (tid % GPB);
+    const bool live = g < a.n;
     const int64_t n = a.n;
+    const int fpart = (a.frames + SPLIT - 1) / SPLIT;
+    const int fb = h * fpart < a.frames ? h * fpart : a.frames;
+    const int fe = fb + fpart < a.frames ? fb + fpart : a.frames;
     __shared__ double red[PB_THREADS / 64][4];
     // per-thread gradient accumulators (FP64) live in LDS, see AccLayout
     __shared__ double acc[LA::N][PB_THREADS];
     // cameras of a chunk of frames (R 0-8, t 9-11, centre 12-14) and the
     // per-wave pose sums of each of its frames
     constexpr int FC = 32;
-    __shared__ float cam[FC][15];
-    __shared__ float wpose[FC][PB_THREADS / 64][12];
+    __shared__ float cam[SPLIT][FC][15];
+    __shared__ float wpose[SPLIT][FC][PB_THREADS / 64 / SPLIT][12];
     __shared__ double iacc[4][PB_THREADS];  // intrinsics gradient, summed over frames
     for (int k = 0; k < 4; ++k) iacc[k][tid] = 0.0;
     // SH coefficient gradients (FP32: at most a few hundred frames are summed)
@@ -306,19 +320,25 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
         base_n = live ? a.goff[i] : 0u;
         if (cnt_n) rec_n = a.rec[i];
     };
-    fetch(0);
+    if (fb < fe) fetch(fb);
 #pragma unroll 1
-    for (int f0 = 0; f0 < a.frames; f0 += FC) {
-        const int nf = a.frames - f0 < FC ? a.frames - f0 : FC;
+    for (int c0 = 0; c0 < fpart; c0 += FC) {  // the same chunk count in every wave (uniform barriers)
+        const int f0 = fb + c0;
+        const int nf = fe - f0 < FC ? (fe - f0 > 0 ? fe - f0 : 0) : FC;
         __syncthreads();  // the previous chunk's cameras and pose sums are consumed
-        if (tid < nf) {
-            const CamD c = load_camera(a.poses + 7 * (f0 + tid));
-            for (int k = 0; k < 9; ++k) cam[tid][k] = c.ok ? static_cast<float>(c.R[k]) : 0.0f;
-            for (int k = 0; k < 3; ++k) cam[tid][9 + k] = c.ok ? static_cast<float>(c.t[k]) : 0.0f;
-            for (int i = 0; i < 3; ++i)
-                cam[tid][12 + i] = c.ok ? static_cast<float>(-(c.R[0 * 3 + i] * c.t[0] + c.R[1 * 3 + i] * c.t[1] +
-                                                               c.R[2 * 3 + i] * c.t[2]))
-                                        : 0.0f;
+        for (int q = tid; q < SPLIT * FC; q += PB_THREADS) {
+            const int hh = q / FC, fi = q % FC;
+            const int ff = hh * fpart + c0 + fi;
+            const int fend = (hh + 1) * fpart < a.frames ? (hh + 1) * fpart : a.frames;
+            if (ff < fend) {
+                const CamD c = load_camera(a.poses + 7 * ff);
+                for (int k = 0; k < 9; ++k) cam[hh][fi][k] = c.ok ? static_cast<float>(c.R[k]) : 0.0f;
+                for (int k = 0; k < 3; ++k) cam[hh][fi][9 + k] = c.ok ? static_cast<float>(c.t[k]) : 0.0f;
+                for (int i = 0; i < 3; ++i)
+                    cam[hh][fi][12 + i] = c.ok ? static_cast<float>(-(c.R[0 * 3 + i] * c.t[0] +
+                                                                      c.R[1 * 3 + i] * c.t[1] + c.R[2 * 3 + i] * c.t[2]))
+                                               : 0.0f;
+            }
         }
         __syncthreads();
 #pragma unroll 1
@@ -327,11 +347,11 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
             uint32_t cnt = cnt_n;
             const uint32_t base = base_n;
             const Record rec = rec_n;
-            if (f + 1 < a.frames) fetch(f + 1);
+            if (f + 1 < fe) fetch(f + 1);
             if (static_cast<int64_t>(base) + cnt > a.k_cap) cnt = 0u;  // only after an internal error
-            const float* camR = cam[fi];
-            const float* camT = cam[fi] + 9;
-            const float* camC = cam[fi] + 12;
+            const float* camR = cam[h][fi];
+            const float* camT = cam[h][fi] + 9;
+            const float* camC = cam[h][fi] + 12;
             float pose[12];
             for (int k = 0; k < 12; ++k) pose[k] = 0.0f;
             if (cnt) {
@@ -401,16 +421,20 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
                 for (int k = 12; k < 16; ++k) v[k] = 0.0f;
                 const float x = reduce_scatter16(v, lane);
                 const int idx = reduce_scatter16_index(lane);
-                if ((lane & 3) == 0 && idx < 12) wpose[fi][w][idx] = x;
+                if ((lane & 3) == 0 && idx < 12) wpose[h][fi][w % (PB_THREADS / 64 / SPLIT)][idx] = x;
             }
         }
         if (a.g_poses) {
             __syncthreads();
-            for (int q = tid; q < nf * 12; q += PB_THREADS) {
-                const int fi = q / 12, k = q - fi * 12;
+            constexpr int WPH = PB_THREADS / 64 / SPLIT;  // waves per part
+            for (int q = tid; q < SPLIT * FC * 12; q += PB_THREADS) {
+                const int hh = q / (FC * 12), r = q % (FC * 12), fi = r / 12, k = r % 12;
+                const int ff = hh * fpart + c0 + fi;
+                const int fend = (hh + 1) * fpart < a.frames ? (hh + 1) * fpart : a.frames;
+                if (ff >= fend) continue;
                 double v = 0.0;
-                for (int ww = 0; ww < PB_THREADS / 64; ++ww) v += static_cast<double>(wpose[fi][ww][k]);
-                a.pose_part[(static_cast<int64_t>(blockIdx.x) * a.frames + f0 + fi) * 12 + k] = v;
+                for (int ww = 0; ww < WPH; ++ww) v += static_cast<double>(wpose[hh][fi][ww][k]);
+                a.pose_part[(static_cast<int64_t>(blockIdx.x) * a.frames + ff) * 12 + k] = v;
             }
         }
     }
@@ -427,7 +451,23 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
             a.intr_part[static_cast<int64_t>(blockIdx.x) * 4 + tid] = v;
         }
     }
-    if (!live) return;
+    if (SPLIT > 1) {  // add the later parts' accumulators to part 0's, in order
+        __syncthreads();
+        if (h == 0) {
+            for (int k = 0; k < LA::N; ++k) {
+                double v = acc[k][tid];
+                for (int hh = 1; hh < SPLIT; ++hh) v += acc[k][tid + hh * GPB];
+                acc[k][tid] = v;
+            }
+            if (SH)
+                for (int k = 0; k < 3 * sh_count(a.sh_degree); ++k) {
+                    float v = acc_sh[k][tid];
+                    for (int hh = 1; hh < SPLIT; ++hh) v += acc_sh[k][tid + hh * GPB];
+                    acc_sh[k][tid] = v;
+                }
+        }
+    }
+    if (!live || h != 0) return;
     if (spline) flush_window();
     auto put = [&](float* dst, int64_t idx, double v) {
         if (!dst) return;
@@ -506,12 +546,21 @@ __global__ __launch_bounds__(256) void k_intr_finalize(Args a, int64_t n_blocks)
     }
 }
 
-int64_t project_bwd_blocks(int64_t n) { return (n + PB_THREADS - 1) / PB_THREADS; }
+// Upper bound over the variants (the split one has the most workgroups).
+int64_t project_bwd_blocks(int64_t n) {
+    constexpr int gpb = PB_THREADS / pb_split<false>();
+    return (n + gpb - 1) / gpb;
+}
+
+static int64_t blocks_for(int64_t n, bool dyn) {
+    const int gpb = PB_THREADS / (dyn ? pb_split<true>() : pb_split<false>());
+    return (n + gpb - 1) / gpb;
+}
 
 hipError_t launch_project_bwd(const Args& a, hipStream_t stream) {
-    const int64_t nb = project_bwd_blocks(a.n);
     const bool dyn = a.n_ctrl > 0 || a.scale_coeffs || a.quat_coeffs;
     const bool sh = a.sh_degree > 0;
+    const int64_t nb = blocks_for(a.n, dyn);
     const dim3 grid(static_cast<uint32_t>(nb > 0 ? nb : 1)), block(PB_THREADS);
     if (nb > 0) {
         if (dyn && sh) hipLaunchKernelGGL((k_project_bwd<true, true>), grid, block, 0, stream, a);
