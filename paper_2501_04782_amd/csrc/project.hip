@@ -71,6 +71,9 @@ __device__ __forceinline__ uint32_t project_and_count(const Args& a, int f, int6
         int tx0, tx1, ty0, ty1;
         if (tile_span(P.u - hx, P.u + hx, a.tiles_x, tx0, tx1) && tile_span(P.v - hy, P.v + hy, a.tiles_y, ty0, ty1)) {
             const double ca = r.a, cb = r.b, cc = r.c;
+            const int rw = tx1 - tx0 + 1;
+            const bool small = rw * (ty1 - ty0 + 1) <= 64;
+            uint64_t mask = 0;
             for (int ty = ty0; ty <= ty1; ++ty)
                 for (int tx = tx0; tx <= tx1; ++tx) {
                     double x0, x1, y0, y1;
@@ -78,8 +81,10 @@ __device__ __forceinline__ uint32_t project_and_count(const Args& a, int f, int6
                     if (ellipse_meets_box<double>(r.u, r.v, ca, cb, cc, x0, x1, y0, y1, BIN_Q_SLACK)) {
                         ++cnt;
                         tally(ty * a.tiles_x + tx);
+                        if (small) mask |= 1ull << ((ty - ty0) * rw + (tx - tx0));
                     }
                 }
+            a.tmask[i] = mask;
             a.rec[i] = r;
             a.rect[i] = make_uint2(static_cast<uint32_t>(tx0) | (static_cast<uint32_t>(tx1) << 16),
                                    static_cast<uint32_t>(ty0) | (static_cast<uint32_t>(ty1) << 16));
@@ -103,29 +108,43 @@ __device__ __forceinline__ void scatter_one(const Args& a, int f, int64_t g, Nex
     const int tx0 = rc.x & 0xffff, tx1 = rc.x >> 16, ty0 = rc.y & 0xffff, ty1 = rc.y >> 16;
     const uint64_t key = (static_cast<uint64_t>(__float_as_uint(r.depth)) << 32) | static_cast<uint64_t>(g);
     const uint32_t base = a.goff[i];
-    const double ca = r.a, cb = r.b, cc = r.c;
     const int64_t tile0 = static_cast<int64_t>(f) * a.tiles;
     uint32_t k = 0;
+    auto emit = [&](int tx, int ty) {
+        const int tl = ty * a.tiles_x + tx;
+        const uint32_t pos = next(tl);
+        // the counts bound every write; a mismatch is an internal error,
+        // reported instead of written out of bounds
+        if (pos >= a.toff[tile0 + tl + 1] || k >= cnt) {
+            a.status[ST_OVERFLOW] = 2u;
+            return;
+        }
+        KeySlot ks;
+        ks.key = key;
+        ks.slot = base + k;
+        ks.pad = 0u;
+        a.kv[pos] = ks;
+        ++k;
+    };
+    const int rw = tx1 - tx0 + 1;
+    if (rw * (ty1 - ty0 + 1) <= 64) {
+        // the count pass left the tiles that passed as a row-major mask over
+        // the rectangle: walk its set bits (same order as the loops below)
+        uint64_t m = a.tmask[i];
+        while (m) {
+            const int b = __builtin_ctzll(m);
+            m &= m - 1;
+            const int ry = b / rw;
+            emit(tx0 + (b - ry * rw), ty0 + ry);
+        }
+        return;
+    }
+    const double ca = r.a, cb = r.b, cc = r.c;
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) {
             double x0, x1, y0, y1;
             tile_box(tx, ty, a.width, a.height, x0, x1, y0, y1);
-            if (ellipse_meets_box<double>(r.u, r.v, ca, cb, cc, x0, x1, y0, y1, BIN_Q_SLACK)) {
-                const int tl = ty * a.tiles_x + tx;
-                const uint32_t pos = next(tl);
-                // the counts bound every write; a mismatch is an internal
-                // error, reported instead of written out of bounds
-                if (pos >= a.toff[tile0 + tl + 1] || k >= cnt) {
-                    a.status[ST_OVERFLOW] = 2u;
-                    continue;
-                }
-                KeySlot ks;
-                ks.key = key;
-                ks.slot = base + k;
-                ks.pad = 0u;
-                a.kv[pos] = ks;
-                ++k;
-            }
+            if (ellipse_meets_box<double>(r.u, r.v, ca, cb, cc, x0, x1, y0, y1, BIN_Q_SLACK)) emit(tx, ty);
         }
 }
 
