@@ -11,39 +11,53 @@
 
 namespace gv {
 
+// One staged entry, 48 bytes.  The conic is stored pre-multiplied by
+// K_EXP = -log2(e)/2, so the per-pixel exponent q' = K_EXP q is the quadratic
+// form itself and the falloff exp(-q/2) is one exp2.  `thr` folds the 3-sigma
+// cut (q <= 9) and the opacity floor (o exp(-q/2) >= 1/255) into a single
+// test q' >= thr; the inert padding entry has thr = +inf.
 struct Staged {
-    float4 p0;  // (u, v) in tile-local pixel-centre coordinates, conic a, 2b
-    float4 p1;  // conic c, opacity, r, g
+    float4 p0;  // (u, v) in tile-local pixel-centre coordinates, K a, K 2b
+    float4 p1;  // K c, opacity, r, g
+    float4 p2;  // b, thr, Gaussian index (bits), unused
 };
+constexpr uint32_t STAGED_BYTES = sizeof(Staged);
+static_assert(STAGED_BYTES == 48, "three 16-byte LDS reads per entry");
+constexpr float INV_K_EXP = 1.0f / K_EXP;
 
-// Gaussian footprint and opacity at a pixel: q = d^T A d with d = pixel - centre,
-// alpha = min(0.99, o exp(-q/2)).  Shared by both kernels so that the backward
-// pass re-derives exactly the forward pass's values and decisions.
+// Scaled footprint q' = K_EXP d^T A d with d = pixel - centre, and the entry's
+// threshold.  Shared by every compositing kernel, forward and adjoint, so
+// that all of them re-derive the same values and decisions.
 __device__ __forceinline__ float footprint_q(float dx, float dy, const float4& p0, const float4& p1) {
     return __builtin_fmaf(p1.x * dy, dy, dx * __builtin_fmaf(p0.z, dx, p0.w * dy));
 }
 
-__device__ __forceinline__ float gauss_falloff(float q) { return __builtin_amdgcn_exp2f(q * K_EXP); }
+__device__ __forceinline__ float entry_threshold(float o) {
+    // -log2(255 o) is where o 2^q' falls to 1/255; +inf for o = 0
+    return fmaxf(Q_MAX * K_EXP, -__builtin_amdgcn_logf(255.0f * o));
+}
 
 // Stage entry `idx` of the tile: gather its record and colour, move the centre
 // to tile-local coordinates (exact subtraction in FP64, then one rounding),
-// and compute the quadrant mask.
+// and compute the quadrant mask.  (a, b, c) returns the unscaled conic.
 __device__ __forceinline__ void stage_entry(const Args& a, int f, uint32_t gid, double ox, double oy, int xlim,
-                                            int ylim, Staged& st, float& blue, uint32_t& mask) {
+                                            int ylim, Staged& st, uint32_t& mask, float3& conic) {
     if (gid >= static_cast<uint64_t>(a.n)) {  // only after an internal error: stage an inert entry
         st.p0 = make_float4(0.f, 0.f, 0.f, 0.f);
         st.p1 = make_float4(0.f, 0.f, 0.f, 0.f);
-        blue = 0.f;
+        st.p2 = make_float4(0.f, __builtin_inff(), 0.f, 0.f);
         mask = 0u;
+        conic = make_float3(0.f, 0.f, 0.f);
         return;
     }
     const Record r = a.rec[static_cast<int64_t>(f) * a.n + gid];
     const ColorOp co = a.col4[static_cast<int64_t>(f) * a.col_stride + gid];
     const float lu = static_cast<float>(r.u - ox);
     const float lv = static_cast<float>(r.v - oy);
-    st.p0 = make_float4(lu, lv, r.a, 2.0f * r.b);
-    st.p1 = make_float4(r.c, co.o, co.r, co.g);
-    blue = co.b;
+    st.p0 = make_float4(lu, lv, K_EXP * r.a, K_EXP * (2.0f * r.b));
+    st.p1 = make_float4(K_EXP * r.c, co.o, co.r, co.g);
+    st.p2 = make_float4(co.b, entry_threshold(co.o), __uint_as_float(gid), 0.f);
+    conic = make_float3(r.a, r.b, r.c);
     uint32_t m = 0;
     for (int qd = 0; qd < 4; ++qd) {
         const int x0 = (qd & 1) * 8, y0 = (qd >> 1) * 8;
@@ -54,6 +68,31 @@ __device__ __forceinline__ void stage_entry(const Args& a, int f, uint32_t gid, 
             m |= 1u << qd;
     }
     mask = m;
+}
+
+// Inert entry that pads the wave lists to whole groups (never reaches a pixel).
+__device__ __forceinline__ void stage_inert(Staged& st) {
+    st.p0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    st.p1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    st.p2 = make_float4(0.f, __builtin_inff(), 0.f, 0.f);
+}
+
+__device__ __forceinline__ const Staged& staged_at(const Staged* sh, uint32_t off) {
+    return *reinterpret_cast<const Staged*>(reinterpret_cast<const char*>(sh) + off);
+}
+
+// Per-entry partials from the wave-summed moments of D = alpha dL/dalpha
+// (sum D dx, sum D dy, sum D dx^2, sum D dx dy, sum D dy^2, sum D) and the
+// colour sums, with the unscaled conic (a, b, c) and opacity o:
+// (dL/du, dL/dv, dL/dA00, dL/dA01, dL/dA11, dL/do, dL/dr, dL/dg, dL/db).
+__device__ __forceinline__ void finish_partials(float (&v)[PART], float ca, float cb, float cc, float o) {
+    const float X = v[0], Y = v[1];
+    v[0] = ca * X + cb * Y;
+    v[1] = cb * X + cc * Y;
+    v[2] = -0.5f * v[2];
+    v[3] = -v[3];
+    v[4] = -0.5f * v[4];
+    v[5] = o > 0.0f ? v[5] / o : 0.0f;
 }
 
 // Entries per unrolled group of the quadrant forward loop.
@@ -78,18 +117,13 @@ __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
     const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
     const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
 
-    // sh[B] is an inert entry (opacity 0) that pads the wave lists to whole groups
+    // sh[B] is an inert entry that pads the wave lists to whole groups; the
+    // lists hold byte offsets into sh
     __shared__ Staged sh[B + 1];
-    __shared__ float shb[B + 1];
     __shared__ uint32_t shm[B];
     __shared__ float red[WG / 64];
-    __shared__ __align__(16) uint16_t wl[WG / 64][B + FWD_GROUP];
-    __shared__ uint32_t shg[VIS ? B : 1];
-    if (tid == 0) {
-        sh[B].p0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        sh[B].p1 = make_float4(0.f, 0.f, 0.f, 0.f);
-        shb[B] = 0.f;
-    }
+    __shared__ __align__(16) uint32_t wl[WG / 64][B + FWD_GROUP];
+    if (tid == 0) stage_inert(sh[B]);
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
     uint32_t last = 0;
@@ -101,14 +135,11 @@ __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
         const uint32_t nb = min(static_cast<uint32_t>(B), e - b0);
         if (tid < static_cast<int>(nb)) {
             Staged st;
-            float blue;
             uint32_t m;
-            const uint32_t gid = a.sgid[b0 + tid];
-            stage_entry(a, f, gid, ox, oy, xlim, ylim, st, blue, m);
+            float3 conic;
+            stage_entry(a, f, a.sgid[b0 + tid], ox, oy, xlim, ylim, st, m, conic);
             sh[tid] = st;
-            shb[tid] = blue;
             shm[tid] = m;
-            if (VIS) shg[tid] = gid;
         }
         __syncthreads();
         if (__ballot(!done) == 0) continue;  // wave-uniform; the barriers are outside
@@ -118,53 +149,54 @@ __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
             const int j = j0 + lane;
             const bool on = j < static_cast<int>(nb) && ((shm[j] >> w) & 1u);
             const uint64_t bal = __ballot(on);
-            if (on) wl[w][cnt + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<uint16_t>(j);
+            if (on) wl[w][cnt + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<uint32_t>(j) * STAGED_BYTES;
             cnt += __popcll(bal);
         }
-        if (lane < FWD_GROUP) wl[w][cnt + lane] = static_cast<uint16_t>(B);
+        if (lane < FWD_GROUP) wl[w][cnt + lane] = static_cast<uint32_t>(B) * STAGED_BYTES;
         __builtin_amdgcn_wave_barrier();
         // Branch-free groups: an entry that misses the pixel, or reaches it
         // after it terminated, adds a zero weight and leaves T unchanged.
+        // loff: byte offset of this lane's last entry taken in this batch.
+        int loff = -1;
         for (int g = 0; g < cnt; g += FWD_GROUP) {
-            static_assert(FWD_GROUP == 8, "one 16-byte read of the wave list per group");
-            const uint4 jj = *reinterpret_cast<const uint4*>(&wl[w][g]);
-            const uint32_t jw[4] = {jj.x, jj.y, jj.z, jj.w};
+            static_assert(FWD_GROUP == 8, "two 16-byte reads of the wave list per group");
+            const uint4 ja = *reinterpret_cast<const uint4*>(&wl[w][g]);
+            const uint4 jb = *reinterpret_cast<const uint4*>(&wl[w][g + 4]);
+            const uint32_t jo[FWD_GROUP] = {ja.x, ja.y, ja.z, ja.w, jb.x, jb.y, jb.z, jb.w};
             float4 P0[FWD_GROUP], P1[FWD_GROUP];
-            float CB[FWD_GROUP];
+            float2 P2[FWD_GROUP];
 #pragma unroll
             for (int r = 0; r < FWD_GROUP; ++r) {
-                const int j = (jw[r >> 1] >> (16 * (r & 1))) & 0xffff;
-                P0[r] = sh[j].p0;
-                P1[r] = sh[j].p1;
-                CB[r] = shb[j];
+                const Staged& st = staged_at(sh, jo[r]);
+                P0[r] = st.p0;
+                P1[r] = st.p1;
+                P2[r] = make_float2(st.p2.x, st.p2.y);
             }
 #pragma unroll
             for (int r = 0; r < FWD_GROUP; ++r) {
-                const int j = (jw[r >> 1] >> (16 * (r & 1))) & 0xffff;
                 const float4 p0 = P0[r];
                 const float4 p1 = P1[r];
-                const float cb = CB[r];
                 const float dx = fx - p0.x, dy = fy - p0.y;
                 const float q = footprint_q(dx, dy, p0, p1);
-                const float al = fminf(ALPHA_MAX, p1.y * gauss_falloff(q));
-                const bool hit = !done && q <= Q_MAX && al >= ALPHA_MIN;
-                const float tn = T * (1.0f - al);
-                const bool stop = hit && tn < T_MIN;  // stop before this entry
-                const bool take = hit && !stop;
-                done = done || stop;
+                const bool hit = !done && q >= P2[r].y;
+                const float al = fminf(ALPHA_MAX, p1.y * __builtin_amdgcn_exp2f(q));
+                const float tn = __builtin_fmaf(-al, T, T);
+                const bool take = hit && tn >= T_MIN;  // else stop before this entry
+                done = done || (hit != take);
                 const float wgt = take ? al * T : 0.0f;
                 c0 = __builtin_fmaf(p1.z, wgt, c0);
                 c1 = __builtin_fmaf(p1.w, wgt, c1);
-                c2 = __builtin_fmaf(cb, wgt, c2);
+                c2 = __builtin_fmaf(P2[r].x, wgt, c2);
                 T = take ? tn : T;
-                last = take ? b0 + j - s + 1 : last;
+                loff = take ? static_cast<int>(jo[r]) : loff;
                 if (VIS && __ballot(take) != 0 && lane == 0) {
-                    const uint32_t gid = shg[j];
+                    const uint32_t gid = __float_as_uint(staged_at(sh, jo[r]).p2.z);
                     if (gid < static_cast<uint64_t>(a.n)) a.vis[static_cast<int64_t>(f) * a.n + gid] = 1;
                 }
             }
             if (__ballot(!done) == 0) break;
         }
+        if (loff >= 0) last = b0 - s + static_cast<uint32_t>(loff) / STAGED_BYTES + 1;
     }
 
     float sq = 0.0f;
@@ -275,17 +307,13 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
     const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
     const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
 
-    // sh[B] is an inert entry (opacity 0) that pads the wave lists to whole groups
+    // sh[B] is an inert entry that pads the wave lists to whole groups; the
+    // lists hold byte offsets into sh
     __shared__ Staged sh[B + 1];
-    __shared__ float shb[B + 1];
     __shared__ uint32_t shm[B];
     __shared__ float acc[WG / 64][9][B];
-    __shared__ uint16_t wl[WG / 64][B + RS_GROUP];
-    if (tid == 0) {
-        sh[B].p0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        sh[B].p1 = make_float4(0.f, 0.f, 0.f, 0.f);
-        shb[B] = 0.f;
-    }
+    __shared__ uint32_t wl[WG / 64][B + RS_GROUP];
+    if (tid == 0) stage_inert(sh[B]);
     __shared__ uint32_t smax;
     __shared__ uint32_t wlast[WG / 64];
 
@@ -335,11 +363,10 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
         const uint32_t nb = static_cast<uint32_t>(bend - b0);
         if (tid < static_cast<int>(nb)) {
             Staged st;
-            float blue;
             uint32_t m;
-            stage_entry(a, f, a.sgid[b0 + tid], ox, oy, xlim, ylim, st, blue, m);
+            float3 conic;
+            stage_entry(a, f, a.sgid[b0 + tid], ox, oy, xlim, ylim, st, m, conic);
             sh[tid] = st;
-            shb[tid] = blue;
             shm[tid] = m;
         }
         __syncthreads();
@@ -350,10 +377,13 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
             const int j = j0 - lane;
             const bool on = j >= 0 && ((shm[j] >> w) & 1u) && b0 + j - s < wmax;
             const uint64_t bal = __ballot(on);
-            if (on) wl[w][cnt + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<uint16_t>(j);
+            if (on) wl[w][cnt + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<uint32_t>(j) * STAGED_BYTES;
             cnt += __popcll(bal);
         }
-        if (lane < RS_GROUP) wl[w][cnt + lane] = static_cast<uint16_t>(B);
+        if (lane < RS_GROUP) wl[w][cnt + lane] = static_cast<uint32_t>(B) * STAGED_BYTES;
+        // this pixel's entries in the batch lie below byte offset lim
+        const int64_t rl = static_cast<int64_t>(last) - (static_cast<int64_t>(b0) - s);
+        const int lim = static_cast<int>(rl < 0 ? 0 : (rl > B ? B : rl)) * static_cast<int>(STAGED_BYTES);
         __builtin_amdgcn_wave_barrier();
         for (int g = 0; g < cnt; g += RS_GROUP) {
             // Branch-free: an entry that does not reach the pixel (or the inert
@@ -362,31 +392,28 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
             // and gives zero partials.
             float P[64];
             P[63] = 0.0f;
-            int J[RS_GROUP];
+            uint32_t J[RS_GROUP];
             float4 P0[RS_GROUP], P1[RS_GROUP];
-            float CB[RS_GROUP];
+            float2 P2[RS_GROUP];
 #pragma unroll
             for (int r = 0; r < RS_GROUP; ++r) J[r] = wl[w][g + r];
 #pragma unroll
             for (int r = 0; r < RS_GROUP; ++r) {
-                P0[r] = sh[J[r]].p0;
-                P1[r] = sh[J[r]].p1;
-                CB[r] = shb[J[r]];
+                const Staged& st = staged_at(sh, J[r]);
+                P0[r] = st.p0;
+                P1[r] = st.p1;
+                P2[r] = make_float2(st.p2.x, st.p2.y);
             }
 #pragma unroll
             for (int r = 0; r < RS_GROUP; ++r) {
-                const int j = J[r];
-                const uint32_t rel = b0 + j - s;
                 const float4 p0 = P0[r];
                 const float4 p1 = P1[r];
-                const float cb = CB[r];
                 const float dx = fx - p0.x, dy = fy - p0.y;
                 const float q = footprint_q(dx, dy, p0, p1);
-                const float G = gauss_falloff(q);
+                const bool on = (static_cast<int>(J[r]) < lim) & (q >= P2[r].y);
+                const float G = __builtin_amdgcn_exp2f(q);
                 const float raw = p1.y * G;
-                const float al0 = fminf(ALPHA_MAX, raw);
-                const bool on = rel < last && q <= Q_MAX && al0 >= ALPHA_MIN;
-                const float al = on ? al0 : 0.0f;
+                const float al = on ? fminf(ALPHA_MAX, raw) : 0.0f;
                 const float inv = __builtin_amdgcn_rcpf(1.0f - al);
                 const float Tj = T * inv;  // transmittance in front of this entry
                 const float wgt = al * Tj;
@@ -395,27 +422,27 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
                 P[r * 9 + 8] = wgt * g2;
                 // dL/dalpha = sum_c g_c (c_c T_j - S_c / (1 - alpha))
                 //           = (T gc - GS) / (1 - alpha), gc = sum_c g_c c_c
-                const float gc = __builtin_fmaf(g2, cb, __builtin_fmaf(g1, p1.w, g0 * p1.z));
+                const float gc = __builtin_fmaf(g2, P2[r].x, __builtin_fmaf(g1, p1.w, g0 * p1.z));
                 const float dal = inv * __builtin_fmaf(T, gc, -GS);
                 GS = __builtin_fmaf(gc, wgt, GS);
                 T = Tj;
-                // a clamped alpha has no gradient w.r.t. the opacity or footprint;
-                // with D = alpha dL/dalpha, dL/dq = -D/2, and the footprint
-                // partials are moments of D over the pixel offsets, to which
-                // the conic is applied once per entry after the reduction
-                const float dalc = on && raw < ALPHA_MAX ? dal : 0.0f;
-                const float D = al * dalc;
+                // a clamped alpha has no gradient w.r.t. the opacity or footprint
+                // (alpha = 0 already zeroes entries that do not reach the pixel);
+                // with D = alpha dL/dalpha, dL/dq = -D/2 and dL/do = D/o, and the
+                // footprint partials are moments of D over the pixel offsets, to
+                // which the conic is applied once per entry after the reduction
+                const float D = raw < ALPHA_MAX ? al * dal : 0.0f;
                 const float X = D * dx, Y = D * dy;
                 P[r * 9 + 0] = X;
                 P[r * 9 + 1] = Y;
                 P[r * 9 + 2] = X * dx;
                 P[r * 9 + 3] = X * dy;
                 P[r * 9 + 4] = Y * dy;
-                P[r * 9 + 5] = dalc * G;
+                P[r * 9 + 5] = D;
             }
             const float tot = reduce_scatter64(P, lane);
             const int r = lane / 9;
-            if (lane < 9 * RS_GROUP && g + r < cnt) acc[w][lane - 9 * r][wl[w][g + r]] = tot;
+            if (lane < 9 * RS_GROUP && g + r < cnt) acc[w][lane - 9 * r][wl[w][g + r] / STAGED_BYTES] = tot;
         }
         __syncthreads();
         if (tid < static_cast<int>(nb)) {
@@ -428,15 +455,8 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
                     if (((m >> ww) & 1u) && rel < wlast[ww]) x += acc[ww][k][tid];
                 v[k] = x;
             }
-            // moments -> (du, dv, dA00, dA01, dA11); conic (a, b, c) with b the off-diagonal
             const Staged st = sh[tid];
-            const float ca = st.p0.z, cb2 = st.p0.w, cc = st.p1.x;
-            const float X = v[0], Y = v[1];
-            v[0] = ca * X + 0.5f * cb2 * Y;
-            v[1] = 0.5f * cb2 * X + cc * Y;
-            v[2] = -0.5f * v[2];
-            v[3] = -v[3];
-            v[4] = -0.5f * v[4];
+            finish_partials(v, st.p0.z * INV_K_EXP, 0.5f * st.p0.w * INV_K_EXP, st.p1.x * INV_K_EXP, st.p1.y);
             const uint32_t slot = a.sslot[b0 + tid];
             if (slot < a.k_cap) {
                 store_partials(a.part, slot, v);
@@ -514,8 +534,10 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x, int lane) {
 // Stage the batch [b0, b0 + nb) and its quadrant masks (threads t < B).  The
 // compacted kernels read staged entries at lane-dependent indices, so they are
 // staged structure-of-arrays (4-byte stride: lanes reading different entries
-// fall into different banks): sv[0..8][j] = local u, local v, conic a, 2b, c,
-// opacity, r, g, b.
+// fall into different banks): sv[0..SV - 1][j] = local u, local v, K a, K 2b,
+// K c, opacity, r, g, b, threshold (as in Staged).
+constexpr int SV = 10;
+
 template <int B>
 __device__ __forceinline__ void stage_batch_masks(const Args& a, int f, uint32_t b0, uint32_t nb, double ox, double oy,
                                                   int xlim, int ylim, float (*sv)[B], uint64_t (*qmask)[B]) {
@@ -524,13 +546,13 @@ __device__ __forceinline__ void stage_batch_masks(const Args& a, int f, uint32_t
         uint64_t qm[4] = {0ull, 0ull, 0ull, 0ull};
         if (t < static_cast<int>(nb)) {
             Staged st;
-            float blue;
             uint32_t m;
-            stage_entry(a, f, a.sgid[b0 + t], ox, oy, xlim, ylim, st, blue, m);
+            float3 cn;
+            stage_entry(a, f, a.sgid[b0 + t], ox, oy, xlim, ylim, st, m, cn);
             sv[0][t] = st.p0.x; sv[1][t] = st.p0.y; sv[2][t] = st.p0.z; sv[3][t] = st.p0.w;
             sv[4][t] = st.p1.x; sv[5][t] = st.p1.y; sv[6][t] = st.p1.z; sv[7][t] = st.p1.w;
-            sv[8][t] = blue;
-            if (m) coverage_masks(st.p0.x, st.p0.y, st.p0.z, 0.5f * st.p0.w, st.p1.x, xlim, ylim, qm);
+            sv[8][t] = st.p2.x; sv[9][t] = st.p2.y;
+            if (m) coverage_masks(st.p0.x, st.p0.y, cn.x, cn.y, cn.z, xlim, ylim, qm);
         }
         for (int q = 0; q < 4; ++q) qmask[q][t] = qm[q];
     }
@@ -564,7 +586,7 @@ __global__ __launch_bounds__(WG) void k_composite_fwd_c(Args a) {
     const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
     const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
 
-    __shared__ float sv[9][B];
+    __shared__ float sv[SV][B];
     __shared__ uint64_t qmask[4][B];
     __shared__ float red[WG / 64];
 
@@ -598,10 +620,9 @@ __global__ __launch_bounds__(WG) void k_composite_fwd_c(Args a) {
                 const float4 p1 = make_float4(sv[4][j], sv[5][j], 0.0f, 0.0f);
                 const float dx = fx - p0.x, dy = fy - p0.y;
                 const float q = footprint_q(dx, dy, p0, p1);
-                if (q > Q_MAX) continue;
-                const float al = fminf(ALPHA_MAX, p1.y * gauss_falloff(q));
-                if (al < ALPHA_MIN) continue;
-                const float tn = T * (1.0f - al);
+                if (!(q >= sv[9][j])) continue;
+                const float al = fminf(ALPHA_MAX, p1.y * __builtin_amdgcn_exp2f(q));
+                const float tn = __builtin_fmaf(-al, T, T);
                 if (tn < T_MIN) {
                     done = true;
                     break;
@@ -662,7 +683,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
     const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
     const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
 
-    __shared__ float sv[9][B];
+    __shared__ float sv[SV][B];
     __shared__ uint64_t qmask[4][B];
     __shared__ float acc[WG / 64][9][B];
     __shared__ uint32_t smax;
@@ -735,11 +756,9 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
                 const float4 p1 = make_float4(sv[4][j], sv[5][j], sv[6][j], sv[7][j]);
                 const float dx = fx - p0.x, dy = fy - p0.y;
                 const float q = footprint_q(dx, dy, p0, p1);
-                if (q > Q_MAX) continue;
-                const float G = gauss_falloff(q);
-                const float raw = p1.y * G;
+                if (!(q >= sv[9][j])) continue;
+                const float raw = p1.y * __builtin_amdgcn_exp2f(q);
                 const float al = fminf(ALPHA_MAX, raw);
-                if (al < ALPHA_MIN) continue;
                 const float inv = 1.0f / (1.0f - al);
                 const float Tj = T * inv;
                 const float wgt = al * Tj;
@@ -753,15 +772,15 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
                 atomicAdd(ac + 6 * B, wgt * g0);
                 atomicAdd(ac + 7 * B, wgt * g1);
                 atomicAdd(ac + 8 * B, wgt * g2);
-                if (raw < ALPHA_MAX) {
-                    const float dq = -0.5f * al * dal;
-                    const float hb = 0.5f * p0.w;
-                    atomicAdd(ac + 0 * B, -2.0f * dq * (p0.z * dx + hb * dy));
-                    atomicAdd(ac + 1 * B, -2.0f * dq * (hb * dx + p1.x * dy));
-                    atomicAdd(ac + 2 * B, dq * dx * dx);
-                    atomicAdd(ac + 3 * B, 2.0f * dq * dx * dy);
-                    atomicAdd(ac + 4 * B, dq * dy * dy);
-                    atomicAdd(ac + 5 * B, dal * G);
+                if (raw < ALPHA_MAX) {  // moments of D = alpha dL/dalpha, as in the quadrant adjoint
+                    const float D = al * dal;
+                    const float X = D * dx, Y = D * dy;
+                    atomicAdd(ac + 0 * B, X);
+                    atomicAdd(ac + 1 * B, Y);
+                    atomicAdd(ac + 2 * B, X * dx);
+                    atomicAdd(ac + 3 * B, X * dy);
+                    atomicAdd(ac + 4 * B, Y * dy);
+                    atomicAdd(ac + 5 * B, D);
                 }
             }
         }
@@ -769,6 +788,8 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
         if (tid < static_cast<int>(nb)) {
             float v[9];
             for (int k = 0; k < 9; ++k) v[k] = (acc[0][k][tid] + acc[1][k][tid]) + (acc[2][k][tid] + acc[3][k][tid]);
+            finish_partials(v, sv[2][tid] * INV_K_EXP, 0.5f * sv[3][tid] * INV_K_EXP, sv[4][tid] * INV_K_EXP,
+                            sv[5][tid]);
             const uint32_t slot = a.sslot[b0 + tid];
             if (slot < a.k_cap) {
                 store_partials(a.part, slot, v);
