@@ -142,11 +142,15 @@ typedef struct {
  * batch: entries staged in LDS per round of a tile's compositing loop
  * (64, 128 or 256); sort_cap: longest per-tile list sorted in one LDS pass
  * (1024, 2048 or 4096; longer lists are sorted in chunks and merged);
- * compact: bit 0 (forward) / bit 1 (backward) select compositing kernels that
- * first build per-pixel entry lists from closed-form coverage masks instead of
- * letting every staged entry visit every pixel of its 8x8 quadrant;
- * bwd_batch: the backward's LDS batch (0 = same as batch).  Results are
- * identical; only the speed differs. */
+ * compact: compositing kernel choice, 0..7.  The forward by default lets each
+ * 16-lane row of a wave walk the entries meeting its 4x4 pixel block; bit 2
+ * selects the forward in which the whole wave walks the entries meeting its
+ * 8x8 quadrant (the backward always does); bit 0 (forward) / bit 1
+ * (backward), which take precedence, select kernels that first build
+ * per-pixel entry lists from closed-form coverage masks;
+ * bwd_batch: the backward's LDS batch (0 = same as batch).  Images are
+ * identical under every setting and gradients equal up to the order of
+ * floating-point summation; only the speed differs. */
 typedef struct {
     int32_t batch;
     int32_t sort_cap;

@@ -565,7 +565,7 @@ gv_status gv_set_tuning(const gv_tuning* t) {
     if (!batch_ok(t->batch)) return GV_ERR_INVALID_ARG;
     if (t->bwd_batch != 0 && !batch_ok(t->bwd_batch)) return GV_ERR_INVALID_ARG;
     if (t->sort_cap != 1024 && t->sort_cap != 2048 && t->sort_cap != 4096) return GV_ERR_INVALID_ARG;
-    if (t->compact < 0 || t->compact > 3) return GV_ERR_INVALID_ARG;
+    if (t->compact < 0 || t->compact > 7) return GV_ERR_INVALID_ARG;
     Tuning n = current_tuning();
     n.batch = t->batch;
     n.bwd_batch = t->bwd_batch ? t->bwd_batch : t->batch;
@@ -590,17 +590,19 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
     const Tuning saved = current_tuning();
     gv_status result = (he == hipSuccess) ? GV_OK : hip_status(he);
     // The stages are independent (the forward's outputs do not depend on its
-    // kernel variant), so every stage keeps its own fastest setting: six runs
-    // cover the forward kernel (batch x quadrant / compacted), the quadrant
-    // backward (batch) and each sort capacity twice.  The compacted backward
-    // (LDS atomics per lane) measured ten times slower than the quadrant
-    // backward on every clip tried, so it is left to explicit gv_set_tuning.
+    // kernel variant), so every stage keeps its own fastest setting: eight
+    // runs cover the forward kernel (sub-block / quadrant / compacted, at
+    // two or three batch sizes each), the quadrant backward (batch) and each
+    // sort capacity at least twice.  The compacted backward (LDS atomics per
+    // lane) measured ten times slower than the quadrant backward on every
+    // clip tried, so it is left to explicit gv_set_tuning.
     struct Cand { int batch, compact, cap; };
-    const Cand cands[6] = {{64, 0, 1024}, {128, 0, 2048}, {256, 0, 4096},
-                           {64, 1, 2048}, {128, 1, 4096}, {256, 1, 1024}};
-    float fwd_ms[6], bwd_ms[6], sort_ms[6], total_ms[6];
+    constexpr int NC = 8;
+    const Cand cands[NC] = {{64, 0, 1024}, {128, 0, 2048}, {256, 0, 4096}, {128, 4, 4096},
+                            {256, 4, 1024}, {64, 1, 2048},  {128, 1, 1024}, {256, 1, 2048}};
+    float fwd_ms[NC], bwd_ms[NC], sort_ms[NC], total_ms[NC];
     constexpr int REPS = 2;
-    for (int c = 0; c < 6 && result == GV_OK; ++c) {
+    for (int c = 0; c < NC && result == GV_OK; ++c) {
         Tuning t = saved;
         t.batch = t.bwd_batch = cands[c].batch;
         t.compact = cands[c].compact;
@@ -630,14 +632,14 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
     Tuning best = saved;
     if (result == GV_OK) {
         int bf = 0, bb = 0, bs = 0;
-        for (int c = 1; c < 6; ++c) {
+        for (int c = 1; c < NC; ++c) {
             if (fwd_ms[c] < fwd_ms[bf]) bf = c;
             if (bwd_ms[c] < bwd_ms[bb]) bb = c;
             if (sort_ms[c] < sort_ms[bs]) bs = c;
         }
         best.batch = cands[bf].batch;
         best.bwd_batch = cands[bb].batch;
-        best.compact = (cands[bf].compact & 1) | (cands[bb].compact & 2);
+        best.compact = (cands[bf].compact & 5) | (cands[bb].compact & 2);
         best.sort_cap = cands[bs].cap;
     }
     install_tuning(result == GV_OK ? best : saved);

@@ -37,16 +37,15 @@ __device__ __forceinline__ float entry_threshold(float o) {
     return fmaxf(Q_MAX * K_EXP, -__builtin_amdgcn_logf(255.0f * o));
 }
 
-// Stage entry `idx` of the tile: gather its record and colour, move the centre
-// to tile-local coordinates (exact subtraction in FP64, then one rounding),
-// and compute the quadrant mask.  (a, b, c) returns the unscaled conic.
-__device__ __forceinline__ void stage_entry(const Args& a, int f, uint32_t gid, double ox, double oy, int xlim,
-                                            int ylim, Staged& st, uint32_t& mask, float3& conic) {
+// Stage entry `gid` of the tile: gather its record and colour and move the
+// centre to tile-local coordinates (exact subtraction in FP64, then one
+// rounding).  `conic` returns the unscaled conic (a, b, c).
+__device__ __forceinline__ void stage_entry(const Args& a, int f, uint32_t gid, double ox, double oy, Staged& st,
+                                            float3& conic) {
     if (gid >= static_cast<uint64_t>(a.n)) {  // only after an internal error: stage an inert entry
         st.p0 = make_float4(0.f, 0.f, 0.f, 0.f);
         st.p1 = make_float4(0.f, 0.f, 0.f, 0.f);
         st.p2 = make_float4(0.f, __builtin_inff(), 0.f, 0.f);
-        mask = 0u;
         conic = make_float3(0.f, 0.f, 0.f);
         return;
     }
@@ -58,16 +57,23 @@ __device__ __forceinline__ void stage_entry(const Args& a, int f, uint32_t gid, 
     st.p1 = make_float4(K_EXP * r.c, co.o, co.r, co.g);
     st.p2 = make_float4(co.b, entry_threshold(co.o), __uint_as_float(gid), 0.f);
     conic = make_float3(r.a, r.b, r.c);
+}
+
+// 4-bit mask of the 8x8 quadrants whose pixel-centre box the entry's
+// (slightly inflated) 3-sigma ellipse meets.
+__device__ __forceinline__ uint32_t quadrant_mask(const Staged& st, float3 cn, int xlim, int ylim) {
+    if (cn.x == 0.f && cn.y == 0.f && cn.z == 0.f) return 0u;  // inert
     uint32_t m = 0;
     for (int qd = 0; qd < 4; ++qd) {
         const int x0 = (qd & 1) * 8, y0 = (qd >> 1) * 8;
         const int x1 = min(x0 + 7, xlim), y1 = min(y0 + 7, ylim);
         if (x0 > x1 || y0 > y1) continue;
-        if (ellipse_meets_box<float>(lu, lv, r.a, r.b, r.c, static_cast<float>(x0), static_cast<float>(x1),
-                                     static_cast<float>(y0), static_cast<float>(y1), SUB_Q_SLACK))
+        if (ellipse_meets_box<float>(st.p0.x, st.p0.y, cn.x, cn.y, cn.z, static_cast<float>(x0),
+                                     static_cast<float>(x1), static_cast<float>(y0), static_cast<float>(y1),
+                                     SUB_Q_SLACK))
             m |= 1u << qd;
     }
-    mask = m;
+    return m;
 }
 
 // Inert entry that pads the wave lists to whole groups (never reaches a pixel).
@@ -135,11 +141,10 @@ __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
         const uint32_t nb = min(static_cast<uint32_t>(B), e - b0);
         if (tid < static_cast<int>(nb)) {
             Staged st;
-            uint32_t m;
             float3 conic;
-            stage_entry(a, f, a.sgid[b0 + tid], ox, oy, xlim, ylim, st, m, conic);
+            stage_entry(a, f, a.sgid[b0 + tid], ox, oy, st, conic);
             sh[tid] = st;
-            shm[tid] = m;
+            shm[tid] = quadrant_mask(st, conic, xlim, ylim);
         }
         __syncthreads();
         if (__ballot(!done) == 0) continue;  // wave-uniform; the barriers are outside
@@ -363,11 +368,10 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
         const uint32_t nb = static_cast<uint32_t>(bend - b0);
         if (tid < static_cast<int>(nb)) {
             Staged st;
-            uint32_t m;
             float3 conic;
-            stage_entry(a, f, a.sgid[b0 + tid], ox, oy, xlim, ylim, st, m, conic);
+            stage_entry(a, f, a.sgid[b0 + tid], ox, oy, st, conic);
             sh[tid] = st;
-            shm[tid] = m;
+            shm[tid] = quadrant_mask(st, conic, xlim, ylim);
         }
         __syncthreads();
         // this wave's entries, back to front (ballot compaction; the list is
@@ -546,13 +550,12 @@ __device__ __forceinline__ void stage_batch_masks(const Args& a, int f, uint32_t
         uint64_t qm[4] = {0ull, 0ull, 0ull, 0ull};
         if (t < static_cast<int>(nb)) {
             Staged st;
-            uint32_t m;
             float3 cn;
-            stage_entry(a, f, a.sgid[b0 + t], ox, oy, xlim, ylim, st, m, cn);
+            stage_entry(a, f, a.sgid[b0 + t], ox, oy, st, cn);
             sv[0][t] = st.p0.x; sv[1][t] = st.p0.y; sv[2][t] = st.p0.z; sv[3][t] = st.p0.w;
             sv[4][t] = st.p1.x; sv[5][t] = st.p1.y; sv[6][t] = st.p1.z; sv[7][t] = st.p1.w;
             sv[8][t] = st.p2.x; sv[9][t] = st.p2.y;
-            if (m) coverage_masks(st.p0.x, st.p0.y, cn.x, cn.y, cn.z, xlim, ylim, qm);
+            if (quadrant_mask(st, cn, xlim, ylim)) coverage_masks(st.p0.x, st.p0.y, cn.x, cn.y, cn.z, xlim, ylim, qm);
         }
         for (int q = 0; q < 4; ++q) qmask[q][t] = qm[q];
     }
@@ -799,9 +802,223 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Sub-block forward (the default forward).  Each 16-lane row of a wave owns a
+// 4x4 block of the wave's quadrant (row r: block (r & 1, r >> 1); lane l of
+// the row: pixel (l & 3, l >> 2) of the block) and walks its own list of the
+// staged entries whose ellipse meets that block.  The rows advance together,
+// so a wave takes as many steps as its longest block list rather than the
+// length of its quadrant list (0.8x on the 3DGS benchmark clip: the near
+// Gaussians, composited first, are large), and each staged read is a
+// broadcast within a row.  Per pixel the arithmetic is that of the quadrant
+// loop, so images, final transmittances and last indices are identical.
+// ---------------------------------------------------------------------------
+
+// 16-bit mask of the 4x4 blocks (bit 4 q + r: block r of quadrant q) that the
+// entry's slightly inflated 3-sigma ellipse meets.  Per band of four pixel
+// rows, the ellipse restricted to the band is convex, so its x-extent is an
+// interval whose ends lie at the ellipse's right- and leftmost points clamped
+// into the band; a block is kept if its columns meet that interval (widened
+// by a rounding margin).
+__device__ __forceinline__ uint32_t block_mask(const Staged& st, float3 cn, int xlim, int ylim) {
+    const float a = cn.x, b = cn.y, c = cn.z;
+    if (a == 0.f && b == 0.f && c == 0.f) return 0u;  // inert
+    const float lu = st.p0.x, lv = st.p0.y;
+    const float det = static_cast<float>(static_cast<double>(a) * c - static_cast<double>(b) * b);
+    uint32_t all = 0;
+    for (int by = 0; by < 4; ++by)
+        for (int bx = 0; bx < 4; ++bx)
+            if (4 * bx <= xlim && 4 * by <= ylim) all |= 1u << (4 * (2 * (by >> 1) + (bx >> 1)) + 2 * (by & 1) + (bx & 1));
+    if (!(det > 0.0f) || !(a > 0.0f) || !(c > 0.0f)) return all;  // degenerate conic: the exact test decides
+    // hardware sqrt and reciprocals (about 1 ulp): far inside the margins below
+    const float rdet = __builtin_amdgcn_rcpf(det);
+    const float hy = __builtin_amdgcn_sqrtf(SUB_Q_SLACK * a * rdet);  // half-extent in y
+    const float hx = __builtin_amdgcn_sqrtf(SUB_Q_SLACK * c * rdet);  // half-extent in x
+    const float dyr = -b * hx * __builtin_amdgcn_rcpf(c);             // dy of the rightmost point
+    const float aq = a * SUB_Q_SLACK;
+    const float inva = __builtin_amdgcn_rcpf(a);
+    const float tol = 1e-3f + 1e-4f * hy;
+    uint32_t m = 0;
+    for (int by = 0; by < 4; ++by) {
+        const int y0 = 4 * by;
+        if (y0 > ylim) break;
+        const int y1 = min(y0 + 3, ylim);
+        const float d0 = static_cast<float>(y0) - lv, d1 = static_cast<float>(y1) - lv;
+        if (d0 > hy + tol || d1 < -hy - tol) continue;
+        float lo = fmaxf(d0, -hy), hi = fminf(d1, hy);
+        if (lo > hi) lo = hi = fminf(fmaxf(0.5f * (d0 + d1), -hy), hy);  // within the tolerance of a tip
+        const float dr = fminf(fmaxf(dyr, lo), hi);
+        const float dl = fminf(fmaxf(-dyr, lo), hi);
+        const float sr = __builtin_amdgcn_sqrtf(fmaxf(0.0f, aq - det * dr * dr));
+        const float sl = __builtin_amdgcn_sqrtf(fmaxf(0.0f, aq - det * dl * dl));
+        const float xr = (-b * dr + sr) * inva;
+        const float xl = (-b * dl - sl) * inva;
+        const float eps = 0.01f + 1e-4f * (fabsf(xl) + fabsf(xr));
+        const float xlo = lu + xl - eps, xhi = lu + xr + eps;
+        for (int bx = 0; bx < 4; ++bx) {
+            const int x0 = 4 * bx;
+            if (x0 > xlim) break;
+            const int x1 = min(x0 + 3, xlim);
+            if (static_cast<float>(x0) <= xhi && static_cast<float>(x1) >= xlo)
+                m |= 1u << (4 * (2 * (by >> 1) + (bx >> 1)) + 2 * (by & 1) + (bx & 1));
+        }
+    }
+    return m;
+}
+
+// Build the four block lists of wave w over the staged batch, front to back,
+// each padded with the inert entry to `steps` entries, a multiple of G shared
+// by the four lists.  Lists hold byte offsets into the staged array.
+template <int B, int G>
+__device__ __forceinline__ int build_block_lists(uint32_t (*wl)[B + G], const uint32_t* shm, int w, int lane,
+                                                 uint32_t nb) {
+    int c[4] = {0, 0, 0, 0};
+    for (int j0 = 0; j0 < static_cast<int>(nb); j0 += 64) {
+        const int j = j0 + lane;
+        const uint32_t m = j < static_cast<int>(nb) ? (shm[j] >> (4 * w)) & 0xFu : 0u;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bool on = (m >> r) & 1u;
+            const uint64_t bal = __ballot(on);
+            if (on) wl[r][c[r] + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<uint32_t>(j) * STAGED_BYTES;
+            c[r] += __popcll(bal);
+        }
+    }
+    const int cmax = max(max(c[0], c[1]), max(c[2], c[3]));
+    const int steps = (cmax + G - 1) / G * G;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        for (int k = c[r] + lane; k < steps; k += 64) wl[r][k] = static_cast<uint32_t>(B) * STAGED_BYTES;
+    return steps;
+}
+
+template <int B, bool VIS>
+__global__ __launch_bounds__(WG) void k_composite_fwd_sb(Args a) {
+    if (overflowed(a.status)) return;
+    const int f = blockIdx.y;
+    const int tile = blockIdx.x;
+    const int txi = tile % a.tiles_x, tyi = tile / a.tiles_x;
+    const int tid = threadIdx.x, lane = tid & 63, row = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lx = ((w & 1) << 3) | ((row & 1) << 2) | (lane & 3);
+    const int ly = ((w >> 1) << 3) | ((row >> 1) << 2) | ((lane >> 2) & 3);
+    const int px = txi * TILE + lx, py = tyi * TILE + ly;
+    const bool inside = px < a.width && py < a.height;
+    const int64_t seg = static_cast<int64_t>(f) * a.tiles + tile;
+    uint32_t s, e;
+    bucket_range(a, seg, s, e);
+    const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
+    const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
+
+    __shared__ Staged sh[B + 1];
+    __shared__ uint32_t shm[B];
+    __shared__ float red[WG / 64];
+    __shared__ __align__(16) uint32_t wl[WG / 64][4][B + FWD_GROUP];
+    if (tid == 0) stage_inert(sh[B]);
+
+    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    uint32_t last = 0;
+    bool done = !inside;
+    const float fx = static_cast<float>(lx), fy = static_cast<float>(ly);
+    const uint32_t* my = wl[w][row];
+
+    for (uint32_t b0 = s; b0 < e; b0 += B) {
+        if (__syncthreads_count(!done) == 0) break;
+        const uint32_t nb = min(static_cast<uint32_t>(B), e - b0);
+        if (tid < static_cast<int>(nb)) {
+            Staged st;
+            float3 conic;
+            stage_entry(a, f, a.sgid[b0 + tid], ox, oy, st, conic);
+            sh[tid] = st;
+            shm[tid] = block_mask(st, conic, xlim, ylim);
+        }
+        __syncthreads();
+        if (__ballot(!done) == 0) continue;  // wave-uniform; the barriers are outside
+        const int steps = build_block_lists<B, FWD_GROUP>(wl[w], shm, w, lane, nb);
+        __builtin_amdgcn_wave_barrier();
+        // Branch-free groups, as in the quadrant loop; loff: byte offset of
+        // this lane's last entry taken in this batch.
+        int loff = -1;
+        for (int g = 0; g < steps; g += FWD_GROUP) {
+            static_assert(FWD_GROUP == 8, "two 16-byte reads of the block list per group");
+            const uint4 ja = *reinterpret_cast<const uint4*>(my + g);
+            const uint4 jb = *reinterpret_cast<const uint4*>(my + g + 4);
+            const uint32_t jo[FWD_GROUP] = {ja.x, ja.y, ja.z, ja.w, jb.x, jb.y, jb.z, jb.w};
+            float4 P0[FWD_GROUP], P1[FWD_GROUP];
+            float2 P2[FWD_GROUP];
+#pragma unroll
+            for (int r = 0; r < FWD_GROUP; ++r) {
+                const Staged& st = staged_at(sh, jo[r]);
+                P0[r] = st.p0;
+                P1[r] = st.p1;
+                P2[r] = make_float2(st.p2.x, st.p2.y);
+            }
+#pragma unroll
+            for (int r = 0; r < FWD_GROUP; ++r) {
+                const float4 p0 = P0[r];
+                const float4 p1 = P1[r];
+                const float dx = fx - p0.x, dy = fy - p0.y;
+                const float q = footprint_q(dx, dy, p0, p1);
+                const bool hit = !done && q >= P2[r].y;
+                const float al = fminf(ALPHA_MAX, p1.y * __builtin_amdgcn_exp2f(q));
+                const float tn = __builtin_fmaf(-al, T, T);
+                const bool take = hit && tn >= T_MIN;  // else stop before this entry
+                done = done || (hit != take);
+                const float wgt = take ? al * T : 0.0f;
+                c0 = __builtin_fmaf(p1.z, wgt, c0);
+                c1 = __builtin_fmaf(p1.w, wgt, c1);
+                c2 = __builtin_fmaf(P2[r].x, wgt, c2);
+                T = take ? tn : T;
+                loff = take ? static_cast<int>(jo[r]) : loff;
+                if (VIS) {
+                    const uint64_t bal = __ballot(take);
+                    if (((bal >> (16 * row)) & 0xFFFFull) != 0ull && (lane & 15) == 0) {
+                        const uint32_t gid = __float_as_uint(staged_at(sh, jo[r]).p2.z);
+                        if (gid < static_cast<uint64_t>(a.n)) a.vis[static_cast<int64_t>(f) * a.n + gid] = 1;
+                    }
+                }
+            }
+            if (__ballot(!done) == 0) break;
+        }
+        if (loff >= 0) last = b0 - s + static_cast<uint32_t>(loff) / STAGED_BYTES + 1;
+    }
+
+    float sq = 0.0f;
+    if (inside) {
+        const int64_t P = static_cast<int64_t>(a.width) * a.height;
+        const int64_t pix = static_cast<int64_t>(py) * a.width + px;
+        c0 = __builtin_fmaf(T, a.bg[0], c0);
+        c1 = __builtin_fmaf(T, a.bg[1], c1);
+        c2 = __builtin_fmaf(T, a.bg[2], c2);
+        float* img = a.images + static_cast<int64_t>(f) * 3 * P + pix;
+        img[0] = c0;
+        img[P] = c1;
+        img[2 * P] = c2;
+        a.tfin[static_cast<int64_t>(f) * P + pix] = T;
+        a.nlast[static_cast<int64_t>(f) * P + pix] = last;
+        if (a.tfin_out) a.tfin_out[static_cast<int64_t>(f) * P + pix] = T;
+        if (a.targets && a.loss) {
+            const float* tg = a.targets + static_cast<int64_t>(f) * 3 * P + pix;
+            const float d0 = c0 - tg[0], d1 = c1 - tg[P], d2 = c2 - tg[2 * P];
+            sq = d0 * d0 + d1 * d1 + d2 * d2;
+        }
+    }
+    if (a.targets && a.loss) {
+        sq = wave_sum_to_lane63(sq);
+        if (lane == 63) red[w] = sq;
+        __syncthreads();
+        if (tid == 0) a.loss_part[seg] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
+}
+
+// Kernel choice: tune.compact bit 0 selects the compacted forward, else bit 2
+// the quadrant forward, else the sub-block forward runs; bit 1 selects the
+// compacted adjoint, else the quadrant adjoint runs.  The visibility flags use
+// the sub-block or quadrant forward.
 hipError_t launch_composite_fwd(const Args& a, hipStream_t stream) {
     const dim3 grid(static_cast<uint32_t>(a.tiles), static_cast<uint32_t>(a.frames)), block(WG);
-    if ((a.tune.compact & 1) && !a.vis) {
+    const int c = a.tune.compact;
+    if ((c & 1) && !a.vis) {
         switch (a.tune.batch) {
             case 64: hipLaunchKernelGGL(k_composite_fwd_c<64>, grid, block, 0, stream, a); break;
             case 128: hipLaunchKernelGGL(k_composite_fwd_c<128>, grid, block, 0, stream, a); break;
@@ -809,19 +1026,26 @@ hipError_t launch_composite_fwd(const Args& a, hipStream_t stream) {
         }
         return hipGetLastError();
     }
-    if (a.vis) {  // visibility flags: the quadrant kernel
-        switch (a.tune.batch) {
-            case 64: hipLaunchKernelGGL((k_composite_fwd<64, true>), grid, block, 0, stream, a); break;
-            case 128: hipLaunchKernelGGL((k_composite_fwd<128, true>), grid, block, 0, stream, a); break;
-            default: hipLaunchKernelGGL((k_composite_fwd<256, true>), grid, block, 0, stream, a); break;
+#define GV_FWD_SWITCH(KERNEL, VIS)                                                                       \
+    switch (a.tune.batch) {                                                                              \
+        case 64: hipLaunchKernelGGL((KERNEL<64, VIS>), grid, block, 0, stream, a); break;                \
+        case 128: hipLaunchKernelGGL((KERNEL<128, VIS>), grid, block, 0, stream, a); break;              \
+        default: hipLaunchKernelGGL((KERNEL<256, VIS>), grid, block, 0, stream, a); break;               \
+    }
+    if (c & 4) {
+        if (a.vis) {
+            GV_FWD_SWITCH(k_composite_fwd, true)
+        } else {
+            GV_FWD_SWITCH(k_composite_fwd, false)
         }
-        return hipGetLastError();
+    } else {
+        if (a.vis) {
+            GV_FWD_SWITCH(k_composite_fwd_sb, true)
+        } else {
+            GV_FWD_SWITCH(k_composite_fwd_sb, false)
+        }
     }
-    switch (a.tune.batch) {
-        case 64: hipLaunchKernelGGL((k_composite_fwd<64, false>), grid, block, 0, stream, a); break;
-        case 128: hipLaunchKernelGGL((k_composite_fwd<128, false>), grid, block, 0, stream, a); break;
-        default: hipLaunchKernelGGL((k_composite_fwd<256, false>), grid, block, 0, stream, a); break;
-    }
+#undef GV_FWD_SWITCH
     return hipGetLastError();
 }
 

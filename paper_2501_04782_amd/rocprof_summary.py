@@ -125,10 +125,11 @@ def cmd_traffic(a):
 
 def stage_key(stage: str, tuning: dict) -> str:
     """The part of the tuning that changes a stage's kernel (file-name safe)."""
+    c = tuning['compact']
     if stage == "composite_fwd":
-        return f"b{tuning['batch']}-c{tuning['compact'] & 1}"
+        return f"b{tuning['batch']}-" + ("compact" if c & 1 else "quad" if c & 4 else "block")
     if stage == "composite_bwd":
-        return f"b{tuning['bwd_batch']}-c{(tuning['compact'] >> 1) & 1}"
+        return f"b{tuning['bwd_batch']}-" + ("compact" if c & 2 else "quad")
     if stage == "sort":
         return f"cap{tuning['sort_cap']}"
     return "any"

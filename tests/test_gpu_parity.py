@@ -168,9 +168,12 @@ def test_empty_and_single_gaussian():
             check_clip_against_oracle(w, "single Gaussian")
 
 
-@pytest.mark.parametrize("compact,batch,sort_cap", [(3, 256, 4096), (3, 128, 2048), (3, 64, 1024),
-                                                    (0, 256, 4096), (0, 128, 2048), (0, 64, 1024),
-                                                    (1, 128, 2048), (2, 256, 2048)])
+# compact: 0 sub-block forward, 4 quadrant forward, 1 compacted forward;
+# + 2 compacted backward (else the quadrant backward)
+@pytest.mark.parametrize("compact,batch,sort_cap", [(0, 256, 4096), (0, 128, 2048), (0, 64, 1024),
+                                                    (4, 256, 4096), (4, 128, 2048), (4, 64, 1024),
+                                                    (3, 256, 4096), (3, 128, 2048), (3, 64, 1024),
+                                                    (1, 128, 2048), (2, 256, 2048), (6, 64, 1024)])
 def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
     """Batched path on a reduced clip (moving camera, several frames) under
     every setting the autotuner can choose."""

@@ -29,8 +29,18 @@ def marginal(scene, cam, pose, t, g):
     return flags[0] != flags[1]
 
 
-@pytest.mark.parametrize("kind", ["clip", "dense"])
-def test_visibility_counts_match_oracle(kind):
+@pytest.mark.parametrize("kind,compact", [("clip", 0), ("dense", 0), ("clip", 4)])
+def test_visibility_counts_match_oracle(kind, compact):
+    """compact 0: the 4x4-block forward flags contributors; 4: the quadrant forward."""
+    old = raster.get_tuning()
+    raster.set_tuning(old["batch"], old["sort_cap"], compact, old["bwd_batch"])
+    try:
+        check_visibility(kind)
+    finally:
+        raster.set_tuning(old["batch"], old["sort_cap"], old["compact"], old["bwd_batch"])
+
+
+def check_visibility(kind):
     if kind == "clip":
         w = small_workload(80, 128, 96, 3000, 4, trajectory=True, z=(2.0, 10.0), ls=(-3.2, 0.5))
         w["scene"].means[0, :40] += 30.0  # some Gaussians never on screen
