@@ -523,6 +523,34 @@ __device__ __forceinline__ bool ellipse_meets_box(F u, F v, F a, F b, F c, F x0,
     return m <= thr;
 }
 
+// The same test without divisions: rbc = -b / c and rba = -b / a, the slopes
+// of the edge minimisers, computed once per ellipse.  A minimiser off by an
+// ulp changes the edge minimum only in second order.
+template <typename F>
+__device__ __forceinline__ bool ellipse_meets_box_r(F u, F v, F a, F b, F c, F rbc, F rba, F x0, F x1, F y0, F y1,
+                                                    F thr) {
+    const F dx0 = x0 - u, dx1 = x1 - u, dy0 = y0 - v, dy1 = y1 - v;
+    if (dx0 <= F(0) && dx1 >= F(0) && dy0 <= F(0) && dy1 >= F(0)) return true;
+    auto on_x_edge = [&](F dx) {
+        F dy = rbc * dx;
+        dy = dy < dy0 ? dy0 : (dy > dy1 ? dy1 : dy);
+        return a * dx * dx + F(2) * b * dx * dy + c * dy * dy;
+    };
+    auto on_y_edge = [&](F dy) {
+        F dx = rba * dy;
+        dx = dx < dx0 ? dx0 : (dx > dx1 ? dx1 : dx);
+        return a * dx * dx + F(2) * b * dx * dy + c * dy * dy;
+    };
+    F m = on_x_edge(dx0);
+    F t1 = on_x_edge(dx1);
+    m = t1 < m ? t1 : m;
+    t1 = on_y_edge(dy0);
+    m = t1 < m ? t1 : m;
+    t1 = on_y_edge(dy1);
+    m = t1 < m ? t1 : m;
+    return m <= thr;
+}
+
 // Pixel-centre box of tile (tx, ty), clipped to the image.
 __device__ __forceinline__ void tile_box(int tx, int ty, int W, int H, double& x0, double& x1, double& y0,
                                          double& y1) {

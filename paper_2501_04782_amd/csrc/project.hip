@@ -27,13 +27,20 @@ __device__ __forceinline__ bool tile_span(double lo, double hi, int n_tiles, int
     return true;
 }
 
-// Project Gaussian g in frame f: write its record and tile rectangle and call
-// tally(tile) for every 16x16 tile whose pixel-centre box meets its 3-sigma
-// ellipse (exact ellipse-box test).  Returns the number of such tiles.  Frame
-// 0 also writes the per-Gaussian colour/opacity table shared by all frames.
-template <bool EXT, typename Tally>
-__device__ __forceinline__ uint32_t project_and_count(const Args& a, int f, int64_t g, const CamD& cam, double t,
-                                                      Tally tally) {
+// A projected Gaussian's binning data: its ellipse (centre, rounded conic
+// and the edge-minimiser slopes of ellipse_meets_box_r) and its tile
+// rectangle (tx0, ty0, width rw, height rh).
+struct BinShape {
+    double u, v, a, b, c, rbc, rba;
+    int tx0, ty0, rw, rh;
+};
+
+// Project Gaussian g in frame f: write its record, tile rectangle and colour,
+// and return true with its binning shape if it can reach a pixel (visible,
+// opacity at least 1/255, non-empty tile rectangle).  Frame 0 also writes
+// the per-Gaussian colour/opacity table shared by all frames.
+template <bool EXT>
+__device__ __forceinline__ bool project_one(const Args& a, int f, int64_t g, const CamD& cam, double t, BinShape& S) {
     const int64_t i = static_cast<int64_t>(f) * a.n + g;
     if (f == 0 && a.sh_degree == 0) {
         const double eta = load_param(a.opacity_logits, a.dtype, g);
@@ -55,116 +62,165 @@ __device__ __forceinline__ uint32_t project_and_count(const Args& a, int f, int6
         a.col4[i] = co;
     }
     if (P.nonfinite) atomicAdd(&a.status[ST_NONFINITE], 1u);
-    uint32_t cnt = 0;
     // o < 1/255 can never pass the per-pixel alpha test (alpha <= o).
-    if (vis && P.o >= static_cast<double>(ALPHA_MIN) * (1.0 - 1e-6)) {
-        Record r;
-        r.u = P.u;
-        r.v = P.v;
-        r.a = static_cast<float>(P.A[0]);
-        r.b = static_cast<float>(P.A[1]);
-        r.c = static_cast<float>(P.A[2]);
-        r.depth = static_cast<float>(P.m[2]);
-        // axis-aligned box of the 3-sigma ellipse, padded for the rounded conic
-        const double hx = 3.0 * sqrt(P.cov[0]) * (1.0 + 2e-5) + 1e-4;
-        const double hy = 3.0 * sqrt(P.cov[2]) * (1.0 + 2e-5) + 1e-4;
-        int tx0, tx1, ty0, ty1;
-        if (tile_span(P.u - hx, P.u + hx, a.tiles_x, tx0, tx1) && tile_span(P.v - hy, P.v + hy, a.tiles_y, ty0, ty1)) {
-            const double ca = r.a, cb = r.b, cc = r.c;
-            const int rw = tx1 - tx0 + 1;
-            const bool small = rw * (ty1 - ty0 + 1) <= 64;
-            uint64_t mask = 0;
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) {
-                    double x0, x1, y0, y1;
-                    tile_box(tx, ty, a.width, a.height, x0, x1, y0, y1);
-                    if (ellipse_meets_box<double>(r.u, r.v, ca, cb, cc, x0, x1, y0, y1, BIN_Q_SLACK)) {
-                        ++cnt;
-                        tally(ty * a.tiles_x + tx);
-                        if (small) mask |= 1ull << ((ty - ty0) * rw + (tx - tx0));
-                    }
-                }
-            a.tmask[i] = mask;
-            a.rec[i] = r;
-            a.rect[i] = make_uint2(static_cast<uint32_t>(tx0) | (static_cast<uint32_t>(tx1) << 16),
-                                   static_cast<uint32_t>(ty0) | (static_cast<uint32_t>(ty1) << 16));
-        }
-    }
-    a.gcnt[i] = cnt;
-    return cnt;
+    if (!vis || !(P.o >= static_cast<double>(ALPHA_MIN) * (1.0 - 1e-6))) return false;
+    Record r;
+    r.u = P.u;
+    r.v = P.v;
+    r.a = static_cast<float>(P.A[0]);
+    r.b = static_cast<float>(P.A[1]);
+    r.c = static_cast<float>(P.A[2]);
+    r.depth = static_cast<float>(P.m[2]);
+    // axis-aligned box of the 3-sigma ellipse, padded for the rounded conic
+    const double hx = 3.0 * sqrt(P.cov[0]) * (1.0 + 2e-5) + 1e-4;
+    const double hy = 3.0 * sqrt(P.cov[2]) * (1.0 + 2e-5) + 1e-4;
+    int tx0, tx1, ty0, ty1;
+    if (!tile_span(P.u - hx, P.u + hx, a.tiles_x, tx0, tx1) || !tile_span(P.v - hy, P.v + hy, a.tiles_y, ty0, ty1))
+        return false;
+    a.rec[i] = r;
+    a.rect[i] = make_uint2(static_cast<uint32_t>(tx0) | (static_cast<uint32_t>(tx1) << 16),
+                           static_cast<uint32_t>(ty0) | (static_cast<uint32_t>(ty1) << 16));
+    S.u = r.u;
+    S.v = r.v;
+    S.a = r.a;
+    S.b = r.b;
+    S.c = r.c;
+    S.rbc = -S.b / S.c;
+    S.rba = -S.b / S.a;
+    S.tx0 = tx0;
+    S.ty0 = ty0;
+    S.rw = tx1 - tx0 + 1;
+    S.rh = ty1 - ty0 + 1;
+    return true;
 }
 
-// Write key = (fp32 depth bits << 32 | Gaussian index) and the pre-sort slot
-// (goff + k for the k-th tile of this Gaussian) of every intersection of
-// (f, g) at position next(tile) of its tile's bucket.  The decisions repeat
-// project_and_count's exactly (same inputs, same test, no contraction).
-template <typename Next>
-__device__ __forceinline__ void scatter_one(const Args& a, int f, int64_t g, Next next) {
-    const int64_t i = static_cast<int64_t>(f) * a.n + g;
-    const uint32_t cnt = a.gcnt[i];
-    if (cnt == 0) return;
-    const Record r = a.rec[i];
-    const uint2 rc = a.rect[i];
-    const int tx0 = rc.x & 0xffff, tx1 = rc.x >> 16, ty0 = rc.y & 0xffff, ty1 = rc.y >> 16;
-    const uint64_t key = (static_cast<uint64_t>(__float_as_uint(r.depth)) << 32) | static_cast<uint64_t>(g);
-    const uint32_t base = a.goff[i];
-    const int64_t tile0 = static_cast<int64_t>(f) * a.tiles;
-    uint32_t k = 0;
-    auto emit = [&](int tx, int ty) {
-        const int tl = ty * a.tiles_x + tx;
-        const uint32_t pos = next(tl);
-        // the counts bound every write; a mismatch is an internal error,
-        // reported instead of written out of bounds
-        if (pos >= a.toff[tile0 + tl + 1] || k >= cnt) {
-            a.status[ST_OVERFLOW] = 2u;
-            return;
-        }
-        KeySlot ks;
-        ks.key = key;
-        ks.slot = base + k;
-        ks.pad = 0u;
-        a.kv[pos] = ks;
-        ++k;
-    };
-    const int rw = tx1 - tx0 + 1;
-    if (rw * (ty1 - ty0 + 1) <= 64) {
-        // the count pass left the tiles that passed as a row-major mask over
-        // the rectangle: walk its set bits (same order as the loops below)
-        uint64_t m = a.tmask[i];
-        while (m) {
-            const int b = __builtin_ctzll(m);
-            m &= m - 1;
-            const int ry = b / rw;
-            emit(tx0 + (b - ry * rw), ty0 + ry);
-        }
-        return;
-    }
-    const double ca = r.a, cb = r.b, cc = r.c;
-    for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) {
-            double x0, x1, y0, y1;
-            tile_box(tx, ty, a.width, a.height, x0, x1, y0, y1);
-            if (ellipse_meets_box<double>(r.u, r.v, ca, cb, cc, x0, x1, y0, y1, BIN_Q_SLACK)) emit(tx, ty);
-        }
+// Does the ellipse of S meet tile (tx, ty)?  The one test of both binning
+// passes (exact ellipse-box minimum, slack for the fp32 per-pixel test).
+__device__ __forceinline__ bool shape_meets_tile(const Args& a, const BinShape& S, int tx, int ty) {
+    double x0, x1, y0, y1;
+    tile_box(tx, ty, a.width, a.height, x0, x1, y0, y1);
+    return ellipse_meets_box_r<double>(S.u, S.v, S.a, S.b, S.c, S.rbc, S.rba, x0, x1, y0, y1, BIN_Q_SLACK);
 }
+
+__device__ __forceinline__ BinShape shape_from_record(const Record& r, uint2 rc) {
+    BinShape S;
+    S.u = r.u;
+    S.v = r.v;
+    S.a = r.a;
+    S.b = r.b;
+    S.c = r.c;
+    S.rbc = -S.b / S.c;
+    S.rba = -S.b / S.a;
+    S.tx0 = rc.x & 0xffff;
+    S.ty0 = rc.y & 0xffff;
+    S.rw = static_cast<int>(rc.x >> 16) - S.tx0 + 1;
+    S.rh = static_cast<int>(rc.y >> 16) - S.ty0 + 1;
+    return S;
+}
+
+// Exclusive prefix sum of x over the wave and the wave total.
+__device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t x, int lane, uint32_t& total) {
+    uint32_t incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = static_cast<uint32_t>(__shfl_up(static_cast<int>(incl), d, 64));
+        if (lane >= d) incl += t;
+    }
+    total = static_cast<uint32_t>(__shfl(static_cast<int>(incl), 63, 64));
+    return incl - x;
+}
+
+// Lane owning work item `item` of a wave: the last lane whose exclusive
+// start is at most item (lanes with no items share their successor's start).
+__device__ __forceinline__ int owner_of(const uint32_t* start, uint32_t item) {
+    int o = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1)
+        if (start[o + step] <= item) o += step;
+    return o;
+}
+
+// Index of the (k+1)-th set bit of m (k < popcount(m)).
+__device__ __forceinline__ int kth_set_bit(uint64_t m, uint32_t k) {
+    int b = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const uint64_t low = m & ((1ull << w) - 1ull);
+        const uint32_t c = static_cast<uint32_t>(__popcll(low));
+        if (k >= c) {
+            k -= c;
+            m >>= w;
+            b += w;
+        } else {
+            m = low;
+        }
+    }
+    return b;
+}
+
+// Per-wave LDS staging of the cooperative rectangle walk: the cells of the
+// 64 lanes' tile rectangles are dealt out one per lane and step, so a wave
+// takes (total cells) / 64 steps instead of its largest rectangle.
+struct WaveCells {
+    BinShape shape[64];
+    uint32_t start[64];
+    unsigned long long mask[64];
+    uint32_t cnt[64];
+};
 
 // Binning with workgroup-local tile histograms in LDS: each workgroup
 // projects BIN_GROUP Gaussians of one frame, counts their intersections per
 // tile with LDS atomics, stores its histogram and adds it to the frame's tile
-// counts with one global atomic per non-empty tile.
+// counts with one global atomic per non-empty tile.  A Gaussian's passing
+// tiles are also recorded as a row-major mask over its rectangle (rectangles
+// of at most 64 tiles), which the scatter walks.
 template <bool EXT>
 __global__ __launch_bounds__(256) void k_project_lds(Args a) {
     extern __shared__ uint32_t hist[];
+    __shared__ WaveCells wc[4];
     const int f = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int t = threadIdx.x; t < a.tiles; t += 256) hist[t] = 0u;
     __syncthreads();
     const CamD cam = load_camera(a.poses + 7 * f);
     const double tt = a.times ? static_cast<double>(a.times[f]) : static_cast<double>(a.t0);
     const int64_t g0 = static_cast<int64_t>(blockIdx.x) * BIN_GROUP;
+    WaveCells& W = wc[w];
 #pragma unroll 1
     for (int k = 0; k < BIN_GROUP / 256; ++k) {
         const int64_t g = g0 + k * 256 + threadIdx.x;
-        if (g < a.n) project_and_count<EXT>(a, f, g, cam, tt, [&](int tl) { atomicAdd(&hist[tl], 1u); });
+        BinShape S;
+        const bool has = g < a.n && project_one<EXT>(a, f, g, cam, tt, S);
+        const uint32_t ncell = has ? static_cast<uint32_t>(S.rw * S.rh) : 0u;
+        uint32_t total;
+        const uint32_t start = wave_exclusive_scan(ncell, lane, total);
+        W.shape[lane] = S;
+        W.start[lane] = start;
+        W.mask[lane] = 0ull;
+        W.cnt[lane] = 0u;
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t b0 = 0; b0 < total; b0 += 64) {
+            const uint32_t item = b0 + static_cast<uint32_t>(lane);
+            if (item < total) {
+                const int o = owner_of(W.start, item);
+                const uint32_t cell = item - W.start[o];
+                const BinShape& So = W.shape[o];
+                const int ry = static_cast<int>(cell) / So.rw;
+                const int tx = So.tx0 + (static_cast<int>(cell) - ry * So.rw), ty = So.ty0 + ry;
+                if (shape_meets_tile(a, So, tx, ty)) {
+                    atomicAdd(&hist[ty * a.tiles_x + tx], 1u);
+                    atomicAdd(&W.cnt[o], 1u);
+                    if (So.rw * So.rh <= 64) atomicOr(&W.mask[o], 1ull << cell);
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (g < a.n) {
+            const int64_t i = static_cast<int64_t>(f) * a.n + g;
+            a.gcnt[i] = W.cnt[lane];
+            if (has) a.tmask[i] = W.mask[lane];
+        }
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
     uint32_t* bh = a.bhist + (static_cast<int64_t>(f) * a.bin_blocks + blockIdx.x) * a.tiles;
@@ -176,13 +232,67 @@ __global__ __launch_bounds__(256) void k_project_lds(Args a) {
     }
 }
 
+// Write intersection (f, g) -> tile (tx, ty) with pre-sort slot goff + k at
+// position next(tile) of the tile's bucket.  The counts bound every write; a
+// mismatch is an internal error, reported instead of written out of bounds.
+template <typename Next>
+__device__ __forceinline__ void emit_key(const Args& a, int f, uint64_t key, uint32_t slot, int tx, int ty, Next next) {
+    const int tl = ty * a.tiles_x + tx;
+    const uint32_t pos = next(tl);
+    if (pos >= a.toff[static_cast<int64_t>(f) * a.tiles + tl + 1]) {
+        a.status[ST_OVERFLOW] = 2u;
+        return;
+    }
+    KeySlot ks;
+    ks.key = key;
+    ks.slot = slot;
+    ks.pad = 0u;
+    a.kv[pos] = ks;
+}
+
+// Key (fp32 depth bits << 32 | Gaussian index) of (f, g).
+__device__ __forceinline__ uint64_t sort_key(const Record& r, int64_t g) {
+    return (static_cast<uint64_t>(__float_as_uint(r.depth)) << 32) | static_cast<uint64_t>(g);
+}
+
+// Intersections of a Gaussian whose rectangle exceeds 64 tiles (no mask):
+// the tests are repeated in the count pass's row-major order.
+template <typename Next>
+__device__ __forceinline__ void scatter_big(const Args& a, int f, int64_t g, const Record& r, const BinShape& S,
+                                            uint32_t cnt, uint32_t goff, Next next) {
+    const uint64_t key = sort_key(r, g);
+    uint32_t k = 0;
+    for (int ty = S.ty0; ty < S.ty0 + S.rh; ++ty)
+        for (int tx = S.tx0; tx < S.tx0 + S.rw; ++tx)
+            if (shape_meets_tile(a, S, tx, ty)) {
+                if (k >= cnt) {
+                    a.status[ST_OVERFLOW] = 2u;
+                    return;
+                }
+                emit_key(a, f, key, goff + k, tx, ty, next);
+                ++k;
+            }
+}
+
+struct WaveKeys {
+    unsigned long long mask[64];
+    unsigned long long key[64];
+    uint32_t start[64];
+    uint32_t goff[64];
+    int tx0[64], ty0[64], rw[64];
+};
+
 // Scatter counterpart: one global atomic per non-empty (workgroup, tile)
 // reserves the workgroup's range in the tile's bucket; positions inside it are
-// handed out by LDS atomics.
+// handed out by LDS atomics.  A wave deals out its Gaussians' intersections
+// (the set bits of their masks) one per lane and step; the k-th set bit of a
+// mask gets pre-sort slot goff + k, as the count pass ordered them.
 __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
     if (overflowed(a.status)) return;
     extern __shared__ uint32_t base[];
+    __shared__ WaveKeys wk[4];
     const int f = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t* bh = a.bhist + (static_cast<int64_t>(f) * a.bin_blocks + blockIdx.x) * a.tiles;
     const int64_t tile0 = static_cast<int64_t>(f) * a.tiles;
     for (int t = threadIdx.x; t < a.tiles; t += 256) {
@@ -190,16 +300,56 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
         base[t] = v ? a.toff[tile0 + t] + atomicAdd(&a.tcur[tile0 + t], v) : 0u;
     }
     __syncthreads();
+    auto next = [&](int tl) { return atomicAdd(&base[tl], 1u); };
     const int64_t g0 = static_cast<int64_t>(blockIdx.x) * BIN_GROUP;
+    WaveKeys& W = wk[w];
 #pragma unroll 1
     for (int k = 0; k < BIN_GROUP / 256; ++k) {
         const int64_t g = g0 + k * 256 + threadIdx.x;
-        if (g < a.n) scatter_one(a, f, g, [&](int tl) { return atomicAdd(&base[tl], 1u); });
+        const int64_t i = static_cast<int64_t>(f) * a.n + g;
+        const uint32_t cnt = g < a.n ? a.gcnt[i] : 0u;
+        Record r;
+        uint2 rc = make_uint2(0u, 0u);
+        bool small = false;
+        if (cnt) {
+            r = a.rec[i];
+            rc = a.rect[i];
+            small = ((rc.x >> 16) - (rc.x & 0xffff) + 1) * ((rc.y >> 16) - (rc.y & 0xffff) + 1) <= 64u;
+        }
+        uint32_t total;
+        const uint32_t start = wave_exclusive_scan(small ? cnt : 0u, lane, total);
+        W.start[lane] = start;
+        if (small) {
+            W.mask[lane] = a.tmask[i];
+            W.key[lane] = sort_key(r, g);
+            W.goff[lane] = a.goff[i];
+            W.tx0[lane] = rc.x & 0xffff;
+            W.ty0[lane] = rc.y & 0xffff;
+            W.rw[lane] = static_cast<int>(rc.x >> 16) - static_cast<int>(rc.x & 0xffff) + 1;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t b0 = 0; b0 < total; b0 += 64) {
+            const uint32_t item = b0 + static_cast<uint32_t>(lane);
+            if (item < total) {
+                const int o = owner_of(W.start, item);
+                const uint32_t kk = item - W.start[o];
+                const uint64_t m = W.mask[o];
+                if (kk >= static_cast<uint32_t>(__popcll(m))) {  // counts and mask disagree: internal error
+                    a.status[ST_OVERFLOW] = 2u;
+                    continue;
+                }
+                const int bit = kth_set_bit(m, kk);
+                const int ry = bit / W.rw[o];
+                emit_key(a, f, W.key[o], W.goff[o] + kk, W.tx0[o] + (bit - ry * W.rw[o]), W.ty0[o] + ry, next);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (cnt && !small) scatter_big(a, f, g, r, shape_from_record(r, rc), cnt, a.goff[i], next);
     }
 }
 
 // Fallback for tile grids too large for an LDS histogram: global atomics per
-// intersection.
+// intersection, one lane per Gaussian.
 template <bool EXT>
 __global__ __launch_bounds__(256) void k_project(Args a) {
     const int f = blockIdx.y;
@@ -208,7 +358,22 @@ __global__ __launch_bounds__(256) void k_project(Args a) {
     const CamD cam = load_camera(a.poses + 7 * f);
     const double t = a.times ? static_cast<double>(a.times[f]) : static_cast<double>(a.t0);
     uint32_t* tc = a.tcnt + static_cast<int64_t>(f) * a.tiles;
-    project_and_count<EXT>(a, f, g, cam, t, [&](int tl) { atomicAdd(&tc[tl], 1u); });
+    const int64_t i = static_cast<int64_t>(f) * a.n + g;
+    BinShape S;
+    uint32_t cnt = 0;
+    if (project_one<EXT>(a, f, g, cam, t, S)) {
+        uint64_t mask = 0;
+        const bool small = S.rw * S.rh <= 64;
+        for (int ry = 0; ry < S.rh; ++ry)
+            for (int rx = 0; rx < S.rw; ++rx)
+                if (shape_meets_tile(a, S, S.tx0 + rx, S.ty0 + ry)) {
+                    ++cnt;
+                    atomicAdd(&tc[(S.ty0 + ry) * a.tiles_x + S.tx0 + rx], 1u);
+                    if (small) mask |= 1ull << (ry * S.rw + rx);
+                }
+        a.tmask[i] = mask;
+    }
+    a.gcnt[i] = cnt;
 }
 
 __global__ __launch_bounds__(256) void k_scatter(Args a) {
@@ -217,7 +382,13 @@ __global__ __launch_bounds__(256) void k_scatter(Args a) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= a.n) return;
     const int64_t tile0 = static_cast<int64_t>(f) * a.tiles;
-    scatter_one(a, f, g, [&](int tl) { return a.toff[tile0 + tl] + atomicAdd(&a.tcur[tile0 + tl], 1u); });
+    const int64_t i = static_cast<int64_t>(f) * a.n + g;
+    const uint32_t cnt = a.gcnt[i];
+    if (cnt == 0) return;
+    const Record r = a.rec[i];
+    const BinShape S = shape_from_record(r, a.rect[i]);
+    scatter_big(a, f, g, r, S, cnt, a.goff[i],
+                [&](int tl) { return a.toff[tile0 + tl] + atomicAdd(&a.tcur[tile0 + tl], 1u); });
 }
 
 // Copy frame 0's projected records out for inspection: (u, v, A00, A01, A11,
