@@ -1,47 +1,96 @@
 // Per-tile depth sort.  The binning pass already grouped the intersections by
 // (frame, tile) (a counting sort on the tile digit); each tile's bucket is
 // then sorted by the 64-bit key (fp32 depth bits, Gaussian index) in LDS by
-// one workgroup: rank counting for short buckets, a bitonic network up to the
-// LDS capacity.  Keys are unique within a bucket, so the order is fully
-// determined (depth, ties by lower index) whatever order the atomics of the
-// scatter produced.  Buckets longer than the LDS capacity are sorted in LDS
-// chunks and merged in global memory (each element finds its place in the
-// partner run by binary search).
+// one workgroup: ranks by comparison within chunks of 16 keys, then by merging
+// groups of four sorted runs level by level (binary search in the sibling
+// runs).  Keys are unique within a bucket, so the order is fully determined
+// (depth, ties by lower index) whatever order the atomics of the scatter
+// produced.  Buckets longer than the LDS capacity are sorted in LDS chunks and
+// merged in global memory (each element finds its place in the partner run by
+// binary search).
 #include "gv_internal.h"
 
 namespace gv {
 
-// Buckets up to this length are sorted by rank counting (O(n^2 / threads)
-// comparisons, no barriers); longer ones by the bitonic network.
-constexpr int RANK_SORT_MAX = 512;
-
-template <int CAP>
-__device__ __forceinline__ void bitonic_lds(uint64_t* K, uint32_t* V, int m) {
-    for (int k = 2; k <= m; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const int lj = __builtin_ctz(j);  // j is a power of two
-            for (int p = threadIdx.x; p < (m >> 1); p += WG) {
-                const int i = ((p >> lj) << (lj + 1)) | (p & (j - 1));
-                const int l = i + j;
-                const bool asc = (i & k) == 0;
-                const uint64_t ki = K[i], kl = K[l];
-                if ((ki > kl) == asc) {
-                    K[i] = kl;
-                    K[l] = ki;
-                    const uint32_t t = V[i];
-                    V[i] = V[l];
-                    V[l] = t;
-                }
-            }
-            __syncthreads();
-        }
-    }
+// Number of keys below x in the sorted run S[0, len), len <= R (R a power of
+// two): binary lifting over R, reading only inside [0, len).
+__device__ __forceinline__ int count_below(const uint64_t* S, int len, int R, uint64_t x) {
+    int lo = 0;
+    for (int step = R >> 1; step >= 1; step >>= 1)
+        if (lo + step <= len && S[lo + step - 1] < x) lo += step;
+    if (lo < len && S[lo] < x) ++lo;
+    return lo;
 }
 
-__device__ __forceinline__ int next_pow2(int x) {
-    int m = 2;
-    while (m < x) m <<= 1;
-    return m;
+// Ranks of the keys of one bucket segment of len <= CAP keys, in LDS.
+// Thread t owns elements e = t + WG j (their keys and values stay in
+// registers; only keys are exchanged through LDS).  Level 0 ranks every key
+// within its chunk of 16 by comparison with the chunk's keys; each following
+// level merges groups of four sorted runs (16 -> 64 -> 256 -> ...): a key's
+// rank in the merged run is its rank in its own run plus, for each sibling
+// run, the number of that run's keys below it.  Each level writes its sorted
+// runs (key at its rank) for the next level's searches.  Padding keys lie
+// above every real key (real depths are finite) and are distinct, so the
+// ranks of a level are a permutation and every slot is written.  Returns the
+// buffer (SA or SB) holding the keys in sorted order.
+template <int CAP>
+__device__ __forceinline__ uint64_t* lds_sort_ranks(const KeySlot* src, int len, uint64_t* SA, uint64_t* SB,
+                                               uint64_t (&x)[CAP / WG], uint32_t (&v)[CAP / WG],
+                                               int (&rank)[CAP / WG]) {
+    constexpr int EPT = CAP / WG;
+    const int npad = (len + 15) & ~15;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int e = threadIdx.x + WG * j;
+        if (e < len) {
+            const KeySlot ks = src[e];
+            x[j] = ks.key;
+            v[j] = ks.slot;
+        } else {
+            x[j] = 0xFFFFFFFF00000000ull | static_cast<uint32_t>(e);
+            v[j] = 0u;
+        }
+        if (e < npad) SA[e] = x[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int e = threadIdx.x + WG * j;
+        rank[j] = 0;
+        if (e < npad) {
+            const uint64_t* C = SA + (e & ~15);
+            int r = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) r += C[k] < x[j] ? 1 : 0;
+            rank[j] = r;
+            SB[(e & ~15) + r] = x[j];
+        }
+    }
+    __syncthreads();
+    uint64_t* cur = SB;
+    uint64_t* nxt = SA;
+    for (int R = 16; R < npad; R <<= 2) {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int e = threadIdx.x + WG * j;
+            if (e >= npad) continue;
+            const int gb = e & ~(4 * R - 1);  // first element of the group of four runs
+            const int mine = (e - gb) / R;
+            int r = rank[j];
+            for (int t = 0; t < 4; ++t) {
+                const int st = gb + t * R;
+                if (t == mine || st >= npad) continue;
+                r += count_below(cur + st, min(R, npad - st), R, x[j]);
+            }
+            rank[j] = r;
+            nxt[gb + r] = x[j];
+        }
+        __syncthreads();
+        uint64_t* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    return cur;
 }
 
 // Number of elements of the sorted run R[0, len) whose key is strictly smaller.
@@ -63,78 +112,65 @@ __global__ __launch_bounds__(WG) void k_tile_sort(Args a) {
     bucket_range(a, seg, s, e);
     const int64_t n = static_cast<int64_t>(e) - s;
     if (n <= 0) return;
-    __shared__ uint64_t K[CAP];
-    __shared__ uint32_t V[CAP];
-    if (n <= RANK_SORT_MAX) {
-        // short bucket: every element's final position is the number of
-        // smaller keys (keys are unique); no barriers after the load
-        for (int i = threadIdx.x; i < n; i += WG) {
-            const KeySlot ks = a.kv[s + i];
-            K[i] = ks.key;
-            V[i] = ks.slot;
-        }
-        __syncthreads();
-        // each thread ranks element tid and, for buckets longer than WG,
-        // element tid + WG, in one pass over the keys
-        const int nn = static_cast<int>(n);
-        const int i0 = threadIdx.x, i1 = threadIdx.x + WG;
-        const uint64_t k0 = i0 < nn ? K[i0] : ~0ull, k1 = i1 < nn ? K[i1] : ~0ull;
-        int r0 = 0, r1 = 0;
-        if (nn > WG) {
-            for (int k = 0; k < nn; ++k) {
-                const uint64_t x = K[k];
-                r0 += x < k0 ? 1 : 0;
-                r1 += x < k1 ? 1 : 0;
+    constexpr int EPT = CAP / WG;
+    __shared__ uint64_t SA[CAP], SB[CAP];
+    uint64_t x[EPT];
+    uint32_t v[EPT];
+    int rank[EPT];
+    if (n <= CAP) {
+        lds_sort_ranks<CAP>(a.kv + s, static_cast<int>(n), SA, SB, x, v, rank);
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int i = threadIdx.x + WG * j;
+            if (i < n) {
+                a.sgid[s + rank[j]] = static_cast<uint32_t>(x[j]);
+                a.sslot[s + rank[j]] = v[j];
             }
-        } else if (i0 < nn) {
-            int q0 = 0, q1 = 0;
-            int k = 0;
-            for (; k + 1 < nn; k += 2) {
-                q0 += K[k] < k0 ? 1 : 0;
-                q1 += K[k + 1] < k0 ? 1 : 0;
-            }
-            if (k < nn) q0 += K[k] < k0 ? 1 : 0;
-            r0 = q0 + q1;
-        }
-        if (i0 < nn) {
-            a.sgid[s + r0] = static_cast<uint32_t>(k0);
-            a.sslot[s + r0] = V[i0];
-        }
-        if (i1 < nn) {
-            a.sgid[s + r1] = static_cast<uint32_t>(k1);
-            a.sslot[s + r1] = V[i1];
         }
         return;
     }
-    if (n <= CAP) {
-        const int m = next_pow2(static_cast<int>(n));
-        for (int i = threadIdx.x; i < m; i += WG) {
-            const KeySlot ks = i < n ? a.kv[s + i] : KeySlot{~0ull, 0u, 0u};
-            K[i] = ks.key;
-            V[i] = ks.slot;
-        }
+    KeySlot* src = a.kv + s;
+    if (n <= 2 * CAP) {
+        // Two runs: the first is sorted and written back in place, the
+        // second sorted in LDS; the first's keys are then reloaded into the
+        // other LDS buffer and every element adds the number of keys below it
+        // in the other run (binary search in LDS).
+        lds_sort_ranks<CAP>(src, CAP, SA, SB, x, v, rank);
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) src[rank[j]] = KeySlot{x[j], v[j], 0u};
         __syncthreads();
-        bitonic_lds<CAP>(K, V, m);
-        for (int i = threadIdx.x; i < n; i += WG) {
-            a.sgid[s + i] = static_cast<uint32_t>(K[i]);
-            a.sslot[s + i] = V[i];
+        const int len1 = static_cast<int>(n) - CAP;
+        const uint64_t* K1 = lds_sort_ranks<CAP>(src + CAP, len1, SA, SB, x, v, rank);
+        uint64_t* K0 = K1 == SA ? SB : SA;
+        for (int i = threadIdx.x; i < CAP; i += WG) K0[i] = src[i].key;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int i = threadIdx.x + WG * j;
+            if (i < len1) {
+                const int r = rank[j] + count_below(K0, CAP, CAP, x[j]);
+                a.sgid[s + r] = static_cast<uint32_t>(x[j]);
+                a.sslot[s + r] = v[j];
+            }
+            const KeySlot e0 = src[i];
+            const int r0 = i + count_below(K1, len1, CAP, e0.key);
+            a.sgid[s + r0] = static_cast<uint32_t>(e0.key);
+            a.sslot[s + r0] = e0.slot;
         }
         return;
     }
     // Long bucket: sorted runs of CAP in place, then pairwise merges.
-    KeySlot* src = a.kv + s;
     KeySlot* dst = a.tkv + s;
     for (int64_t c0 = 0; c0 < n; c0 += CAP) {
         const int len = static_cast<int>(n - c0 < CAP ? n - c0 : CAP);
-        const int m = next_pow2(len);
-        for (int i = threadIdx.x; i < m; i += WG) {
-            const KeySlot ks = i < len ? src[c0 + i] : KeySlot{~0ull, 0u, 0u};
-            K[i] = ks.key;
-            V[i] = ks.slot;
+        // every thread reads its elements of the chunk before the first
+        // barrier inside lds_sort_ranks, so the chunk may then be overwritten
+        lds_sort_ranks<CAP>(src + c0, len, SA, SB, x, v, rank);
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int i = threadIdx.x + WG * j;
+            if (i < len) src[c0 + rank[j]] = KeySlot{x[j], v[j], 0u};
         }
-        __syncthreads();
-        bitonic_lds<CAP>(K, V, m);
-        for (int i = threadIdx.x; i < len; i += WG) src[c0 + i] = KeySlot{K[i], V[i], 0u};
         __syncthreads();
     }
     for (int64_t w = CAP; w < n; w <<= 1) {
