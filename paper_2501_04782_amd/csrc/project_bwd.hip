@@ -356,11 +356,24 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
             for (int k = 0; k < 12; ++k) pose[k] = 0.0f;
             if (cnt) {
                 double dd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll 2
-                for (uint32_t k = 0; k < cnt; ++k) {
-                    const float* pp = a.part + static_cast<int64_t>(base + k) * PART;
+                // PU records per round, loads issued together (past the end
+                // they repeat a valid record and are not added), summed in
+                // order k = 0, 1, ...
+                constexpr uint32_t PU = 8;
+                for (uint32_t k0 = 0; k0 < cnt; k0 += PU) {
+                    float r[PU][PART];
 #pragma unroll
-                    for (int m = 0; m < PART; ++m) dd[m] += pp[m];
+                    for (uint32_t u = 0; u < PU; ++u) {
+                        const uint32_t k = k0 + u < cnt ? k0 + u : k0;
+                        const float* pp = a.part + static_cast<int64_t>(base + k) * PART;
+#pragma unroll
+                        for (int m = 0; m < PART; ++m) r[u][m] = pp[m];
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < PU; ++u)
+                        if (k0 + u < cnt)
+#pragma unroll
+                            for (int m = 0; m < PART; ++m) dd[m] += r[u][m];
                 }
                 float d[9];
                 for (int k = 0; k < 9; ++k) d[k] = static_cast<float>(dd[k]);
