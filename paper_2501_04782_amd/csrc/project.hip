@@ -233,13 +233,15 @@ __global__ __launch_bounds__(256) void k_project_lds(Args a) {
 }
 
 // Write intersection (f, g) -> tile (tx, ty) with pre-sort slot goff + k at
-// position next(tile) of the tile's bucket.  The counts bound every write; a
-// mismatch is an internal error, reported instead of written out of bounds.
-template <typename Next>
-__device__ __forceinline__ void emit_key(const Args& a, int f, uint64_t key, uint32_t slot, int tx, int ty, Next next) {
+// position next(tile) of the tile's bucket, below end(tile).  The counts
+// bound every write; a mismatch is an internal error, reported instead of
+// written out of bounds.
+template <typename Next, typename End>
+__device__ __forceinline__ void emit_key(const Args& a, uint64_t key, uint32_t slot, int tx, int ty, Next next,
+                                         End end) {
     const int tl = ty * a.tiles_x + tx;
     const uint32_t pos = next(tl);
-    if (pos >= a.toff[static_cast<int64_t>(f) * a.tiles + tl + 1]) {
+    if (pos >= end(tl)) {
         a.status[ST_OVERFLOW] = 2u;
         return;
     }
@@ -257,9 +259,9 @@ __device__ __forceinline__ uint64_t sort_key(const Record& r, int64_t g) {
 
 // Intersections of a Gaussian whose rectangle exceeds 64 tiles (no mask):
 // the tests are repeated in the count pass's row-major order.
-template <typename Next>
-__device__ __forceinline__ void scatter_big(const Args& a, int f, int64_t g, const Record& r, const BinShape& S,
-                                            uint32_t cnt, uint32_t goff, Next next) {
+template <typename Next, typename End>
+__device__ __forceinline__ void scatter_big(const Args& a, int64_t g, const Record& r, const BinShape& S,
+                                            uint32_t cnt, uint32_t goff, Next next, End end) {
     const uint64_t key = sort_key(r, g);
     uint32_t k = 0;
     for (int ty = S.ty0; ty < S.ty0 + S.rh; ++ty)
@@ -269,7 +271,7 @@ __device__ __forceinline__ void scatter_big(const Args& a, int f, int64_t g, con
                     a.status[ST_OVERFLOW] = 2u;
                     return;
                 }
-                emit_key(a, f, key, goff + k, tx, ty, next);
+                emit_key(a, key, goff + k, tx, ty, next, end);
                 ++k;
             }
 }
@@ -289,7 +291,10 @@ struct WaveKeys {
 // mask gets pre-sort slot goff + k, as the count pass ordered them.
 __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
     if (overflowed(a.status)) return;
+    // base[t]: next position of this workgroup's range in tile t's bucket;
+    // lim[t]: the end of that range
     extern __shared__ uint32_t base[];
+    uint32_t* lim = base + a.tiles;
     __shared__ WaveKeys wk[4];
     const int f = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -297,10 +302,13 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
     const int64_t tile0 = static_cast<int64_t>(f) * a.tiles;
     for (int t = threadIdx.x; t < a.tiles; t += 256) {
         const uint32_t v = bh[t];
-        base[t] = v ? a.toff[tile0 + t] + atomicAdd(&a.tcur[tile0 + t], v) : 0u;
+        const uint32_t b = v ? a.toff[tile0 + t] + atomicAdd(&a.tcur[tile0 + t], v) : 0u;
+        base[t] = b;
+        lim[t] = v ? min(b + v, a.toff[tile0 + t + 1]) : 0u;
     }
     __syncthreads();
     auto next = [&](int tl) { return atomicAdd(&base[tl], 1u); };
+    auto end = [&](int tl) { return lim[tl]; };
     const int64_t g0 = static_cast<int64_t>(blockIdx.x) * BIN_GROUP;
     WaveKeys& W = wk[w];
 #pragma unroll 1
@@ -340,11 +348,11 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
                 }
                 const int bit = kth_set_bit(m, kk);
                 const int ry = bit / W.rw[o];
-                emit_key(a, f, W.key[o], W.goff[o] + kk, W.tx0[o] + (bit - ry * W.rw[o]), W.ty0[o] + ry, next);
+                emit_key(a, W.key[o], W.goff[o] + kk, W.tx0[o] + (bit - ry * W.rw[o]), W.ty0[o] + ry, next, end);
             }
         }
         __builtin_amdgcn_wave_barrier();
-        if (cnt && !small) scatter_big(a, f, g, r, shape_from_record(r, rc), cnt, a.goff[i], next);
+        if (cnt && !small) scatter_big(a, g, r, shape_from_record(r, rc), cnt, a.goff[i], next, end);
     }
 }
 
@@ -387,8 +395,9 @@ __global__ __launch_bounds__(256) void k_scatter(Args a) {
     if (cnt == 0) return;
     const Record r = a.rec[i];
     const BinShape S = shape_from_record(r, a.rect[i]);
-    scatter_big(a, f, g, r, S, cnt, a.goff[i],
-                [&](int tl) { return a.toff[tile0 + tl] + atomicAdd(&a.tcur[tile0 + tl], 1u); });
+    scatter_big(a, g, r, S, cnt, a.goff[i],
+                [&](int tl) { return a.toff[tile0 + tl] + atomicAdd(&a.tcur[tile0 + tl], 1u); },
+                [&](int tl) { return a.toff[tile0 + tl + 1]; });
 }
 
 // Copy frame 0's projected records out for inspection: (u, v, A00, A01, A11,
@@ -451,7 +460,7 @@ hipError_t launch_scatter(const Args& a, hipStream_t stream) {
     if (a.n <= 0) return hipSuccess;
     if (a.bhist) {
         hipLaunchKernelGGL(k_scatter_lds, dim3(static_cast<uint32_t>(a.bin_blocks), a.frames), dim3(256),
-                           sizeof(uint32_t) * a.tiles, stream, a);
+                           2 * sizeof(uint32_t) * a.tiles, stream, a);
     } else {
         hipLaunchKernelGGL(k_scatter, dim3(static_cast<uint32_t>((a.n + 255) / 256), a.frames), dim3(256), 0, stream,
                            a);
