@@ -601,7 +601,7 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
     const Cand cands[NC] = {{64, 0, 1024}, {128, 0, 2048}, {256, 0, 4096}, {128, 4, 4096},
                             {256, 4, 1024}, {64, 1, 2048},  {128, 1, 1024}, {256, 1, 2048}};
     float fwd_ms[NC], bwd_ms[NC], sort_ms[NC], total_ms[NC];
-    constexpr int REPS = 2;
+    constexpr int REPS = 3;
     for (int c = 0; c < NC && result == GV_OK; ++c) {
         Tuning t = saved;
         t.batch = t.bwd_batch = cands[c].batch;

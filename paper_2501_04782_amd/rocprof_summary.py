@@ -154,6 +154,53 @@ def read_traffic(path: str, stage: str, workload: str, tuning: str):
         return None
 
 
+def counters_per_kernel(db: str):
+    """{kernel: {counter: mean per dispatch}} of a --pmc run."""
+    con = sqlite3.connect(db)
+    per = defaultdict(lambda: defaultdict(float))
+    for did, name, cname, val in con.execute(
+            "select dispatch_id, kernel_name, counter_name, value from counters_collection"):
+        per[name][(cname, did)] += val
+    out = {}
+    for name, d in per.items():
+        by = defaultdict(list)
+        for (cname, _), v in d.items():
+            by[cname].append(v)
+        out[name] = {c: sum(v) / len(v) for c, v in by.items()}
+    return out
+
+
+def cmd_counters(a):
+    """Per-kernel SQ counter means (per dispatch) of one or more --pmc runs,
+    with the derived VALU issue share (instructions x 4 cycles over the
+    SIMD-cycles of the kernel's duration) when a kernel trace is given."""
+    merged = defaultdict(dict)
+    for db in a.dbs:
+        for k, d in counters_per_kernel(db).items():
+            merged[k].update(d)
+    dur = {k: sum(v) / len(v) for k, v in kernel_durations(a.trace).items()} if a.trace else {}
+    cols = sorted({c for d in merged.values() for c in d})
+    print(f"# {a.title}\n")
+    print("Commands (from the repository root on the GPU box):\n")
+    print("```\n" + a.command + "\n```\n")
+    print("Means per dispatch.  VALU share = SQ_INSTS_VALU x 4 cycles / (kernel time x 2.4 GHz x 1024 SIMDs).\n")
+    print("| kernel | " + " | ".join(cols) + (" | avg ms | VALU share |" if dur else " |"))
+    print("|---|" + "---|" * len(cols) + ("---|---|" if dur else ""))
+    for k in sorted(merged, key=lambda n: -merged[n].get("SQ_INSTS_VALU", 0.0)):
+        d = merged[k]
+        if d.get("SQ_WAVES", 1.0) < 100:
+            continue
+        n = k.split("(")[0].replace("|", "/")
+        row = f"| `{n}` | " + " | ".join(f"{d.get(c, 0.0):.3g}" for c in cols)
+        if dur:
+            t = dur.get(k)
+            share = d.get("SQ_INSTS_VALU", 0.0) * 4 / (t * 1e-9 * 2.4e9 * 1024) if t else float("nan")
+            row += f" | {t / 1e6:.4f} | {share:.2f} |" if t else " | - | - |"
+        else:
+            row += " |"
+        print(row)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -173,8 +220,13 @@ def main():
     t.add_argument("--workload", required=True)
     t.add_argument("--tuning", required=True, help="the stage key (stage_key) the counters were taken with")
     t.add_argument("--command", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("dbs", nargs="+")
+    c.add_argument("--trace", help="kernel-trace results db of the same workload (durations)")
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", required=True)
     a = ap.parse_args()
-    cmd_stats(a) if a.cmd == "stats" else cmd_traffic(a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
 
 
 if __name__ == "__main__":
