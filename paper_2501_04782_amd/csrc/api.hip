@@ -601,15 +601,17 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
     const Cand cands[NC] = {{64, 0, 1024}, {128, 0, 2048}, {256, 0, 4096}, {128, 4, 4096},
                             {256, 4, 1024}, {64, 1, 2048},  {128, 1, 1024}, {256, 1, 2048}};
     float fwd_ms[NC], bwd_ms[NC], sort_ms[NC], total_ms[NC];
+    for (int c = 0; c < NC; ++c) fwd_ms[c] = bwd_ms[c] = sort_ms[c] = total_ms[c] = 0.f;
+    // Round-robin over the candidates, so that clock or cache drift during
+    // the measurement affects all of them alike; round 0 warms up.
     constexpr int REPS = 3;
-    for (int c = 0; c < NC && result == GV_OK; ++c) {
-        Tuning t = saved;
-        t.batch = t.bwd_batch = cands[c].batch;
-        t.compact = cands[c].compact;
-        t.sort_cap = cands[c].cap;
-        install_tuning(t);
-        fwd_ms[c] = bwd_ms[c] = sort_ms[c] = total_ms[c] = 0.f;
-        for (int r = 0; r <= REPS && result == GV_OK; ++r) {  // run 0 warms up
+    for (int r = 0; r <= REPS && result == GV_OK; ++r) {
+        for (int c = 0; c < NC && result == GV_OK; ++c) {
+            Tuning t = saved;
+            t.batch = t.bwd_batch = cands[c].batch;
+            t.compact = cands[c].compact;
+            t.sort_cap = cands[c].cap;
+            install_tuning(t);
             gv_status s = enqueue_batch(scene, cam, poses, times, frames, targets, nullptr, flags, images, loss,
                                         grads, dL_dposes, ws, ws_bytes, st, &tm);
             if (s == GV_OK && hipEventSynchronize(tm.ev[GV_STAGES]) != hipSuccess) s = GV_ERR_HIP;

@@ -314,23 +314,23 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
 #pragma unroll 1
     for (int k = 0; k < BIN_GROUP / 256; ++k) {
         const int64_t g = g0 + k * 256 + threadIdx.x;
-        const int64_t i = static_cast<int64_t>(f) * a.n + g;
+        // all of the Gaussian's loads are issued together (one memory round
+        // trip); a Gaussian without intersections ignores them
+        const int64_t i = static_cast<int64_t>(f) * a.n + (g < a.n ? g : 0);
         const uint32_t cnt = g < a.n ? a.gcnt[i] : 0u;
-        Record r;
-        uint2 rc = make_uint2(0u, 0u);
-        bool small = false;
-        if (cnt) {
-            r = a.rec[i];
-            rc = a.rect[i];
-            small = ((rc.x >> 16) - (rc.x & 0xffff) + 1) * ((rc.y >> 16) - (rc.y & 0xffff) + 1) <= 64u;
-        }
+        const Record r = a.rec[i];
+        const uint2 rc = a.rect[i];
+        const uint64_t tm = a.tmask[i];
+        const uint32_t go = a.goff[i];
+        const bool small =
+            cnt && ((rc.x >> 16) - (rc.x & 0xffff) + 1) * ((rc.y >> 16) - (rc.y & 0xffff) + 1) <= 64u;
         uint32_t total;
         const uint32_t start = wave_exclusive_scan(small ? cnt : 0u, lane, total);
         W.start[lane] = start;
         if (small) {
-            W.mask[lane] = a.tmask[i];
+            W.mask[lane] = tm;
             W.key[lane] = sort_key(r, g);
-            W.goff[lane] = a.goff[i];
+            W.goff[lane] = go;
             W.tx0[lane] = rc.x & 0xffff;
             W.ty0[lane] = rc.y & 0xffff;
             W.rw[lane] = static_cast<int>(rc.x >> 16) - static_cast<int>(rc.x & 0xffff) + 1;
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
             }
         }
         __builtin_amdgcn_wave_barrier();
-        if (cnt && !small) scatter_big(a, g, r, shape_from_record(r, rc), cnt, a.goff[i], next, end);
+        if (cnt && !small) scatter_big(a, g, r, shape_from_record(r, rc), cnt, go, next, end);
     }
 }
 
