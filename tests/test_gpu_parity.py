@@ -186,14 +186,45 @@ def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
         raster.set_tuning(old["batch"], old["sort_cap"], old["compact"], old["bwd_batch"])
 
 
-def test_long_tile_buckets_use_the_merge_sort():
-    """Many large Gaussians over a small image: buckets far longer than the
-    LDS sort capacity (chunked LDS sort + global merges)."""
-    w = small_workload(14, 48, 32, 5000, 1, z=(2.0, 6.0), ls=(-1.2, 0.3))
+def tile_bucket_sizes(w, f=0):
+    """Entries per 16x16 tile of frame f from the oracle's projection: the
+    Gaussians whose 3-sigma ellipse meets the tile's pixel-centre box."""
+    cam = w["camera"]
+    p = oracle.project(w["scene"], cam, w["poses"][f].astype(np.float64), float(w["times"][f]))
+    ok = p["valid"] > 0
+    u, v, a, b, c = p["u"][ok], p["v"][ok], p["A00"][ok], p["A01"][ok], p["A11"][ok]
+    sizes = []
+    for ty in range((cam.height + 15) // 16):
+        for tx in range((cam.width + 15) // 16):
+            x0, x1 = tx * 16 + 0.5, min(tx * 16 + 15.5, cam.width - 0.5)
+            y0, y1 = ty * 16 + 0.5, min(ty * 16 + 15.5, cam.height - 0.5)
+            dx0, dx1, dy0, dy1 = x0 - u, x1 - u, y0 - v, y1 - v
+            best = np.where((dx0 <= 0) & (dx1 >= 0) & (dy0 <= 0) & (dy1 >= 0), 0.0, np.inf)
+            for dx in (dx0, dx1):
+                dy = np.clip(-b * dx / c, dy0, dy1)
+                best = np.minimum(best, a * dx * dx + 2 * b * dx * dy + c * dy * dy)
+            for dy in (dy0, dy1):
+                dx = np.clip(-b * dy / a, dx0, dx1)
+                best = np.minimum(best, a * dx * dx + 2 * b * dx * dy + c * dy * dy)
+            sizes.append(int((best <= 9.0).sum()))
+    return np.array(sizes)
+
+
+# (Gaussians, sort capacity, regime of the largest bucket): chunked LDS sort +
+# global merges; two runs merged in LDS; one LDS pass at the largest capacity
+@pytest.mark.parametrize("n,cap,regime", [(5000, 1024, "global"), (1600, 1024, "two runs"), (3000, 4096, "one pass")])
+def test_long_tile_buckets(n, cap, regime):
+    """Many large Gaussians over a small image: buckets beyond the LDS sort
+    capacity, between one and two capacities, and within the largest one."""
+    w = small_workload(14, 48, 32, n, 1, z=(2.0, 6.0), ls=(-1.2, 0.3))
+    sizes = tile_bucket_sizes(w)
+    say(f"[long buckets n={n} cap={cap}] bucket sizes {sorted(sizes.tolist())}")
+    big = sizes.max()
+    assert {"global": big > 2 * cap, "two runs": cap < big <= 2 * cap, "one pass": 2048 < big <= cap}[regime], big
     old = raster.get_tuning()
-    raster.set_tuning(old["batch"], 1024, old["compact"], old["bwd_batch"])
+    raster.set_tuning(old["batch"], cap, old["compact"], old["bwd_batch"])
     try:
-        out = check_clip_against_oracle(w, "long buckets")
+        check_clip_against_oracle(w, f"long buckets n={n} cap={cap}")
     finally:
         raster.set_tuning(old["batch"], old["sort_cap"], old["compact"], old["bwd_batch"])
 
