@@ -35,7 +35,7 @@ __device__ __forceinline__ void add_rot_partial(int e, float v, const float q[4]
 // conic is read from the forward record (the FP64 value rounded once: exactly
 // the one the compositing kernels used); the rest is recomputed.
 struct AdjIn {
-    float mu[3], s[3], qh[4], qn, R[9], Sig[6], m[3], T[6], A[3], o;
+    float mu[3], s[3], qh[4], iqn, R[9], Sig[6], m[3], iz, T[6], A[3], o;
     float N[4];  // B-spline weights of control points span .. span + 3
     int span;
 };
@@ -49,29 +49,13 @@ __device__ __forceinline__ float cubic_in_t(const Args& a, const void* coeffs, i
     return t * (c1 + t * (c2 + t * c3));
 }
 
+// Shape part of the adjoint inputs at time t: scales, normalised quaternion
+// (and 1/|q|), rotation, 3D covariance and opacity.  Static Gaussians (DYN
+// false) compute it once; t enters only through Eq. 3's polynomials.
 template <bool DYN>
-__device__ __forceinline__ void adjoint_inputs(const Args& a, int64_t g, const Record& rec, const float* Rc,
-                                               const float* tc, float t, AdjIn& P) {
+__device__ __forceinline__ void shape_inputs(const Args& a, int64_t g, float t, AdjIn& P) {
     const int64_t n = a.n;
     float q[4];
-    P.span = 0;
-    if (DYN && a.n_ctrl > 0) {
-        P.span = spline_basis<float>(a.n_ctrl, fminf(fmaxf(t, 0.0f), 1.0f), P.N);
-        for (int k = 0; k < 3; ++k) {
-            float mu = 0.0f;
-            for (int r = 0; r < 4; ++r)
-                if (P.N[r] != 0.0f)
-                    mu += P.N[r] * static_cast<float>(
-                                       load_param(a.ctrl, a.dtype, (static_cast<int64_t>(P.span + r) * 3 + k) * n + g));
-            P.mu[k] = mu;
-        }
-    } else {
-        for (int k = 0; k < 3; ++k) {
-            float mu = static_cast<float>(load_param(a.means, a.dtype, k * n + g));
-            if (a.mean_coeffs) mu = mu + cubic_in_t(a, a.mean_coeffs, 3, k, g, t);
-            P.mu[k] = mu;
-        }
-    }
     for (int k = 0; k < 3; ++k) {
         float ls = static_cast<float>(load_param(a.log_scales, a.dtype, k * n + g));
         if (DYN && a.scale_coeffs) ls = ls + cubic_in_t(a, a.scale_coeffs, 3, k, g, t);
@@ -81,8 +65,8 @@ __device__ __forceinline__ void adjoint_inputs(const Args& a, int64_t g, const R
         q[k] = static_cast<float>(load_param(a.quats, a.dtype, k * n + g));
         if (DYN && a.quat_coeffs) q[k] = q[k] + cubic_in_t(a, a.quat_coeffs, 4, k, g, t);
     }
-    P.qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    for (int k = 0; k < 4; ++k) P.qh[k] = q[k] / P.qn;
+    P.iqn = 1.0f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int k = 0; k < 4; ++k) P.qh[k] = q[k] * P.iqn;
     const float eta = static_cast<float>(load_param(a.opacity_logits, a.dtype, g));
     P.o = 1.0f / (1.0f + expf(-eta));
     {
@@ -103,9 +87,38 @@ __device__ __forceinline__ void adjoint_inputs(const Args& a, int64_t g, const R
         P.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
         P.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
     }
+}
+
+// Frame part: the mean at time t (B-spline, cubic or static), its camera-space
+// position, the projection Jacobian times the camera rotation, and the conic
+// of the forward record (the FP64 value rounded once: exactly the one the
+// compositing kernels used).
+template <bool DYN>
+__device__ __forceinline__ void frame_inputs(const Args& a, int64_t g, const Record& rec, const float* Rc,
+                                             const float* tc, float t, AdjIn& P) {
+    const int64_t n = a.n;
+    P.span = 0;
+    if (DYN && a.n_ctrl > 0) {
+        P.span = spline_basis<float>(a.n_ctrl, fminf(fmaxf(t, 0.0f), 1.0f), P.N);
+        for (int k = 0; k < 3; ++k) {
+            float mu = 0.0f;
+            for (int r = 0; r < 4; ++r)
+                if (P.N[r] != 0.0f)
+                    mu += P.N[r] * static_cast<float>(
+                                       load_param(a.ctrl, a.dtype, (static_cast<int64_t>(P.span + r) * 3 + k) * n + g));
+            P.mu[k] = mu;
+        }
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            float mu = static_cast<float>(load_param(a.means, a.dtype, k * n + g));
+            if (a.mean_coeffs) mu = mu + cubic_in_t(a, a.mean_coeffs, 3, k, g, t);
+            P.mu[k] = mu;
+        }
+    }
     for (int i = 0; i < 3; ++i)
         P.m[i] = tc[i] + Rc[i * 3 + 0] * P.mu[0] + Rc[i * 3 + 1] * P.mu[1] + Rc[i * 3 + 2] * P.mu[2];
-    const float iz = 1.0f / P.m[2];
+    P.iz = 1.0f / P.m[2];
+    const float iz = P.iz;
     const float j00 = a.fx * iz, j02 = -a.fx * P.m[0] * iz * iz;
     const float j11 = a.fy * iz, j12 = -a.fy * P.m[1] * iz * iz;
     for (int j = 0; j < 3; ++j) {
@@ -117,11 +130,36 @@ __device__ __forceinline__ void adjoint_inputs(const Args& a, int64_t g, const R
     P.A[2] = rec.c;
 }
 
+// dL/dSig (symmetric, stored xx xy xz yy yz zz) -> gradients of the stored
+// log-scales (out 0-2) and the unnormalised quaternion (out 3-6), through
+// Sig = M M^T, M = R diag(s): dM = 2 G M, dR = dM diag(s), ds_j = sum_i dM_ij R_ij.
+__device__ __forceinline__ void sigma_adjoint(const float G[6], const AdjIn& P, float out[7]) {
+    const float Gm[9] = {G[0], G[1], G[2], G[1], G[3], G[4], G[2], G[4], G[5]};
+    float ds[3] = {0.f, 0.f, 0.f};
+    float gq[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const float V = Gm[i * 3 + 0] * P.R[0 * 3 + j] + Gm[i * 3 + 1] * P.R[1 * 3 + j] +
+                            Gm[i * 3 + 2] * P.R[2 * 3 + j];
+            const float dM = 2.0f * P.s[j] * V;
+            ds[j] += dM * P.R[i * 3 + j];
+            add_rot_partial(i * 3 + j, dM * P.s[j], P.qh, gq);
+        }
+    for (int k = 0; k < 3; ++k) out[k] = ds[k] * P.s[k];
+    // q_hat = q / |q|
+    const float dot = P.qh[0] * gq[0] + P.qh[1] * gq[1] + P.qh[2] * gq[2] + P.qh[3] * gq[3];
+    for (int k = 0; k < 4; ++k) out[3 + k] = (gq[k] - P.qh[k] * dot) * P.iqn;
+}
+
 // Chain rule for one (frame, Gaussian).  d: dL/d(u, v, A00, A01, A11, o, r, g,
 // b) with A01 the single off-diagonal conic parameter (it enters q twice).
 // Writes the gradients w.r.t. the frame's parameter values to gout (mean 0-2,
-// log-scales 3-5, quaternion 6-9, opacity logit 10, colour 11-13) and adds
-// the pose gradient (dL/dRc row-major 0-8, dL/dtc 9-11) to pose.
+// log-scales 3-5, quaternion 6-9, opacity logit 10, colour 11-13; with
+// SIGMA_OUT, dL/dSig at 3-8 instead of 3-9) and adds the pose gradient
+// (dL/dRc row-major 0-8, dL/dtc 9-11) to pose.
+template <bool SIGMA_OUT>
 __device__ __forceinline__ void projection_adjoint(const Args& a, const float* Rc, const AdjIn& P,
                                                    const float d[9], float gout[14], float (&pose)[12],
                                                    float gintr[4]) {
@@ -151,8 +189,8 @@ __device__ __forceinline__ void projection_adjoint(const Args& a, const float* R
         dT[i * 3 + 2] = 2.0f * (c0 * S[2] + c1 * S[4] + c2 * S[5]);
     }
     // T = J Rc with J = [[j00, 0, j02], [0, j11, j12]]
-    const float mx = P.m[0], my = P.m[1], mz = P.m[2];
-    const float iz = 1.0f / mz, iz2 = iz * iz, iz3 = iz2 * iz;
+    const float mx = P.m[0], my = P.m[1];
+    const float iz = P.iz, iz2 = iz * iz, iz3 = iz2 * iz;
     const float fx = a.fx, fy = a.fy;
     const float j00 = fx * iz, j02 = -fx * mx * iz2, j11 = fy * iz, j12 = -fy * my * iz2;
     float dJ00 = 0.f, dJ02 = 0.f, dJ11 = 0.f, dJ12 = 0.f;
@@ -184,27 +222,21 @@ __device__ __forceinline__ void projection_adjoint(const Args& a, const float* R
     }
     for (int i = 0; i < 3; ++i)
         for (int k = 0; k < 3; ++k) pose[i * 3 + k] += dm[i] * P.mu[k];
-    // Sig = M M^T, M = R diag(s): dM = 2 (T^T C T) M, i.e. with U = C T R,
-    // dM_ij = 2 s_j (T_0i U_0j + T_1i U_1j); then dR = dM diag(s), ds_j = sum_i dM_ij R_ij
-    float U[6];
-    for (int r = 0; r < 2; ++r)
-        for (int j = 0; j < 3; ++j)
-            U[r * 3 + j] = CT[r * 3 + 0] * P.R[0 * 3 + j] + CT[r * 3 + 1] * P.R[1 * 3 + j] +
-                           CT[r * 3 + 2] * P.R[2 * 3 + j];
-    float ds[3] = {0.f, 0.f, 0.f};
-    float gq[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const float dM = 2.0f * P.s[j] * (Tm[i] * U[j] + Tm[3 + i] * U[3 + j]);
-            ds[j] += dM * P.R[i * 3 + j];
-            add_rot_partial(i * 3 + j, dM * P.s[j], P.qh, gq);
-        }
-    for (int k = 0; k < 3; ++k) gout[3 + k] = ds[k] * P.s[k];
-    // q_hat = q / |q|
-    const float dot = P.qh[0] * gq[0] + P.qh[1] * gq[1] + P.qh[2] * gq[2] + P.qh[3] * gq[3];
-    for (int k = 0; k < 4; ++k) gout[6 + k] = (gq[k] - P.qh[k] * dot) / P.qn;
+    // dL/dSig = T^T C T; static Gaussians return it (summed over frames and
+    // taken through sigma_adjoint once), the others apply sigma_adjoint per frame
+    float G[6];
+    G[0] = Tm[0] * CT[0] + Tm[3] * CT[3];
+    G[1] = Tm[0] * CT[1] + Tm[3] * CT[4];
+    G[2] = Tm[0] * CT[2] + Tm[3] * CT[5];
+    G[3] = Tm[1] * CT[1] + Tm[4] * CT[4];
+    G[4] = Tm[1] * CT[2] + Tm[4] * CT[5];
+    G[5] = Tm[2] * CT[2] + Tm[5] * CT[5];
+    if (SIGMA_OUT) {
+        for (int k = 0; k < 6; ++k) gout[3 + k] = G[k];
+        gout[9] = 0.0f;
+    } else {
+        sigma_adjoint(G, P, gout + 3);
+    }
     gout[10] = d[5] * P.o * (1.0f - P.o);
     gout[11] = d[6];
     gout[12] = d[7];
@@ -212,8 +244,8 @@ __device__ __forceinline__ void projection_adjoint(const Args& a, const float* R
 }
 
 // Accumulator slots (FP64, in LDS) of the projection adjoint kernel.  The
-// static layout holds the 14 per-frame parameter gradients (mean 0-2,
-// log-scales 3-5, quaternion 6-9, opacity 10, colour 11-13) and the cubic mean
+// static layout holds the per-frame gradients of the mean (0-2), dL/dSig
+// (3-8; slot 9 unused), opacity (10) and colour (11-13), and the cubic mean
 // coefficients 14-22.  The dynamic layout (B-spline means and/or polynomial
 // log-scales and quaternions, Eq. 2-3) holds the 14 at 0-13, a window of four
 // control points 14-25 (point span + r, axis k at 14 + 3 r + k), the
@@ -311,6 +343,10 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
     if (spline && live && !a.accumulate)
         for (int64_t i = 0; i < static_cast<int64_t>(a.n_ctrl) * 3; ++i) a.g_ctrl[i * n + g] = 0.0f;
 
+    // a static Gaussian's shape (scales, rotation, 3D covariance, opacity) is
+    // the same in every frame
+    AdjIn Pstatic = {};
+    if (!DYN && live) shape_inputs<false>(a, g, 0.0f, Pstatic);
     // the next frame's count, slot offset and record are loaded one frame ahead
     uint32_t cnt_n = 0u, base_n = 0u;
     Record rec_n = {};
@@ -378,10 +414,11 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
                 float d[9];
                 for (int k = 0; k < 9; ++k) d[k] = static_cast<float>(dd[k]);
                 const float t = a.times ? a.times[f] : a.t0;
-                AdjIn P;
-                adjoint_inputs<DYN>(a, g, rec, camR, camT, t, P);
+                AdjIn P = Pstatic;
+                if (DYN) shape_inputs<DYN>(a, g, t, P);
+                frame_inputs<DYN>(a, g, rec, camR, camT, t, P);
                 float go[14], gi[4];
-                projection_adjoint(a, camR, P, d, go, pose, gi);
+                projection_adjoint<!DYN>(a, camR, P, d, go, pose, gi);
                 if (a.g_intr)
                     for (int k = 0; k < 4; ++k) iacc[k][tid] += gi[k];
                 if (SH) {
@@ -487,12 +524,21 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
         if (a.accumulate) dst[idx] += static_cast<float>(v);
         else dst[idx] = static_cast<float>(v);
     };
+    double gsq[7];  // log-scales, quaternion
+    if (DYN) {
+        for (int k = 0; k < 7; ++k) gsq[k] = acc[3 + k][tid];
+    } else {  // dL/dSig summed over the frames, through the shape once
+        float Gs[6], o7[7];
+        for (int k = 0; k < 6; ++k) Gs[k] = static_cast<float>(acc[3 + k][tid]);
+        sigma_adjoint(Gs, Pstatic, o7);
+        for (int k = 0; k < 7; ++k) gsq[k] = o7[k];
+    }
     for (int k = 0; k < 3; ++k) {
         if (a.n_ctrl == 0) put(a.g_means, k * n + g, acc[k][tid]);
-        put(a.g_log_scales, k * n + g, acc[3 + k][tid]);
+        put(a.g_log_scales, k * n + g, gsq[k]);
         put(a.g_colors, k * n + g, acc[11 + k][tid]);
     }
-    for (int k = 0; k < 4; ++k) put(a.g_quats, k * n + g, acc[6 + k][tid]);
+    for (int k = 0; k < 4; ++k) put(a.g_quats, k * n + g, gsq[3 + k]);
     put(a.g_opacity, g, acc[10][tid]);
     if (!DYN && a.mean_coeffs)
         for (int c = 0; c < 3; ++c)
