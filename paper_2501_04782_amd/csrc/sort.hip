@@ -12,15 +12,19 @@
 
 namespace gv {
 
-// Number of keys below x in the sorted run S[0, len), len <= R (R a power of
-// two): binary lifting over R, reading only inside [0, len).
-__device__ __forceinline__ int count_below(const uint64_t* S, int len, int R, uint64_t x) {
+// Number of keys below x in the sorted run S[0, R) (R a power of two; slots
+// past the run's keys hold keys above every real key): binary lifting.
+__device__ __forceinline__ int count_below(const uint64_t* S, int R, uint64_t x) {
     int lo = 0;
     for (int step = R >> 1; step >= 1; step >>= 1)
-        if (lo + step <= len && S[lo + step - 1] < x) lo += step;
-    if (lo < len && S[lo] < x) ++lo;
+        if (S[lo + step - 1] < x) lo += step;
+    if (S[lo] < x) ++lo;
     return lo;
 }
+
+// Keys that pad the LDS buffers: above every real key (whose high word is the
+// bit pattern of a finite depth) and distinct from each other.
+__device__ __forceinline__ uint64_t pad_key(int e) { return 0xFFFFFFFF00000000ull | static_cast<uint32_t>(e); }
 
 // Ranks of the keys of one bucket segment of len <= CAP keys, in LDS.
 // Thread t owns elements e = t + WG j (their keys and values stay in
@@ -39,6 +43,11 @@ __device__ __forceinline__ uint64_t* lds_sort_ranks(const KeySlot* src, int len,
                                                int (&rank)[CAP / WG]) {
     constexpr int EPT = CAP / WG;
     const int npad = (len + 15) & ~15;
+    // the last level merges groups of `top` keys; slots [npad, top) of both
+    // buffers keep padding keys, so every run searched has its full length
+    int top = 16;
+    while (top < npad) top <<= 2;
+    top = min(top, CAP);
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         const int e = threadIdx.x + WG * j;
@@ -47,10 +56,11 @@ __device__ __forceinline__ uint64_t* lds_sort_ranks(const KeySlot* src, int len,
             x[j] = ks.key;
             v[j] = ks.slot;
         } else {
-            x[j] = 0xFFFFFFFF00000000ull | static_cast<uint32_t>(e);
+            x[j] = pad_key(e);
             v[j] = 0u;
         }
         if (e < npad) SA[e] = x[j];
+        else if (e < top) SA[e] = SB[e] = pad_key(e);
     }
     __syncthreads();
 #pragma unroll
@@ -80,7 +90,7 @@ __device__ __forceinline__ uint64_t* lds_sort_ranks(const KeySlot* src, int len,
             for (int t = 0; t < 4; ++t) {
                 const int st = gb + t * R;
                 if (t == mine || st >= npad) continue;
-                r += count_below(cur + st, min(R, npad - st), R, x[j]);
+                r += count_below(cur + st, R, x[j]);
             }
             rank[j] = r;
             nxt[gb + r] = x[j];
@@ -142,18 +152,22 @@ __global__ __launch_bounds__(WG) void k_tile_sort(Args a) {
         const int len1 = static_cast<int>(n) - CAP;
         const uint64_t* K1 = lds_sort_ranks<CAP>(src + CAP, len1, SA, SB, x, v, rank);
         uint64_t* K0 = K1 == SA ? SB : SA;
+        // run 1's keys and padding fill K1[0, top1) (the group size of its last level)
+        int top1 = 16;
+        while (top1 < ((len1 + 15) & ~15)) top1 <<= 2;
+        top1 = min(top1, CAP);
         for (int i = threadIdx.x; i < CAP; i += WG) K0[i] = src[i].key;
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             const int i = threadIdx.x + WG * j;
             if (i < len1) {
-                const int r = rank[j] + count_below(K0, CAP, CAP, x[j]);
+                const int r = rank[j] + count_below(K0, CAP, x[j]);
                 a.sgid[s + r] = static_cast<uint32_t>(x[j]);
                 a.sslot[s + r] = v[j];
             }
             const KeySlot e0 = src[i];
-            const int r0 = i + count_below(K1, len1, CAP, e0.key);
+            const int r0 = i + count_below(K1, top1, e0.key);
             a.sgid[s + r0] = static_cast<uint32_t>(e0.key);
             a.sslot[s + r0] = e0.slot;
         }
