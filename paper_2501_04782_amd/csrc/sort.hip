@@ -2,8 +2,7 @@
 // (frame, tile) (a counting sort on the tile digit); each tile's bucket is
 // then sorted by the 64-bit key (fp32 depth bits, Gaussian index) in LDS by
 // one workgroup: ranks by comparison within chunks of 16 keys, then by merging
-// groups of four sorted runs level by level (binary search in the sibling
-// runs).  Keys are unique within a bucket, so the order is fully determined
+// pairs of sorted runs level by level (binary search in the other run).  Keys are unique within a bucket, so the order is fully determined
 // (depth, ties by lower index) whatever order the atomics of the scatter
 // produced.  Buckets longer than the LDS capacity are sorted in LDS chunks and
 // merged in global memory (each element finds its place in the partner run by
@@ -30,9 +29,9 @@ __device__ __forceinline__ uint64_t pad_key(int e) { return 0xFFFFFFFF00000000ul
 // Thread t owns elements e = t + WG j (their keys and values stay in
 // registers; only keys are exchanged through LDS).  Level 0 ranks every key
 // within its chunk of 16 by comparison with the chunk's keys; each following
-// level merges groups of four sorted runs (16 -> 64 -> 256 -> ...): a key's
-// rank in the merged run is its rank in its own run plus, for each sibling
-// run, the number of that run's keys below it.  Each level writes its sorted
+// level merges pairs of sorted runs (16 -> 32 -> 64 -> ...): a key's rank in
+// the merged run is its rank in its own run plus the number of the other
+// run's keys below it.  Each level writes its sorted
 // runs (key at its rank) for the next level's searches.  Padding keys lie
 // above every real key (real depths are finite) and are distinct, so the
 // ranks of a level are a permutation and every slot is written.  Returns the
@@ -46,8 +45,7 @@ __device__ __forceinline__ uint64_t* lds_sort_ranks(const KeySlot* src, int len,
     // the last level merges groups of `top` keys; slots [npad, top) of both
     // buffers keep padding keys, so every run searched has its full length
     int top = 16;
-    while (top < npad) top <<= 2;
-    top = min(top, CAP);
+    while (top < npad) top <<= 1;
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         const int e = threadIdx.x + WG * j;
@@ -79,19 +77,15 @@ __device__ __forceinline__ uint64_t* lds_sort_ranks(const KeySlot* src, int len,
     __syncthreads();
     uint64_t* cur = SB;
     uint64_t* nxt = SA;
-    for (int R = 16; R < npad; R <<= 2) {
+    for (int R = 16; R < npad; R <<= 1) {
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             const int e = threadIdx.x + WG * j;
             if (e >= npad) continue;
-            const int gb = e & ~(4 * R - 1);  // first element of the group of four runs
-            const int mine = (e - gb) / R;
+            const int gb = e & ~(2 * R - 1);  // first element of the pair of runs
+            const int st = (e & R) ? gb : gb + R;  // the other run
             int r = rank[j];
-            for (int t = 0; t < 4; ++t) {
-                const int st = gb + t * R;
-                if (t == mine || st >= npad) continue;
-                r += count_below(cur + st, R, x[j]);
-            }
+            if (st < npad) r += count_below(cur + st, R, x[j]);
             rank[j] = r;
             nxt[gb + r] = x[j];
         }
@@ -154,8 +148,7 @@ __global__ __launch_bounds__(WG) void k_tile_sort(Args a) {
         uint64_t* K0 = K1 == SA ? SB : SA;
         // run 1's keys and padding fill K1[0, top1) (the group size of its last level)
         int top1 = 16;
-        while (top1 < ((len1 + 15) & ~15)) top1 <<= 2;
-        top1 = min(top1, CAP);
+        while (top1 < ((len1 + 15) & ~15)) top1 <<= 1;
         for (int i = threadIdx.x; i < CAP; i += WG) K0[i] = src[i].key;
         __syncthreads();
 #pragma unroll
