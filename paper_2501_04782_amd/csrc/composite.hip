@@ -1,12 +1,13 @@
 // Front-to-back alpha compositing of each 16x16 tile (forward) and its adjoint
 // (back to front, transmittance recomputed by division from the stored final
 // value).  One 256-thread workgroup per (frame, tile); wave w owns the 8x8
-// quadrant (w & 1, w >> 1), lane l the pixel (l & 7, l >> 3) in it.  The
-// tile's depth-sorted entries are staged through LDS in batches of B; at
-// staging each entry gets a 4-bit mask of the quadrants its 3-sigma ellipse
-// meets, so a wave skips entries that cannot touch its pixels with one scalar
-// branch.  Lanes leave the loop when their pixel terminates and a workgroup
-// stops staging once every pixel has terminated.
+// quadrant (w & 1, w >> 1).  The tile's depth-sorted entries are staged
+// through LDS in batches of B, each with a mask of the parts of the tile its
+// 3-sigma ellipse meets: in the quadrant kernels lane l owns pixel
+// (l & 7, l >> 3) of its quadrant and a wave walks the entries meeting the
+// quadrant; in the sub-block forward each 16-lane row owns a 4x4 block and
+// walks the entries meeting the block.  Lanes leave the loop when their pixel
+// terminates and a workgroup stops staging once every pixel has terminated.
 #include "gv_internal.h"
 
 namespace gv {
