@@ -130,14 +130,26 @@ __device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t x, int lane, ui
     return incl - x;
 }
 
-// Lane owning work item `item` of a wave: the last lane whose exclusive
-// start is at most item (lanes with no items share their successor's start).
-__device__ __forceinline__ int owner_of(const uint32_t* start, uint32_t item) {
-    int o = 0;
-#pragma unroll
-    for (int step = 32; step >= 1; step >>= 1)
-        if (start[o + step] <= item) o += step;
-    return o;
+// Lane owning work item b0 + lane of a wave whose lanes deal out `cnt` items
+// each from exclusive starts `start`: the last lane with items whose start is
+// at most the item.  Each owner whose first item falls in [b0, b0 + 64) marks
+// that position in `own` (64 slots of the wave, in LDS); an item's owner is
+// the mark at or below its position, or, before the first mark, the owner of
+// item b0 (the last lane with items starting at or before b0).
+__device__ __forceinline__ int chunk_owner(uint32_t* own, uint32_t start, uint32_t cnt, uint32_t b0, int lane) {
+    own[lane] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    if (cnt && start >= b0 && start - b0 < 64u) own[start - b0] = static_cast<uint32_t>(lane) + 1u;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t mark = own[lane];
+    const uint64_t marks = __ballot(mark != 0u);
+    const uint64_t before = __ballot(cnt != 0u && start <= b0);
+    const int carry = before ? 63 - __builtin_clzll(before) : 0;
+    const uint64_t upto = marks & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+    const int src = upto ? 63 - __builtin_clzll(upto) : 0;
+    const int m = __shfl(static_cast<int>(mark), src, 64);
+    __builtin_amdgcn_wave_barrier();
+    return upto ? m - 1 : carry;
 }
 
 // Index of the (k+1)-th set bit of m (k < popcount(m)).
@@ -164,6 +176,7 @@ __device__ __forceinline__ int kth_set_bit(uint64_t m, uint32_t k) {
 struct WaveCells {
     BinShape shape[64];
     uint32_t start[64];
+    uint32_t own[64];
     unsigned long long mask[64];
     uint32_t cnt[64];
 };
@@ -201,8 +214,8 @@ __global__ __launch_bounds__(256) void k_project_lds(Args a) {
         __builtin_amdgcn_wave_barrier();
         for (uint32_t b0 = 0; b0 < total; b0 += 64) {
             const uint32_t item = b0 + static_cast<uint32_t>(lane);
+            const int o = chunk_owner(W.own, start, ncell, b0, lane);
             if (item < total) {
-                const int o = owner_of(W.start, item);
                 const uint32_t cell = item - W.start[o];
                 const BinShape& So = W.shape[o];
                 const int ry = static_cast<int>(cell) / So.rw;
@@ -280,6 +293,7 @@ struct WaveKeys {
     unsigned long long mask[64];
     unsigned long long key[64];
     uint32_t start[64];
+    uint32_t own[64];
     uint32_t goff[64];
     int tx0[64], ty0[64], rw[64];
 };
@@ -338,8 +352,8 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
         __builtin_amdgcn_wave_barrier();
         for (uint32_t b0 = 0; b0 < total; b0 += 64) {
             const uint32_t item = b0 + static_cast<uint32_t>(lane);
+            const int o = chunk_owner(W.own, start, small ? cnt : 0u, b0, lane);
             if (item < total) {
-                const int o = owner_of(W.start, item);
                 const uint32_t kk = item - W.start[o];
                 const uint64_t m = W.mask[o];
                 if (kk >= static_cast<uint32_t>(__popcll(m))) {  // counts and mask disagree: internal error
