@@ -350,11 +350,12 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
     // the next frame's count, slot offset and record are loaded one frame ahead
     uint32_t cnt_n = 0u, base_n = 0u;
     Record rec_n = {};
+    // (unconditional loads: no wait on the count before the record is requested)
     auto fetch = [&](int f) {
-        const int64_t i = static_cast<int64_t>(f) * a.n + g;
+        const int64_t i = static_cast<int64_t>(f) * a.n + (live ? g : 0);
         cnt_n = live ? a.gcnt[i] : 0u;
         base_n = live ? a.goff[i] : 0u;
-        if (cnt_n) rec_n = a.rec[i];
+        rec_n = a.rec[i];
     };
     if (fb < fe) fetch(fb);
 #pragma unroll 1
