@@ -392,13 +392,13 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
             float pose[12];
             for (int k = 0; k < 12; ++k) pose[k] = 0.0f;
             if (cnt) {
-                double dd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
                 // PU records per round, loads issued together (past the end
                 // they repeat a valid record and are not added), summed in
-                // order k = 0, 1, ...
+                // order k = 0, 1, ...; the first round is requested before the
+                // frame's projection inputs are computed, which do not need it
                 constexpr uint32_t PU = 8;
-                for (uint32_t k0 = 0; k0 < cnt; k0 += PU) {
-                    float r[PU][PART];
+                float r[PU][PART];
+                auto load_round = [&](uint32_t k0) {
 #pragma unroll
                     for (uint32_t u = 0; u < PU; ++u) {
                         const uint32_t k = k0 + u < cnt ? k0 + u : k0;
@@ -406,18 +406,25 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
 #pragma unroll
                         for (int m = 0; m < PART; ++m) r[u][m] = pp[m];
                     }
+                };
+                load_round(0);
+                const float t = a.times ? a.times[f] : a.t0;
+                AdjIn P = Pstatic;
+                if (DYN) shape_inputs<DYN>(a, g, t, P);
+                frame_inputs<DYN>(a, g, rec, camR, camT, t, P);
+                double dd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                for (uint32_t k0 = 0;;) {
 #pragma unroll
                     for (uint32_t u = 0; u < PU; ++u)
                         if (k0 + u < cnt)
 #pragma unroll
                             for (int m = 0; m < PART; ++m) dd[m] += r[u][m];
+                    k0 += PU;
+                    if (k0 >= cnt) break;
+                    load_round(k0);
                 }
                 float d[9];
                 for (int k = 0; k < 9; ++k) d[k] = static_cast<float>(dd[k]);
-                const float t = a.times ? a.times[f] : a.t0;
-                AdjIn P = Pstatic;
-                if (DYN) shape_inputs<DYN>(a, g, t, P);
-                frame_inputs<DYN>(a, g, rec, camR, camT, t, P);
                 float go[14], gi[4];
                 projection_adjoint<!DYN>(a, camR, P, d, go, pose, gi);
                 if (a.g_intr)
