@@ -325,17 +325,38 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
     auto end = [&](int tl) { return lim[tl]; };
     const int64_t g0 = static_cast<int64_t>(blockIdx.x) * BIN_GROUP;
     WaveKeys& W = wk[w];
+    // A Gaussian's count, record, rectangle, mask and slot offset, requested
+    // together (one memory round trip; a Gaussian without intersections
+    // ignores them), and the next round's requested before this round's keys
+    // are dealt out.
+    struct In {
+        uint32_t cnt;
+        Record r;
+        uint2 rc;
+        uint64_t tm;
+        uint32_t go;
+    };
+    auto load_in = [&](int k, In& x) {
+        const int64_t g = g0 + k * 256 + threadIdx.x;
+        const int64_t i = static_cast<int64_t>(f) * a.n + (g < a.n ? g : 0);
+        x.cnt = g < a.n ? a.gcnt[i] : 0u;
+        x.r = a.rec[i];
+        x.rc = a.rect[i];
+        x.tm = a.tmask[i];
+        x.go = a.goff[i];
+    };
+    In nxt;
+    load_in(0, nxt);
 #pragma unroll 1
     for (int k = 0; k < BIN_GROUP / 256; ++k) {
         const int64_t g = g0 + k * 256 + threadIdx.x;
-        // all of the Gaussian's loads are issued together (one memory round
-        // trip); a Gaussian without intersections ignores them
-        const int64_t i = static_cast<int64_t>(f) * a.n + (g < a.n ? g : 0);
-        const uint32_t cnt = g < a.n ? a.gcnt[i] : 0u;
-        const Record r = a.rec[i];
-        const uint2 rc = a.rect[i];
-        const uint64_t tm = a.tmask[i];
-        const uint32_t go = a.goff[i];
+        const In cur = nxt;
+        if (k + 1 < BIN_GROUP / 256) load_in(k + 1, nxt);
+        const uint32_t cnt = cur.cnt;
+        const Record& r = cur.r;
+        const uint2 rc = cur.rc;
+        const uint64_t tm = cur.tm;
+        const uint32_t go = cur.go;
         const bool small =
             cnt && ((rc.x >> 16) - (rc.x & 0xffff) + 1) * ((rc.y >> 16) - (rc.y & 0xffff) + 1) <= 64u;
         uint32_t total;
