@@ -64,14 +64,15 @@ __device__ __forceinline__ void stage_entry(const Args& a, int f, uint32_t gid, 
 // (slightly inflated) 3-sigma ellipse meets.
 __device__ __forceinline__ uint32_t quadrant_mask(const Staged& st, float3 cn, int xlim, int ylim) {
     if (cn.x == 0.f && cn.y == 0.f && cn.z == 0.f) return 0u;  // inert
+    const float rbc = -cn.y / cn.z, rba = -cn.y / cn.x;  // edge-minimiser slopes, once per entry
     uint32_t m = 0;
     for (int qd = 0; qd < 4; ++qd) {
         const int x0 = (qd & 1) * 8, y0 = (qd >> 1) * 8;
         const int x1 = min(x0 + 7, xlim), y1 = min(y0 + 7, ylim);
         if (x0 > x1 || y0 > y1) continue;
-        if (ellipse_meets_box<float>(st.p0.x, st.p0.y, cn.x, cn.y, cn.z, static_cast<float>(x0),
-                                     static_cast<float>(x1), static_cast<float>(y0), static_cast<float>(y1),
-                                     SUB_Q_SLACK))
+        if (ellipse_meets_box_r<float>(st.p0.x, st.p0.y, cn.x, cn.y, cn.z, rbc, rba, static_cast<float>(x0),
+                                       static_cast<float>(x1), static_cast<float>(y0), static_cast<float>(y1),
+                                       SUB_Q_SLACK))
             m |= 1u << qd;
     }
     return m;
