@@ -64,7 +64,9 @@ __device__ __forceinline__ void stage_entry(const Args& a, int f, uint32_t gid, 
 // (slightly inflated) 3-sigma ellipse meets.
 __device__ __forceinline__ uint32_t quadrant_mask(const Staged& st, float3 cn, int xlim, int ylim) {
     if (cn.x == 0.f && cn.y == 0.f && cn.z == 0.f) return 0u;  // inert
-    const float rbc = -cn.y / cn.z, rba = -cn.y / cn.x;  // edge-minimiser slopes, once per entry
+    // edge-minimiser slopes, once per entry (an ulp off moves an edge minimum
+    // only in second order)
+    const float rbc = -cn.y * __builtin_amdgcn_rcpf(cn.z), rba = -cn.y * __builtin_amdgcn_rcpf(cn.x);
     uint32_t m = 0;
     for (int qd = 0; qd < 4; ++qd) {
         const int x0 = (qd & 1) * 8, y0 = (qd >> 1) * 8;
@@ -100,7 +102,7 @@ __device__ __forceinline__ void finish_partials(float (&v)[PART], float ca, floa
     v[2] = -0.5f * v[2];
     v[3] = -v[3];
     v[4] = -0.5f * v[4];
-    v[5] = o > 0.0f ? v[5] / o : 0.0f;
+    v[5] = o > 0.0f ? v[5] * __builtin_amdgcn_rcpf(o) : 0.0f;
 }
 
 // Entries per unrolled group of the quadrant forward loop.
@@ -454,11 +456,17 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
         if (tid < static_cast<int>(nb)) {
             const uint32_t m = shm[tid];
             const uint32_t rel = b0 + tid - s;
+            // a wave's slot holds this entry's sums only if the entry was in
+            // its list; the waves are added in a fixed order
+            bool in[WG / 64];
+#pragma unroll
+            for (int ww = 0; ww < WG / 64; ++ww) in[ww] = ((m >> ww) & 1u) && rel < wlast[ww];
             float v[9];
+#pragma unroll
             for (int k = 0; k < 9; ++k) {
                 float x = 0.0f;
-                for (int ww = 0; ww < WG / 64; ++ww)
-                    if (((m >> ww) & 1u) && rel < wlast[ww]) x += acc[ww][k][tid];
+#pragma unroll
+                for (int ww = 0; ww < WG / 64; ++ww) x += in[ww] ? acc[ww][k][tid] : 0.0f;
                 v[k] = x;
             }
             const Staged st = sh[tid];
