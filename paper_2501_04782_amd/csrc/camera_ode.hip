@@ -5,8 +5,8 @@
 // 8 -> 64 -> 64 -> 7 tanh MLP, so latency, not throughput, is what matters:
 // lane j owns hidden unit j and keeps its weights in VGPRs (row j of W1 and W2,
 // column j of W3, and for the adjoint also column j of W2); the hidden layer
-// is exchanged through LDS (broadcast reads) and the 7 outputs are wave
-// reductions (DPP).  The state z is carried in FP64, the MLP runs in FP32.
+// is exchanged through LDS (broadcast reads) and the 7 outputs are summed over
+// the lanes by one reduce-scatter.  The state z is carried in FP64, the MLP runs in FP32.
 // The forward pass records every evaluation's input and both hidden
 // activations so that the adjoint needs no recomputation.
 #include "gv_internal.h"
@@ -36,6 +36,28 @@ OdeLayout ode_layout(int frames, int substeps) {
 
 __device__ __forceinline__ float ode_tanh(float x) { return tanhf(x); }
 
+// Sum of 8 values over the 64 lanes at once: cross-half and cross-row swaps,
+// then DPP within rows; afterwards lanes 8 i .. 8 i + 7 hold the wave total of
+// value i.  The order of the additions is fixed.
+__device__ __forceinline__ float reduce_scatter8(float (&v)[8], int lane) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 4]), false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 2]), false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    const bool b3 = lane & 8;
+    const float keep = b3 ? v[1] : v[0], send = b3 ? v[0] : v[1];
+    float x = keep + dpp_f(send, 0x128);
+    x = x + dpp_f(x, 0x141);
+    x = x + dpp_f(x, 0x4E);
+    return x + dpp_f(x, 0xB1);
+}
+
 // One MLP evaluation at (y, t); lanes hold hidden unit j = lane.  Returns the
 // 7 outputs (uniform).  If rec != nullptr, stores x, h1, h2 there.
 __device__ __forceinline__ void mlp_eval(const double y[ODE_S], double t, const float w1[8], float b1,
@@ -53,10 +75,11 @@ __device__ __forceinline__ void mlp_eval(const double y[ODE_S], double t, const 
     float a2 = b2;
     for (int k = 0; k < ODE_H; ++k) a2 = __builtin_fmaf(w2[k], h1s[k], a2);
     const float h2 = ode_tanh(a2);
-    for (int i = 0; i < ODE_S; ++i) {
-        const float s = wave_sum_to_lane63(w3[i] * h2);
-        out[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s), 63)) + b3[i];
-    }
+    float v[8];
+    for (int i = 0; i < ODE_S; ++i) v[i] = w3[i] * h2;
+    v[7] = 0.0f;
+    const float sum = reduce_scatter8(v, j);
+    for (int i = 0; i < ODE_S; ++i) out[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sum), 8 * i)) + b3[i];
     if (rec) {
         if (j < 8) rec[j] = x[j];
         rec[8 + j] = h1;
@@ -156,10 +179,12 @@ __device__ __forceinline__ void mlp_vjp(const float* rec, const double dy[ODE_S]
     const float da1 = dh1 * (1.0f - h1 * h1);
     for (int m = 0; m < 8; ++m) G.gw1[m] = __builtin_fmaf(da1, x[m], G.gw1[m]);
     G.gb1 += da1;
-    for (int m = 0; m < ODE_S; ++m) {
-        const float s = wave_sum_to_lane63(w1[m] * da1);
-        gx[m] = static_cast<double>(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(s), 63)));
-    }
+    float v[8];
+    for (int m = 0; m < ODE_S; ++m) v[m] = w1[m] * da1;
+    v[7] = 0.0f;
+    const float sum = reduce_scatter8(v, j);
+    for (int m = 0; m < ODE_S; ++m)
+        gx[m] = static_cast<double>(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(sum), 8 * m)));
     __syncthreads();
 }
 
