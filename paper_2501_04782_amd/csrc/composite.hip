@@ -251,6 +251,34 @@ __global__ __launch_bounds__(WG) void k_loss_finalize(Args a) {
     if (threadIdx.x == 0) a.loss[f] = overflowed(a.status) ? 0.0f : red[0] * a.loss_norm;
 }
 
+// One halving step of the reduce-scatter below for lane pairs that differ in
+// lane bit 3 or 2 (the bank bits of a DPP row): lanes with the bit clear
+// return a + (a of the partner), the others b + (b of the partner).  Two DPP
+// adds whose bank masks split the lanes replace a select-then-add; s_nop 1
+// gives the wait states a DPP read of a VGPR needs after a VALU write of it.
+// partner lane ^ 8; lane bit 3 clear: banks 0 and 1
+__device__ __forceinline__ float dpp_pair_add_ror8(float a, float b) {
+    float r;
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %1, %1 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %0, %2, %2 row_ror:8 row_mask:0xf bank_mask:0xc"
+        : "=&v"(r)
+        : "v"(a), "v"(b));
+    return r;
+}
+// partner lane 7 - p within each 8 lanes; lane bit 2 clear: banks 0 and 2
+__device__ __forceinline__ float dpp_pair_add_mirror(float a, float b) {
+    float r;
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %1, %1 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+        "v_add_f32_dpp %0, %2, %2 row_half_mirror row_mask:0xf bank_mask:0xa"
+        : "=&v"(r)
+        : "v"(a), "v"(b));
+    return r;
+}
+
 // Sum over the 64 lanes of 64 values at once: after six halving stages
 // (cross-half swaps for 32 and 16 lanes, DPP within rows for the rest) lane l holds
 // the wave total of value l.  Exact in the order of its additions, which is
@@ -266,20 +294,14 @@ __device__ __forceinline__ float reduce_scatter64(float (&v)[64], int lane) {
         const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 16]), false, false);
         v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
-    const bool b8 = lane & 8, b4 = lane & 4, b2 = lane & 2, b1 = lane & 1;
+    const bool b2 = lane & 2, b1 = lane & 1;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const float keep = b8 ? v[i + 8] : v[i], send = b8 ? v[i] : v[i + 8];
-        v[i] = keep + dpp_f(send, 0x128);  // row_ror:8 (partner lane ^ 8)
-    }
+    for (int i = 0; i < 8; ++i) v[i] = dpp_pair_add_ror8(v[i], v[i + 8]);
+    // row_half_mirror pairs lane p with 7 - p within each 8 lanes: always
+    // across bit 2, and with the later xor-2 / xor-1 stages it still merges
+    // all 8 lanes
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        // row_half_mirror pairs lane p with 7 - p within each 8 lanes: always
-        // across bit 2, and with the later xor-2 / xor-1 stages it still merges
-        // all 8 lanes
-        const float keep = b4 ? v[i + 4] : v[i], send = b4 ? v[i] : v[i + 4];
-        v[i] = keep + dpp_f(send, 0x141);
-    }
+    for (int i = 0; i < 4; ++i) v[i] = dpp_pair_add_mirror(v[i], v[i + 4]);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const float keep = b2 ? v[i + 2] : v[i], send = b2 ? v[i] : v[i + 2];
@@ -423,23 +445,26 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
                 const float raw = p1.y * G;
                 const float al = on ? fminf(ALPHA_MAX, raw) : 0.0f;
                 const float inv = __builtin_amdgcn_rcpf(1.0f - al);
+                const float ai = al * inv;
                 const float Tj = T * inv;  // transmittance in front of this entry
-                const float wgt = al * Tj;
+                const float wgt = ai * T;  // alpha T_j
                 P[r * 9 + 6] = wgt * g0;
                 P[r * 9 + 7] = wgt * g1;
                 P[r * 9 + 8] = wgt * g2;
                 // dL/dalpha = sum_c g_c (c_c T_j - S_c / (1 - alpha))
-                //           = (T gc - GS) / (1 - alpha), gc = sum_c g_c c_c
-                const float gc = __builtin_fmaf(g2, P2[r].x, __builtin_fmaf(g1, p1.w, g0 * p1.z));
-                const float dal = inv * __builtin_fmaf(T, gc, -GS);
-                GS = __builtin_fmaf(gc, wgt, GS);
+                //           = (T gc - GS) / (1 - alpha), gc = sum_c g_c c_c, so
+                // alpha dL/dalpha = wgt gc - ai GS, and wgt gc is the colour
+                // partials weighted by the colour
+                const float wgc = __builtin_fmaf(P2[r].x, P[r * 9 + 8], __builtin_fmaf(p1.w, P[r * 9 + 7], p1.z * P[r * 9 + 6]));
+                const float Dal = __builtin_fmaf(-ai, GS, wgc);
+                GS = GS + wgc;
                 T = Tj;
                 // a clamped alpha has no gradient w.r.t. the opacity or footprint
                 // (alpha = 0 already zeroes entries that do not reach the pixel);
                 // with D = alpha dL/dalpha, dL/dq = -D/2 and dL/do = D/o, and the
                 // footprint partials are moments of D over the pixel offsets, to
                 // which the conic is applied once per entry after the reduction
-                const float D = raw < ALPHA_MAX ? al * dal : 0.0f;
+                const float D = raw < ALPHA_MAX ? Dal : 0.0f;
                 const float X = D * dx, Y = D * dy;
                 P[r * 9 + 0] = X;
                 P[r * 9 + 1] = Y;
