@@ -60,24 +60,69 @@ __device__ __forceinline__ void stage_entry(const Args& a, int f, uint32_t gid, 
     conic = make_float3(r.a, r.b, r.c);
 }
 
-// 4-bit mask of the 8x8 quadrants whose pixel-centre box the entry's
-// (slightly inflated) 3-sigma ellipse meets.
-__device__ __forceinline__ uint32_t quadrant_mask(const Staged& st, float3 cn, int xlim, int ylim) {
-    if (cn.x == 0.f && cn.y == 0.f && cn.z == 0.f) return 0u;  // inert
-    // edge-minimiser slopes, once per entry (an ulp off moves an edge minimum
-    // only in second order)
-    const float rbc = -cn.y * __builtin_amdgcn_rcpf(cn.z), rba = -cn.y * __builtin_amdgcn_rcpf(cn.x);
+// Mask of the S x S pixel blocks of the tile that the entry's slightly
+// inflated 3-sigma ellipse meets: S = 8, the four quadrants (bit q); S = 4,
+// the 16 blocks (bit 4 q + r: block r of quadrant q).  Per band of S pixel
+// rows, the ellipse restricted to the band is convex, so its x-extent is an
+// interval whose ends lie at the ellipse's right- and leftmost points clamped
+// into the band; a block is kept if its columns meet that interval (widened
+// by a rounding margin).
+template <int S>
+__device__ __forceinline__ uint32_t band_mask(const Staged& st, float3 cn, int xlim, int ylim) {
+    constexpr int NB = TILE / S;
+    auto bit = [](int by, int bx) {
+        return S == 8 ? 2 * by + bx : 4 * (2 * (by >> 1) + (bx >> 1)) + 2 * (by & 1) + (bx & 1);
+    };
+    const float a = cn.x, b = cn.y, c = cn.z;
+    if (a == 0.f && b == 0.f && c == 0.f) return 0u;  // inert
+    const float lu = st.p0.x, lv = st.p0.y;
+    const float det = static_cast<float>(static_cast<double>(a) * c - static_cast<double>(b) * b);
+    uint32_t all = 0;
+    for (int by = 0; by < NB; ++by)
+        for (int bx = 0; bx < NB; ++bx)
+            if (S * bx <= xlim && S * by <= ylim) all |= 1u << bit(by, bx);
+    if (!(det > 0.0f) || !(a > 0.0f) || !(c > 0.0f)) return all;  // degenerate conic: the exact test decides
+    // hardware sqrt and reciprocals (about 1 ulp): far inside the margins below
+    const float rdet = __builtin_amdgcn_rcpf(det);
+    const float hy = __builtin_amdgcn_sqrtf(SUB_Q_SLACK * a * rdet);  // half-extent in y
+    const float hx = __builtin_amdgcn_sqrtf(SUB_Q_SLACK * c * rdet);  // half-extent in x
+    const float dyr = -b * hx * __builtin_amdgcn_rcpf(c);             // dy of the rightmost point
+    const float aq = a * SUB_Q_SLACK;
+    const float inva = __builtin_amdgcn_rcpf(a);
+    const float tol = 1e-3f + 1e-4f * hy;
     uint32_t m = 0;
-    for (int qd = 0; qd < 4; ++qd) {
-        const int x0 = (qd & 1) * 8, y0 = (qd >> 1) * 8;
-        const int x1 = min(x0 + 7, xlim), y1 = min(y0 + 7, ylim);
-        if (x0 > x1 || y0 > y1) continue;
-        if (ellipse_meets_box_r<float>(st.p0.x, st.p0.y, cn.x, cn.y, cn.z, rbc, rba, static_cast<float>(x0),
-                                       static_cast<float>(x1), static_cast<float>(y0), static_cast<float>(y1),
-                                       SUB_Q_SLACK))
-            m |= 1u << qd;
+    for (int by = 0; by < NB; ++by) {
+        const int y0 = S * by;
+        if (y0 > ylim) break;
+        const int y1 = min(y0 + S - 1, ylim);
+        const float d0 = static_cast<float>(y0) - lv, d1 = static_cast<float>(y1) - lv;
+        if (d0 > hy + tol || d1 < -hy - tol) continue;
+        float lo = fmaxf(d0, -hy), hi = fminf(d1, hy);
+        if (lo > hi) lo = hi = fminf(fmaxf(0.5f * (d0 + d1), -hy), hy);  // within the tolerance of a tip
+        const float dr = fminf(fmaxf(dyr, lo), hi);
+        const float dl = fminf(fmaxf(-dyr, lo), hi);
+        const float sr = __builtin_amdgcn_sqrtf(fmaxf(0.0f, aq - det * dr * dr));
+        const float sl = __builtin_amdgcn_sqrtf(fmaxf(0.0f, aq - det * dl * dl));
+        const float xr = (-b * dr + sr) * inva;
+        const float xl = (-b * dl - sl) * inva;
+        const float eps = 0.01f + 1e-4f * (fabsf(xl) + fabsf(xr));
+        const float xlo = lu + xl - eps, xhi = lu + xr + eps;
+        for (int bx = 0; bx < NB; ++bx) {
+            const int x0 = S * bx;
+            if (x0 > xlim) break;
+            const int x1 = min(x0 + S - 1, xlim);
+            if (static_cast<float>(x0) <= xhi && static_cast<float>(x1) >= xlo) m |= 1u << bit(by, bx);
+        }
     }
     return m;
+}
+
+__device__ __forceinline__ uint32_t quadrant_mask(const Staged& st, float3 cn, int xlim, int ylim) {
+    return band_mask<8>(st, cn, xlim, ylim);
+}
+
+__device__ __forceinline__ uint32_t block_mask(const Staged& st, float3 cn, int xlim, int ylim) {
+    return band_mask<4>(st, cn, xlim, ylim);
 }
 
 // Inert entry that pads the wave lists to whole groups (never reaches a pixel).
@@ -486,12 +531,17 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
             bool in[WG / 64];
 #pragma unroll
             for (int ww = 0; ww < WG / 64; ++ww) in[ww] = ((m >> ww) & 1u) && rel < wlast[ww];
+            // every slot is read (stale slots are in bounds) and selected, so
+            // that the sums compile without branches
             float v[9];
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 float x = 0.0f;
 #pragma unroll
-                for (int ww = 0; ww < WG / 64; ++ww) x += in[ww] ? acc[ww][k][tid] : 0.0f;
+                for (int ww = 0; ww < WG / 64; ++ww) {
+                    const float r = acc[ww][k][tid];
+                    x += in[ww] ? r : 0.0f;
+                }
                 v[k] = x;
             }
             const Staged st = sh[tid];
@@ -848,58 +898,6 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
 // broadcast within a row.  Per pixel the arithmetic is that of the quadrant
 // loop, so images, final transmittances and last indices are identical.
 // ---------------------------------------------------------------------------
-
-// 16-bit mask of the 4x4 blocks (bit 4 q + r: block r of quadrant q) that the
-// entry's slightly inflated 3-sigma ellipse meets.  Per band of four pixel
-// rows, the ellipse restricted to the band is convex, so its x-extent is an
-// interval whose ends lie at the ellipse's right- and leftmost points clamped
-// into the band; a block is kept if its columns meet that interval (widened
-// by a rounding margin).
-__device__ __forceinline__ uint32_t block_mask(const Staged& st, float3 cn, int xlim, int ylim) {
-    const float a = cn.x, b = cn.y, c = cn.z;
-    if (a == 0.f && b == 0.f && c == 0.f) return 0u;  // inert
-    const float lu = st.p0.x, lv = st.p0.y;
-    const float det = static_cast<float>(static_cast<double>(a) * c - static_cast<double>(b) * b);
-    uint32_t all = 0;
-    for (int by = 0; by < 4; ++by)
-        for (int bx = 0; bx < 4; ++bx)
-            if (4 * bx <= xlim && 4 * by <= ylim) all |= 1u << (4 * (2 * (by >> 1) + (bx >> 1)) + 2 * (by & 1) + (bx & 1));
-    if (!(det > 0.0f) || !(a > 0.0f) || !(c > 0.0f)) return all;  // degenerate conic: the exact test decides
-    // hardware sqrt and reciprocals (about 1 ulp): far inside the margins below
-    const float rdet = __builtin_amdgcn_rcpf(det);
-    const float hy = __builtin_amdgcn_sqrtf(SUB_Q_SLACK * a * rdet);  // half-extent in y
-    const float hx = __builtin_amdgcn_sqrtf(SUB_Q_SLACK * c * rdet);  // half-extent in x
-    const float dyr = -b * hx * __builtin_amdgcn_rcpf(c);             // dy of the rightmost point
-    const float aq = a * SUB_Q_SLACK;
-    const float inva = __builtin_amdgcn_rcpf(a);
-    const float tol = 1e-3f + 1e-4f * hy;
-    uint32_t m = 0;
-    for (int by = 0; by < 4; ++by) {
-        const int y0 = 4 * by;
-        if (y0 > ylim) break;
-        const int y1 = min(y0 + 3, ylim);
-        const float d0 = static_cast<float>(y0) - lv, d1 = static_cast<float>(y1) - lv;
-        if (d0 > hy + tol || d1 < -hy - tol) continue;
-        float lo = fmaxf(d0, -hy), hi = fminf(d1, hy);
-        if (lo > hi) lo = hi = fminf(fmaxf(0.5f * (d0 + d1), -hy), hy);  // within the tolerance of a tip
-        const float dr = fminf(fmaxf(dyr, lo), hi);
-        const float dl = fminf(fmaxf(-dyr, lo), hi);
-        const float sr = __builtin_amdgcn_sqrtf(fmaxf(0.0f, aq - det * dr * dr));
-        const float sl = __builtin_amdgcn_sqrtf(fmaxf(0.0f, aq - det * dl * dl));
-        const float xr = (-b * dr + sr) * inva;
-        const float xl = (-b * dl - sl) * inva;
-        const float eps = 0.01f + 1e-4f * (fabsf(xl) + fabsf(xr));
-        const float xlo = lu + xl - eps, xhi = lu + xr + eps;
-        for (int bx = 0; bx < 4; ++bx) {
-            const int x0 = 4 * bx;
-            if (x0 > xlim) break;
-            const int x1 = min(x0 + 3, xlim);
-            if (static_cast<float>(x0) <= xhi && static_cast<float>(x1) >= xlo)
-                m |= 1u << (4 * (2 * (by >> 1) + (bx >> 1)) + 2 * (by & 1) + (bx & 1));
-        }
-    }
-    return m;
-}
 
 // Build the four block lists of wave w over the staged batch, front to back,
 // each padded with the inert entry to `steps` entries, a multiple of G shared
