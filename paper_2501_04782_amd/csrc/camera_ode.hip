@@ -58,6 +58,21 @@ __device__ __forceinline__ float reduce_scatter8(float (&v)[8], int lane) {
     return x + dpp_f(x, 0xB1);
 }
 
+// Copy a 64-float LDS row into registers: every read is issued, then a
+// scheduling barrier keeps the arithmetic that uses them after the reads.
+__device__ __forceinline__ void lds_row(const float* row, float (&r)[ODE_H]) {
+    const float4* q = reinterpret_cast<const float4*>(row);
+#pragma unroll
+    for (int k = 0; k < ODE_H / 4; ++k) {
+        const float4 v = q[k];
+        r[4 * k] = v.x;
+        r[4 * k + 1] = v.y;
+        r[4 * k + 2] = v.z;
+        r[4 * k + 3] = v.w;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // One MLP evaluation at (y, t); lanes hold hidden unit j = lane.  Returns the
 // 7 outputs (uniform).  If rec != nullptr, stores x, h1, h2 there.
 __device__ __forceinline__ void mlp_eval(const double y[ODE_S], double t, const float w1[8], float b1,
@@ -72,8 +87,12 @@ __device__ __forceinline__ void mlp_eval(const double y[ODE_S], double t, const 
     const float h1 = ode_tanh(a1);
     h1s[j] = h1;
     __syncthreads();
+    // the single wave cannot hide LDS latency behind other waves: all of the
+    // hidden layer's reads are issued before the first product
+    float hv[ODE_H];
+    lds_row(h1s, hv);
     float a2 = b2;
-    for (int k = 0; k < ODE_H; ++k) a2 = __builtin_fmaf(w2[k], h1s[k], a2);
+    for (int k = 0; k < ODE_H; ++k) a2 = __builtin_fmaf(w2[k], hv[k], a2);
     const float h2 = ode_tanh(a2);
     float v[8];
     for (int i = 0; i < ODE_S; ++i) v[i] = w3[i] * h2;
@@ -95,11 +114,11 @@ __device__ __forceinline__ void write_pose(const double z[ODE_S], float* pose) {
     for (int k = 4; k < ODE_S; ++k) pose[k] = static_cast<float>(z[k]);
 }
 
-__global__ __launch_bounds__(64) void k_ode_fwd(const float* __restrict__ theta, const float* __restrict__ z0,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_ode_fwd(const float* __restrict__ theta, const float* __restrict__ z0,
                                                 int frames, int substeps, float* __restrict__ poses,
                                                 float* __restrict__ acts, double* __restrict__ zf) {
     const int j = threadIdx.x;
-    __shared__ float h1s[ODE_H];
+    __shared__ __align__(16) float h1s[ODE_H];
     float w1[8], w2[ODE_H], w3[ODE_S], b3[ODE_S];
     for (int k = 0; k < 8; ++k) w1[k] = theta[OFF_W1 + j * 8 + k];
     const float b1 = theta[OFF_B1 + j];
@@ -193,7 +212,7 @@ __global__ __launch_bounds__(64) void k_ode_bwd(const float* __restrict__ theta,
                                                 const double* __restrict__ zf, float* __restrict__ dtheta,
                                                 float* __restrict__ dz0) {
     const int j = threadIdx.x;
-    __shared__ float h1s[ODE_H];
+    __shared__ __align__(16) float h1s[ODE_H];
     __shared__ float da2s[ODE_H];
     float w1[8], w2c[ODE_H], w3[ODE_S];
     for (int k = 0; k < 8; ++k) w1[k] = theta[OFF_W1 + j * 8 + k];
