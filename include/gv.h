@@ -142,15 +142,17 @@ typedef struct {
  * batch: entries staged in LDS per round of a tile's compositing loop
  * (64, 128 or 256); sort_cap: longest per-tile list sorted in one LDS pass
  * (1024, 2048 or 4096; longer lists are sorted in chunks and merged);
- * compact: compositing kernel choice, 0..7.  The forward by default lets each
- * 16-lane row of a wave walk the entries meeting its 4x4 pixel block; bit 2
- * selects the forward in which the whole wave walks the entries meeting its
- * 8x8 quadrant (the backward always does); bit 0 (forward) / bit 1
- * (backward), which take precedence, select kernels that first build
- * per-pixel entry lists from closed-form coverage masks;
- * bwd_batch: the backward's LDS batch (0 = same as batch).  Images are
- * identical under every setting and gradients equal up to the order of
- * floating-point summation; only the speed differs. */
+ * compact: compositing kernel choice, 0..7.  With bit 2 set the forward lets
+ * each wave walk the entries meeting its 8x8 quadrant (as the backward always
+ * does); with it clear each 16-lane row of a wave walks the entries meeting
+ * its 4x4 pixel block; bit 0 (forward) / bit 1 (backward), which take
+ * precedence, select kernels that first build per-pixel entry lists from
+ * closed-form coverage masks;
+ * bwd_batch: the backward's LDS batch (0 = same as batch).
+ * Defaults: batch 256, sort_cap 1024, compact 4, bwd_batch 128.  Images are
+ * identical under every setting and gradients equal up to floating-point
+ * rounding (order of summation, and the compacted backward's arithmetic);
+ * only the speed differs. */
 typedef struct {
     int32_t batch;
     int32_t sort_cap;

@@ -30,7 +30,7 @@ hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t count, unsi
 
 static thread_local int32_t g_last_hip = 0;
 static std::mutex g_tune_mu;
-static Tuning g_tune = {256, 2048, 128, 0};
+static Tuning g_tune = {256, 1024, 128, 4};  // the autotuner's choice on the 960x540 benchmark clip
 
 Tuning current_tuning() {
     std::lock_guard<std::mutex> lk(g_tune_mu);

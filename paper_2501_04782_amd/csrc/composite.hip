@@ -888,7 +888,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
 }
 
 // ---------------------------------------------------------------------------
-// Sub-block forward (the default forward).  Each 16-lane row of a wave owns a
+// Sub-block forward.  Each 16-lane row of a wave owns a
 // 4x4 block of the wave's quadrant (row r: block (r & 1, r >> 1); lane l of
 // the row: pixel (l & 3, l >> 2) of the block) and walks its own list of the
 // staged entries whose ellipse meets that block.  The rows advance together,
