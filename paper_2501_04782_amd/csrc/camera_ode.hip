@@ -8,7 +8,10 @@
 // is exchanged through LDS (broadcast reads) and the 7 outputs are summed over
 // the lanes by one reduce-scatter.  The state z is carried in FP64, the MLP runs in FP32.
 // The forward pass records every evaluation's input and both hidden
-// activations so that the adjoint needs no recomputation.
+// activations so that the adjoint needs no recomputation; the adjoint's
+// serial chain records each evaluation's cotangents, and the parameter
+// gradient (outer products summed over the evaluations) is formed from those
+// records by parallel kernels afterwards.
 #include "gv_internal.h"
 
 namespace gv {
@@ -19,18 +22,26 @@ constexpr int ODE_REC = 8 + ODE_H + ODE_H;  // x, h1, h2 of one evaluation
 // offsets of the parameter blocks in theta
 constexpr int OFF_W1 = 0, OFF_B1 = 512, OFF_W2 = 576, OFF_B2 = 4672, OFF_W3 = 4736, OFF_B3 = 5184, N_THETA = 5191;
 
+constexpr int ODE_ADJ = ODE_H + ODE_H + 8;  // da1, da2, dy (+ pad) of one evaluation
+constexpr int ODE_CHUNKS = 64;              // partial sums of the parameter gradient
+
 struct OdeLayout {
-    size_t acts, zf, total;
+    size_t evals, chunks, chunk;
+    size_t acts, zf, adj, part, total;
 };
 
 static inline size_t ode_align(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 OdeLayout ode_layout(int frames, int substeps) {
     OdeLayout L;
-    const size_t evals = static_cast<size_t>(frames - 1) * substeps * 4;
+    L.evals = static_cast<size_t>(frames - 1) * substeps * 4;
+    L.chunks = L.evals < ODE_CHUNKS ? (L.evals > 0 ? L.evals : 1) : ODE_CHUNKS;
+    L.chunk = (L.evals + L.chunks - 1) / L.chunks;
     L.acts = 0;
-    L.zf = ode_align(evals * ODE_REC * sizeof(float));
-    L.total = L.zf + ode_align(static_cast<size_t>(frames) * ODE_S * sizeof(double));
+    L.zf = ode_align(L.evals * ODE_REC * sizeof(float));
+    L.adj = L.zf + ode_align(static_cast<size_t>(frames) * ODE_S * sizeof(double));
+    L.part = L.adj + ode_align(L.evals * ODE_ADJ * sizeof(float));
+    L.total = L.part + ode_align(L.chunks * N_THETA * sizeof(float));
     return L;
 }
 
@@ -165,39 +176,30 @@ __device__ __forceinline__ void pose_cotangent(const double* z, const float* dp,
     for (int k = 4; k < ODE_S; ++k) out[k] = dp[k];
 }
 
-struct OdeGrad {
-    float gw1[8], gb1, gw2[ODE_H], gb2, gw3[ODE_S], gb3[ODE_S];
-};
-
-// Vector-Jacobian product of one recorded evaluation with upstream dy;
-// accumulates the parameter gradient and returns dL/dy (state part).
-__device__ __forceinline__ void mlp_vjp(const float* rec, const double dy[ODE_S], const float w1[8],
-                                        const float w2c[ODE_H], const float w3[ODE_S], float* h1s, float* da2s,
-                                        OdeGrad& G, double gx[ODE_S]) {
+// Vector-Jacobian product of one recorded evaluation with upstream dy: returns
+// dL/dy (state part) and records the evaluation's cotangents (da1, da2 of the
+// hidden pre-activations, dy) in adj; the parameter gradient is summed from
+// these records afterwards, off the serial chain.
+__device__ __forceinline__ void mlp_vjp(float h1, float h2, const double dy[ODE_S], const float w1[8],
+                                        const float w2c[ODE_H], const float w3[ODE_S], float* da2s, float* adj,
+                                        double gx[ODE_S]) {
     const int j = threadIdx.x;
-    float x[8];
-    for (int k = 0; k < 8; ++k) x[k] = rec[k];
-    const float h1 = rec[8 + j];
-    const float h2 = rec[8 + ODE_H + j];
     float dyf[ODE_S];
     for (int i = 0; i < ODE_S; ++i) dyf[i] = static_cast<float>(dy[i]);
     float dh2 = 0.0f;
-    for (int i = 0; i < ODE_S; ++i) {
-        G.gw3[i] = __builtin_fmaf(dyf[i], h2, G.gw3[i]);
-        G.gb3[i] += dyf[i];
-        dh2 = __builtin_fmaf(w3[i], dyf[i], dh2);
-    }
+    for (int i = 0; i < ODE_S; ++i) dh2 = __builtin_fmaf(w3[i], dyf[i], dh2);
     const float da2 = dh2 * (1.0f - h2 * h2);
-    h1s[j] = h1;
     da2s[j] = da2;
     __syncthreads();
-    for (int k = 0; k < ODE_H; ++k) G.gw2[k] = __builtin_fmaf(da2, h1s[k], G.gw2[k]);
-    G.gb2 += da2;
+    float dv[ODE_H];
+    lds_row(da2s, dv);
     float dh1 = 0.0f;
-    for (int k = 0; k < ODE_H; ++k) dh1 = __builtin_fmaf(w2c[k], da2s[k], dh1);
+    for (int k = 0; k < ODE_H; ++k) dh1 = __builtin_fmaf(w2c[k], dv[k], dh1);
     const float da1 = dh1 * (1.0f - h1 * h1);
-    for (int m = 0; m < 8; ++m) G.gw1[m] = __builtin_fmaf(da1, x[m], G.gw1[m]);
-    G.gb1 += da1;
+    adj[j] = da1;
+    adj[ODE_H + j] = da2;
+    if (j == 0)
+        for (int i = 0; i < ODE_S; ++i) adj[2 * ODE_H + i] = dyf[i];
     float v[8];
     for (int m = 0; m < ODE_S; ++m) v[m] = w1[m] * da1;
     v[7] = 0.0f;
@@ -209,25 +211,24 @@ __device__ __forceinline__ void mlp_vjp(const float* rec, const double dy[ODE_S]
 
 __global__ __launch_bounds__(64) void k_ode_bwd(const float* __restrict__ theta, int frames, int substeps,
                                                 const float* __restrict__ dposes, const float* __restrict__ acts,
-                                                const double* __restrict__ zf, float* __restrict__ dtheta,
+                                                const double* __restrict__ zf, float* __restrict__ adj,
                                                 float* __restrict__ dz0) {
     const int j = threadIdx.x;
-    __shared__ __align__(16) float h1s[ODE_H];
-    __shared__ float da2s[ODE_H];
+    __shared__ __align__(16) float da2s[ODE_H];
     float w1[8], w2c[ODE_H], w3[ODE_S];
     for (int k = 0; k < 8; ++k) w1[k] = theta[OFF_W1 + j * 8 + k];
     for (int k = 0; k < ODE_H; ++k) w2c[k] = theta[OFF_W2 + k * ODE_H + j];
     for (int i = 0; i < ODE_S; ++i) w3[i] = theta[OFF_W3 + i * ODE_H + j];
-    OdeGrad G;
-    for (int k = 0; k < 8; ++k) G.gw1[k] = 0.0f;
-    for (int k = 0; k < ODE_H; ++k) G.gw2[k] = 0.0f;
-    for (int i = 0; i < ODE_S; ++i) G.gw3[i] = G.gb3[i] = 0.0f;
-    G.gb1 = G.gb2 = 0.0f;
 
     double lam[ODE_S];
     pose_cotangent(zf + ODE_S * (frames - 1), dposes + ODE_S * (frames - 1), lam);
     if (frames > 1) {
         const double h = 1.0 / (static_cast<double>(substeps) * (frames - 1));
+        // The evaluations are taken in descending order; this lane's hidden
+        // activations of the next one are requested while the current one is
+        // differentiated (one wave: nothing else hides their latency).
+        const size_t elast = static_cast<size_t>(frames - 1) * substeps * 4 - 1;
+        float nh1 = acts[elast * ODE_REC + 8 + j], nh2 = acts[elast * ODE_REC + 8 + ODE_H + j];
         for (int f = frames - 1; f >= 1; --f) {
             for (int s = substeps - 1; s >= 0; --s) {
                 const size_t e0 = (static_cast<size_t>(f - 1) * substeps + s) * 4;
@@ -239,13 +240,21 @@ __global__ __launch_bounds__(64) void k_ode_bwd(const float* __restrict__ theta,
                     dk[2][k] = (h / 3.0) * lam[k];
                     dk[3][k] = (h / 6.0) * lam[k];
                 }
-                mlp_vjp(acts + (e0 + 3) * ODE_REC, dk[3], w1, w2c, w3, h1s, da2s, G, gx);
+                auto vjp = [&](size_t e, const double dy[ODE_S]) {
+                    const float h1 = nh1, h2 = nh2;
+                    if (e > 0) {
+                        nh1 = acts[(e - 1) * ODE_REC + 8 + j];
+                        nh2 = acts[(e - 1) * ODE_REC + 8 + ODE_H + j];
+                    }
+                    mlp_vjp(h1, h2, dy, w1, w2c, w3, da2s, adj + e * ODE_ADJ, gx);
+                };
+                vjp(e0 + 3, dk[3]);
                 for (int k = 0; k < ODE_S; ++k) { dz[k] += gx[k]; dk[2][k] += h * gx[k]; }
-                mlp_vjp(acts + (e0 + 2) * ODE_REC, dk[2], w1, w2c, w3, h1s, da2s, G, gx);
+                vjp(e0 + 2, dk[2]);
                 for (int k = 0; k < ODE_S; ++k) { dz[k] += gx[k]; dk[1][k] += 0.5 * h * gx[k]; }
-                mlp_vjp(acts + (e0 + 1) * ODE_REC, dk[1], w1, w2c, w3, h1s, da2s, G, gx);
+                vjp(e0 + 1, dk[1]);
                 for (int k = 0; k < ODE_S; ++k) { dz[k] += gx[k]; dk[0][k] += 0.5 * h * gx[k]; }
-                mlp_vjp(acts + (e0 + 0) * ODE_REC, dk[0], w1, w2c, w3, h1s, da2s, G, gx);
+                vjp(e0, dk[0]);
                 for (int k = 0; k < ODE_S; ++k) lam[k] = dz[k] + gx[k];
             }
             double c[ODE_S];
@@ -253,15 +262,44 @@ __global__ __launch_bounds__(64) void k_ode_bwd(const float* __restrict__ theta,
             for (int k = 0; k < ODE_S; ++k) lam[k] += c[k];
         }
     }
-    for (int k = 0; k < 8; ++k) dtheta[OFF_W1 + j * 8 + k] = G.gw1[k];
-    dtheta[OFF_B1 + j] = G.gb1;
-    for (int k = 0; k < ODE_H; ++k) dtheta[OFF_W2 + j * ODE_H + k] = G.gw2[k];
-    dtheta[OFF_B2 + j] = G.gb2;
-    for (int i = 0; i < ODE_S; ++i) dtheta[OFF_W3 + i * ODE_H + j] = G.gw3[i];
-    if (j == 0) {
-        for (int i = 0; i < ODE_S; ++i) dtheta[OFF_B3 + i] = G.gb3[i];
+    if (j == 0)
         for (int k = 0; k < ODE_S; ++k) dz0[k] = static_cast<float>(lam[k]);
+}
+
+// Parameter gradient from the recorded evaluations (x, h1, h2 in acts; da1,
+// da2, dy in adj): dW1 = sum da1 x^T, db1 = sum da1, dW2 = sum da2 h1^T,
+// db2 = sum da2, dW3 = sum dy h2^T, db3 = sum dy.  Thread p of chunk c sums
+// parameter p over the evaluations [c chunk, (c + 1) chunk) in order; the
+// chunks are then added in order, so the result is reproducible.
+__global__ __launch_bounds__(256) void k_ode_grad_part(const float* __restrict__ acts, const float* __restrict__ adj,
+                                                       int64_t evals, int64_t chunk, float* __restrict__ part) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= N_THETA) return;
+    const int64_t e0 = blockIdx.y * chunk;
+    const int64_t e1 = e0 + chunk < evals ? e0 + chunk : evals;
+    // parameter p as (cotangent index in adj, activation index in acts or -1)
+    int ia, ix;
+    if (p < OFF_B1) ia = p / 8, ix = p % 8;                                          // W1[j][k]
+    else if (p < OFF_W2) ia = p - OFF_B1, ix = -1;                                   // b1[j]
+    else if (p < OFF_B2) ia = ODE_H + (p - OFF_W2) / ODE_H, ix = 8 + (p - OFF_W2) % ODE_H;  // W2[j][k]
+    else if (p < OFF_W3) ia = ODE_H + (p - OFF_B2), ix = -1;                         // b2[j]
+    else if (p < OFF_B3) ia = 2 * ODE_H + (p - OFF_W3) / ODE_H, ix = 8 + ODE_H + (p - OFF_W3) % ODE_H;  // W3[i][j]
+    else ia = 2 * ODE_H + (p - OFF_B3), ix = -1;                                     // b3[i]
+    float acc = 0.0f;
+    for (int64_t e = e0; e < e1; ++e) {
+        const float g = adj[e * ODE_ADJ + ia];
+        acc = ix >= 0 ? __builtin_fmaf(g, acts[e * ODE_REC + ix], acc) : acc + g;
     }
+    part[blockIdx.y * static_cast<int64_t>(N_THETA) + p] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_ode_grad_final(const float* __restrict__ part, int64_t chunks,
+                                                        float* __restrict__ dtheta) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= N_THETA) return;
+    float acc = 0.0f;
+    for (int64_t c = 0; c < chunks; ++c) acc += part[c * N_THETA + p];
+    dtheta[p] = acc;
 }
 
 }  // namespace gv
@@ -298,9 +336,17 @@ gv_status gv_camera_ode_bwd(const float* theta, const float* z0, int32_t frames,
     const OdeLayout L = ode_layout(frames, substeps);
     if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255u)) return GV_ERR_WORKSPACE;
     char* b = static_cast<char*>(ws);
-    hipLaunchKernelGGL(k_ode_bwd, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), theta, frames, substeps,
-                       dL_dposes, reinterpret_cast<const float*>(b + L.acts), reinterpret_cast<const double*>(b + L.zf),
-                       dtheta, dz0);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const float* acts = reinterpret_cast<const float*>(b + L.acts);
+    float* adj = reinterpret_cast<float*>(b + L.adj);
+    float* part = reinterpret_cast<float*>(b + L.part);
+    hipLaunchKernelGGL(k_ode_bwd, dim3(1), dim3(64), 0, st, theta, frames, substeps, dL_dposes, acts,
+                       reinterpret_cast<const double*>(b + L.zf), adj, dz0);
+    const dim3 pg((N_THETA + 255) / 256, static_cast<uint32_t>(L.chunks));
+    hipLaunchKernelGGL(k_ode_grad_part, pg, dim3(256), 0, st, acts, adj, static_cast<int64_t>(L.evals),
+                       static_cast<int64_t>(L.chunk), part);
+    hipLaunchKernelGGL(k_ode_grad_final, dim3((N_THETA + 255) / 256), dim3(256), 0, st, part,
+                       static_cast<int64_t>(L.chunks), dtheta);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? GV_OK : GV_ERR_HIP;
 }
