@@ -314,11 +314,35 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t* bh = a.bhist + (static_cast<int64_t>(f) * a.bin_blocks + blockIdx.x) * a.tiles;
     const int64_t tile0 = static_cast<int64_t>(f) * a.tiles;
-    for (int t = threadIdx.x; t < a.tiles; t += 256) {
-        const uint32_t v = bh[t];
-        const uint32_t b = v ? a.toff[tile0 + t] + atomicAdd(&a.tcur[tile0 + t], v) : 0u;
-        base[t] = b;
-        lim[t] = v ? min(b + v, a.toff[tile0 + t + 1]) : 0u;
+    // eight tiles per thread at a time: all counts are requested, then all
+    // reservations, so each batch costs two memory round trips, not sixteen
+    constexpr int RT = 8;
+    for (int t0 = 0; t0 < a.tiles; t0 += 256 * RT) {
+        uint32_t v[RT], o[RT], lo[RT], hi[RT];
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            const int t = t0 + k * 256 + threadIdx.x;
+            v[k] = t < a.tiles ? bh[t] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            const int t = t0 + k * 256 + threadIdx.x;
+            o[k] = lo[k] = hi[k] = 0u;
+            if (v[k]) {
+                o[k] = atomicAdd(&a.tcur[tile0 + t], v[k]);
+                lo[k] = a.toff[tile0 + t];
+                hi[k] = a.toff[tile0 + t + 1];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            const int t = t0 + k * 256 + threadIdx.x;
+            if (t < a.tiles) {
+                const uint32_t b = v[k] ? lo[k] + o[k] : 0u;
+                base[t] = b;
+                lim[t] = v[k] ? min(b + v[k], hi[k]) : 0u;
+            }
+        }
     }
     __syncthreads();
     auto next = [&](int tl) { return atomicAdd(&base[tl], 1u); };
