@@ -185,17 +185,20 @@ __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
     bool done = !inside;
     const float fx = static_cast<float>(lx), fy = static_cast<float>(ly);
 
+    // each batch's entry ids are requested during the previous batch's loop
+    uint32_t gnext = tid < static_cast<int>(min(static_cast<uint32_t>(B), e - s)) ? a.sgid[s + tid] : 0u;
     for (uint32_t b0 = s; b0 < e; b0 += B) {
         if (__syncthreads_count(!done) == 0) break;
         const uint32_t nb = min(static_cast<uint32_t>(B), e - b0);
         if (tid < static_cast<int>(nb)) {
             Staged st;
             float3 conic;
-            stage_entry(a, f, a.sgid[b0 + tid], ox, oy, st, conic);
+            stage_entry(a, f, gnext, ox, oy, st, conic);
             sh[tid] = st;
             shm[tid] = quadrant_mask(st, conic, xlim, ylim);
         }
         __syncthreads();
+        if (e - b0 > B && tid < static_cast<int>(min(static_cast<uint32_t>(B), e - b0 - B))) gnext = a.sgid[b0 + B + tid];
         if (__ballot(!done) == 0) continue;  // wave-uniform; the barriers are outside
         // this wave's entries, front to back (ballot compaction)
         int cnt = 0;
@@ -425,6 +428,13 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
     if (last) atomicMax(&smax, last);
     __syncthreads();
     const uint32_t used = smax;
+    // each batch's entry ids are requested during the previous batch's loop
+    // (the first batch's before the zero partials)
+    uint32_t gnext = 0;
+    {
+        const uint32_t b0f = used > B ? s + used - B : s;
+        if (tid < static_cast<int>(s + used - b0f)) gnext = a.sgid[b0f + tid];
+    }
     // entries no pixel reached get zero partials
     for (uint32_t i = s + used + tid; i < e; i += WG) {
         const uint32_t slot = a.sslot[i];
@@ -440,11 +450,18 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
         if (tid < static_cast<int>(nb)) {
             Staged st;
             float3 conic;
-            stage_entry(a, f, a.sgid[b0 + tid], ox, oy, st, conic);
+            stage_entry(a, f, gnext, ox, oy, st, conic);
             sh[tid] = st;
             shm[tid] = quadrant_mask(st, conic, xlim, ylim);
         }
         __syncthreads();
+        // this batch's slots (for the flush) and the next batch's ids, in
+        // flight during the loop
+        const uint32_t slot = tid < static_cast<int>(nb) ? a.sslot[b0 + tid] : 0u;
+        if (b0 > s) {
+            const uint32_t b0n = b0 - s > B ? b0 - B : s;
+            if (tid < static_cast<int>(b0 - b0n)) gnext = a.sgid[b0n + tid];
+        }
         // this wave's entries, back to front (ballot compaction; the list is
         // written and read by this wave only)
         int cnt = 0;
@@ -546,7 +563,6 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
             }
             const Staged st = sh[tid];
             finish_partials(v, st.p0.z * INV_K_EXP, 0.5f * st.p0.w * INV_K_EXP, st.p1.x * INV_K_EXP, st.p1.y);
-            const uint32_t slot = a.sslot[b0 + tid];
             if (slot < a.k_cap) {
                 store_partials(a.part, slot, v);
             }
@@ -955,17 +971,20 @@ __global__ __launch_bounds__(WG) void k_composite_fwd_sb(Args a) {
     const float fx = static_cast<float>(lx), fy = static_cast<float>(ly);
     const uint32_t* my = wl[w][row];
 
+    // each batch's entry ids are requested during the previous batch's loop
+    uint32_t gnext = tid < static_cast<int>(min(static_cast<uint32_t>(B), e - s)) ? a.sgid[s + tid] : 0u;
     for (uint32_t b0 = s; b0 < e; b0 += B) {
         if (__syncthreads_count(!done) == 0) break;
         const uint32_t nb = min(static_cast<uint32_t>(B), e - b0);
         if (tid < static_cast<int>(nb)) {
             Staged st;
             float3 conic;
-            stage_entry(a, f, a.sgid[b0 + tid], ox, oy, st, conic);
+            stage_entry(a, f, gnext, ox, oy, st, conic);
             sh[tid] = st;
             shm[tid] = block_mask(st, conic, xlim, ylim);
         }
         __syncthreads();
+        if (e - b0 > B && tid < static_cast<int>(min(static_cast<uint32_t>(B), e - b0 - B))) gnext = a.sgid[b0 + B + tid];
         if (__ballot(!done) == 0) continue;  // wave-uniform; the barriers are outside
         const int steps = build_block_lists<B, FWD_GROUP>(wl[w], shm, w, lane, nb);
         __builtin_amdgcn_wave_barrier();
