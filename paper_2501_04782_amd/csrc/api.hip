@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <new>
 
 #include "gv_internal.h"
 
@@ -454,6 +455,32 @@ gv_status gv_render_batch_timed(const gv_scene* scene, const gv_camera* cam, con
     return s;
 }
 
+// Instantiate a captured graph and hand it out; every failure path releases
+// what was made (no exception crosses the C ABI).
+static gv_status finish_graph(gv_status s, hipError_t capture_err, hipGraph_t graph, gv_graph** out) {
+    if (s == GV_OK && capture_err != hipSuccess) s = hip_status(capture_err);
+    if (s != GV_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return s;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return hip_status(e);
+    }
+    gv_graph* g = new (std::nothrow) gv_graph;
+    if (!g) {
+        hipGraphExecDestroy(exec);
+        hipGraphDestroy(graph);
+        return GV_ERR_HIP;
+    }
+    g->graph = graph;
+    g->exec = exec;
+    *out = g;
+    return GV_OK;
+}
+
 gv_status gv_batch_graph_create(const gv_scene* scene, const gv_camera* cam, const float* poses, const float* times,
                                 int32_t frames, const float* targets, const float* dL_dimages, uint32_t flags,
                                 float* images, float* loss, gv_grads* grads, float* dL_dposes, void* ws,
@@ -472,22 +499,7 @@ gv_status gv_batch_graph_create(const gv_scene* scene, const gv_camera* cam, con
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
     hipStreamDestroy(cs);
-    if (s != GV_OK) {
-        if (graph) hipGraphDestroy(graph);
-        return s;
-    }
-    if (e != hipSuccess) return hip_status(e);
-    hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        hipGraphDestroy(graph);
-        return hip_status(e);
-    }
-    gv_graph* g = new gv_graph;
-    g->graph = graph;
-    g->exec = exec;
-    *out = g;
-    return GV_OK;
+    return finish_graph(s, e, graph, out);
 }
 
 gv_status gv_fit_graph_create(const gv_scene* scene, const gv_camera* cam, const float* theta, const float* z0,
@@ -515,22 +527,7 @@ gv_status gv_fit_graph_create(const gv_scene* scene, const gv_camera* cam, const
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
     hipStreamDestroy(cs);
-    if (s != GV_OK) {
-        if (graph) hipGraphDestroy(graph);
-        return s;
-    }
-    if (e != hipSuccess) return hip_status(e);
-    hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        hipGraphDestroy(graph);
-        return hip_status(e);
-    }
-    gv_graph* g = new gv_graph;
-    g->graph = graph;
-    g->exec = exec;
-    *out = g;
-    return GV_OK;
+    return finish_graph(s, e, graph, out);
 }
 
 gv_status gv_batch_graph_launch(gv_graph* graph, void* stream) {
