@@ -19,6 +19,7 @@ namespace gv {
 constexpr int ODE_H = 64;
 constexpr int ODE_S = 7;
 constexpr int ODE_REC = 8 + ODE_H + ODE_H;  // x, h1, h2 of one evaluation
+static_assert(ODE_REC % 4 == 0, "records start on 16-byte boundaries");
 // offsets of the parameter blocks in theta
 constexpr int OFF_W1 = 0, OFF_B1 = 512, OFF_W2 = 576, OFF_B2 = 4672, OFF_W3 = 4736, OFF_B3 = 5184, N_THETA = 5191;
 
@@ -111,7 +112,10 @@ __device__ __forceinline__ void mlp_eval(const double y[ODE_S], double t, const 
     const float sum = reduce_scatter8(v, j);
     for (int i = 0; i < ODE_S; ++i) out[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sum), 8 * i)) + b3[i];
     if (rec) {
-        if (j < 8) rec[j] = x[j];
+        if (j == 0) {  // x is uniform: one lane writes it (records are 16-byte aligned)
+            reinterpret_cast<float4*>(rec)[0] = make_float4(x[0], x[1], x[2], x[3]);
+            reinterpret_cast<float4*>(rec)[1] = make_float4(x[4], x[5], x[6], x[7]);
+        }
         rec[8 + j] = h1;
         rec[8 + ODE_H + j] = h2;
     }
