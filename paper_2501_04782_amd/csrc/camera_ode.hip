@@ -169,6 +169,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 }
 
 // Cotangent of the state from the cotangent of the pose (q/|q|, t).
+// The value lane k holds (wave-uniform result).
+__device__ __forceinline__ double lane_value(double v, int k) {
+    const uint64_t b = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(b), k);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(b >> 32), k);
+    return __longlong_as_double((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 __device__ __forceinline__ void pose_cotangent(const double* z, const float* dp, double out[ODE_S]) {
     const double n = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3]);
     double qh[4], dot = 0.0;
@@ -234,6 +242,11 @@ __global__ __launch_bounds__(64) void k_ode_bwd(const float* __restrict__ theta,
         const size_t elast = static_cast<size_t>(frames - 1) * substeps * 4 - 1;
         float nh1 = acts[elast * ODE_REC + 8 + j], nh2 = acts[elast * ODE_REC + 8 + ODE_H + j];
         for (int f = frames - 1; f >= 1; --f) {
+            // frame f - 1's state and pose cotangent, needed after this
+            // frame's substeps: requested now, one component per lane (vector
+            // loads, which the LDS waits of the substeps do not wait for)
+            const double zl = j < ODE_S ? zf[ODE_S * (f - 1) + j] : 0.0;
+            const float dl = j < ODE_S ? dposes[ODE_S * (f - 1) + j] : 0.0f;
             for (int s = substeps - 1; s >= 0; --s) {
                 const size_t e0 = (static_cast<size_t>(f - 1) * substeps + s) * 4;
                 double dz[ODE_S], dk[4][ODE_S], gx[ODE_S];
@@ -261,8 +274,13 @@ __global__ __launch_bounds__(64) void k_ode_bwd(const float* __restrict__ theta,
                 vjp(e0, dk[0]);
                 for (int k = 0; k < ODE_S; ++k) lam[k] = dz[k] + gx[k];
             }
-            double c[ODE_S];
-            pose_cotangent(zf + ODE_S * (f - 1), dposes + ODE_S * (f - 1), c);
+            double zk[ODE_S], c[ODE_S];
+            float dp[ODE_S];
+            for (int k = 0; k < ODE_S; ++k) {
+                zk[k] = lane_value(zl, k);
+                dp[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dl), k));
+            }
+            pose_cotangent(zk, dp, c);
             for (int k = 0; k < ODE_S; ++k) lam[k] += c[k];
         }
     }
