@@ -12,7 +12,7 @@ import oracle
 from oracle import camera_ode as ode_ref
 from parity_util import GRAD_TOL, PIXEL_TOL, compare_grads, device_inputs, knife_edge, oracle_frame, \
     planar_to_pixels, rel_err, workspace_for
-from test_gpu_parity import run_clip, say
+from test_gpu_parity import run_clip, say, small_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -99,3 +99,26 @@ def test_camera_ode_fitting_step_full_size_sampled():
     assert e1 <= GRAD_TOL and e2 <= GRAD_TOL, (e1, e2)
     fit.close()
     say(f"[fit step] poses err {ep:.2e} dtheta err {e1:.2e} dz0 err {e2:.2e}")
+
+
+def test_tile_grid_beyond_lds_histogram_sampled():
+    """A 4128x1056 frame has 258 x 66 = 17,028 tiles, more than the 16,384 an
+    LDS tile histogram holds, so binning takes the count and scatter kernels
+    with one global atomic per intersection.  Images and gradients on sampled
+    pixels against the oracle."""
+    W, H = 4128, 1056
+    assert ((W + 15) // 16) * ((H + 15) // 16) > 16384
+    w = small_workload(43, W, H, 4000, 2, trajectory=True, ls=(-4.5, 0.5))
+    w["name"] = "large grid"
+    frames = [0, 1]
+    pix, refs, dls, dl = sampled_upstream(w, frames, 1024, 44)
+    say("[large grid] gpu batch")
+    out, ws, _ = run_clip(w, dl=dl)
+    check_pixels(out["images"].cpu().numpy(), frames, pix, refs, "large grid")
+    say("[large grid] oracle backward")
+    g_ref, dposes_ref, _ = oracle.render_clip_grads(w["scene"], w["camera"], w["poses"].astype(np.float64),
+                                                    w["times"], frames, pix, dls)
+    ge = compare_grads(out["grads"], g_ref, "large grid")
+    pe = rel_err(out["dL_dposes"].cpu().numpy()[frames], dposes_ref[frames])
+    assert pe <= GRAD_TOL, pe
+    say(f"[large grid] grads={ge} pose={pe:.2e} intersections={ws.status()['intersections']}")
