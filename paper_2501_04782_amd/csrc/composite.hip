@@ -393,7 +393,6 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
     __shared__ float acc[WG / 64][9][B];
     __shared__ uint32_t wl[WG / 64][B + RS_GROUP];
     if (tid == 0) stage_inert(sh[B]);
-    __shared__ uint32_t smax;
     __shared__ uint32_t wlast[WG / 64];
 
     // per-pixel state: T after the current entry and GS = sum_c g_c S_c, the
@@ -418,16 +417,16 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
         }
         GS = T * (g0 * a.bg[0] + g1 * a.bg[1] + g2 * a.bg[2]);
     }
-    if (tid == 0) smax = 0;
-    // entries at or past a wave's last contributor need no work in that wave
+    // entries at or past a wave's last contributor need no work in that wave,
+    // and entries past the tile's last contributor none at all
     uint32_t wmax = last;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) wmax = max(wmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(wmax), d)));
     if (lane == 0) wlast[w] = wmax;
     __syncthreads();
-    if (last) atomicMax(&smax, last);
-    __syncthreads();
-    const uint32_t used = smax;
+    uint32_t used = 0;
+#pragma unroll
+    for (int ww = 0; ww < WG / 64; ++ww) used = max(used, wlast[ww]);
     // each batch's entry ids are requested during the previous batch's loop
     // (the first batch's before the zero partials)
     uint32_t gnext = 0;
