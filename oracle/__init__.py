@@ -62,7 +62,7 @@ def _load():
         lib.gvo_project.argtypes = [ctypes.POINTER(_Frame), _dp]
         lib.gvo_project.restype = ctypes.c_int
         lib.gvo_render.argtypes = [ctypes.POINTER(_Frame), ctypes.c_int64, _i64p, _dp, _dp, _i64p, _dp,
-                                   _dp, ctypes.POINTER(_Grads), ctypes.c_int]
+                                   _dp, ctypes.POINTER(_Grads), ctypes.c_int, _dp, _dp]
         lib.gvo_render.restype = ctypes.c_int
         lib.gvo_bspline_basis.argtypes = [ctypes.c_int32, ctypes.c_double, _dp]
         lib.gvo_bspline_basis.restype = ctypes.c_int
@@ -71,7 +71,7 @@ def _load():
         lib.gvo_abi_version.restype = ctypes.c_int
         lib.gvo_contributors.argtypes = [ctypes.POINTER(_Frame), ctypes.POINTER(ctypes.c_uint8), ctypes.c_int]
         lib.gvo_contributors.restype = ctypes.c_int
-        if lib.gvo_abi_version() != 5:
+        if lib.gvo_abi_version() != 6:
             raise RuntimeError("liboracle.so is stale: rebuild it (python -m oracle.build)")
         _lib = lib
     return _lib
@@ -174,12 +174,17 @@ def zero_grads(scene) -> dict:
 
 def render_frame(scene, cam, pose7, t: float = 0.0, pixels: Optional[np.ndarray] = None,
                  dL_dC: Optional[np.ndarray] = None, grads: Optional[dict] = None,
-                 threads: int = 0) -> dict:
+                 threads: int = 0, stake_tol: Optional[Sequence[float]] = None) -> dict:
     """Render one frame at the listed pixels (linear y*W+x; None = all).
 
     Returns color [P][3], T_final [P], n_contrib [P], margins [P][4] and, when
     dL_dC [P][3] is given, the gradient dict (accumulated into ``grads`` if
-    passed) of sum_p dL_dC[p] . C[p].
+    passed) of sum_p dL_dC[p] . C[p].  With ``stake_tol`` (relative margins
+    of the 3-sigma cut, the 1/255 cut and the stop) it also returns
+    ``stake`` [P]: the blending weight that decisions within those margins
+    control (an entry's alpha*T for a cut, the remaining transmittance for
+    the stop), so that a pixel taken the other way at such a decision can
+    differ by at most stake times the colour range.
     """
     s = scene_f64(scene)
     fr = _frame(s, cam, pose7, t)
@@ -205,12 +210,18 @@ def render_frame(scene, cam, pose7, t: float = 0.0, pixels: Optional[np.ndarray]
                          _ptr(grads["opacity_logits"]), _ptr(grads["colors"]), _ptr(grads.get("mean_coeffs")),
                          _ptr(grads["pose"]), _ptr(grads.get("ctrl")), _ptr(grads.get("scale_coeffs")),
                          _ptr(grads.get("quat_coeffs")), _ptr(grads.get("sh")), _ptr(grads.get("intrinsics")))
+    tol = stake = None
+    if stake_tol is not None:
+        tol = np.ascontiguousarray(np.asarray(stake_tol, dtype=np.float64).reshape(3))
+        stake = np.zeros(npx)
     rc = _load().gvo_render(ctypes.byref(fr), npx, pix_p, _ptr(color), _ptr(T), nc.ctypes.data_as(_i64p),
                             _ptr(mg), _ptr(dl), ctypes.byref(gstruct) if gstruct is not None else None,
-                            int(threads))
+                            int(threads), _ptr(tol), _ptr(stake))
     if rc != 0:
         raise RuntimeError(f"gvo_render failed with code {rc}")
     out = dict(color=color, T_final=T, n_contrib=nc, margins=mg)
+    if stake is not None:
+        out["stake"] = stake
     if dl is not None:
         out["grads"] = grads
     return out
@@ -243,13 +254,60 @@ def render_image(scene, cam, pose7, t: float = 0.0, threads: int = 0) -> dict:
                 n_contrib=r["n_contrib"].reshape(H, W), margins=r["margins"].reshape(H, W, 4))
 
 
-def l2_loss_and_grad(images: np.ndarray, targets: np.ndarray):
-    """Standard L2 reconstruction loss (Sec. 4.1), read as the mean over all
-    frames, channels and pixels, and its gradient w.r.t. the images."""
+def l2_loss_and_grad(images: np.ndarray, targets: np.ndarray, per_frame: bool = False):
+    """The L2 reconstruction loss of Sec. 4.1, read as the mean over all
+    frames, channels and pixels of the squared difference, and its gradient
+    with respect to the images (same shape).  With per_frame=True the loss is
+    returned as each frame's share (leading axis = frames), which sums to the
+    mean: share_f = sum over frame f of (image - target)^2 / (number of
+    values in all frames)."""
     images = np.asarray(images, np.float64)
     targets = np.asarray(targets, np.float64)
+    if images.shape != targets.shape:
+        raise ValueError(f"images {images.shape} and targets {targets.shape} differ in shape")
     diff = images - targets
-    return float(np.mean(diff * diff)), 2.0 * diff / diff.size
+    sq = diff * diff
+    grad = 2.0 * diff / diff.size
+    if per_frame:
+        return sq.reshape(sq.shape[0], -1).sum(axis=1) / diff.size, grad
+    return float(np.mean(sq)), grad
+
+
+def _rotation(q) -> np.ndarray:
+    """Rotation matrix of the quaternion q (w, x, y, z) after normalisation."""
+    q = np.asarray(q, np.float64)
+    w, x, y, z = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def trajectory_error(poses, ref_poses) -> dict:
+    """Error of a camera trajectory against a reference pose table (the
+    learned camera of Sec. 3.4 judged by per-frame poses).  Poses are
+    world-to-camera 7-vectors (q_w, q_x, q_y, q_z, t_x, t_y, t_z), q not
+    necessarily unit.  Per frame: the camera centre c = -R^T t and the
+    rotation R; the translation error is |c - c_ref|, the rotation error the
+    geodesic angle of R R_ref^T, atan2(sin, cos) with sin the norm of the
+    matrix's skew part and cos = (trace - 1) / 2.  Returns the root mean square
+    translation error, the mean angle (radians) and the per-frame values."""
+    poses = np.asarray(poses, np.float64).reshape(-1, 7)
+    ref = np.asarray(ref_poses, np.float64).reshape(-1, 7)
+    if poses.shape != ref.shape:
+        raise ValueError("pose tables differ in length")
+    terr = np.zeros(len(poses))
+    ang = np.zeros(len(poses))
+    for f in range(len(poses)):
+        R, Rr = _rotation(poses[f, :4]), _rotation(ref[f, :4])
+        c = -R.T @ poses[f, 4:]
+        cr = -Rr.T @ ref[f, 4:]
+        terr[f] = np.linalg.norm(c - cr)
+        D = R @ Rr.T
+        s = 0.5 * np.linalg.norm([D[2, 1] - D[1, 2], D[0, 2] - D[2, 0], D[1, 0] - D[0, 1]])
+        ang[f] = np.arctan2(s, 0.5 * (np.trace(D) - 1.0))
+    n = max(len(poses), 1)
+    return dict(translation_rmse=float(np.sqrt(np.sum(terr ** 2) / n)), mean_angle=float(np.sum(ang) / n),
+                translation=terr, angle=ang)
 
 
 def render_clip_grads(scene, cam, poses: np.ndarray, times: Sequence[float], frames: Sequence[int],

@@ -454,13 +454,27 @@ static int clist_push(clist_t *L, contrib_t c)
 static void upd(double *m, double v) { if (v < *m) *m = v; }
 
 /* Step 6 at one pixel centre.  margins: [0] |q-9|/9 where the cut-off decides,
- * [1] |255 alpha - 1|, [2] |T(1-alpha) - 1e-4|/1e-4, [3] |o G - 0.99|/0.99. */
+ * [1] |255 alpha - 1|, [2] |T(1-alpha) - 1e-4|/1e-4, [3] |o G - 0.99|/0.99.
+ *
+ * Optional stake (when stake_tol != NULL): an upper bound on the blending
+ * weight that the pixel's set-aside decisions control, i.e. how much of the
+ * composite could change if an implementation with slightly different
+ * rounding took one of them the other way.  An entry whose 3-sigma or
+ * 1/255 decision lies within stake_tol[0] / stake_tol[1] of its threshold
+ * puts its weight alpha T at stake (included or not, it moves the colour by
+ * at most alpha T times the colour range).  Those entries also scale the
+ * transmittance of every later entry by up to a factor 1 - alpha, so a stop
+ * decision within stake_tol[2] plus that accumulated factor puts the whole
+ * remaining transmittance T at stake (everything from that entry on is
+ * bounded by it), and nothing after it is added. */
 static int composite_pixel(const gvo_frame *fr, const proj_t *P, const int64_t *order, int64_t nv,
                            double px, double py, double C[3], double *Tout, int64_t *ncontrib,
-                           double margins[4], clist_t *L)
+                           double margins[4], clist_t *L, const double *stake_tol, double *stake)
 {
     double T = 1.0;
     int64_t nc = 0;
+    double st = 0.0, slack = 0.0;
+    int tail_at_stake = 0;
     C[0] = C[1] = C[2] = 0.0;
     for (int k = 0; k < 4; ++k) margins[k] = INFINITY;
     const double alpha_at_cut_factor = exp(-0.5 * Q_MAX);
@@ -469,15 +483,33 @@ static int composite_pixel(const gvo_frame *fr, const proj_t *P, const int64_t *
         const proj_t *p = &P[g];
         double dx = px - p->u, dy = py - p->v;
         double q = p->A[0][0] * dx * dx + (p->A[0][1] + p->A[1][0]) * dx * dy + p->A[1][1] * dy * dy;
-        if (p->o * alpha_at_cut_factor >= ALPHA_MIN) upd(&margins[0], fabs(q - Q_MAX) / Q_MAX);
+        const double mq = fabs(q - Q_MAX) / Q_MAX;
+        if (p->o * alpha_at_cut_factor >= ALPHA_MIN) upd(&margins[0], mq);
+        if (stake_tol && !tail_at_stake && mq < stake_tol[0] && p->o * alpha_at_cut_factor >= ALPHA_MIN) {
+            /* the weight this entry would have just inside the cut */
+            double w = p->o * exp(-0.5 * q);
+            w = (w < ALPHA_MAX ? w : ALPHA_MAX);
+            st += w * T;
+            slack += w;
+        }
         if (q > Q_MAX) continue;
         double G = exp(-0.5 * q);
         double a = p->o * G;
         double alpha = a < ALPHA_MAX ? a : ALPHA_MAX;
-        upd(&margins[1], fabs(alpha / ALPHA_MIN - 1.0));
+        const double ma = fabs(alpha / ALPHA_MIN - 1.0);
+        upd(&margins[1], ma);
+        if (stake_tol && !tail_at_stake && ma < stake_tol[1]) {
+            st += alpha * T;
+            slack += alpha;
+        }
         if (alpha < ALPHA_MIN) continue;
         double Tn = T * (1.0 - alpha);
-        upd(&margins[2], fabs(Tn - T_MIN) / T_MIN);
+        const double ms = fabs(Tn - T_MIN) / T_MIN;
+        upd(&margins[2], ms);
+        if (stake_tol && !tail_at_stake && ms < stake_tol[2] + 1.02 * slack) {
+            st += T;
+            tail_at_stake = 1;
+        }
         if (Tn < T_MIN) break;
         upd(&margins[3], fabs(a - ALPHA_MAX) / ALPHA_MAX);
         for (int ch = 0; ch < 3; ++ch) C[ch] += p->col[ch] * alpha * T;
@@ -491,6 +523,7 @@ static int composite_pixel(const gvo_frame *fr, const proj_t *P, const int64_t *
     for (int ch = 0; ch < 3; ++ch) C[ch] += T * fr->bg[ch];
     *Tout = T;
     *ncontrib = nc;
+    if (stake) *stake = st;
     return 0;
 }
 
@@ -709,11 +742,13 @@ int gvo_project(const gvo_frame *fr, double *out)
 
 /* Render the listed pixels (linear index y*W + x; pix == NULL means all
  * pixels in raster order) and, if dL_dC is given, accumulate (+=) the
- * gradient of sum_p dL_dC[p] . C[p] into grads.  Returns 0, or -1 when out
- * of memory, -2 for an invalid pose. */
+ * gradient of sum_p dL_dC[p] . C[p] into grads.  With stake_tol (3 relative
+ * margins) and stake given, stake[i] is the weight at stake in pixel i (see
+ * composite_pixel).  Returns 0, or -1 when out of memory, -2 for an invalid
+ * pose. */
 int gvo_render(const gvo_frame *fr, int64_t n_pix, const int64_t *pix, double *color,
                double *T_final, int64_t *n_contrib, double *margins, const double *dL_dC,
-               gvo_grads *grads, int n_threads)
+               gvo_grads *grads, int n_threads, const double *stake_tol, double *stake)
 {
     cam_t cam;
     int ok;
@@ -762,7 +797,7 @@ int gvo_render(const gvo_frame *fr, int64_t n_pix, const int64_t *pix, double *c
             int64_t nc;
             L.len = 0;
             if (composite_pixel(fr, P, order, nv, (double)x + 0.5, (double)y + 0.5, C, &T, &nc, mg,
-                                bwd ? &L : NULL)) {
+                                bwd ? &L : NULL, stake ? stake_tol : NULL, stake ? &stake[i] : NULL)) {
                 err = -1;
                 continue;
             }
@@ -847,7 +882,7 @@ int gvo_contributors(const gvo_frame *fr, uint8_t *flags, int n_threads)
                 int64_t nc;
                 L.len = 0;
                 if (composite_pixel(fr, P, order, nv, (double)(i % fr->width) + 0.5, (double)(i / fr->width) + 0.5,
-                                    C, &T, &nc, mg, &L)) {
+                                    C, &T, &nc, mg, &L, NULL, NULL)) {
                     err = -1;
                     continue;
                 }
@@ -864,4 +899,4 @@ int gvo_contributors(const gvo_frame *fr, uint8_t *flags, int n_threads)
     return err;
 }
 
-int gvo_abi_version(void) { return 5; }
+int gvo_abi_version(void) { return 6; }
