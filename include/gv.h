@@ -141,7 +141,8 @@ typedef struct {
 /* Tunables of the rasterizer kernels (chosen by gv_autotune, or set directly).
  * batch: entries staged in LDS per round of a tile's compositing loop
  * (64, 128 or 256); sort_cap: longest per-tile list sorted in one LDS pass
- * (1024, 2048 or 4096; longer lists are sorted in chunks and merged);
+ * (512, 1024, 2048 or 4096; lists up to twice that merge two LDS-sorted
+ * runs, longer lists are sorted in chunks and merged in global memory);
  * compact: compositing kernel choice, 0..7.  With bit 2 set the forward lets
  * each wave walk the entries meeting its 8x8 quadrant (as the backward always
  * does); with it clear each 16-lane row of a wave walks the entries meeting
@@ -259,6 +260,18 @@ gv_status gv_camera_ode_bwd(const float *theta, const float *z0, int32_t frames,
                             const float *dL_dposes, float *dtheta, float *dz0, void *ws, size_t ws_bytes,
                             void *stream);
 
+/* Trajectory error of a camera path against a reference pose table (Sec. 3.4:
+ * the learned camera of Eq. 1 judged by per-frame poses).  poses and
+ * ref_poses: device [frames][7] world->camera (qw, qx, qy, qz, tx, ty, tz),
+ * quaternions need not be unit.  Per frame f (device, [frames][2], fp32):
+ * per_frame[2f] = distance between the camera centres -R^T t, per_frame[2f+1]
+ * = angle (radians, in [0, pi]) of the relative rotation R R_ref^T.
+ * summary (device, [2]): root mean square of the centre distances and mean
+ * angle.  Computed in FP64; stream-ordered, no synchronisation.
+ * GV_ERR_INVALID_ARG for null pointers or frames outside [1, 100000]. */
+gv_status gv_pose_error(const float *poses, const float *ref_poses, int32_t frames, float *per_frame,
+                        float *summary, void *stream);
+
 /* One fitting step of the learned-camera form, captured into one HIP graph
  * (launch/destroy with gv_batch_graph_launch / gv_batch_graph_destroy):
  * gv_camera_ode_fwd (theta, z0 -> poses [F][7]), then gv_render_batch with
@@ -285,8 +298,10 @@ gv_status gv_autotune(const gv_scene *scene, const gv_camera *cam, const float *
 
 /* Device status word of a workspace (host outputs; synchronises the device):
  * out[0] = 1 if the intersection capacity overflowed (2: internal binning
- * inconsistency; outputs invalid), out[1] = number of
- * Gaussians skipped for non-finite parameters (last projection), out[2..3] =
+ * inconsistency; outputs invalid), out[1] = number of (frame, Gaussian)
+ * pairs skipped for non-finite parameters in the last call's projection (a
+ * Gaussian with a NaN or infinite parameter is dropped and counted once per
+ * frame; its gradients are zero), out[2..3] =
  * low/high 32 bits of the intersection count of the last projection. */
 gv_status gv_device_status(const void *ws, uint32_t out[4]);
 

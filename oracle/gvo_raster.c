@@ -6,10 +6,11 @@
  * call this file; only the test suite, the smoke check and the CPU-baseline
  * leg of the benchmark do.  It shares no code with the HIP kernels.
  *
- * What it computes (paper Sec. 3.1: Gaussians with mean mu, covariance
- * Sigma = (RS)(RS)^T, colour c and opacity o are projected and rasterized onto
- * the image plane and fitted by a reconstruction loss; the rasterizer itself is
- * the one of 3D Gaussian Splatting, which the paper cites).  The plain,
+ * What it computes (paper Sec. 3.1: the footprints of Gaussians with mean mu,
+ * covariance Sigma = (RS)(RS)^T, colour c and opacity o are splatted onto the
+ * image plane, and the parameters are fitted by comparing the images with the
+ * video; the rasterizer itself is the one of 3D Gaussian Splatting, which the
+ * paper cites).  The plain,
  * tile-free definition is written out, per pixel, with no binning:
  *
  *   1. Time evaluation (Sec. 3.2, Eq. 2-3).  Either

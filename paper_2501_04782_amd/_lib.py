@@ -98,6 +98,7 @@ _SIGS = [
     ("gv_camera_ode_fwd", c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("gv_camera_ode_bwd", c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_size_t, c_void_p]),
+    ("gv_pose_error", c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     ("gv_get_tuning", c_int32, [ctypes.POINTER(GvTuning)]),
     ("gv_set_tuning", c_int32, [ctypes.POINTER(GvTuning)]),
     ("gv_autotune", c_int32, [ctypes.POINTER(GvScene), ctypes.POINTER(GvCamera), c_void_p, c_void_p, c_int32,

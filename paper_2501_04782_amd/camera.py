@@ -59,6 +59,22 @@ def camera_ode_bwd(theta: torch.Tensor, z0: torch.Tensor, frames: int, substeps:
     return dtheta, dz0
 
 
+def pose_error(poses: torch.Tensor, ref_poses: torch.Tensor) -> dict:
+    """Trajectory error of a camera path against a reference pose table
+    (gv_pose_error): root mean square distance of the camera centres, mean
+    relative rotation angle (radians) and the per-frame values.  Reads the
+    results back (synchronises the stream)."""
+    F = int(poses.shape[0])
+    _need(poses, (F, 7), torch.float32, "poses")
+    _need(ref_poses, (F, 7), torch.float32, "ref_poses")
+    per_frame = torch.empty(F, 2, device=poses.device)
+    summary = torch.empty(2, device=poses.device)
+    L.check(L.load().gv_pose_error(_ptr(poses), _ptr(ref_poses), F, _ptr(per_frame), _ptr(summary), _stream()),
+            "gv_pose_error")
+    pf, sm = per_frame.cpu().numpy(), summary.cpu().numpy()
+    return dict(translation_rmse=float(sm[0]), mean_angle=float(sm[1]), translation=pf[:, 0], angle=pf[:, 1])
+
+
 class CameraODE(torch.autograd.Function):
     """poses = ODE(theta, z0); backward through the discrete adjoint."""
 

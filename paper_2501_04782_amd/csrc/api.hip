@@ -561,7 +561,8 @@ gv_status gv_set_tuning(const gv_tuning* t) {
     if (!t) return GV_ERR_INVALID_ARG;
     if (!batch_ok(t->batch)) return GV_ERR_INVALID_ARG;
     if (t->bwd_batch != 0 && !batch_ok(t->bwd_batch)) return GV_ERR_INVALID_ARG;
-    if (t->sort_cap != 1024 && t->sort_cap != 2048 && t->sort_cap != 4096) return GV_ERR_INVALID_ARG;
+    if (t->sort_cap != 512 && t->sort_cap != 1024 && t->sort_cap != 2048 && t->sort_cap != 4096)
+        return GV_ERR_INVALID_ARG;
     if (t->compact < 0 || t->compact > 7) return GV_ERR_INVALID_ARG;
     Tuning n = current_tuning();
     n.batch = t->batch;

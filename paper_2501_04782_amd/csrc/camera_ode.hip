@@ -324,6 +324,64 @@ __global__ __launch_bounds__(256) void k_ode_grad_final(const float* __restrict_
     dtheta[p] = acc;
 }
 
+// Trajectory error of a camera path against a reference pose table (the
+// per-frame poses judging the learned camera of Sec. 3.4).  Per frame, in
+// FP64: the camera centre c = -R(q)^T t of each pose and the distance between
+// the two centres; the rotation error is the angle of the relative rotation
+// R(q) R(q_ref)^T, taken from the relative quaternion q (x) conj(q_ref) as
+// 2 atan2(|vector part|, |scalar part|) (both quaternions normalised first).
+// One workgroup; the two sums are reduced in a fixed order.
+constexpr int PE_WG = 256;
+
+__device__ __forceinline__ void pose_centre(const float* p, double qn[4], double c[3]) {
+    double q[4] = {p[0], p[1], p[2], p[3]};
+    const double r = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int k = 0; k < 4; ++k) qn[k] = q[k] / r;
+    const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+    const double R[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+                            {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+                            {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+    for (int i = 0; i < 3; ++i) c[i] = -(R[0][i] * p[4] + R[1][i] * p[5] + R[2][i] * p[6]);
+}
+
+__global__ __launch_bounds__(PE_WG) void k_pose_error(const float* __restrict__ poses, const float* __restrict__ ref,
+                                                      int32_t frames, float* __restrict__ per_frame,
+                                                      float* __restrict__ summary) {
+    __shared__ double s_t[PE_WG], s_a[PE_WG];
+    double st = 0.0, sa = 0.0;
+    for (int f = threadIdx.x; f < frames; f += PE_WG) {
+        double q1[4], c1[3], q2[4], c2[3];
+        pose_centre(poses + 7 * f, q1, c1);
+        pose_centre(ref + 7 * f, q2, c2);
+        const double dx = c1[0] - c2[0], dy = c1[1] - c2[1], dz = c1[2] - c2[2];
+        const double te = sqrt(dx * dx + dy * dy + dz * dz);
+        // relative quaternion q1 (x) conj(q2)
+        const double w = q1[0] * q2[0] + q1[1] * q2[1] + q1[2] * q2[2] + q1[3] * q2[3];
+        const double vx = q2[0] * q1[1] - q1[0] * q2[1] - (q1[2] * q2[3] - q1[3] * q2[2]);
+        const double vy = q2[0] * q1[2] - q1[0] * q2[2] - (q1[3] * q2[1] - q1[1] * q2[3]);
+        const double vz = q2[0] * q1[3] - q1[0] * q2[3] - (q1[1] * q2[2] - q1[2] * q2[1]);
+        const double ang = 2.0 * atan2(sqrt(vx * vx + vy * vy + vz * vz), fabs(w));
+        per_frame[2 * f] = static_cast<float>(te);
+        per_frame[2 * f + 1] = static_cast<float>(ang);
+        st += te * te;
+        sa += ang;
+    }
+    s_t[threadIdx.x] = st;
+    s_a[threadIdx.x] = sa;
+    __syncthreads();
+    for (int h = PE_WG / 2; h > 0; h >>= 1) {
+        if (static_cast<int>(threadIdx.x) < h) {
+            s_t[threadIdx.x] += s_t[threadIdx.x + h];
+            s_a[threadIdx.x] += s_a[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        summary[0] = static_cast<float>(sqrt(s_t[0] / frames));
+        summary[1] = static_cast<float>(s_a[0] / frames);
+    }
+}
+
 }  // namespace gv
 
 using namespace gv;
@@ -369,6 +427,15 @@ gv_status gv_camera_ode_bwd(const float* theta, const float* z0, int32_t frames,
                        static_cast<int64_t>(L.chunk), part);
     hipLaunchKernelGGL(k_ode_grad_final, dim3((N_THETA + 255) / 256), dim3(256), 0, st, part,
                        static_cast<int64_t>(L.chunks), dtheta);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GV_OK : GV_ERR_HIP;
+}
+
+gv_status gv_pose_error(const float* poses, const float* ref_poses, int32_t frames, float* per_frame, float* summary,
+                        void* stream) {
+    if (!poses || !ref_poses || !per_frame || !summary || frames < 1 || frames > 100000) return GV_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_pose_error, dim3(1), dim3(PE_WG), 0, static_cast<hipStream_t>(stream), poses, ref_poses,
+                       frames, per_frame, summary);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? GV_OK : GV_ERR_HIP;
 }

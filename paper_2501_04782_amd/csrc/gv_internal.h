@@ -71,7 +71,7 @@ enum : int { ST_OVERFLOW = 0, ST_NONFINITE = 1, ST_K_LO = 2, ST_K_HI = 3, ST_WOR
 
 struct Tuning {
     int batch;      // 64 / 128 / 256 entries per LDS round of the forward compositing kernel
-    int sort_cap;   // 1024 / 2048 / 4096
+    int sort_cap;   // 512 / 1024 / 2048 / 4096
     int bwd_batch;  // the same for the backward compositing kernel
     int compact;    // bit 0 / bit 1: compacted forward / backward compositing (coverage masks + per-lane entry
                     // walks); else bit 2: quadrant forward (clear: 4x4-block forward); the backward walks

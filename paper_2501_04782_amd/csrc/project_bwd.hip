@@ -536,10 +536,17 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
     if (DYN) {
         for (int k = 0; k < 7; ++k) gsq[k] = acc[3 + k][tid];
     } else {  // dL/dSig summed over the frames, through the shape once
+        // a Gaussian culled in every frame (e.g. for non-finite parameters)
+        // has dL/dSig = 0 exactly; its shape may hold NaN, so it is not taken
+        // through the chain (0 * NaN would poison its gradient)
         float Gs[6], o7[7];
-        for (int k = 0; k < 6; ++k) Gs[k] = static_cast<float>(acc[3 + k][tid]);
-        sigma_adjoint(Gs, Pstatic, o7);
-        for (int k = 0; k < 7; ++k) gsq[k] = o7[k];
+        bool touched = false;
+        for (int k = 0; k < 6; ++k) {
+            Gs[k] = static_cast<float>(acc[3 + k][tid]);
+            touched = touched || Gs[k] != 0.0f;
+        }
+        if (touched) sigma_adjoint(Gs, Pstatic, o7);
+        for (int k = 0; k < 7; ++k) gsq[k] = touched ? o7[k] : 0.0;
     }
     for (int k = 0; k < 3; ++k) {
         if (a.n_ctrl == 0) put(a.g_means, k * n + g, acc[k][tid]);

@@ -208,6 +208,7 @@ hipError_t launch_tile_sort(const Args& a, int64_t segments, hipStream_t stream)
     if (segments <= 0) return hipSuccess;
     const dim3 grid(static_cast<uint32_t>(segments)), block(WG);
     switch (a.tune.sort_cap) {
+        case 512: hipLaunchKernelGGL(k_tile_sort<512>, grid, block, 0, stream, a); break;
         case 1024: hipLaunchKernelGGL(k_tile_sort<1024>, grid, block, 0, stream, a); break;
         case 2048: hipLaunchKernelGGL(k_tile_sort<2048>, grid, block, 0, stream, a); break;
         default: hipLaunchKernelGGL(k_tile_sort<4096>, grid, block, 0, stream, a); break;

@@ -401,6 +401,17 @@ def estimate_capacity(scene: Scene, camera: Camera, poses: torch.Tensor, times: 
 # autograd
 # ---------------------------------------------------------------------------
 
+def _raise_on_overflow(ws: Workspace, where: str) -> None:
+    """The batched forward never synchronises; an autograd caller gets its
+    images back only after the status words have been read (one small copy),
+    so an exceeded intersection capacity raises instead of returning
+    unwritten images."""
+    st = ws.status()
+    if st["overflow"]:
+        raise L.GvError(L.GV_ERR_CAPACITY, f"{where}: {st['intersections']} intersections for a capacity of "
+                                           f"{ws.k_capacity}")
+
+
 class RasterizeFrame(torch.autograd.Function):
     """image = render(params, pose) for one frame; backward through render_bwd.
     The workspace must not be reused by another forward before backward."""
@@ -430,6 +441,7 @@ class RasterizeClip(torch.autograd.Function):
     def forward(ctx, means, log_scales, quats, opacity_logits, colors, mean_coeffs, sh, poses, times, camera, ws):
         scene = Scene(means, log_scales, quats, opacity_logits, colors, mean_coeffs, sh=sh)
         out = render_batch(scene, camera, poses, times, ws, forward=True, backward=False)
+        _raise_on_overflow(ws, "RasterizeClip")
         ctx.save_for_backward(means, log_scales, quats, opacity_logits, colors, mean_coeffs, sh, poses, times,
                               out["images"])
         ctx.camera, ctx.ws = camera, ws
@@ -457,6 +469,7 @@ class RasterizeDynamicClip(torch.autograd.Function):
         scene = Scene(None, log_scales, quats, opacity_logits, colors, ctrl=ctrl, scale_coeffs=scale_coeffs,
                       quat_coeffs=quat_coeffs)
         out = render_batch(scene, camera, poses, times, ws, forward=True, backward=False)
+        _raise_on_overflow(ws, "RasterizeDynamicClip")
         ctx.save_for_backward(ctrl, log_scales, quats, opacity_logits, colors, scale_coeffs, quat_coeffs, poses,
                               times, out["images"])
         ctx.camera, ctx.ws = camera, ws

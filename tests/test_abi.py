@@ -103,6 +103,10 @@ def test_entry_points_reject_bad_arguments_before_touching_the_device():
     assert lib.gv_camera_ode_workspace_bytes(100, 4, ctypes.byref(sz)) == L.GV_OK and sz.value > 396 * 4 * 136 * 4
     assert lib.gv_camera_ode_workspace_bytes(0, 4, ctypes.byref(sz)) == L.GV_ERR_INVALID_ARG
     assert lib.gv_camera_ode_fwd(None, None, 10, 4, None, None, 0, None) == L.GV_ERR_INVALID_ARG
+    # trajectory error: argument checks happen before any launch
+    assert lib.gv_pose_error(None, None, 10, None, None, None) == L.GV_ERR_INVALID_ARG
+    dummy = ctypes.c_void_p(256)
+    assert lib.gv_pose_error(dummy, dummy, 0, dummy, dummy, None) == L.GV_ERR_INVALID_ARG
 
 
 def test_tuning_table_validation():

@@ -1,8 +1,20 @@
-"""Full-size parity of the two remaining benchmark configurations, in the
-launch configuration bench.py times, on sampled pixels the oracle computes one
-by one: the 1920x1080, 500k-Gaussian bf16 clip with cubic means (32 frames),
-and the camera-ODE fitting step (100 frames at 960x540, 200k Gaussians:
-ODE forward -> batched raster fwd+bwd -> ODE adjoint in one graph)."""
+"""Full-size parity of the benchmark configurations, in the launch
+configuration bench.py times, on whole 16x16 tiles the oracle computes pixel
+by pixel: each checked frame's longest tile bucket, its densest tile (most
+contributors at the tile centre in the oracle) and random tiles, on five
+frames per clip.
+
+* the 960x540 frame of 100k Gaussians through the plain per-frame path;
+* the benchmark clip (50 frames at 960x540, 200k Gaussians) through the
+  captured graph with the fused L2 loss (Sec. 4.1), and again at sort
+  capacity 512, where every bucket above 1024 entries takes the global-merge
+  path of the per-tile sort;
+* the 32-frame 1920x1080 clip of 500k bf16 Gaussians with cubic means;
+* the camera-ODE fitting step (100 frames: ODE forward -> batched raster
+  fwd+bwd -> ODE adjoint in one graph), with the trajectory error of the
+  learned camera against the ground-truth pose table;
+* a 4128x1056 clip whose tile grid exceeds the LDS tile histogram.
+"""
 import numpy as np
 import pytest
 import torch
@@ -10,64 +22,193 @@ import torch
 import gv_synth
 import oracle
 from oracle import camera_ode as ode_ref
-from parity_util import GRAD_TOL, PIXEL_TOL, compare_grads, device_inputs, knife_edge, oracle_frame, \
-    planar_to_pixels, rel_err, workspace_for
+from parity_util import (GRAD_TOL, PIXEL_TOL, PixelTally, colour_range, compare_grads, compare_poses, device_inputs,
+                         knife_edge, oracle_frame, planar_to_pixels, rel_err, sample_tiles, tile_pixels,
+                         workspace_for)
 from test_gpu_parity import run_clip, say, small_workload
 
 pytestmark = pytest.mark.gpu
 
 if torch.cuda.is_available():
     from paper_2501_04782_amd import camera as gvcam
+    from paper_2501_04782_amd import raster
 
 
-def sampled_upstream(w, frames, npix, seed, widen=1.0):
-    """Oracle results on `npix` random pixels of each listed frame and a random
-    upstream gradient supported on those pixels (zero at knife-edge pixels)."""
+def sampled_tiles(w, frames, seed, n_random=2, widen=1.0, label=""):
+    """Whole tiles of each listed frame (longest bucket, densest, random) and
+    the oracle's results there; returns (pixel lists, oracle results, bucket
+    sizes of the chosen tiles)."""
+    rng = np.random.default_rng(seed)
+    pix, refs, info = [], [], []
+    for f in frames:
+        tiles, sizes = sample_tiles(w, f, n_random, rng)
+        p = tile_pixels(w, tiles)
+        say(f"[{label}] frame {f}: tiles {tiles} bucket sizes {[int(sizes[t]) for t in tiles]} "
+            f"(frame max {int(sizes.max())}), {p.size} pixels; oracle")
+        pix.append(p)
+        refs.append(oracle_frame(w, f, pixels=p, widen=widen))
+        info.append(int(sizes.max()))
+    return pix, refs, info
+
+
+def sampled_upstream(w, frames, pix, refs, seed, widen=1.0):
+    """A random upstream gradient supported on the sampled pixels (zero at
+    set-aside ones): per frame [P_f][3] and the dense [F][3][H][W] array."""
     H, W = w["camera"].height, w["camera"].width
     rng = np.random.default_rng(seed)
-    pix = [np.sort(rng.choice(H * W, npix, replace=False)) for _ in frames]
-    refs, dls = [], []
-    for f, p in zip(frames, pix):
-        say(f"[{w.get('name', 'clip')}] oracle frame {f}")
-        r = oracle_frame(w, f, pixels=p)
-        refs.append(r)
-        d = rng.normal(0, 1, (p.size, 3))
-        d[knife_edge(r["margins"], grads=True, widen=widen)] = 0.0
-        dls.append(d)
+    dls = []
     dl = np.zeros((w["frames"], 3, H * W), np.float32)
-    for f, p, d in zip(frames, pix, dls):
-        dl[f][:, p] = d.T
-    return pix, refs, dls, dl.reshape(w["frames"], 3, H, W)
-
-
-def check_pixels(imgs, frames, pix, refs, label, widen=1.0):
     for f, p, r in zip(frames, pix, refs):
-        got = planar_to_pixels(imgs[f])[p]
-        d = np.abs(got - r["color"]).max(axis=1)
-        ke = knife_edge(r["margins"], widen=widen)
-        assert d[~ke].max() <= PIXEL_TOL, (label, f, d[~ke].max())
-        say(f"[{label}] frame {f}: max|d|={d[~ke].max():.2e} knife-edge={ke.sum()}/{p.size}")
+        d = rng.normal(0, 1, (p.size, 3)).astype(np.float32).astype(np.float64)
+        d[knife_edge(r["margins"], grads=True, widen=widen) | (r["stake"] > 0)] = 0.0
+        dls.append(d)
+        dl[f][:, p] = d.T
+    return dls, dl.reshape(w["frames"], 3, H, W)
+
+
+def check_sampled_pixels(imgs, frames, pix, refs, w, label, widen=1.0):
+    tally = PixelTally(label)
+    crange = colour_range(w)
+    for f, p, r in zip(frames, pix, refs):
+        tally.add(planar_to_pixels(imgs[f])[p], r, crange, widen=widen, where=f" frame {f}")
+    stats = tally.finish()
+    say(f"[{label}] pixels {stats}")
+    return stats
+
+
+def test_frame540p_n100k_full_size_sampled():
+    """960x540, 100k Gaussians, per-frame path at full size; gradients with an
+    upstream gradient supported on the sampled tiles."""
+    w = gv_synth.make_workload("frame540p_n100k", targets=False)
+    frames = [0]
+    pix, refs, _ = sampled_tiles(w, frames, 20, n_random=6, label="540p n100k")
+    dls, dl = sampled_upstream(w, frames, pix, refs, 20)
+    scene, cam, poses, times = device_inputs(w)
+    ws = workspace_for(scene, cam, poses, times)
+    Tf = torch.empty(w["camera"].height, w["camera"].width, device="cuda")
+    img = raster.render_fwd(scene, cam, poses[0].contiguous(), 0.0, ws, T_final=Tf)
+    g, dpose = raster.render_bwd(scene, cam, poses[0].contiguous(), 0.0, ws, img,
+                                 dL_dimage=torch.from_numpy(dl[0]).cuda())
+    torch.cuda.synchronize()
+    check_sampled_pixels(img.cpu().numpy()[None], frames, pix, refs, w, "540p n100k")
+    # final transmittance: the relative error the stop decision sees
+    r = refs[0]
+    free = ~(knife_edge(r["margins"]) | (r["stake"] > 0))
+    t_rel = np.abs(Tf.cpu().numpy().reshape(-1)[pix[0]] - r["T_final"]) / r["T_final"]
+    assert t_rel[free].max() <= 1e-3, t_rel[free].max()  # well inside the stop margin
+    say(f"[540p n100k] T_final relative error: max {t_rel[free].max():.2e}, "
+        f"99.9th percentile {np.percentile(t_rel[free], 99.9):.2e}")
+    gref = oracle_frame(w, 0, pixels=pix[0], dL_dC=dls[0])["grads"]
+    ge = compare_grads(g, gref, "540p n100k")
+    pe = compare_poses(dpose, gref["pose"], "540p n100k")
+    say(f"[540p n100k] grads={ge} pose={pe:.2e}")
+
+
+def test_clip540p_f50_n200k_fused_l2_full_size():
+    """The benchmark clip in the benchmark's launch configuration (captured
+    graph, fused L2 loss).  The targets equal the GPU's own image except on
+    the sampled tiles, where they are seeded U[0, 1]: the residual, so the
+    loss and every gradient, then lives only where the oracle is evaluated.
+    Per-frame losses, all parameter gradients and the pose gradients are
+    compared with the oracle's L2 loss (Sec. 4.1) and adjoint."""
+    w = gv_synth.make_workload("clip540p_f50_n200k", targets=False)
+    F, H, W = w["frames"], w["camera"].height, w["camera"].width
+    frames = [0, 12, 24, 37, 49]
+    pix, refs, longest = sampled_tiles(w, frames, 21, label="clip540p")
+    assert max(longest) > 1024  # buckets beyond one LDS pass at the default capacity
+    scene, cam, poses, times = device_inputs(w)
+    ws = workspace_for(scene, cam, poses, times, margin=1.3)
+    say("[clip540p] gpu forward (images the targets are built from)")
+    fwd = raster.render_batch(scene, cam, poses, times, ws, forward=True, backward=False)
+    torch.cuda.synchronize()
+    assert ws.status()["overflow"] == 0
+    base = fwd["images"].clone()
+    tg = base.cpu().numpy().reshape(F, 3, H * W)
+    rng = np.random.default_rng(22)
+    img_s, tgt_s = [], []
+    for f, p, r in zip(frames, pix, refs):
+        vals = rng.random((p.size, 3)).astype(np.float32)
+        free = ~(knife_edge(r["margins"], grads=True) | (r["stake"] > 0))
+        tg[f][:, p[free]] = vals[free].T
+        t_s = tg[f][:, p].T.astype(np.float64)               # [P_f][3]
+        c_s = np.where(free[:, None], r["color"], t_s)        # zero residual where set aside
+        img_s.append(c_s)
+        tgt_s.append(t_s)
+    targets = torch.from_numpy(tg.reshape(F, 3, H, W)).cuda()
+    say("[clip540p] gpu graph (fwd+bwd, fused L2)")
+    g = raster.BatchGraph(scene, cam, poses, times, ws, targets=targets)
+    g.launch()
+    torch.cuda.synchronize()
+    assert ws.status()["overflow"] == 0
+    assert torch.equal(g.images, base)
+    check_sampled_pixels(g.images.cpu().numpy(), frames, pix, refs, w, "clip540p")
+    # oracle loss and upstream gradient on the sampled pixels, scaled from
+    # the sample's mean to the clip's mean (the rest has zero residual)
+    n_full = F * 3 * H * W
+    loss_ref = np.zeros(F)
+    dls = []
+    for k, (f, c_s, t_s) in enumerate(zip(frames, img_s, tgt_s)):
+        share, grad = oracle.l2_loss_and_grad(c_s.T[None], t_s.T[None], per_frame=True)
+        scale = c_s.size / n_full
+        loss_ref[f] = share[0] * scale
+        dls.append(grad[0].T * scale)
+    loss_gpu = g.loss.cpu().numpy().astype(np.float64)
+    resid_bound = np.zeros(F)
+    for f, c_s, t_s in zip(frames, img_s, tgt_s):
+        resid_bound[f] = np.sum(2 * np.abs(c_s - t_s) * PIXEL_TOL + PIXEL_TOL ** 2) / n_full
+    bound = resid_bound + 1e-5 * loss_ref
+    assert np.all(np.abs(loss_gpu - loss_ref) <= bound), (loss_gpu[frames], loss_ref[frames], bound[frames])
+    assert np.all(np.delete(loss_gpu, frames) == 0.0)
+    say(f"[clip540p] loss rel err per frame {np.abs(loss_gpu - loss_ref)[frames] / loss_ref[frames]}")
+    say("[clip540p] oracle backward")
+    g_ref, dposes_ref, _ = oracle.render_clip_grads(w["scene"], w["camera"], w["poses"].astype(np.float64),
+                                                    w["times"], frames, pix, dls)
+    ge = compare_grads(g.grads, g_ref, "clip540p")
+    gp = g.dL_dposes.cpu().numpy()
+    pe = compare_poses(gp[frames], dposes_ref[frames], "clip540p")
+    assert np.all(np.delete(gp, frames, axis=0) == 0.0)
+    say(f"[clip540p] grads={ge} pose={pe:.2e} intersections={ws.status()['intersections']}")
+    # the same step at sort capacity 512: buckets above 1024 entries are sorted
+    # in LDS chunks and merged in global memory; the order is fully determined,
+    # so every image and gradient is bitwise the same
+    old = raster.get_tuning()
+    raster.set_tuning(old["batch"], 512, old["compact"], old["bwd_batch"])
+    try:
+        g2 = raster.BatchGraph(scene, cam, poses, times, ws, targets=targets)
+        g2.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(g2.images, base)
+        assert torch.equal(g2.loss, g.loss)
+        for k, v in g.grads.items():
+            if v is not None:
+                assert torch.equal(g2.grads[k], v), k
+        assert torch.equal(g2.dL_dposes, g.dL_dposes)
+        g2.close()
+    finally:
+        raster.set_tuning(old["batch"], old["sort_cap"], old["compact"], old["bwd_batch"])
+    g.close()
 
 
 def test_clip1080p_bf16_cubic_full_size_sampled():
     w = gv_synth.make_workload("clip1080p_f32_n500k_bf16", targets=False)
-    frames = [0, 15, 31]
-    pix, refs, dls, dl = sampled_upstream(w, frames, 512, 40)
+    frames = [0, 8, 15, 23, 31]
+    pix, refs, _ = sampled_tiles(w, frames, 40, n_random=1, label="clip1080p")
+    dls, dl = sampled_upstream(w, frames, pix, refs, 40)
     say("[clip1080p] gpu batch")
     out, ws, _ = run_clip(w, dl=dl)
-    check_pixels(out["images"].cpu().numpy(), frames, pix, refs, "clip1080p")
+    check_sampled_pixels(out["images"].cpu().numpy(), frames, pix, refs, w, "clip1080p")
     say("[clip1080p] oracle backward")
     g_ref, dposes_ref, _ = oracle.render_clip_grads(w["scene"], w["camera"], w["poses"].astype(np.float64),
                                                     w["times"], frames, pix, dls)
     ge = compare_grads(out["grads"], g_ref, "clip1080p")
-    pe = rel_err(out["dL_dposes"].cpu().numpy()[frames], dposes_ref[frames])
-    assert pe <= GRAD_TOL, pe
+    pe = compare_poses(out["dL_dposes"].cpu().numpy()[frames], dposes_ref[frames], "clip1080p")
     say(f"[clip1080p] grads={ge} pose={pe:.2e} intersections={ws.status()['intersections']}")
 
 
 def test_camera_ode_fitting_step_full_size_sampled():
     w = gv_synth.make_workload("clip540p_f100_n200k", targets=False)
     F, S = w["frames"], 4
+    gt_poses = w["poses"].copy()
     theta = gv_synth.init_mlp_theta(np.random.default_rng(7)).astype(np.float32)
     z0 = w["poses"][0].astype(np.float32)
     scene, cam, _, times = device_inputs(w)
@@ -79,9 +220,21 @@ def test_camera_ode_fitting_step_full_size_sampled():
     poses_ref = ode_ref.camera_ode_fwd(theta.astype(np.float64), z0.astype(np.float64), F, S)
     ep = rel_err(poses_gpu.cpu().numpy(), poses_ref)
     assert ep < 1e-5, ep
+    # trajectory error of the learned camera against the ground-truth pose
+    # table: the GPU's poses and the FP64 RK4 poses are judged alike
+    e_gpu = oracle.trajectory_error(poses_gpu.cpu().numpy(), gt_poses)
+    e_ref = oracle.trajectory_error(poses_ref, gt_poses)
+    assert abs(e_gpu["translation_rmse"] - e_ref["translation_rmse"]) <= 1e-5 * max(e_ref["translation_rmse"], 1.0)
+    assert abs(e_gpu["mean_angle"] - e_ref["mean_angle"]) <= 1e-5
+    assert e_ref["translation"][0] < 1e-6 and e_ref["angle"][0] < 1e-6  # z0 is the frame-0 pose
+    judged = gvcam.pose_error(poses_gpu, torch.from_numpy(gt_poses).cuda())
+    assert judged["translation_rmse"] == pytest.approx(e_gpu["translation_rmse"], rel=1e-5, abs=1e-7)
+    assert judged["mean_angle"] == pytest.approx(e_gpu["mean_angle"], rel=1e-5, abs=1e-6)
+    say(f"[fit step] trajectory error: rmse {e_ref['translation_rmse']:.4e} angle {e_ref['mean_angle']:.4e} rad")
     w["poses"] = poses_gpu.cpu().numpy()
-    frames = [0, 50, 99]
-    pix, refs, dls, dl = sampled_upstream(w, frames, 512, 41)
+    frames = [0, 25, 50, 75, 99]
+    pix, refs, _ = sampled_tiles(w, frames, 41, n_random=1, label="fit step")
+    dls, dl = sampled_upstream(w, frames, pix, refs, 41)
     ws = workspace_for(scene, cam, poses_gpu, times)
     say("[fit step] gpu graph")
     fit = gvcam.FitGraph(scene, cam, th, z, F, S, times, ws, dL_dimages=torch.from_numpy(dl).cuda())
@@ -89,7 +242,7 @@ def test_camera_ode_fitting_step_full_size_sampled():
     torch.cuda.synchronize()
     assert ws.status()["overflow"] == 0
     assert torch.equal(fit.poses, poses_gpu)
-    check_pixels(fit.images.cpu().numpy(), frames, pix, refs, "fit step")
+    check_sampled_pixels(fit.images.cpu().numpy(), frames, pix, refs, w, "fit step")
     say("[fit step] oracle backward + discrete adjoint")
     g_ref, dposes_ref, _ = oracle.render_clip_grads(w["scene"], w["camera"], w["poses"].astype(np.float64),
                                                     w["times"], frames, pix, dls)
@@ -105,20 +258,19 @@ def test_tile_grid_beyond_lds_histogram_sampled():
     """A 4128x1056 frame has 258 x 66 = 17,028 tiles, more than the 16,384 an
     LDS tile histogram holds, so binning takes the count and scatter kernels
     with one global atomic per intersection.  Images and gradients on sampled
-    pixels against the oracle."""
+    tiles against the oracle."""
     W, H = 4128, 1056
     assert ((W + 15) // 16) * ((H + 15) // 16) > 16384
     w = small_workload(43, W, H, 4000, 2, trajectory=True, ls=(-4.5, 0.5))
-    w["name"] = "large grid"
     frames = [0, 1]
-    pix, refs, dls, dl = sampled_upstream(w, frames, 1024, 44)
+    pix, refs, _ = sampled_tiles(w, frames, 44, n_random=4, label="large grid")
+    dls, dl = sampled_upstream(w, frames, pix, refs, 44)
     say("[large grid] gpu batch")
     out, ws, _ = run_clip(w, dl=dl)
-    check_pixels(out["images"].cpu().numpy(), frames, pix, refs, "large grid")
+    check_sampled_pixels(out["images"].cpu().numpy(), frames, pix, refs, w, "large grid")
     say("[large grid] oracle backward")
     g_ref, dposes_ref, _ = oracle.render_clip_grads(w["scene"], w["camera"], w["poses"].astype(np.float64),
                                                     w["times"], frames, pix, dls)
     ge = compare_grads(out["grads"], g_ref, "large grid")
-    pe = rel_err(out["dL_dposes"].cpu().numpy()[frames], dposes_ref[frames])
-    assert pe <= GRAD_TOL, pe
+    pe = compare_poses(out["dL_dposes"].cpu().numpy()[frames], dposes_ref[frames], "large grid")
     say(f"[large grid] grads={ge} pose={pe:.2e} intersections={ws.status()['intersections']}")
