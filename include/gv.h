@@ -190,6 +190,24 @@ gv_status gv_project_fwd(const gv_scene *scene, const gv_camera *cam, const floa
 gv_status gv_render_fwd(const gv_scene *scene, const gv_camera *cam, const float *pose7, float t,
                         float *image, float *T_final, void *ws, size_t ws_bytes, void *stream);
 
+/* gv_render_fwd without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  The call allocates nothing: its scratch
+ * space is a fixed device array of GV_NOALLOC_SCRATCH_BYTES (64 MiB) inside
+ * the library, one per GPU (each device holds its own copy until the process
+ * ends).  Arguments, outputs, the one synchronisation and the error codes are
+ * those of gv_render_fwd, plus: GV_ERR_WORKSPACE (nothing enqueued) when the
+ * frame's fixed arrays exceed the scratch (about 73 B per Gaussian, 8 B per
+ * pixel and 12 B per 16x16 tile), GV_ERR_CAPACITY when its (Gaussian, tile)
+ * intersections do not fit in the rest (76 B each).  All calls on one GPU
+ * share that GPU's array: calls that overlap on one GPU (from different
+ * streams or host threads) race and must be ordered by the caller.  The
+ * array keeps the last call's contents; every value a call reads is written
+ * by that call first (counters are cleared by fill kernels). */
+#define GV_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+gv_status gv_render_fwd_noalloc(const gv_scene *scene, const gv_camera *cam, const float *pose7, float t,
+                                float *image, float *T_final, void *stream);
+
 /* Backward of the last gv_render_fwd on this workspace (same scene, camera,
  * pose, t and image buffer).  Upstream gradient: dL_dimage [3][H][W], or,
  * with GV_LOSS_L2 in flags, the gradient of the L2 loss against `target`

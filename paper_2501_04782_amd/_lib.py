@@ -74,6 +74,8 @@ _SIGS = [
                                  c_void_p, c_void_p, c_size_t, c_void_p]),
     ("gv_render_fwd", c_int32, [ctypes.POINTER(GvScene), ctypes.POINTER(GvCamera), c_void_p, c_float, c_void_p,
                                 c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("gv_render_fwd_noalloc", c_int32, [ctypes.POINTER(GvScene), ctypes.POINTER(GvCamera), c_void_p, c_float,
+                                        c_void_p, c_void_p, c_void_p]),
     ("gv_render_bwd", c_int32, [ctypes.POINTER(GvScene), ctypes.POINTER(GvCamera), c_void_p, c_float, c_void_p,
                                 c_void_p, c_void_p, c_float, c_uint32, ctypes.POINTER(GvGrads), c_void_p, c_void_p,
                                 c_size_t, c_void_p]),

@@ -227,6 +227,32 @@ static unsigned long long* scan_tmp(const Args& a, const Layout& L) {
     return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(a.status) - L.status + L.scan_tmp);
 }
 
+// Scratch of gv_render_fwd_noalloc: a fixed device array, one copy per GPU
+// (each device holds its own at its own address until the process ends).
+// Host code never uses the array's name as an address: the address is taken
+// once per device with hipGetSymbolAddress, with that device current, and
+// kept in g_scratch_ptr.
+constexpr size_t NOALLOC_SCRATCH_BYTES = GV_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[MAX_DEVICES] = {};
+
+static gv_status scratch_of_current_device(void** out) {
+    int dev = -1;
+    GV_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return GV_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        GV_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255u) != 0u) return GV_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GV_OK;
+}
+
 // Optional HIP events between the stages of a launch sequence (GV_STAGES).
 struct StageTimer {
     hipEvent_t ev[GV_STAGES + 1];
@@ -372,6 +398,17 @@ gv_status gv_render_fwd(const gv_scene* scene, const gv_camera* cam, const float
     if (s != GV_OK) return s;
     GV_TRY(launch_composite_fwd(a, st));
     return GV_OK;
+}
+
+gv_status gv_render_fwd_noalloc(const gv_scene* scene, const gv_camera* cam, const float* pose7, float t,
+                                float* image, float* T_final, void* stream) {
+    if (!image || !pose7 || !scene_ok(scene) || !camera_ok(cam)) return GV_ERR_INVALID_ARG;
+    // the frame's fixed arrays must fit before the device is touched
+    if (make_layout(*cam, scene->n, 1, 0).total > NOALLOC_SCRATCH_BYTES) return GV_ERR_WORKSPACE;
+    void* ws = nullptr;
+    const gv_status s = scratch_of_current_device(&ws);
+    if (s != GV_OK) return s;
+    return gv_render_fwd(scene, cam, pose7, t, image, T_final, ws, NOALLOC_SCRATCH_BYTES, stream);
 }
 
 gv_status gv_render_bwd(const gv_scene* scene, const gv_camera* cam, const float* pose7, float t, const float* image,

@@ -222,6 +222,21 @@ def render_fwd(scene: Scene, camera: Camera, pose7: torch.Tensor, t: float, ws: 
     return image
 
 
+def render_fwd_noalloc(scene: Scene, camera: Camera, pose7: torch.Tensor, t: float, image: torch.Tensor,
+                       T_final: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """render_fwd into caller-given outputs with the library's fixed scratch
+    instead of a workspace (no device allocation; calls on one GPU must not
+    overlap)."""
+    _need(pose7, (7,), torch.float32, "pose7")
+    H, W = camera.height, camera.width
+    _need(image, (3, H, W), torch.float32, "image")
+    if T_final is not None:
+        _need(T_final, (H, W), torch.float32, "T_final")
+    L.check(L.load().gv_render_fwd_noalloc(ctypes.byref(scene.c()), ctypes.byref(camera.c()), _ptr(pose7), float(t),
+                                           _ptr(image), _ptr(T_final), _stream()), "gv_render_fwd_noalloc")
+    return image
+
+
 def render_bwd(scene: Scene, camera: Camera, pose7: torch.Tensor, t: float, ws: Workspace, image: torch.Tensor,
                dL_dimage: Optional[torch.Tensor] = None, target: Optional[torch.Tensor] = None,
                loss_scale: float = 0.0, grads: Optional[dict] = None, dL_dpose7: Optional[torch.Tensor] = None,
