@@ -26,15 +26,19 @@ import numpy as np
 METRIC = "fwd+bwd frames/s at 960×540, 200k Gaussians (batched vs per-frame), % HBM roof"
 ODE_WORKLOAD = "clip540p_f100_n200k"
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
-# FP32 vector peak without packed-FP32 instructions (this build disables them):
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
-ALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
-# Algorithmic FP32 operations per contributing (pixel, Gaussian) pair
-# (footprint 9, falloff 2, opacity/clamp 2, transmittance 2, colour 6 = 21 in
-# the forward; the adjoint re-derives those 13 and adds 46 for the colour,
-# alpha, conic and centre partials and the suffix colour).
-FLOPS_FWD_PER_PAIR = 21
-FLOPS_BWD_PER_PAIR = 59
+# FP32 vector peaks: the published 157.3 TFLOP/s counts packed FP32 (two
+# operations per lane and instruction); this build disables packed FP32
+# instructions, so what it can issue is the non-packed rate,
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s.
+ALU_PEAK = 157.3e12
+ALU_PEAK_NONPACKED = 256 * 4 * 16 * 2 * 2.4e9
+# LDS: 128 bytes per clock per CU
+LDS_PEAK = 256 * 128 * 2.4e9
+# Algorithmic FP32 operations per contributing (pixel, Gaussian) pair, the
+# hot-path scope table's per-pair estimates: about 25 in the forward
+# compositing and 70 in its adjoint.
+FLOPS_FWD_PER_PAIR = 25
+FLOPS_BWD_PER_PAIR = 70
 PARAM_BYTES = 56           # fp32: means 3, log-scales 3, quats 4, opacity 1, colour 3
 
 
@@ -52,81 +56,148 @@ def algorithmic_bytes(N, V, K, P, F, p=PARAM_BYTES, pg=PARAM_BYTES):
     return F * (per_frame_fwd + per_frame_bwd)
 
 
-def stage_bytes(stage, N, V, K, P, F):
-    """Algorithmic bytes of one launch of a stage over the whole clip."""
+def stage_bytes(stage, N, V, K, P, F, p=PARAM_BYTES):
+    """Algorithmic bytes of one launch of a stage over the whole clip, from the
+    hot-path table's per-unit figures (K intersections, V visible Gaussians
+    per frame, P pixels per frame, F frames)."""
     if stage == "composite_fwd":
-        # per intersection: sorted index 4 + record 32 + colour 16; per pixel:
-        # image 12 + T_final 4 + last index 4 written, target 12 read
-        return K * (4 + 32 + 16) + F * P * (12 + 4 + 4 + 12)
+        # per entry: sorted index 4 + gathered record 36; per pixel: RGB 12,
+        # final transmittance 4, last index 4 written, target 12 read (fused L2)
+        return K * 40 + F * P * (20 + 12)
     if stage == "composite_bwd":
-        # per intersection: index 4 + slot 4 + record 32 + colour 16 read,
-        # 36 B of partials written; per pixel image/target 24 + T/last 8 read
-        return K * (4 + 4 + 32 + 16 + 36) + F * P * (24 + 8)
+        # per pixel: upstream gradient (or target) 12, T_final 4, last index 4;
+        # per entry: sorted index 4 + gathered record 36 read, 9-float partial 36 written
+        return F * P * 20 + K * 76
     if stage == "project_bwd":
-        return F * V * 36 + F * N * PARAM_BYTES + N * 56 + K * 36
+        # partials read once, parameters read once, gradients written once
+        return K * 36 + N * (p + 56)
     if stage == "project":
-        return F * N * PARAM_BYTES + F * V * (32 + 8 + 4)
+        return F * N * p + F * V * 40
     if stage == "sort":
-        return K * (8 + 4) * 2 + K * 8
+        return K * 12 * 2
     if stage == "scatter":
-        return F * V * 48 + K * 12
+        return K * 12 + F * V * 8
     return 0
 
 
-def quick_clip(name, dev, steps=3):
-    """Frames/s of one batched fwd+bwd step (one HIP graph) on another
-    workload, with the installed tuning; for the camera-ODE workload the step
-    is the fitting graph (ODE forward -> batch -> ODE adjoint)."""
+def host_info() -> dict:
+    """Host cores the CPU baseline could use."""
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = None
+    return dict(nproc=os.cpu_count(), affinity=aff, omp_num_threads=os.environ.get("OMP_NUM_THREADS"))
+
+
+def counters_summary(c: dict, pairs) -> dict:
+    """Per-launch counter figures of the dominant kernel from its committed
+    rocprofv3 summary (SQ counters summed over the chip per dispatch):
+    VALU lane-instructions per contributing pair, VALU issue share and lane
+    utilisation, LDS utilisation (cycles the LDS serves indexed accesses) and
+    LDS bandwidth against its peak, and the profile's own kernel time."""
+    ms = c["avg_ms"]
+    sec = ms * 1e-3
+    # cycles the kernel ran: GRBM_GUI_ACTIVE is counted per XCC (8 summed)
+    cycles = c["GRBM_GUI_ACTIVE"] / 8 if "GRBM_GUI_ACTIVE" in c else sec * 2.4e9
+    out = dict(avg_ms=round(ms, 4), valu_insts=c["SQ_INSTS_VALU"],
+               valu_issue_share=round(c["SQ_INSTS_VALU"] * 4 / (cycles * 1024), 3),
+               clock_ghz=round(cycles / sec / 1e9, 3))
+    if pairs:
+        out["valu_lane_insts_per_pair"] = round(c["SQ_INSTS_VALU"] * 64 / pairs, 1)
+    if "SQ_THREAD_CYCLES_VALU" in c and c.get("SQ_ACTIVE_INST_VALU"):
+        out["valu_lane_util"] = round(c["SQ_THREAD_CYCLES_VALU"] / (c["SQ_ACTIVE_INST_VALU"] * 64), 3)
+    if "SQ_LDS_IDX_ACTIVE" in c:
+        out["lds_util"] = round(c["SQ_LDS_IDX_ACTIVE"] / (cycles * 256), 3)
+    if "SQ_LDS_BANK_CONFLICT" in c:
+        out["lds_bank_conflict_share"] = round(c["SQ_LDS_BANK_CONFLICT"] / (cycles * 256), 3)
+    if "SQ_INSTS_LDS_LOAD_BANDWIDTH" in c and "SQ_INSTS_LDS_STORE_BANDWIDTH" in c:
+        lds_bytes = 64 * (c["SQ_INSTS_LDS_LOAD_BANDWIDTH"] + c["SQ_INSTS_LDS_STORE_BANDWIDTH"])
+        out["lds_bytes"] = lds_bytes
+        out["lds_bw_frac"] = round(lds_bytes / sec / LDS_PEAK, 3)
+    return out
+
+
+def cpu_protocol(dev) -> dict:
+    """The FP64 oracle's per-frame forward and forward+backward times on this
+    host, next to the GPU's plain per-frame path on the same frames: the
+    128x128 frame of 2k Gaussians in full (all threads and one thread), one
+    full 960x540 frame of 100k Gaussians, the first two frames of the
+    benchmark clip in full, and the first two frames of the 1920x1080 clip of
+    500k Gaussians on a stated pixel sample (extrapolated by pixel count)."""
     import torch
     import gv_synth
-    from paper_2501_04782_amd import camera, raster
-    w = gv_synth.make_workload(name, seed=0, targets=True)
-    F, N = w["frames"], w["n"]
-    scene = raster.Scene.from_synth(w["scene"], dev)
-    cam = raster.Camera.of(w["camera"])
-    poses = torch.from_numpy(w["poses"]).to(dev)
-    times = torch.from_numpy(w["times"]).to(dev)
-    targets = torch.from_numpy(w["targets"]).to(dev)
-    cap = raster.estimate_capacity(scene, cam, poses, times, margin=1.3)
-    ws = raster.Workspace(cam, N, F, cap, device=dev)
-    info = dict(workload=name, frames=F, gaussians=N, width=cam.width, height=cam.height)
-    if name == ODE_WORKLOAD:
-        gt = raster.render_batch(scene, cam, poses, times, ws, forward=True, backward=False)
-        targets = gt["images"].clone()
-        theta = torch.from_numpy(gv_synth.init_mlp_theta(np.random.default_rng(7)).astype(np.float32)).to(dev)
-        graph = camera.FitGraph(scene, cam, theta, poses[0].clone(), F, 4, times, ws, targets=targets)
-        info["step"] = "camera ODE forward (RK4, 4 substeps) -> batched fwd+bwd -> ODE adjoint, one graph"
-    else:
-        graph = raster.BatchGraph(scene, cam, poses, times, ws, targets=targets)
-        info["step"] = "batched fwd+bwd with fused L2, one graph"
-    graph.launch()
-    torch.cuda.synchronize()
-    st = ws.status()
-    if st["overflow"]:
-        raise RuntimeError(f"{name}: intersection capacity overflow")
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        graph.launch()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    info.update(ms_per_step=round(1e3 * dt, 3), frames_per_s=round(F / dt, 1),
-                intersections_per_frame=int(st["intersections"] / F))
-    if name == ODE_WORKLOAD:
-        ows = camera.OdeWorkspace(F, 4, device=dev)
-        th = torch.from_numpy(gv_synth.init_mlp_theta(np.random.default_rng(7)).astype(np.float32)).to(dev)
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        p = camera.camera_ode_fwd(th, poses[0].clone(), F, 4, ows)
+    import oracle
+    from paper_2501_04782_amd import raster
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    out = dict(host=host_info(), threads=threads, configs=[])
+
+    def gpu_per_frame(w, frames):
+        scene = raster.Scene.from_synth(w["scene"], dev)
+        cam = raster.Camera.of(w["camera"])
+        poses = torch.from_numpy(np.ascontiguousarray(w["poses"], np.float32)).to(dev)
+        times = [float(x) for x in w["times"]]
+        F, H, W = w["frames"], cam.height, cam.width
+        ws1 = raster.Workspace(cam, scene.n, 1, 0, device=dev)
+        kmax = max(int(raster.project_fwd(scene, cam, poses[f].contiguous(), times[f], ws1)[1].sum().item())
+                   for f in frames)
+        ws = raster.Workspace(cam, scene.n, 1, int(kmax * 1.25) + 4096, device=dev)
+        tg = torch.rand(3, H, W, device=dev)
+        img = torch.empty(3, H, W, device=dev)
+        grads = raster.grad_buffers(scene)
+
+        def step(f):
+            raster.render_fwd(scene, cam, poses[f].contiguous(), times[f], ws, image=img)
+            raster.render_bwd(scene, cam, poses[f].contiguous(), times[f], ws, img, target=tg,
+                              loss_scale=2.0 / (3 * H * W), grads=grads)
+        for f in frames:
+            step(f)
         torch.cuda.synchronize()
-        e[0].record()
-        p = camera.camera_ode_fwd(th, poses[0].clone(), F, 4, ows)
-        e[1].record()
-        camera.camera_ode_bwd(th, poses[0].clone(), F, 4, torch.ones_like(p), ows)
-        e[2].record()
+        reps = 5
+        t = time.perf_counter()
+        for _ in range(reps):
+            for f in frames:
+                step(f)
         torch.cuda.synchronize()
-        info.update(ode_fwd_ms=round(e[0].elapsed_time(e[1]), 4), ode_bwd_ms=round(e[1].elapsed_time(e[2]), 4))
-    del graph, ws
-    torch.cuda.empty_cache()
-    return info
+        return (time.perf_counter() - t) / (reps * len(frames))
+
+    def oracle_frame_times(w, f, nthreads, npx=None, seed=0):
+        H, W = w["camera"].height, w["camera"].width
+        P = H * W
+        rng = np.random.default_rng(seed)
+        pix = None if npx is None else np.sort(rng.choice(P, npx, replace=False))
+        n = P if npx is None else npx
+        dl = rng.normal(0, 1, (n, 3)) * (2.0 / (3.0 * P))
+        pose = w["poses"][f].astype(np.float64)
+        t0 = time.perf_counter()
+        oracle.render_frame(w["scene"], w["camera"], pose, float(w["times"][f]), pixels=pix, threads=nthreads)
+        t1 = time.perf_counter()
+        oracle.render_frame(w["scene"], w["camera"], pose, float(w["times"][f]), pixels=pix, dL_dC=dl,
+                            threads=nthreads)
+        t2 = time.perf_counter()
+        scale = P / n
+        return (t1 - t0) * scale, (t2 - t1) * scale
+
+    plan = [("frame128_n2k", [0], None, [threads, 1]), ("frame540p_n100k", [0], None, [threads]),
+            ("clip540p_f50_n200k", [0, 1], None, [threads]), ("clip1080p_f32_n500k_bf16", [0, 1], 20736, [threads])]
+    for name, frames, npx, thread_list in plan:
+        w = gv_synth.make_workload(name, seed=0, targets=False)
+        gpu_s = gpu_per_frame(w, frames)
+        for nt in thread_list:
+            fw, fb = [], []
+            for f in frames:
+                a, b = oracle_frame_times(w, f, nt, npx)
+                fw.append(a)
+                fb.append(b)
+                log(f"[cpu protocol] {name} frame {f} threads {nt}: fwd {a:.2f} s, fwd+bwd {b:.2f} s")
+            rec = dict(workload=name, frames=frames, threads=nt, cpu_fwd_s_per_frame=round(float(np.mean(fw)), 4),
+                       cpu_fwd_bwd_s_per_frame=round(float(np.mean(fb)), 4),
+                       gpu_per_frame_fwd_bwd_ms=round(1e3 * gpu_s, 4),
+                       gpu_over_cpu=round(float(np.mean(fb)) / gpu_s, 1))
+            if npx is not None:
+                rec["sample"] = (f"{npx} random pixels per frame, times scaled by pixel count "
+                                 f"({w['camera'].width * w['camera'].height} per frame)")
+            out["configs"].append(rec)
+    return out
 
 
 def micro_benchmarks(scene_np, targets, dev):
@@ -184,6 +255,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary measurements (ODE fitting step, 1080p bf16 clip, dynamics, SH, "
                          "Adan, pyramid, visibility)")
+    ap.add_argument("--cpu-protocol", action="store_true",
+                    help="only time the FP64 oracle per frame on the host (four workloads, see cpu_protocol) next "
+                         "to the GPU's per-frame path, print one JSON line and exit (several minutes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration) and exit")
     args = ap.parse_args()
@@ -216,6 +290,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "reps": 3}))
+        return
+
+    if args.cpu_protocol:
+        print(json.dumps(cpu_protocol(dev)), flush=True)
         return
 
     log(f"[bench] building inputs: {args.workload}")
@@ -280,6 +358,10 @@ def main():
         torch.cuda.synchronize()
         ode_info = dict(fwd_ms=round(e0.elapsed_time(e1), 4), bwd_ms=round(e1.elapsed_time(e2), 4),
                         substeps=ode_substeps, mlp_evals=4 * ode_substeps * (F - 1))
+        te = camera.pose_error(p, poses)
+        ode_info["trajectory_error"] = dict(translation_rmse=round(te["translation_rmse"], 6),
+                                            mean_angle_rad=round(te["mean_angle"], 6),
+                                            of="ODE poses at the initial theta vs the ground-truth pose table")
         log(f"[bench] camera ODE: {ode_info}")
     else:
         graph = raster.BatchGraph(scene, cam, poses, times, ws, targets=targets)
@@ -344,55 +426,83 @@ def main():
                          batched_speedup=round(fps / pf_fps, 3))
         log(f"[bench] per-frame path: {pf_fps:.1f} frames/s (batched x{fps / pf_fps:.2f})")
 
-    # CPU baseline: the FP64 oracle (fwd + bwd) on a bounded pixel sample of frame 0
+    # CPU baseline: the FP64 oracle (fwd + bwd) on a bounded pixel sample
+    # spread over five frames of the clip.  Its per-pixel contributor counts
+    # also give the number of contributing (pixel, Gaussian) pairs of the
+    # step, which the compositing kernels' operation counts are priced on.
     cpu = None
     mean_contrib = None
     if not args.no_cpu_baseline:
         import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        host = host_info()
+        cpu_frames = sorted({0, F // 4, F // 2, (3 * F) // 4, F - 1})
         rng = np.random.default_rng(1)
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 
         def run(npx):
-            pix = np.sort(rng.choice(P, npx, replace=False))
-            dl = rng.normal(0, 1, (npx, 3)) * (2.0 / (3.0 * P * F))
-            t = time.perf_counter()
-            r = oracle.render_frame(w["scene"], w["camera"], w["poses"][0].astype(np.float64), 0.0, pixels=pix,
-                                    dL_dC=dl, threads=cores)
-            return time.perf_counter() - t, r
+            t_all, nc = 0.0, []
+            for f in cpu_frames:
+                pix = np.sort(rng.choice(P, npx, replace=False))
+                dl = rng.normal(0, 1, (npx, 3)) * (2.0 / (3.0 * P * F))
+                t = time.perf_counter()
+                r = oracle.render_frame(w["scene"], w["camera"], w["poses"][f].astype(np.float64),
+                                        float(w["times"][f]), pixels=pix, dL_dC=dl, threads=threads)
+                t_all += time.perf_counter() - t
+                nc.append(r["n_contrib"])
+            return t_all, np.concatenate(nc)
 
-        log("[bench] CPU oracle pilot")
-        t_pilot, _ = run(1024)
-        npx = int(min(P, max(1024, 1024 * args.cpu_seconds / max(t_pilot, 1e-3))))
-        log(f"[bench] CPU oracle sample: {npx} pixels (pilot {t_pilot:.2f} s)")
-        t_cpu, r = run(npx)
-        mean_contrib = float(np.mean(r["n_contrib"]))
-        cpu_fps = npx / (t_cpu * P)
-        cpu = dict(value=cpu_fps, unit="frames/s", cores=cores, kind="oracle",
-                   sample=f"{npx} random pixels of frame 0 (of {P}), forward+backward incl. projection and "
-                          f"depth sort of all {N} Gaussians, {t_cpu:.1f} s; scaled by pixel count")
-        log(f"[bench] CPU oracle: {cpu_fps:.3e} frames/s on {cores} threads")
+        log("[bench] CPU oracle pilots")
+        # two pilot sizes separate the per-frame fixed cost (projection and
+        # depth sort of all Gaussians) from the per-pixel cost
+        t_a, _ = run(256)
+        t_b, _ = run(1024)
+        per_px = max((t_b - t_a) / 768, 1e-9)
+        fixed = max(t_a - 256 * per_px, 0.0)
+        npx = int(min(P, max(1024, (args.cpu_seconds - fixed) / per_px)))
+        log(f"[bench] CPU oracle sample: {npx} pixels in each of frames {cpu_frames} "
+            f"(pilots {t_a:.2f} s / {t_b:.2f} s)")
+        t_cpu, nc = run(npx)
+        mean_contrib = float(np.mean(nc))
+        cpu_fps = len(cpu_frames) * npx / (t_cpu * P)
+        cpu = dict(value=cpu_fps, unit="frames/s", cores=threads, kind="oracle",
+                   sample=f"{npx} random pixels in each of frames {cpu_frames} (of {P} per frame), forward+backward "
+                          f"incl. projection and depth sort of all {N} Gaussians per frame, {t_cpu:.1f} s; "
+                          "scaled by pixel count", host=host)
+        log(f"[bench] CPU oracle: {cpu_fps:.3e} frames/s on {threads} threads ({host})")
 
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel, priced on the hot-path table's
+    # per-unit figures: bytes per pixel and per intersection, operations per
+    # contributing pair (E = the oracle's mean contributors per pixel x P x F)
     dom = max(stage_ms, key=stage_ms.get)
     t_dom = stage_ms[dom] / 1e3
     from paper_2501_04782_amd import rocprof_summary
     key = rocprof_summary.stage_key(dom, tuning)
     traffic = rocprof_summary.read_traffic(
         os.path.join(ROOT, "profiles", f"{dom}_{args.workload}_{key}_hbm_traffic.txt"), dom, args.workload, key)
-    bytes_dom = stage_bytes(dom, N, V, K, P, F)
+    counters = rocprof_summary.read_counters(
+        os.path.join(ROOT, "profiles", f"{dom}_{args.workload}_{key}_sq.txt"), dom, args.workload, key)
+    bytes_dom = stage_bytes(dom, N, V, K, P, F, param_bytes)
     hbm_ach = bytes_dom / t_dom if bytes_dom else 0.0
     roof = dict(bound="hbm", achieved=round(hbm_ach / 1e9, 2), peak=HBM_PEAK / 1e9, unit="GB/s",
                 frac=round(hbm_ach / HBM_PEAK, 4), traffic=traffic, kernel=dom,
                 avg_ms=round(stage_ms[dom], 4), algorithmic_bytes=int(bytes_dom))
     if mean_contrib is not None and dom in ("composite_fwd", "composite_bwd"):
         pairs = mean_contrib * P * F
-        flops = pairs * (FLOPS_FWD_PER_PAIR if dom == "composite_fwd" else FLOPS_BWD_PER_PAIR)
-        alu_ach = flops / t_dom
+        per_pair = FLOPS_FWD_PER_PAIR if dom == "composite_fwd" else FLOPS_BWD_PER_PAIR
+        alu_ach = pairs * per_pair / t_dom
+        alu = dict(alu_frac=round(alu_ach / ALU_PEAK, 4), alu_frac_nonpacked=round(alu_ach / ALU_PEAK_NONPACKED, 4),
+                   alu_peak_nonpacked=round(ALU_PEAK_NONPACKED / 1e12, 2), flops_per_pair=per_pair,
+                   contributing_pairs=int(pairs))
         if alu_ach / ALU_PEAK > hbm_ach / HBM_PEAK:
             roof = dict(bound="alu", achieved=round(alu_ach / 1e12, 3), peak=round(ALU_PEAK / 1e12, 2),
                         unit="TFLOP/s", frac=round(alu_ach / ALU_PEAK, 4), traffic=traffic, kernel=dom,
-                        avg_ms=round(stage_ms[dom], 4), contributing_pairs=int(pairs),
+                        avg_ms=round(stage_ms[dom], 4), algorithmic_bytes=int(bytes_dom),
                         hbm_frac=round(hbm_ach / HBM_PEAK, 4))
+        roof.update(alu)
+        if counters is not None:
+            roof["profile"] = counters_summary(counters, pairs)
+    elif counters is not None:
+        roof["profile"] = counters_summary(counters, None)
     b_alg = algorithmic_bytes(N, V, K, P, F, param_bytes, grad_bytes)
 
     extras = None

@@ -11,8 +11,14 @@ Two summaries are produced:
   sources and the tuning it was taken with, so that a reader can tell when
   the figures no longer describe the code.
 
+* ``kernel-counters``: the SQ counters per dispatch of one kernel from one or
+  more ``--pmc`` runs and its average duration from a kernel trace, with the
+  same source hash and tuning key, for bench.py to read back.
+
 Usage (from the repository root):
   python3 -m paper_2501_04782_amd.rocprof_summary stats DB --title T --command C
+  python3 -m paper_2501_04782_amd.rocprof_summary kernel-counters --kernel K DB [DB ...] --trace T \
+      --stage S --workload W --tuning KEY --command C
   python3 -m paper_2501_04782_amd.rocprof_summary traffic --kernel K --fetch-db A --write-db B \
       --copy-fetch-db C --copy-write-db D --copy-bytes N --stage S --workload W --tuning b,c,m --command C
 """
@@ -154,6 +160,60 @@ def read_traffic(path: str, stage: str, workload: str, tuning: str):
         return None
 
 
+def read_counters(path: str, stage: str, workload: str, tuning: str):
+    """{counter: value per dispatch, avg_ms} from a kernel-counters summary, or
+    None when absent or taken from other sources, tuning or workload."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ": " in line and not line.startswith("|"):
+                k, v = line.strip().split(": ", 1)
+                kv[k] = v
+    try:
+        if not (kv["stage"] == stage and kv["workload"] == workload and kv["tuning"] == tuning
+                and kv["source_sha256"] == source_hash(stage)):
+            return None
+        out = {k: float(v) for k, v in kv.items() if k.startswith("SQ_")}
+        out["avg_ms"] = float(kv["avg_ms"])
+        return out
+    except (KeyError, ValueError):
+        return None
+
+
+def cmd_kernel_counters(a):
+    merged = {}
+    for db in a.dbs:
+        for k, d in counters_per_kernel(db).items():
+            if a.kernel in k:
+                merged.update(d)
+    durs = [v for k, vs in kernel_durations(a.trace).items() if a.kernel in k for v in vs]
+    if not merged or not durs:
+        raise SystemExit(f"no dispatches of {a.kernel}")
+    ms = sum(durs) / len(durs) / 1e6
+    print(f"# SQ counters of `{a.kernel}` ({a.stage}), workload {a.workload}\n")
+    print("Commands (from the repository root on the GPU box, after `cd /tmp && export TMPDIR=/tmp`, "
+          "R = repository root):\n")
+    print("```\n" + a.command + "\n```\n")
+    print("| counter | per dispatch |")
+    print("|---|---|")
+    for c in sorted(merged):
+        print(f"| {c} | {merged[c]:.6g} |")
+    print(f"| kernel time (ms, trace average over {len(durs)} dispatches) | {ms:.4f} |")
+    print()
+    print("Machine-readable (read by bench.py; ignored when the source hash or tuning differ):\n")
+    print("```")
+    print(f"stage: {a.stage}")
+    print(f"workload: {a.workload}")
+    print(f"tuning: {a.tuning}")
+    print(f"source_sha256: {source_hash(a.stage)}")
+    print(f"avg_ms: {ms:.6f}")
+    for c in sorted(merged):
+        print(f"{c}: {merged[c]:.6e}")
+    print("```")
+
+
 def counters_per_kernel(db: str):
     """{kernel: {counter: mean per dispatch}} of a --pmc run."""
     con = sqlite3.connect(db)
@@ -225,8 +285,17 @@ def main():
     c.add_argument("--trace", help="kernel-trace results db of the same workload (durations)")
     c.add_argument("--title", required=True)
     c.add_argument("--command", required=True)
+    k = sub.add_parser("kernel-counters")
+    k.add_argument("dbs", nargs="+")
+    k.add_argument("--kernel", required=True, help="substring of the kernel name")
+    k.add_argument("--trace", required=True, help="kernel-trace results db of the same command")
+    k.add_argument("--stage", required=True, choices=sorted(STAGE_SOURCES))
+    k.add_argument("--workload", required=True)
+    k.add_argument("--tuning", required=True)
+    k.add_argument("--command", required=True)
     a = ap.parse_args()
-    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters,
+     "kernel-counters": cmd_kernel_counters}[a.cmd](a)
 
 
 if __name__ == "__main__":
