@@ -13,29 +13,34 @@
 namespace gv {
 
 // One staged entry, 48 bytes.  The conic is stored pre-multiplied by
-// K_EXP = -log2(e)/2, so the per-pixel exponent q' = K_EXP q is the quadratic
-// form itself and the falloff exp(-q/2) is one exp2.  `thr` folds the 3-sigma
-// cut (q <= 9) and the opacity floor (o exp(-q/2) >= 1/255) into a single
+// K_EXP = -log2(e)/2 and the exponent carries log2 of the opacity, so the
+// per-pixel exponent q' = K_EXP q + log2 o is the quadratic form plus a
+// constant and the unclamped alpha o exp(-q/2) is one exp2.  `thr` folds the
+// 3-sigma cut (q <= 9) and the opacity floor (alpha >= 1/255) into a single
 // test q' >= thr; the inert padding entry has thr = +inf.
 struct Staged {
     float4 p0;  // (u, v) in tile-local pixel-centre coordinates, K a, K 2b
-    float4 p1;  // K c, opacity, r, g
-    float4 p2;  // b, thr, Gaussian index (bits), unused
+    float4 p1;  // K c, log2 o, r, g
+    float4 p2;  // b, thr, Gaussian index (bits), opacity
 };
 constexpr uint32_t STAGED_BYTES = sizeof(Staged);
 static_assert(STAGED_BYTES == 48, "three 16-byte LDS reads per entry");
 constexpr float INV_K_EXP = 1.0f / K_EXP;
 
-// Scaled footprint q' = K_EXP d^T A d with d = pixel - centre, and the entry's
-// threshold.  Shared by every compositing kernel, forward and adjoint, so
-// that all of them re-derive the same values and decisions.
+// Exponent q' = K_EXP d^T A d + log2 o with d = pixel - centre (2^q' is the
+// unclamped alpha), and the entry's threshold.  Shared by every compositing
+// kernel, forward and adjoint, so that all of them re-derive the same values
+// and decisions.
 __device__ __forceinline__ float footprint_q(float dx, float dy, const float4& p0, const float4& p1) {
-    return __builtin_fmaf(p1.x * dy, dy, dx * __builtin_fmaf(p0.z, dx, p0.w * dy));
+    return __builtin_fmaf(p1.x * dy, dy, __builtin_fmaf(dx, __builtin_fmaf(p0.z, dx, p0.w * dy), p1.y));
 }
 
-__device__ __forceinline__ float entry_threshold(float o) {
-    // -log2(255 o) is where o 2^q' falls to 1/255; +inf for o = 0
-    return fmaxf(Q_MAX * K_EXP, -__builtin_amdgcn_logf(255.0f * o));
+// log2 of the opacity as staged (-inf for o = 0, whose entries never pass)
+__device__ __forceinline__ float log2_opacity(float o) { return __builtin_amdgcn_logf(o); }
+
+__device__ __forceinline__ float entry_threshold(float lo) {
+    // q <= 9 is q' >= 9 K_EXP + log2 o; alpha >= 1/255 is q' >= -log2 255
+    return fmaxf(__builtin_fmaf(Q_MAX, K_EXP, lo), -7.99435343685885793773f);
 }
 
 // Stage entry `gid` of the tile: gather its record and colour and move the
@@ -54,9 +59,10 @@ __device__ __forceinline__ void stage_entry(const Args& a, int f, uint32_t gid, 
     const ColorOp co = a.col4[static_cast<int64_t>(f) * a.col_stride + gid];
     const float lu = static_cast<float>(r.u - ox);
     const float lv = static_cast<float>(r.v - oy);
+    const float lo = log2_opacity(co.o);
     st.p0 = make_float4(lu, lv, K_EXP * r.a, K_EXP * (2.0f * r.b));
-    st.p1 = make_float4(K_EXP * r.c, co.o, co.r, co.g);
-    st.p2 = make_float4(co.b, entry_threshold(co.o), __uint_as_float(gid), 0.f);
+    st.p1 = make_float4(K_EXP * r.c, lo, co.r, co.g);
+    st.p2 = make_float4(co.b, entry_threshold(lo), __uint_as_float(gid), co.o);
     conic = make_float3(r.a, r.b, r.c);
 }
 
@@ -236,7 +242,7 @@ __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
                 const float dx = fx - p0.x, dy = fy - p0.y;
                 const float q = footprint_q(dx, dy, p0, p1);
                 const bool hit = !done && q >= P2[r].y;
-                const float al = fminf(ALPHA_MAX, p1.y * __builtin_amdgcn_exp2f(q));
+                const float al = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(q));
                 const float tn = __builtin_fmaf(-al, T, T);
                 const bool take = hit && tn >= T_MIN;  // else stop before this entry
                 done = done || (hit != take);
@@ -502,8 +508,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
                 const float dx = fx - p0.x, dy = fy - p0.y;
                 const float q = footprint_q(dx, dy, p0, p1);
                 const bool on = (static_cast<int>(J[r]) < lim) & (q >= P2[r].y);
-                const float G = __builtin_amdgcn_exp2f(q);
-                const float raw = p1.y * G;
+                const float raw = __builtin_amdgcn_exp2f(q);
                 const float al = on ? fminf(ALPHA_MAX, raw) : 0.0f;
                 const float inv = __builtin_amdgcn_rcpf(1.0f - al);
                 const float ai = al * inv;
@@ -561,7 +566,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
                 v[k] = x;
             }
             const Staged st = sh[tid];
-            finish_partials(v, st.p0.z * INV_K_EXP, 0.5f * st.p0.w * INV_K_EXP, st.p1.x * INV_K_EXP, st.p1.y);
+            finish_partials(v, st.p0.z * INV_K_EXP, 0.5f * st.p0.w * INV_K_EXP, st.p1.x * INV_K_EXP, st.p2.w);
             if (slot < a.k_cap) {
                 store_partials(a.part, slot, v);
             }
@@ -639,8 +644,8 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x, int lane) {
 // compacted kernels read staged entries at lane-dependent indices, so they are
 // staged structure-of-arrays (4-byte stride: lanes reading different entries
 // fall into different banks): sv[0..SV - 1][j] = local u, local v, K a, K 2b,
-// K c, opacity, r, g, b, threshold (as in Staged).
-constexpr int SV = 10;
+// K c, log2 opacity, r, g, b, threshold (as in Staged), opacity.
+constexpr int SV = 11;
 
 template <int B>
 __device__ __forceinline__ void stage_batch_masks(const Args& a, int f, uint32_t b0, uint32_t nb, double ox, double oy,
@@ -654,7 +659,7 @@ __device__ __forceinline__ void stage_batch_masks(const Args& a, int f, uint32_t
             stage_entry(a, f, a.sgid[b0 + t], ox, oy, st, cn);
             sv[0][t] = st.p0.x; sv[1][t] = st.p0.y; sv[2][t] = st.p0.z; sv[3][t] = st.p0.w;
             sv[4][t] = st.p1.x; sv[5][t] = st.p1.y; sv[6][t] = st.p1.z; sv[7][t] = st.p1.w;
-            sv[8][t] = st.p2.x; sv[9][t] = st.p2.y;
+            sv[8][t] = st.p2.x; sv[9][t] = st.p2.y; sv[10][t] = st.p2.w;
             if (quadrant_mask(st, cn, xlim, ylim)) coverage_masks(st.p0.x, st.p0.y, cn.x, cn.y, cn.z, xlim, ylim, qm);
         }
         for (int q = 0; q < 4; ++q) qmask[q][t] = qm[q];
@@ -724,7 +729,7 @@ __global__ __launch_bounds__(WG) void k_composite_fwd_c(Args a) {
                 const float dx = fx - p0.x, dy = fy - p0.y;
                 const float q = footprint_q(dx, dy, p0, p1);
                 if (!(q >= sv[9][j])) continue;
-                const float al = fminf(ALPHA_MAX, p1.y * __builtin_amdgcn_exp2f(q));
+                const float al = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(q));
                 const float tn = __builtin_fmaf(-al, T, T);
                 if (tn < T_MIN) {
                     done = true;
@@ -860,7 +865,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
                 const float dx = fx - p0.x, dy = fy - p0.y;
                 const float q = footprint_q(dx, dy, p0, p1);
                 if (!(q >= sv[9][j])) continue;
-                const float raw = p1.y * __builtin_amdgcn_exp2f(q);
+                const float raw = __builtin_amdgcn_exp2f(q);
                 const float al = fminf(ALPHA_MAX, raw);
                 const float inv = 1.0f / (1.0f - al);
                 const float Tj = T * inv;
@@ -892,7 +897,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
             float v[9];
             for (int k = 0; k < 9; ++k) v[k] = (acc[0][k][tid] + acc[1][k][tid]) + (acc[2][k][tid] + acc[3][k][tid]);
             finish_partials(v, sv[2][tid] * INV_K_EXP, 0.5f * sv[3][tid] * INV_K_EXP, sv[4][tid] * INV_K_EXP,
-                            sv[5][tid]);
+                            sv[10][tid]);
             const uint32_t slot = a.sslot[b0 + tid];
             if (slot < a.k_cap) {
                 store_partials(a.part, slot, v);
@@ -1011,7 +1016,7 @@ __global__ __launch_bounds__(WG) void k_composite_fwd_sb(Args a) {
                 const float dx = fx - p0.x, dy = fy - p0.y;
                 const float q = footprint_q(dx, dy, p0, p1);
                 const bool hit = !done && q >= P2[r].y;
-                const float al = fminf(ALPHA_MAX, p1.y * __builtin_amdgcn_exp2f(q));
+                const float al = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(q));
                 const float tn = __builtin_fmaf(-al, T, T);
                 const bool take = hit && tn >= T_MIN;  // else stop before this entry
                 done = done || (hit != take);

@@ -176,7 +176,8 @@ def test_empty_and_single_gaussian():
 @pytest.mark.parametrize("compact,batch,sort_cap", [(0, 256, 4096), (0, 128, 2048), (0, 64, 1024),
                                                     (4, 256, 4096), (4, 128, 2048), (4, 64, 1024),
                                                     (3, 256, 4096), (3, 128, 2048), (3, 64, 1024),
-                                                    (1, 128, 2048), (2, 256, 2048), (6, 64, 1024)])
+                                                    (1, 128, 2048), (2, 256, 2048), (6, 64, 1024),
+                                                    (4, 64, 512)])
 def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
     """Batched path on a reduced clip (moving camera, several frames) under
     every setting the autotuner can choose."""
@@ -191,9 +192,10 @@ def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
 
 # (Gaussians, sort capacity, regime of the largest bucket): chunked LDS sort +
 # global merges; two runs merged in LDS; one LDS pass at the largest capacity
-@pytest.mark.parametrize("n,cap,regime", [(5000, 1024, "global"), (1600, 1024, "two runs"), (3000, 4096, "one pass"),
-                                          (1600, 512, "global")])
-def test_long_tile_buckets(n, cap, regime):
+@pytest.mark.parametrize("n,cap,regime,compact", [(5000, 1024, "global", 4), (1600, 1024, "two runs", 4),
+                                                  (3000, 4096, "one pass", 4), (1600, 512, "global", 4),
+                                                  (5000, 1024, "global", 6)])
+def test_long_tile_buckets(n, cap, regime, compact):
     """Many large Gaussians over a small image: buckets beyond the LDS sort
     capacity, between one and two capacities, and within the largest one."""
     w = small_workload(14, 48, 32, n, 1, z=(2.0, 6.0), ls=(-1.2, 0.3))
@@ -202,9 +204,9 @@ def test_long_tile_buckets(n, cap, regime):
     big = sizes.max()
     assert {"global": big > 2 * cap, "two runs": cap < big <= 2 * cap, "one pass": 2048 < big <= cap}[regime], big
     old = raster.get_tuning()
-    raster.set_tuning(old["batch"], cap, old["compact"], old["bwd_batch"])
+    raster.set_tuning(old["batch"], cap, compact, old["bwd_batch"])
     try:
-        check_clip_against_oracle(w, f"long buckets n={n} cap={cap}")
+        check_clip_against_oracle(w, f"long buckets n={n} cap={cap} compact={compact}")
     finally:
         raster.set_tuning(old["batch"], old["sort_cap"], old["compact"], old["bwd_batch"])
 
