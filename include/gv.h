@@ -303,11 +303,18 @@ gv_status gv_fit_graph_create(const gv_scene *scene, const gv_camera *cam, const
                               gv_grads *grads, float *dL_dposes, float *dtheta, float *dz0, void *ws, size_t ws_bytes,
                               gv_graph **out);
 
-/* Tunables: read/set the process-wide table; gv_autotune times candidate
- * settings on the given batch problem (it runs gv_render_batch several times
- * on the caller's buffers, overwriting its outputs, and synchronises) and
- * installs the fastest; the choice is also written as one JSON line to
- * cache_path when cache_path is not NULL. */
+/* Tunables: read/set the process-wide table.  gv_autotune installs the
+ * fastest setting for the given batch problem.  With cache_path, it first
+ * looks there for a line with this problem's key (device architecture,
+ * width, height, N to a quarter octave, frames, parameter dtype, dynamics,
+ * SH degree) and installs that line's setting without timing anything;
+ * otherwise it times the options of each stage (forward kernel x LDS batch,
+ * backward LDS batch, sort capacity: nine runs per round, three timed rounds
+ * after a warm-up round, each stage keeping its own fastest option since no
+ * stage's output depends on another's kernel) by running gv_render_batch on
+ * the caller's buffers (overwriting its outputs; synchronises) and, with
+ * cache_path, appends the choice as one JSON line.  `chosen` (host, or NULL)
+ * receives the installed setting. */
 gv_status gv_get_tuning(gv_tuning *out);
 gv_status gv_set_tuning(const gv_tuning *t);
 gv_status gv_autotune(const gv_scene *scene, const gv_camera *cam, const float *poses, const float *times,

@@ -610,10 +610,82 @@ gv_status gv_set_tuning(const gv_tuning* t) {
     return GV_OK;
 }
 
+// Key of a tuning-cache line: the settings of one problem shape.
+struct TuneKey {
+    char arch[32];
+    int width, height, n_bucket, frames, dtype, dynamics, sh_degree;
+};
+
+static bool same_key(const TuneKey& a, const TuneKey& b) {
+    return strcmp(a.arch, b.arch) == 0 && a.width == b.width && a.height == b.height && a.n_bucket == b.n_bucket &&
+           a.frames == b.frames && a.dtype == b.dtype && a.dynamics == b.dynamics && a.sh_degree == b.sh_degree;
+}
+
+static const char* TUNE_LINE =
+    "{\"arch\": \"%31[^\"]\", \"width\": %d, \"height\": %d, \"n_bucket\": %d, \"frames\": %d, \"dtype\": %d, "
+    "\"dynamics\": %d, \"sh_degree\": %d, \"batch\": %d, \"bwd_batch\": %d, \"sort_cap\": %d, \"compact\": %d}";
+
+// The first line of the cache file with this key, if any.
+static bool cached_tuning(const char* path, const TuneKey& key, Tuning& out) {
+    FILE* fp = fopen(path, "r");
+    if (!fp) return false;
+    char line[512];
+    bool found = false;
+    while (!found && fgets(line, sizeof(line), fp)) {
+        TuneKey k{};
+        Tuning t = current_tuning();
+        if (sscanf(line, TUNE_LINE, k.arch, &k.width, &k.height, &k.n_bucket, &k.frames, &k.dtype, &k.dynamics,
+                   &k.sh_degree, &t.batch, &t.bwd_batch, &t.sort_cap, &t.compact) == 12 &&
+            same_key(k, key)) {
+            out = t;
+            found = true;
+        }
+    }
+    fclose(fp);
+    return found;
+}
+
+static bool tuning_valid(const Tuning& t) {
+    return batch_ok(t.batch) && batch_ok(t.bwd_batch) &&
+           (t.sort_cap == 512 || t.sort_cap == 1024 || t.sort_cap == 2048 || t.sort_cap == 4096) && t.compact >= 0 &&
+           t.compact <= 7;
+}
+
 gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* poses, const float* times,
                       int32_t frames, const float* targets, float* images, float* loss, gv_grads* grads,
                       float* dL_dposes, void* ws, size_t ws_bytes, const char* cache_path, gv_tuning* chosen) {
-    if (!targets || !images || !grads) return GV_ERR_INVALID_ARG;
+    if (!targets || !images || !grads || !scene_ok(scene) || !camera_ok(cam)) return GV_ERR_INVALID_ARG;
+    TuneKey key{};
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            const char* c = strchr(prop.gcnArchName, ':');  // drop feature suffixes (":sramecc+:xnack-")
+            const size_t len = c ? static_cast<size_t>(c - prop.gcnArchName) : strlen(prop.gcnArchName);
+            memcpy(key.arch, prop.gcnArchName, len < sizeof(key.arch) - 1 ? len : sizeof(key.arch) - 1);
+        }
+        if (!key.arch[0]) strcpy(key.arch, "unknown");
+        key.width = cam->width;
+        key.height = cam->height;
+        key.n_bucket = scene->n > 0 ? static_cast<int>(floor(4.0 * log2(static_cast<double>(scene->n)))) : -1;
+        key.frames = frames;
+        key.dtype = scene->dtype;
+        key.dynamics = (scene->mean_coeffs ? 1 : 0) | (scene->n_ctrl > 0 ? 2 : 0) |
+                       (scene->scale_coeffs || scene->quat_coeffs ? 4 : 0);
+        key.sh_degree = scene->sh_degree;
+    }
+    Tuning best = current_tuning();
+    if (cache_path && cached_tuning(cache_path, key, best) && tuning_valid(best)) {
+        install_tuning(best);
+        if (chosen) {
+            memset(chosen, 0, sizeof(*chosen));
+            chosen->batch = best.batch;
+            chosen->sort_cap = best.sort_cap;
+            chosen->compact = best.compact;
+            chosen->bwd_batch = best.bwd_batch;
+        }
+        return GV_OK;
+    }
     const uint32_t flags = GV_FWD | GV_BWD | GV_LOSS_L2;
     hipStream_t st;
     GV_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -624,28 +696,31 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
     for (; made <= GV_STAGES && he == hipSuccess; ++made) he = hipEventCreate(&tm.ev[made]);
     const Tuning saved = current_tuning();
     gv_status result = (he == hipSuccess) ? GV_OK : hip_status(he);
-    // The stages are independent (the forward's outputs do not depend on its
-    // kernel variant), so every stage keeps its own fastest setting: eight
-    // runs cover the forward kernel (sub-block / quadrant / compacted, at
-    // two or three batch sizes each), the quadrant backward (batch) and each
-    // sort capacity at least twice.  The compacted backward (LDS atomics per
-    // lane) measured ten times slower than the quadrant backward on every
-    // clip tried, so it is left to explicit gv_set_tuning.
-    struct Cand { int batch, compact, cap; };
-    constexpr int NC = 8;
-    const Cand cands[NC] = {{64, 0, 1024}, {128, 0, 2048}, {256, 0, 4096}, {128, 4, 4096},
-                            {256, 4, 1024}, {64, 1, 2048},  {128, 1, 1024}, {256, 1, 2048}};
-    float fwd_ms[NC], bwd_ms[NC], sort_ms[NC], total_ms[NC];
-    for (int c = 0; c < NC; ++c) fwd_ms[c] = bwd_ms[c] = sort_ms[c] = total_ms[c] = 0.f;
-    // Round-robin over the candidates, so that clock or cache drift during
-    // the measurement affects all of them alike; round 0 warms up.
+    // The stages are independent (no stage's output depends on another
+    // stage's kernel variant), so every stage keeps its own fastest option,
+    // timed on every run that used it.  Options: forward kernel (4x4-block,
+    // quadrant or compacted) x LDS batch (64, 128, 256); backward batch (64,
+    // 128, 256) of the quadrant adjoint; sort capacity (512 ... 4096).  Run c
+    // takes forward option c, backward option c mod 3 and sort option c mod 4,
+    // so nine runs per round try every option of every stage.  The compacted
+    // backward (LDS atomics per lane) measured ten times slower than the
+    // quadrant backward on every clip tried and is left to gv_set_tuning.
+    constexpr int NF = 9, NB = 3, NS = 4;
+    const int f_kernel[3] = {0, 4, 1};
+    const int batches[3] = {64, 128, 256};
+    const int caps[NS] = {512, 1024, 2048, 4096};
+    float fwd_ms[NF] = {}, bwd_ms[NB] = {}, sort_ms[NS] = {};
+    int bwd_n[NB] = {}, sort_n[NS] = {};
+    // Round-robin over the runs, so that clock or cache drift during the
+    // measurement affects all options alike; round 0 warms up.
     constexpr int REPS = 3;
     for (int r = 0; r <= REPS && result == GV_OK; ++r) {
-        for (int c = 0; c < NC && result == GV_OK; ++c) {
+        for (int c = 0; c < NF && result == GV_OK; ++c) {
             Tuning t = saved;
-            t.batch = t.bwd_batch = cands[c].batch;
-            t.compact = cands[c].compact;
-            t.sort_cap = cands[c].cap;
+            t.compact = f_kernel[c / 3];
+            t.batch = batches[c % 3];
+            t.bwd_batch = batches[c % NB];
+            t.sort_cap = caps[c % NS];
             install_tuning(t);
             gv_status s = enqueue_batch(scene, cam, poses, times, frames, targets, nullptr, flags, images, loss,
                                         grads, dL_dposes, ws, ws_bytes, st, &tm);
@@ -660,24 +735,26 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
             if (r == 0) continue;
             float ms[GV_STAGES];
             for (int i = 0; i < GV_STAGES; ++i) hipEventElapsedTime(&ms[i], tm.ev[i], tm.ev[i + 1]);
-            fwd_ms[c] += ms[4] / REPS;
-            bwd_ms[c] += ms[6] / REPS;
-            sort_ms[c] += ms[3] / REPS;
-            for (int i = 0; i < GV_STAGES; ++i) total_ms[c] += ms[i] / REPS;
+            fwd_ms[c] += ms[4];
+            bwd_ms[c % NB] += ms[6];
+            bwd_n[c % NB] += 1;
+            sort_ms[c % NS] += ms[3];
+            sort_n[c % NS] += 1;
         }
     }
-    Tuning best = saved;
+    best = saved;
     if (result == GV_OK) {
         int bf = 0, bb = 0, bs = 0;
-        for (int c = 1; c < NC; ++c) {
+        for (int c = 1; c < NF; ++c)
             if (fwd_ms[c] < fwd_ms[bf]) bf = c;
-            if (bwd_ms[c] < bwd_ms[bb]) bb = c;
-            if (sort_ms[c] < sort_ms[bs]) bs = c;
-        }
-        best.batch = cands[bf].batch;
-        best.bwd_batch = cands[bb].batch;
-        best.compact = (cands[bf].compact & 5) | (cands[bb].compact & 2);
-        best.sort_cap = cands[bs].cap;
+        for (int c = 1; c < NB; ++c)
+            if (bwd_ms[c] / bwd_n[c] < bwd_ms[bb] / bwd_n[bb]) bb = c;
+        for (int c = 1; c < NS; ++c)
+            if (sort_ms[c] / sort_n[c] < sort_ms[bs] / sort_n[bs]) bs = c;
+        best.compact = f_kernel[bf / 3];
+        best.batch = batches[bf % 3];
+        best.bwd_batch = batches[bb];
+        best.sort_cap = caps[bs];
     }
     install_tuning(result == GV_OK ? best : saved);
     for (int i = 0; i < made && i <= GV_STAGES; ++i) hipEventDestroy(tm.ev[i]);
@@ -694,10 +771,11 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
         FILE* fp = fopen(cache_path, "a");
         if (fp) {
             fprintf(fp,
-                    "{\"arch\": \"gfx950\", \"width\": %d, \"height\": %d, \"n\": %lld, \"frames\": %d, "
-                    "\"dtype\": %d, \"batch\": %d, \"bwd_batch\": %d, \"sort_cap\": %d, \"compact\": %d}\n",
-                    cam->width, cam->height, static_cast<long long>(scene->n), frames, scene->dtype, best.batch,
-                    best.bwd_batch, best.sort_cap, best.compact);
+                    "{\"arch\": \"%s\", \"width\": %d, \"height\": %d, \"n_bucket\": %d, \"frames\": %d, "
+                    "\"dtype\": %d, \"dynamics\": %d, \"sh_degree\": %d, \"batch\": %d, \"bwd_batch\": %d, "
+                    "\"sort_cap\": %d, \"compact\": %d}\n",
+                    key.arch, key.width, key.height, key.n_bucket, key.frames, key.dtype, key.dynamics,
+                    key.sh_degree, best.batch, best.bwd_batch, best.sort_cap, best.compact);
             fclose(fp);
         }
     }

@@ -8,7 +8,9 @@
   a torch loss back-propagated through them against the oracle adjoint, and
   an undersized workspace that must raise;
 * the trajectory-error judge of the learned camera (gv_pose_error) against
-  the oracle's.
+  the oracle's;
+* the autotuner's cache: a tuned choice is written, read back for the same
+  problem key, and a hand-written line is installed as written.
 """
 import numpy as np
 import pytest
@@ -274,3 +276,41 @@ def test_pose_error_matches_oracle():
     assert j["angle"][3] == pytest.approx(np.pi, abs=3e-3)
     assert j["translation_rmse"] == pytest.approx(e["translation_rmse"], rel=1e-6)
     assert j["mean_angle"] == pytest.approx(e["mean_angle"], rel=1e-6)
+
+
+# ---------------------------------------------------------------- autotuner
+
+
+def test_autotune_cache_read_back(tmp_path):
+    """gv_autotune times the options and appends its choice to the cache; the
+    same problem is then served from the cache without timing, and a cache
+    line written by hand for the problem's key is installed as written."""
+    w = small_workload(74, 96, 64, 1500, 3, trajectory=True)
+    scene, cam, poses, times = device_inputs(w)
+    ws = workspace_for(scene, cam, poses, times)
+    targets = torch.rand(3, 3, 64, 96, device="cuda")
+    old = raster.get_tuning()
+    cache = tmp_path / "tune.jsonl"
+    try:
+        t1 = raster.autotune(scene, cam, poses, times, ws, targets, cache_path=str(cache))
+        lines = cache.read_text().splitlines()
+        assert len(lines) == 1 and raster.get_tuning() == t1
+        assert t1["batch"] in (64, 128, 256) and t1["bwd_batch"] in (64, 128, 256)
+        assert t1["sort_cap"] in (512, 1024, 2048, 4096) and t1["compact"] in (0, 1, 4)
+        t2 = raster.autotune(scene, cam, poses, times, ws, targets, cache_path=str(cache))
+        assert t2 == t1 and len(cache.read_text().splitlines()) == 1
+        # a hand-written line for the same key wins if it comes first
+        forced = lines[0]
+        for k, v in (("batch", 64), ("bwd_batch", 256), ("sort_cap", 2048), ("compact", 0)):
+            forced = forced.replace(f'"{k}": {t1[k]}', f'"{k}": {v}')
+        cache.write_text(forced + "\n" + lines[0] + "\n")
+        t3 = raster.autotune(scene, cam, poses, times, ws, targets, cache_path=str(cache))
+        assert t3 == dict(batch=64, sort_cap=2048, compact=0, bwd_batch=256), t3
+        # another problem (different frame count) is tuned anew and appended
+        ws2 = workspace_for(scene, cam, poses[:2].contiguous(), times[:2].contiguous())
+        raster.autotune(scene, cam, poses[:2].contiguous(), times[:2].contiguous(), ws2, targets[:2].contiguous(),
+                        cache_path=str(cache))
+        assert len(cache.read_text().splitlines()) == 3
+        say(f"[autotune] chose {t1}; cache lines {len(cache.read_text().splitlines())}")
+    finally:
+        raster.set_tuning(old["batch"], old["sort_cap"], old["compact"], old["bwd_batch"])
