@@ -117,6 +117,66 @@ def counters_summary(c: dict, pairs) -> dict:
     return out
 
 
+def quick_clip(name, dev, steps=3):
+    """Frames/s of one batched fwd+bwd step (one HIP graph) on another
+    workload, with the installed tuning; for the camera-ODE workload the step
+    is the fitting graph (ODE forward -> batch -> ODE adjoint)."""
+    import torch
+    import gv_synth
+    from paper_2501_04782_amd import camera, raster
+    w = gv_synth.make_workload(name, seed=0, targets=True)
+    F, N = w["frames"], w["n"]
+    scene = raster.Scene.from_synth(w["scene"], dev)
+    cam = raster.Camera.of(w["camera"])
+    poses = torch.from_numpy(w["poses"]).to(dev)
+    times = torch.from_numpy(w["times"]).to(dev)
+    targets = torch.from_numpy(w["targets"]).to(dev)
+    cap = raster.estimate_capacity(scene, cam, poses, times, margin=1.3)
+    ws = raster.Workspace(cam, N, F, cap, device=dev)
+    info = dict(workload=name, frames=F, gaussians=N, width=cam.width, height=cam.height)
+    if name == ODE_WORKLOAD:
+        gt = raster.render_batch(scene, cam, poses, times, ws, forward=True, backward=False)
+        targets = gt["images"].clone()
+        theta = torch.from_numpy(gv_synth.init_mlp_theta(np.random.default_rng(7)).astype(np.float32)).to(dev)
+        graph = camera.FitGraph(scene, cam, theta, poses[0].clone(), F, 4, times, ws, targets=targets)
+        info["step"] = "camera ODE forward (RK4, 4 substeps) -> batched fwd+bwd -> ODE adjoint, one graph"
+    else:
+        graph = raster.BatchGraph(scene, cam, poses, times, ws, targets=targets)
+        info["step"] = "batched fwd+bwd with fused L2, one graph"
+    graph.launch()
+    torch.cuda.synchronize()
+    st = ws.status()
+    if st["overflow"]:
+        raise RuntimeError(f"{name}: intersection capacity overflow")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.launch()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    info.update(ms_per_step=round(1e3 * dt, 3), frames_per_s=round(F / dt, 1),
+                intersections_per_frame=int(st["intersections"] / F))
+    if name == ODE_WORKLOAD:
+        # the learned camera's trajectory against the ground-truth pose table
+        te = camera.pose_error(graph.poses, poses)
+        info["trajectory_error"] = dict(translation_rmse=round(te["translation_rmse"], 6),
+                                        mean_angle_rad=round(te["mean_angle"], 6), of="ODE poses at the initial theta")
+        ows = camera.OdeWorkspace(F, 4, device=dev)
+        th = torch.from_numpy(gv_synth.init_mlp_theta(np.random.default_rng(7)).astype(np.float32)).to(dev)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        p = camera.camera_ode_fwd(th, poses[0].clone(), F, 4, ows)
+        torch.cuda.synchronize()
+        e[0].record()
+        p = camera.camera_ode_fwd(th, poses[0].clone(), F, 4, ows)
+        e[1].record()
+        camera.camera_ode_bwd(th, poses[0].clone(), F, 4, torch.ones_like(p), ows)
+        e[2].record()
+        torch.cuda.synchronize()
+        info.update(ode_fwd_ms=round(e[0].elapsed_time(e[1]), 4), ode_bwd_ms=round(e[1].elapsed_time(e[2]), 4))
+    del graph, ws
+    torch.cuda.empty_cache()
+    return info
+
+
 def cpu_protocol(dev) -> dict:
     """The FP64 oracle's per-frame forward and forward+backward times on this
     host, next to the GPU's plain per-frame path on the same frames: the
