@@ -175,7 +175,7 @@ def read_counters(path: str, stage: str, workload: str, tuning: str):
         if not (kv["stage"] == stage and kv["workload"] == workload and kv["tuning"] == tuning
                 and kv["source_sha256"] == source_hash(stage)):
             return None
-        out = {k: float(v) for k, v in kv.items() if k.startswith("SQ_")}
+        out = {k: float(v) for k, v in kv.items() if k.startswith(("SQ_", "GRBM_"))}
         out["avg_ms"] = float(kv["avg_ms"])
         return out
     except (KeyError, ValueError):
