@@ -179,11 +179,13 @@ def quick_clip(name, dev, steps=3):
 
 def cpu_protocol(dev) -> dict:
     """The FP64 oracle's per-frame forward and forward+backward times on this
-    host, next to the GPU's plain per-frame path on the same frames: the
-    128x128 frame of 2k Gaussians in full (all threads and one thread), one
-    full 960x540 frame of 100k Gaussians, the first two frames of the
-    benchmark clip in full, and the first two frames of the 1920x1080 clip of
-    500k Gaussians on a stated pixel sample (extrapolated by pixel count)."""
+    host, in its per-pixel definition and in its tiled form, next to the GPU's
+    plain per-frame path on the same frames: the 128x128 frame of 2k Gaussians
+    in full (all threads and one thread), one full 960x540 frame of 100k
+    Gaussians, the first two frames of the benchmark clip in full, and the
+    first two frames of the 1920x1080 clip of 500k Gaussians (the per-pixel
+    definition on a stated pixel sample, extrapolated by pixel count; the
+    tiled form on whole frames)."""
     import torch
     import gv_synth
     import oracle
@@ -220,7 +222,7 @@ def cpu_protocol(dev) -> dict:
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / (reps * len(frames))
 
-    def oracle_frame_times(w, f, nthreads, npx=None, seed=0):
+    def oracle_frame_times(w, f, nthreads, npx=None, seed=0, tile=0):
         H, W = w["camera"].height, w["camera"].width
         P = H * W
         rng = np.random.default_rng(seed)
@@ -229,10 +231,11 @@ def cpu_protocol(dev) -> dict:
         dl = rng.normal(0, 1, (n, 3)) * (2.0 / (3.0 * P))
         pose = w["poses"][f].astype(np.float64)
         t0 = time.perf_counter()
-        oracle.render_frame(w["scene"], w["camera"], pose, float(w["times"][f]), pixels=pix, threads=nthreads)
+        oracle.render_frame(w["scene"], w["camera"], pose, float(w["times"][f]), pixels=pix, threads=nthreads,
+                            tile=tile)
         t1 = time.perf_counter()
         oracle.render_frame(w["scene"], w["camera"], pose, float(w["times"][f]), pixels=pix, dL_dC=dl,
-                            threads=nthreads)
+                            threads=nthreads, tile=tile)
         t2 = time.perf_counter()
         scale = P / n
         return (t1 - t0) * scale, (t2 - t1) * scale
@@ -242,21 +245,25 @@ def cpu_protocol(dev) -> dict:
     for name, frames, npx, thread_list in plan:
         w = gv_synth.make_workload(name, seed=0, targets=False)
         gpu_s = gpu_per_frame(w, frames)
-        for nt in thread_list:
-            fw, fb = [], []
-            for f in frames:
-                a, b = oracle_frame_times(w, f, nt, npx)
-                fw.append(a)
-                fb.append(b)
-                log(f"[cpu protocol] {name} frame {f} threads {nt}: fwd {a:.2f} s, fwd+bwd {b:.2f} s")
-            rec = dict(workload=name, frames=frames, threads=nt, cpu_fwd_s_per_frame=round(float(np.mean(fw)), 4),
-                       cpu_fwd_bwd_s_per_frame=round(float(np.mean(fb)), 4),
-                       gpu_per_frame_fwd_bwd_ms=round(1e3 * gpu_s, 4),
-                       gpu_over_cpu=round(float(np.mean(fb)) / gpu_s, 1))
-            if npx is not None:
-                rec["sample"] = (f"{npx} random pixels per frame, times scaled by pixel count "
-                                 f"({w['camera'].width * w['camera'].height} per frame)")
-            out["configs"].append(rec)
+        # the per-pixel definition (every pixel over every Gaussian), then the
+        # tiled form (whole frames always)
+        for form, tile, sample in (("per-pixel", 0, npx), ("tiled", 16, None)):
+            for nt in thread_list:
+                fw, fb = [], []
+                for f in frames:
+                    a, b = oracle_frame_times(w, f, nt, sample, tile=tile)
+                    fw.append(a)
+                    fb.append(b)
+                    log(f"[cpu protocol] {name} {form} frame {f} threads {nt}: fwd {a:.2f} s, fwd+bwd {b:.2f} s")
+                rec = dict(workload=name, form=form, frames=frames, threads=nt,
+                           cpu_fwd_s_per_frame=round(float(np.mean(fw)), 4),
+                           cpu_fwd_bwd_s_per_frame=round(float(np.mean(fb)), 4),
+                           gpu_per_frame_fwd_bwd_ms=round(1e3 * gpu_s, 4),
+                           gpu_over_cpu=round(float(np.mean(fb)) / gpu_s, 1))
+                if sample is not None:
+                    rec["sample"] = (f"{sample} random pixels per frame, times scaled by pixel count "
+                                     f"({w['camera'].width * w['camera'].height} per frame)")
+                out["configs"].append(rec)
     return out
 
 
@@ -486,49 +493,40 @@ def main():
                          batched_speedup=round(fps / pf_fps, 3))
         log(f"[bench] per-frame path: {pf_fps:.1f} frames/s (batched x{fps / pf_fps:.2f})")
 
-    # CPU baseline: the FP64 oracle (fwd + bwd) on a bounded pixel sample
-    # spread over five frames of the clip.  Its per-pixel contributor counts
-    # also give the number of contributing (pixel, Gaussian) pairs of the
-    # step, which the compositing kernels' operation counts are priced on.
+    # CPU baseline: the FP64 oracle in its tiled form (results identical to
+    # its per-pixel definition) on whole frames of the clip, forward and
+    # backward, as many as fit in the time budget (at least five, spread over
+    # the clip).  Its contributor counts give the number of contributing
+    # (pixel, Gaussian) pairs the compositing kernels' operations are priced on.
     cpu = None
     mean_contrib = None
     if not args.no_cpu_baseline:
         import oracle
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
         host = host_info()
-        cpu_frames = sorted({0, F // 4, F // 2, (3 * F) // 4, F - 1})
+        spread = [0, F - 1, F // 2, F // 4, (3 * F) // 4]
+        order = list(dict.fromkeys(spread + list(range(F))))
         rng = np.random.default_rng(1)
-
-        def run(npx):
-            t_all, nc = 0.0, []
-            for f in cpu_frames:
-                pix = np.sort(rng.choice(P, npx, replace=False))
-                dl = rng.normal(0, 1, (npx, 3)) * (2.0 / (3.0 * P * F))
-                t = time.perf_counter()
-                r = oracle.render_frame(w["scene"], w["camera"], w["poses"][f].astype(np.float64),
-                                        float(w["times"][f]), pixels=pix, dL_dC=dl, threads=threads)
-                t_all += time.perf_counter() - t
-                nc.append(r["n_contrib"])
-            return t_all, np.concatenate(nc)
-
-        log("[bench] CPU oracle pilots")
-        # two pilot sizes separate the per-frame fixed cost (projection and
-        # depth sort of all Gaussians) from the per-pixel cost
-        t_a, _ = run(256)
-        t_b, _ = run(1024)
-        per_px = max((t_b - t_a) / 768, 1e-9)
-        fixed = max(t_a - 256 * per_px, 0.0)
-        npx = int(min(P, max(1024, (args.cpu_seconds - fixed) / per_px)))
-        log(f"[bench] CPU oracle sample: {npx} pixels in each of frames {cpu_frames} "
-            f"(pilots {t_a:.2f} s / {t_b:.2f} s)")
-        t_cpu, nc = run(npx)
+        dl = rng.normal(0, 1, (P, 3)) * (2.0 / (3.0 * P * F))
+        t_cpu, done, nc = 0.0, [], []
+        log("[bench] CPU oracle (tiled form, whole frames)")
+        for f in order:
+            t = time.perf_counter()
+            r = oracle.render_frame(w["scene"], w["camera"], w["poses"][f].astype(np.float64), float(w["times"][f]),
+                                    dL_dC=dl, threads=threads, tile=16)
+            t_cpu += time.perf_counter() - t
+            done.append(f)
+            nc.append(float(np.mean(r["n_contrib"])))
+            if len(done) >= len(spread) and t_cpu >= args.cpu_seconds:
+                break
         mean_contrib = float(np.mean(nc))
-        cpu_fps = len(cpu_frames) * npx / (t_cpu * P)
+        cpu_fps = len(done) / t_cpu
         cpu = dict(value=cpu_fps, unit="frames/s", cores=threads, kind="oracle",
-                   sample=f"{npx} random pixels in each of frames {cpu_frames} (of {P} per frame), forward+backward "
-                          f"incl. projection and depth sort of all {N} Gaussians per frame, {t_cpu:.1f} s; "
-                          "scaled by pixel count", host=host)
-        log(f"[bench] CPU oracle: {cpu_fps:.3e} frames/s on {threads} threads ({host})")
+                   sample=f"{len(done)} whole frames of the clip (first frames {done[:5]}), forward+backward incl. "
+                          f"projection, binning and depth sort of all {N} Gaussians per frame, {t_cpu:.1f} s; "
+                          "the oracle's tiled form (each pixel visits its 16x16 tile's candidates; results "
+                          "identical to the per-pixel definition)", host=host)
+        log(f"[bench] CPU oracle: {cpu_fps:.3f} frames/s on {threads} threads ({host})")
 
     # roofline of the dominant kernel, priced on the hot-path table's
     # per-unit figures: bytes per pixel and per intersection, operations per

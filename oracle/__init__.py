@@ -6,7 +6,10 @@ no code with the HIP path (``paper_2501_04782_amd``) and imports nothing from
 it; the only module both sides use is ``gv_synth`` (seeded input draws).
 
 * ``gvo_raster.c``: the tile-free, per-pixel definition of 3D Gaussian
-  splatting image formation (paper Sec. 3.1) and its adjoint, in FP64.
+  splatting image formation (paper Sec. 3.1) and its adjoint, in FP64, and a
+  tiled form of it for speed (each pixel visits only the Gaussians whose
+  footprint box meets its tile, in the same order, with identical results:
+  ``tests/test_oracle_tiled.py``).
 * ``camera_ode.py``: the camera-motion Neural ODE (Eq. 1, Sec. 3.4) with RK4
   and its discrete adjoint, in FP64 numpy.
 * this file: ctypes marshalling around ``gvo_raster.c``, a clip loop and the
@@ -64,6 +67,8 @@ def _load():
         lib.gvo_render.argtypes = [ctypes.POINTER(_Frame), ctypes.c_int64, _i64p, _dp, _dp, _i64p, _dp,
                                    _dp, ctypes.POINTER(_Grads), ctypes.c_int, _dp, _dp]
         lib.gvo_render.restype = ctypes.c_int
+        lib.gvo_render_tiled.argtypes = lib.gvo_render.argtypes + [ctypes.c_int]
+        lib.gvo_render_tiled.restype = ctypes.c_int
         lib.gvo_bspline_basis.argtypes = [ctypes.c_int32, ctypes.c_double, _dp]
         lib.gvo_bspline_basis.restype = ctypes.c_int
         lib.gvo_sh_basis.argtypes = [ctypes.c_int32, _dp, _dp, _dp]
@@ -71,7 +76,7 @@ def _load():
         lib.gvo_abi_version.restype = ctypes.c_int
         lib.gvo_contributors.argtypes = [ctypes.POINTER(_Frame), ctypes.POINTER(ctypes.c_uint8), ctypes.c_int]
         lib.gvo_contributors.restype = ctypes.c_int
-        if lib.gvo_abi_version() != 6:
+        if lib.gvo_abi_version() != 7:
             raise RuntimeError("liboracle.so is stale: rebuild it (python -m oracle.build)")
         _lib = lib
     return _lib
@@ -174,7 +179,7 @@ def zero_grads(scene) -> dict:
 
 def render_frame(scene, cam, pose7, t: float = 0.0, pixels: Optional[np.ndarray] = None,
                  dL_dC: Optional[np.ndarray] = None, grads: Optional[dict] = None,
-                 threads: int = 0, stake_tol: Optional[Sequence[float]] = None) -> dict:
+                 threads: int = 0, stake_tol: Optional[Sequence[float]] = None, tile: int = 0) -> dict:
     """Render one frame at the listed pixels (linear y*W+x; None = all).
 
     Returns color [P][3], T_final [P], n_contrib [P], margins [P][4] and, when
@@ -185,6 +190,11 @@ def render_frame(scene, cam, pose7, t: float = 0.0, pixels: Optional[np.ndarray]
     control (an entry's alpha*T for a cut, the remaining transmittance for
     the stop), so that a pixel taken the other way at such a decision can
     differ by at most stake times the colour range.
+
+    tile > 0 selects the tiled form: each pixel visits only the Gaussians whose
+    footprint box meets its tile (in the same global order), with results
+    identical to the per-pixel definition (margins from 1e-3 up may read
+    larger); it is the fast form for timing and large frames.
     """
     s = scene_f64(scene)
     fr = _frame(s, cam, pose7, t)
@@ -214,9 +224,9 @@ def render_frame(scene, cam, pose7, t: float = 0.0, pixels: Optional[np.ndarray]
     if stake_tol is not None:
         tol = np.ascontiguousarray(np.asarray(stake_tol, dtype=np.float64).reshape(3))
         stake = np.zeros(npx)
-    rc = _load().gvo_render(ctypes.byref(fr), npx, pix_p, _ptr(color), _ptr(T), nc.ctypes.data_as(_i64p),
-                            _ptr(mg), _ptr(dl), ctypes.byref(gstruct) if gstruct is not None else None,
-                            int(threads), _ptr(tol), _ptr(stake))
+    args = (ctypes.byref(fr), npx, pix_p, _ptr(color), _ptr(T), nc.ctypes.data_as(_i64p), _ptr(mg), _ptr(dl),
+            ctypes.byref(gstruct) if gstruct is not None else None, int(threads), _ptr(tol), _ptr(stake))
+    rc = _load().gvo_render_tiled(*args, int(tile)) if tile > 0 else _load().gvo_render(*args)
     if rc != 0:
         raise RuntimeError(f"gvo_render failed with code {rc}")
     out = dict(color=color, T_final=T, n_contrib=nc, margins=mg)
