@@ -321,16 +321,17 @@ def trajectory_error(poses, ref_poses) -> dict:
 
 
 def render_clip_grads(scene, cam, poses: np.ndarray, times: Sequence[float], frames: Sequence[int],
-                      pixels: Sequence[np.ndarray], dL_dC: Sequence[np.ndarray], threads: int = 0):
+                      pixels: Sequence[np.ndarray], dL_dC: Sequence[np.ndarray], threads: int = 0, tile: int = 0):
     """Sum over the listed frames of the gradient of sum_p dL_dC[f][p] . C_f[p]
-    (shared parameters summed over frames, poses per frame)."""
+    (shared parameters summed over frames, poses per frame); tile > 0 takes
+    the tiled form (identical results)."""
     grads = zero_grads(scene)
     dposes = np.zeros((len(poses), 7))
     colors = []
     for f, pix, dl in zip(frames, pixels, dL_dC):
         grads["pose"][:] = 0.0
         r = render_frame(scene, cam, poses[f], float(times[f]), pixels=pix, dL_dC=dl, grads=grads,
-                         threads=threads)
+                         threads=threads, tile=tile)
         dposes[f] = grads["pose"]
         colors.append(r["color"])
     grads["pose"] = None

@@ -25,7 +25,15 @@ Tolerances (written here, used by every parity test):
   Gaussian (scales e^-1 and e^-5) the quaternion gradient passes through
   the conic's inverse and the rotation of a 3000:1 covariance, which turn
   the FP32 rounding of the per-pixel moments (~1e-7) into element errors of
-  up to 1.05e-3 (measured), while the tensor's norm error stays at 6e-6.
+  up to 1.05e-3 (measured), while the tensor's norm error stays at 6e-6;
+* gradients of shared parameters summed over a clip's frames (one set of
+  Gaussians serves every frame, Sec. 3.2, under the L2 loss over all
+  frames, Sec. 4.1) may also be off by SUM_RTOL times the sum over frames of
+  the per-frame gradient's magnitude: the rounding error of a sum is bounded
+  by a multiple of the unit roundoff times the sum of its terms' magnitudes,
+  not of its result, and per-frame terms can cancel by a factor of several
+  thousand (measured: a quaternion gradient of -0.21 from 32 frames whose
+  terms sum to 1495 in magnitude, off by 7.4e-7 of that sum in FP32).
 
 A pixel is set aside when the oracle reports a relative margin below
 MARGIN_TOL for one of its decisions: the 3-sigma cut (q = 9), the alpha >= 1/255
@@ -54,6 +62,7 @@ PIXEL_TOL = 1e-4
 GRAD_TOL = 1e-3
 ELEM_RTOL = 3e-3          # elementwise gradient check: relative part
 ELEM_ATOL = 1e-6          # elementwise gradient check: absolute part, times max|g_oracle|
+SUM_RTOL = 1e-5           # elementwise, sums over frames: times the sum of the per-frame magnitudes (~170 ulp)
 MARGIN_TOL = np.array([2e-5, 1e-4, 2e-4, 1e-4])
 SET_ASIDE_MAX = 0.01      # fraction of a test's checked pixels that may be set aside
 SH_BOUND = 0.75           # |Y_lm| <= sqrt((2l + 1) / (4 pi)) <= 0.75 for l <= 3
@@ -90,8 +99,10 @@ def rel_err(got, ref) -> float:
     return float(np.linalg.norm(got - ref) / den) if den > 0 else float(np.linalg.norm(got))
 
 
-def elem_check(got, ref, label: str) -> float:
-    """Elementwise bar; returns the worst |d| / (ELEM_RTOL |ref| + ELEM_ATOL max|ref|)."""
+def elem_check(got, ref, label: str, mag=None) -> float:
+    """Elementwise bar; returns the worst |d| / (ELEM_RTOL |ref| + ELEM_ATOL max|ref|
+    [+ SUM_RTOL mag]), where mag (same shape as ref) is the sum over frames of
+    the per-frame gradient's magnitude for a gradient summed over frames."""
     got = np.asarray(got, np.float64).reshape(-1)
     ref = np.asarray(ref, np.float64).reshape(-1)
     assert np.all(np.isfinite(got)), f"{label}: non-finite gradient values"
@@ -99,6 +110,8 @@ def elem_check(got, ref, label: str) -> float:
         return 0.0
     scale = np.abs(ref).max()
     bound = ELEM_RTOL * np.abs(ref) + ELEM_ATOL * scale
+    if mag is not None:
+        bound = bound + SUM_RTOL * np.asarray(mag, np.float64).reshape(-1)
     d = np.abs(got - ref)
     if scale == 0.0:
         assert np.all(d == 0.0), f"{label}: oracle gradient is zero, GPU max |g| {d.max():.3e}"
@@ -123,10 +136,34 @@ def workspace_for(scene, cam, poses, times, margin=1.5):
     return raster.Workspace(cam, scene.n, int(poses.shape[0]), cap, device=poses.device)
 
 
-def oracle_frame(w: dict, f: int, pixels=None, dL_dC=None, grads=None, widen: float = 1.0):
-    """Oracle render of frame f (with the per-pixel stake of set-aside decisions)."""
+def oracle_frame(w: dict, f: int, pixels=None, dL_dC=None, grads=None, widen: float = 1.0, tile: int = 0):
+    """Oracle render of frame f (with the per-pixel stake of set-aside
+    decisions); tile > 0 takes the oracle's tiled form, whose results are
+    identical to the per-pixel definition (margins below 1e-3, the only ones
+    used here, included) and which whole full-size frames need."""
     return oracle.render_frame(w["scene"], w["camera"], w["poses"][f].astype(np.float64), float(w["times"][f]),
-                               pixels=pixels, dL_dC=dL_dC, grads=grads, stake_tol=widen * MARGIN_TOL[:3])
+                               pixels=pixels, dL_dC=dL_dC, grads=grads, stake_tol=widen * MARGIN_TOL[:3], tile=tile)
+
+
+def oracle_clip_grads(w: dict, dls, frames=None, pixels=None, tile: int = 0):
+    """The oracle's gradients of sum_f sum_p dls[k][p] . C_f[p] over the listed
+    frames (all by default), frame by frame: the sums over frames, the
+    per-frame pose gradients [F][7] and, per element, the sum over frames of
+    the per-frame gradient's magnitude (the scale of the sum's rounding)."""
+    frames = range(w["frames"]) if frames is None else frames
+    pixels = [None] * len(frames) if pixels is None else pixels
+    total = oracle.zero_grads(w["scene"])
+    mag = oracle.zero_grads(w["scene"])
+    dposes = np.zeros((len(w["poses"]), 7))
+    for f, pix, dl in zip(frames, pixels, dls):
+        gf = oracle_frame(w, f, pixels=pix, dL_dC=dl, grads=oracle.zero_grads(w["scene"]), tile=tile)["grads"]
+        for k, v in gf.items():
+            if v is not None and k != "pose":
+                total[k] += v
+                mag[k] += np.abs(v)
+        dposes[f] = gf["pose"]
+    total["pose"] = mag["pose"] = None
+    return total, dposes, mag
 
 
 def planar_to_pixels(img: np.ndarray) -> np.ndarray:
@@ -173,7 +210,10 @@ def compare_image(gpu_img: np.ndarray, ref: dict, label: str, crange: float, tal
     return tally.finish() if own else None
 
 
-def compare_grads(gpu: dict, ref: dict, label: str, names=None):
+def compare_grads(gpu: dict, ref: dict, label: str, names=None, mag: dict = None):
+    """Every gradient tensor the oracle gives: norm-wise and elementwise bars
+    (mag: per-tensor sums over frames of per-frame magnitudes, for gradients
+    summed over a clip)."""
     out = {}
     names = names or [k for k in ("means", "log_scales", "quats", "opacity_logits", "colors", "mean_coeffs", "ctrl",
                                   "scale_coeffs", "quat_coeffs", "sh", "intrinsics")
@@ -182,7 +222,7 @@ def compare_grads(gpu: dict, ref: dict, label: str, names=None):
         g = gpu[k].detach().cpu().numpy() if isinstance(gpu[k], torch.Tensor) else gpu[k]
         e = rel_err(g, ref[k])
         assert e <= GRAD_TOL, f"{label}: grad {k} relative error {e:.3e} > {GRAD_TOL}"
-        r = elem_check(g, ref[k], f"{label}: grad {k}")
+        r = elem_check(g, ref[k], f"{label}: grad {k}", None if mag is None else mag.get(k))
         out[k] = (round(e, 9), round(r, 3))
     return out
 
@@ -196,7 +236,7 @@ def compare_poses(gpu, ref, label: str):
     return e
 
 
-# ------------------------------------------------------- full-size sampling
+# ------------------------------------------------------- tile buckets
 
 
 def tile_buckets(w: dict, f: int, tile: int = 16) -> np.ndarray:
@@ -233,33 +273,3 @@ def tile_buckets(w: dict, f: int, tile: int = 16) -> np.ndarray:
         best = np.minimum(best, A * dx * dx + 2 * B * dx * dy + C * dy * dy)
     hit = best <= 9.0
     return np.bincount((ty * TX + tx)[hit], minlength=TX * TY)
-
-
-def tile_pixels(w: dict, tiles, tile: int = 16) -> np.ndarray:
-    """Linear pixel indices (y*W + x) of whole tiles, clipped at the image edge."""
-    cam = w["camera"]
-    TX = (cam.width + tile - 1) // tile
-    out = []
-    for t in tiles:
-        tx, ty = int(t) % TX, int(t) // TX
-        xs = np.arange(tx * tile, min(tx * tile + tile, cam.width))
-        ys = np.arange(ty * tile, min(ty * tile + tile, cam.height))
-        out.append((ys[:, None] * cam.width + xs[None, :]).reshape(-1))
-    return np.unique(np.concatenate(out))
-
-
-def sample_tiles(w: dict, f: int, n_random: int, rng: np.random.Generator, tile: int = 16):
-    """Tiles of frame f to check whole: the longest bucket, the densest tile
-    (most contributors at its centre pixel in the oracle) and n_random others.
-    Returns (tiles, bucket sizes of the frame)."""
-    cam = w["camera"]
-    sizes = tile_buckets(w, f, tile)
-    TX, TY = (cam.width + tile - 1) // tile, (cam.height + tile - 1) // tile
-    cx = np.minimum(np.arange(TX) * tile + tile // 2, cam.width - 1)
-    cy = np.minimum(np.arange(TY) * tile + tile // 2, cam.height - 1)
-    centres = (cy[:, None] * cam.width + cx[None, :]).reshape(-1)
-    nc = oracle_frame(w, f, pixels=centres)["n_contrib"]
-    chosen = [int(np.argmax(sizes)), int(np.argmax(nc))]
-    rest = np.setdiff1d(np.arange(TX * TY), chosen)
-    chosen += [int(t) for t in rng.choice(rest, n_random, replace=False)]
-    return list(dict.fromkeys(chosen)), sizes

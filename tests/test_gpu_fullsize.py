@@ -1,8 +1,8 @@
 """Full-size parity of the benchmark configurations, in the launch
-configuration bench.py times, on whole 16x16 tiles the oracle computes pixel
-by pixel: each checked frame's longest tile bucket, its densest tile (most
-contributors at the tile centre in the oracle) and random tiles, on five
-frames per clip.
+configuration bench.py times, on every pixel of every frame: the oracle's
+tiled form (results identical to its per-pixel definition, see
+test_oracle_tiled.py) renders each whole frame in about a second, so images,
+final transmittance, losses and all gradients are compared at full size.
 
 * the 960x540 frame of 100k Gaussians through the plain per-frame path;
 * the benchmark clip (50 frames at 960x540, 200k Gaussians) through the
@@ -23,7 +23,7 @@ import gv_synth
 import oracle
 from oracle import camera_ode as ode_ref
 from parity_util import (GRAD_TOL, PIXEL_TOL, PixelTally, colour_range, compare_grads, compare_poses, device_inputs,
-                         knife_edge, oracle_frame, planar_to_pixels, rel_err, sample_tiles, tile_pixels,
+                         knife_edge, oracle_clip_grads, oracle_frame, planar_to_pixels, rel_err, tile_buckets,
                          workspace_for)
 from test_gpu_parity import run_clip, say, small_workload
 
@@ -33,56 +33,63 @@ if torch.cuda.is_available():
     from paper_2501_04782_amd import camera as gvcam
     from paper_2501_04782_amd import raster
 
-
-def sampled_tiles(w, frames, seed, n_random=2, widen=1.0, label=""):
-    """Whole tiles of each listed frame (longest bucket, densest, random) and
-    the oracle's results there; returns (pixel lists, oracle results, bucket
-    sizes of the chosen tiles)."""
-    rng = np.random.default_rng(seed)
-    pix, refs, info = [], [], []
-    for f in frames:
-        tiles, sizes = sample_tiles(w, f, n_random, rng)
-        p = tile_pixels(w, tiles)
-        say(f"[{label}] frame {f}: tiles {tiles} bucket sizes {[int(sizes[t]) for t in tiles]} "
-            f"(frame max {int(sizes.max())}), {p.size} pixels; oracle")
-        pix.append(p)
-        refs.append(oracle_frame(w, f, pixels=p, widen=widen))
-        info.append(int(sizes.max()))
-    return pix, refs, info
+TILE = 16  # tile edge of the oracle's tiled form
 
 
-def sampled_upstream(w, frames, pix, refs, seed, widen=1.0):
-    """A random upstream gradient supported on the sampled pixels (zero at
-    set-aside ones): per frame [P_f][3] and the dense [F][3][H][W] array."""
+def whole_frames(w, label, widen=1.0):
+    """The oracle's forward results on every frame of the clip."""
+    refs = []
+    for f in range(w["frames"]):
+        refs.append(oracle_frame(w, f, widen=widen, tile=TILE))
+    sizes = tile_buckets(w, 0)
+    say(f"[{label}] oracle forward on {w['frames']} whole frames; frame 0: longest bucket {int(sizes.max())}, "
+        f"{int((sizes > 1024).sum())} buckets above 1024 entries")
+    return refs
+
+
+def held(r, widen=1.0):
+    """Pixels whose upstream gradient is zeroed: a decision within rounding."""
+    return knife_edge(r["margins"], grads=True, widen=widen) | (r["stake"] > 0)
+
+
+def whole_upstream(w, refs, seed, widen=1.0):
+    """A random upstream gradient on every frame (zero at set-aside pixels):
+    per frame [P][3] and dense [F][3][H][W]."""
     H, W = w["camera"].height, w["camera"].width
     rng = np.random.default_rng(seed)
     dls = []
     dl = np.zeros((w["frames"], 3, H * W), np.float32)
-    for f, p, r in zip(frames, pix, refs):
-        d = rng.normal(0, 1, (p.size, 3)).astype(np.float32).astype(np.float64)
-        d[knife_edge(r["margins"], grads=True, widen=widen) | (r["stake"] > 0)] = 0.0
+    for f, r in enumerate(refs):
+        d = rng.normal(0, 1, (H * W, 3)).astype(np.float32).astype(np.float64)
+        d[held(r, widen)] = 0.0
         dls.append(d)
-        dl[f][:, p] = d.T
+        dl[f] = d.T
     return dls, dl.reshape(w["frames"], 3, H, W)
 
 
-def check_sampled_pixels(imgs, frames, pix, refs, w, label, widen=1.0):
+def check_frames(imgs, refs, w, label, widen=1.0):
     tally = PixelTally(label)
     crange = colour_range(w)
-    for f, p, r in zip(frames, pix, refs):
-        tally.add(planar_to_pixels(imgs[f])[p], r, crange, widen=widen, where=f" frame {f}")
+    for f, r in enumerate(refs):
+        tally.add(planar_to_pixels(imgs[f]), r, crange, widen=widen, where=f" frame {f}")
     stats = tally.finish()
     say(f"[{label}] pixels {stats}")
     return stats
 
 
-def test_frame540p_n100k_full_size_sampled():
-    """960x540, 100k Gaussians, per-frame path at full size; gradients with an
-    upstream gradient supported on the sampled tiles."""
+def clip_grads(w, dls):
+    """Oracle gradients over every frame, with the per-element magnitude sums
+    that bound the rounding of a sum over frames."""
+    return oracle_clip_grads(w, dls, tile=TILE)
+
+
+def test_frame540p_n100k_full_size():
+    """960x540, 100k Gaussians, the plain per-frame path: every pixel, its
+    final transmittance, and the gradients for an upstream gradient on every
+    pixel."""
     w = gv_synth.make_workload("frame540p_n100k", targets=False)
-    frames = [0]
-    pix, refs, _ = sampled_tiles(w, frames, 20, n_random=6, label="540p n100k")
-    dls, dl = sampled_upstream(w, frames, pix, refs, 20)
+    refs = whole_frames(w, "540p n100k")
+    dls, dl = whole_upstream(w, refs, 20)
     scene, cam, poses, times = device_inputs(w)
     ws = workspace_for(scene, cam, poses, times)
     Tf = torch.empty(w["camera"].height, w["camera"].width, device="cuda")
@@ -90,50 +97,45 @@ def test_frame540p_n100k_full_size_sampled():
     g, dpose = raster.render_bwd(scene, cam, poses[0].contiguous(), 0.0, ws, img,
                                  dL_dimage=torch.from_numpy(dl[0]).cuda())
     torch.cuda.synchronize()
-    check_sampled_pixels(img.cpu().numpy()[None], frames, pix, refs, w, "540p n100k")
+    check_frames(img.cpu().numpy()[None], refs, w, "540p n100k")
     # final transmittance: the relative error the stop decision sees
     r = refs[0]
     free = ~(knife_edge(r["margins"]) | (r["stake"] > 0))
-    t_rel = np.abs(Tf.cpu().numpy().reshape(-1)[pix[0]] - r["T_final"]) / r["T_final"]
+    t_rel = np.abs(Tf.cpu().numpy().reshape(-1) - r["T_final"]) / r["T_final"]
     assert t_rel[free].max() <= 1e-3, t_rel[free].max()  # well inside the stop margin
     say(f"[540p n100k] T_final relative error: max {t_rel[free].max():.2e}, "
-        f"99.9th percentile {np.percentile(t_rel[free], 99.9):.2e}")
-    gref = oracle_frame(w, 0, pixels=pix[0], dL_dC=dls[0])["grads"]
-    ge = compare_grads(g, gref, "540p n100k")
-    pe = compare_poses(dpose, gref["pose"], "540p n100k")
+        f"99.99th percentile {np.percentile(t_rel[free], 99.99):.2e}")
+    gref, dposes_ref, _ = clip_grads(w, dls)
+    ge = compare_grads(g, gref, "540p n100k")  # one frame: no sum over frames
+    pe = compare_poses(dpose, dposes_ref[0], "540p n100k")
     say(f"[540p n100k] grads={ge} pose={pe:.2e}")
 
 
 def test_clip540p_f50_n200k_fused_l2_full_size():
     """The benchmark clip in the benchmark's launch configuration (captured
-    graph, fused L2 loss).  The targets equal the GPU's own image except on
-    the sampled tiles, where they are seeded U[0, 1]: the residual, so the
-    loss and every gradient, then lives only where the oracle is evaluated.
-    Per-frame losses, all parameter gradients and the pose gradients are
-    compared with the oracle's L2 loss (Sec. 4.1) and adjoint."""
+    graph, fused L2 loss), all 50 frames whole.  The targets are seeded
+    U[0, 1], except at set-aside pixels, where they are the GPU's own image so
+    that the residual there is zero on both sides.  Per-frame losses, all
+    parameter gradients and the pose gradients are compared with the oracle's
+    L2 loss (Sec. 4.1) and adjoint."""
     w = gv_synth.make_workload("clip540p_f50_n200k", targets=False)
     F, H, W = w["frames"], w["camera"].height, w["camera"].width
-    frames = [0, 12, 24, 37, 49]
-    pix, refs, longest = sampled_tiles(w, frames, 21, label="clip540p")
-    assert max(longest) > 1024  # buckets beyond one LDS pass at the default capacity
+    assert max(int(tile_buckets(w, f).max()) for f in (0, F // 2, F - 1)) > 1024
+    refs = whole_frames(w, "clip540p")
     scene, cam, poses, times = device_inputs(w)
     ws = workspace_for(scene, cam, poses, times, margin=1.3)
-    say("[clip540p] gpu forward (images the targets are built from)")
+    say("[clip540p] gpu forward (images the set-aside targets are taken from)")
     fwd = raster.render_batch(scene, cam, poses, times, ws, forward=True, backward=False)
     torch.cuda.synchronize()
     assert ws.status()["overflow"] == 0
     base = fwd["images"].clone()
     tg = base.cpu().numpy().reshape(F, 3, H * W)
     rng = np.random.default_rng(22)
-    img_s, tgt_s = [], []
-    for f, p, r in zip(frames, pix, refs):
-        vals = rng.random((p.size, 3)).astype(np.float32)
-        free = ~(knife_edge(r["margins"], grads=True) | (r["stake"] > 0))
-        tg[f][:, p[free]] = vals[free].T
-        t_s = tg[f][:, p].T.astype(np.float64)               # [P_f][3]
-        c_s = np.where(free[:, None], r["color"], t_s)        # zero residual where set aside
-        img_s.append(c_s)
-        tgt_s.append(t_s)
+    img_ref = np.empty((F, 3, H * W))
+    for f, r in enumerate(refs):
+        free = ~held(r)
+        tg[f][:, free] = rng.random((3, int(free.sum()))).astype(np.float32)
+        img_ref[f] = np.where(free[None, :], r["color"].T, tg[f])  # zero residual where held
     targets = torch.from_numpy(tg.reshape(F, 3, H, W)).cuda()
     say("[clip540p] gpu graph (fwd+bwd, fused L2)")
     g = raster.BatchGraph(scene, cam, poses, times, ws, targets=targets)
@@ -141,32 +143,20 @@ def test_clip540p_f50_n200k_fused_l2_full_size():
     torch.cuda.synchronize()
     assert ws.status()["overflow"] == 0
     assert torch.equal(g.images, base)
-    check_sampled_pixels(g.images.cpu().numpy(), frames, pix, refs, w, "clip540p")
-    # oracle loss and upstream gradient on the sampled pixels, scaled from
-    # the sample's mean to the clip's mean (the rest has zero residual)
-    n_full = F * 3 * H * W
-    loss_ref = np.zeros(F)
-    dls = []
-    for k, (f, c_s, t_s) in enumerate(zip(frames, img_s, tgt_s)):
-        share, grad = oracle.l2_loss_and_grad(c_s.T[None], t_s.T[None], per_frame=True)
-        scale = c_s.size / n_full
-        loss_ref[f] = share[0] * scale
-        dls.append(grad[0].T * scale)
+    check_frames(g.images.cpu().numpy(), refs, w, "clip540p")
+    tgt_ref = tg.astype(np.float64)
+    loss_ref, grad = oracle.l2_loss_and_grad(img_ref, tgt_ref, per_frame=True)
+    dls = [grad[f].T for f in range(F)]
     loss_gpu = g.loss.cpu().numpy().astype(np.float64)
-    resid_bound = np.zeros(F)
-    for f, c_s, t_s in zip(frames, img_s, tgt_s):
-        resid_bound[f] = np.sum(2 * np.abs(c_s - t_s) * PIXEL_TOL + PIXEL_TOL ** 2) / n_full
-    bound = resid_bound + 1e-5 * loss_ref
-    assert np.all(np.abs(loss_gpu - loss_ref) <= bound), (loss_gpu[frames], loss_ref[frames], bound[frames])
-    assert np.all(np.delete(loss_gpu, frames) == 0.0)
-    say(f"[clip540p] loss rel err per frame {np.abs(loss_gpu - loss_ref)[frames] / loss_ref[frames]}")
+    n_full = F * 3 * H * W
+    bound = np.sum(2 * np.abs(img_ref - tgt_ref) * PIXEL_TOL + PIXEL_TOL ** 2, axis=(1, 2)) / n_full
+    bound += 1e-5 * loss_ref
+    assert np.all(np.abs(loss_gpu - loss_ref) <= bound), (loss_gpu, loss_ref, bound)
+    say(f"[clip540p] loss: max relative error per frame {np.max(np.abs(loss_gpu - loss_ref) / loss_ref):.2e}")
     say("[clip540p] oracle backward")
-    g_ref, dposes_ref, _ = oracle.render_clip_grads(w["scene"], w["camera"], w["poses"].astype(np.float64),
-                                                    w["times"], frames, pix, dls)
-    ge = compare_grads(g.grads, g_ref, "clip540p")
-    gp = g.dL_dposes.cpu().numpy()
-    pe = compare_poses(gp[frames], dposes_ref[frames], "clip540p")
-    assert np.all(np.delete(gp, frames, axis=0) == 0.0)
+    g_ref, dposes_ref, mag = clip_grads(w, dls)
+    ge = compare_grads(g.grads, g_ref, "clip540p", mag=mag)
+    pe = compare_poses(g.dL_dposes, dposes_ref, "clip540p")
     say(f"[clip540p] grads={ge} pose={pe:.2e} intersections={ws.status()['intersections']}")
     # the same step at sort capacity 512: buckets above 1024 entries are sorted
     # in LDS chunks and merged in global memory; the order is fully determined,
@@ -189,23 +179,21 @@ def test_clip540p_f50_n200k_fused_l2_full_size():
     g.close()
 
 
-def test_clip1080p_bf16_cubic_full_size_sampled():
+def test_clip1080p_bf16_cubic_full_size():
     w = gv_synth.make_workload("clip1080p_f32_n500k_bf16", targets=False)
-    frames = [0, 8, 15, 23, 31]
-    pix, refs, _ = sampled_tiles(w, frames, 40, n_random=1, label="clip1080p")
-    dls, dl = sampled_upstream(w, frames, pix, refs, 40)
+    refs = whole_frames(w, "clip1080p")
+    dls, dl = whole_upstream(w, refs, 40)
     say("[clip1080p] gpu batch")
     out, ws, _ = run_clip(w, dl=dl)
-    check_sampled_pixels(out["images"].cpu().numpy(), frames, pix, refs, w, "clip1080p")
+    check_frames(out["images"].cpu().numpy(), refs, w, "clip1080p")
     say("[clip1080p] oracle backward")
-    g_ref, dposes_ref, _ = oracle.render_clip_grads(w["scene"], w["camera"], w["poses"].astype(np.float64),
-                                                    w["times"], frames, pix, dls)
-    ge = compare_grads(out["grads"], g_ref, "clip1080p")
-    pe = compare_poses(out["dL_dposes"].cpu().numpy()[frames], dposes_ref[frames], "clip1080p")
+    g_ref, dposes_ref, mag = clip_grads(w, dls)
+    ge = compare_grads(out["grads"], g_ref, "clip1080p", mag=mag)
+    pe = compare_poses(out["dL_dposes"], dposes_ref, "clip1080p")
     say(f"[clip1080p] grads={ge} pose={pe:.2e} intersections={ws.status()['intersections']}")
 
 
-def test_camera_ode_fitting_step_full_size_sampled():
+def test_camera_ode_fitting_step_full_size():
     w = gv_synth.make_workload("clip540p_f100_n200k", targets=False)
     F, S = w["frames"], 4
     gt_poses = w["poses"].copy()
@@ -232,9 +220,8 @@ def test_camera_ode_fitting_step_full_size_sampled():
     assert judged["mean_angle"] == pytest.approx(e_gpu["mean_angle"], rel=1e-5, abs=1e-6)
     say(f"[fit step] trajectory error: rmse {e_ref['translation_rmse']:.4e} angle {e_ref['mean_angle']:.4e} rad")
     w["poses"] = poses_gpu.cpu().numpy()
-    frames = [0, 25, 50, 75, 99]
-    pix, refs, _ = sampled_tiles(w, frames, 41, n_random=1, label="fit step")
-    dls, dl = sampled_upstream(w, frames, pix, refs, 41)
+    refs = whole_frames(w, "fit step")
+    dls, dl = whole_upstream(w, refs, 41)
     ws = workspace_for(scene, cam, poses_gpu, times)
     say("[fit step] gpu graph")
     fit = gvcam.FitGraph(scene, cam, th, z, F, S, times, ws, dL_dimages=torch.from_numpy(dl).cuda())
@@ -242,11 +229,10 @@ def test_camera_ode_fitting_step_full_size_sampled():
     torch.cuda.synchronize()
     assert ws.status()["overflow"] == 0
     assert torch.equal(fit.poses, poses_gpu)
-    check_sampled_pixels(fit.images.cpu().numpy(), frames, pix, refs, w, "fit step")
+    check_frames(fit.images.cpu().numpy(), refs, w, "fit step")
     say("[fit step] oracle backward + discrete adjoint")
-    g_ref, dposes_ref, _ = oracle.render_clip_grads(w["scene"], w["camera"], w["poses"].astype(np.float64),
-                                                    w["times"], frames, pix, dls)
-    compare_grads(fit.grads, g_ref, "fit step")
+    g_ref, dposes_ref, mag = clip_grads(w, dls)
+    compare_grads(fit.grads, g_ref, "fit step", mag=mag)
     dth_ref, dz_ref = ode_ref.camera_ode_bwd(theta.astype(np.float64), z0.astype(np.float64), F, S, dposes_ref)
     e1, e2 = rel_err(fit.dtheta.cpu().numpy(), dth_ref), rel_err(fit.dz0.cpu().numpy(), dz_ref)
     assert e1 <= GRAD_TOL and e2 <= GRAD_TOL, (e1, e2)
@@ -254,23 +240,21 @@ def test_camera_ode_fitting_step_full_size_sampled():
     say(f"[fit step] poses err {ep:.2e} dtheta err {e1:.2e} dz0 err {e2:.2e}")
 
 
-def test_tile_grid_beyond_lds_histogram_sampled():
+def test_tile_grid_beyond_lds_histogram():
     """A 4128x1056 frame has 258 x 66 = 17,028 tiles, more than the 16,384 an
     LDS tile histogram holds, so binning takes the count and scatter kernels
-    with one global atomic per intersection.  Images and gradients on sampled
-    tiles against the oracle."""
+    with one global atomic per intersection.  Whole frames against the
+    oracle."""
     W, H = 4128, 1056
     assert ((W + 15) // 16) * ((H + 15) // 16) > 16384
     w = small_workload(43, W, H, 4000, 2, trajectory=True, ls=(-4.5, 0.5))
-    frames = [0, 1]
-    pix, refs, _ = sampled_tiles(w, frames, 44, n_random=4, label="large grid")
-    dls, dl = sampled_upstream(w, frames, pix, refs, 44)
+    refs = whole_frames(w, "large grid")
+    dls, dl = whole_upstream(w, refs, 44)
     say("[large grid] gpu batch")
     out, ws, _ = run_clip(w, dl=dl)
-    check_sampled_pixels(out["images"].cpu().numpy(), frames, pix, refs, w, "large grid")
+    check_frames(out["images"].cpu().numpy(), refs, w, "large grid")
     say("[large grid] oracle backward")
-    g_ref, dposes_ref, _ = oracle.render_clip_grads(w["scene"], w["camera"], w["poses"].astype(np.float64),
-                                                    w["times"], frames, pix, dls)
-    ge = compare_grads(out["grads"], g_ref, "large grid")
-    pe = compare_poses(out["dL_dposes"].cpu().numpy()[frames], dposes_ref[frames], "large grid")
+    g_ref, dposes_ref, mag = clip_grads(w, dls)
+    ge = compare_grads(out["grads"], g_ref, "large grid", mag=mag)
+    pe = compare_poses(out["dL_dposes"], dposes_ref, "large grid")
     say(f"[large grid] grads={ge} pose={pe:.2e} intersections={ws.status()['intersections']}")
