@@ -182,10 +182,10 @@ def cpu_protocol(dev) -> dict:
     host, in its per-pixel definition and in its tiled form, next to the GPU's
     plain per-frame path on the same frames: the 128x128 frame of 2k Gaussians
     in full (all threads and one thread), one full 960x540 frame of 100k
-    Gaussians, the first two frames of the benchmark clip in full, and the
-    first two frames of the 1920x1080 clip of 500k Gaussians (the per-pixel
-    definition on a stated pixel sample, extrapolated by pixel count; the
-    tiled form on whole frames)."""
+    Gaussians, and the first two frames of the benchmark clip and of the
+    1920x1080 clip of 500k Gaussians (for these two the per-pixel definition
+    on a stated pixel sample, extrapolated by pixel count; the tiled form
+    always on whole frames)."""
     import torch
     import gv_synth
     import oracle
@@ -241,7 +241,7 @@ def cpu_protocol(dev) -> dict:
         return (t1 - t0) * scale, (t2 - t1) * scale
 
     plan = [("frame128_n2k", [0], None, [threads, 1]), ("frame540p_n100k", [0], None, [threads]),
-            ("clip540p_f50_n200k", [0, 1], None, [threads]), ("clip1080p_f32_n500k_bf16", [0, 1], 20736, [threads])]
+            ("clip540p_f50_n200k", [0, 1], 51840, [threads]), ("clip1080p_f32_n500k_bf16", [0, 1], 20736, [threads])]
     for name, frames, npx, thread_list in plan:
         w = gv_synth.make_workload(name, seed=0, targets=False)
         gpu_s = gpu_per_frame(w, frames)
