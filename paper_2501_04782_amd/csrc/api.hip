@@ -31,7 +31,7 @@ hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t count, unsi
 
 static thread_local int32_t g_last_hip = 0;
 static std::mutex g_tune_mu;
-static Tuning g_tune = {256, 1024, 128, 4};  // the autotuner's choice on the 960x540 benchmark clip
+static Tuning g_tune = {256, 1024, 128, 12};  // the autotuner's choice on the 960x540 benchmark clip
 
 Tuning current_tuning() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -600,7 +600,7 @@ gv_status gv_set_tuning(const gv_tuning* t) {
     if (t->bwd_batch != 0 && !batch_ok(t->bwd_batch)) return GV_ERR_INVALID_ARG;
     if (t->sort_cap != 512 && t->sort_cap != 1024 && t->sort_cap != 2048 && t->sort_cap != 4096)
         return GV_ERR_INVALID_ARG;
-    if (t->compact < 0 || t->compact > 7) return GV_ERR_INVALID_ARG;
+    if (t->compact < 0 || t->compact > 15) return GV_ERR_INVALID_ARG;
     Tuning n = current_tuning();
     n.batch = t->batch;
     n.bwd_batch = t->bwd_batch ? t->bwd_batch : t->batch;
@@ -648,7 +648,7 @@ static bool cached_tuning(const char* path, const TuneKey& key, Tuning& out) {
 static bool tuning_valid(const Tuning& t) {
     return batch_ok(t.batch) && batch_ok(t.bwd_batch) &&
            (t.sort_cap == 512 || t.sort_cap == 1024 || t.sort_cap == 2048 || t.sort_cap == 4096) && t.compact >= 0 &&
-           t.compact <= 7;
+           t.compact <= 15;
 }
 
 gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* poses, const float* times,
@@ -699,27 +699,31 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
     // The stages are independent (no stage's output depends on another
     // stage's kernel variant), so every stage keeps its own fastest option,
     // timed on every run that used it.  Options: forward kernel (4x4-block,
-    // quadrant or compacted) x LDS batch (64, 128, 256); backward batch (64,
-    // 128, 256) of the quadrant adjoint; sort capacity (512 ... 4096).  Run c
-    // takes forward option c, backward option c mod 3 and sort option c mod 4,
-    // so nine runs per round try every option of every stage.  The compacted
-    // backward (LDS atomics per lane) measured ten times slower than the
-    // quadrant backward on every clip tried and is left to gv_set_tuning.
-    constexpr int NF = 9, NB = 3, NS = 4;
+    // quadrant or compacted) x LDS batch (64, 128, 256); backward kernel
+    // (one quadrant per wave at batch 64, 128, 256; two quadrants per wave at
+    // batch 64, 128); sort capacity (512 ... 4096).  Run c takes forward
+    // option c, backward option c mod 5 and sort option c mod 4, so ten runs
+    // per round try every option of every stage.  The compacted backward (LDS
+    // atomics per lane) measured ten times slower than the quadrant backward
+    // on every clip tried and is left to gv_set_tuning.
+    constexpr int NF = 10, NB = 5, NS = 4;
     const int f_kernel[3] = {0, 4, 1};
     const int batches[3] = {64, 128, 256};
+    const int b_batch[NB] = {64, 128, 256, 64, 128};
+    const int b_pair[NB] = {0, 0, 0, 8, 8};
     const int caps[NS] = {512, 1024, 2048, 4096};
-    float fwd_ms[NF] = {}, bwd_ms[NB] = {}, sort_ms[NS] = {};
-    int bwd_n[NB] = {}, sort_n[NS] = {};
+    float fwd_ms[9] = {}, bwd_ms[NB] = {}, sort_ms[NS] = {};
+    int fwd_n[9] = {}, bwd_n[NB] = {}, sort_n[NS] = {};
     // Round-robin over the runs, so that clock or cache drift during the
     // measurement affects all options alike; round 0 warms up.
     constexpr int REPS = 3;
     for (int r = 0; r <= REPS && result == GV_OK; ++r) {
         for (int c = 0; c < NF && result == GV_OK; ++c) {
             Tuning t = saved;
-            t.compact = f_kernel[c / 3];
-            t.batch = batches[c % 3];
-            t.bwd_batch = batches[c % NB];
+            const int fc = c % 9;  // the tenth run repeats forward option 0
+            t.compact = f_kernel[fc / 3] | b_pair[c % NB];
+            t.batch = batches[fc % 3];
+            t.bwd_batch = b_batch[c % NB];
             t.sort_cap = caps[c % NS];
             install_tuning(t);
             gv_status s = enqueue_batch(scene, cam, poses, times, frames, targets, nullptr, flags, images, loss,
@@ -735,7 +739,8 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
             if (r == 0) continue;
             float ms[GV_STAGES];
             for (int i = 0; i < GV_STAGES; ++i) hipEventElapsedTime(&ms[i], tm.ev[i], tm.ev[i + 1]);
-            fwd_ms[c] += ms[4];
+            fwd_ms[c % 9] += ms[4];
+            fwd_n[c % 9] += 1;
             bwd_ms[c % NB] += ms[6];
             bwd_n[c % NB] += 1;
             sort_ms[c % NS] += ms[3];
@@ -745,15 +750,15 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
     best = saved;
     if (result == GV_OK) {
         int bf = 0, bb = 0, bs = 0;
-        for (int c = 1; c < NF; ++c)
-            if (fwd_ms[c] < fwd_ms[bf]) bf = c;
+        for (int c = 1; c < 9; ++c)
+            if (fwd_ms[c] / fwd_n[c] < fwd_ms[bf] / fwd_n[bf]) bf = c;
         for (int c = 1; c < NB; ++c)
             if (bwd_ms[c] / bwd_n[c] < bwd_ms[bb] / bwd_n[bb]) bb = c;
         for (int c = 1; c < NS; ++c)
             if (sort_ms[c] / sort_n[c] < sort_ms[bs] / sort_n[bs]) bs = c;
-        best.compact = f_kernel[bf / 3];
+        best.compact = f_kernel[bf / 3] | b_pair[bb];
         best.batch = batches[bf % 3];
-        best.bwd_batch = batches[bb];
+        best.bwd_batch = b_batch[bb];
         best.sort_cap = caps[bs];
     }
     install_tuning(result == GV_OK ? best : saved);

@@ -576,6 +576,251 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
 }
 
 // ---------------------------------------------------------------------------
+// Paired-quadrant adjoint.  A 128-thread workgroup owns a 16x16 tile: wave w
+// takes the quadrants 2w (lanes 0-31) and 2w + 1 (lanes 32-63), the top or
+// bottom half of the tile, and each lane two pixels of its quadrant, (x, y)
+// and (x, y + 4).  Each half-wave walks its own quadrant's list (the two
+// lists padded with the inert entry to a common length of whole groups); a
+// lane adds its two pixels' partials in registers, and one reduce-scatter
+// over the 32 lanes of each half (one instruction stream for both halves)
+// leaves lane l of a half with the sums 2l and 2l + 1 of that half's group.
+// The reduce-scatter is thus paid once per 128 pixels instead of once per 64.
+// The two quadrants of a wave add their sums into one zeroed LDS slot per
+// entry and partial: two addends give the same sum in either order, so the
+// result does not depend on the order of the LDS additions.
+// ---------------------------------------------------------------------------
+constexpr int WG2 = 128;
+
+// Sums over the 32 lanes of each half-wave of 64 values at once: lane l
+// (l < 32 within its half) ends with the half's totals of values 2l (return
+// .x) and 2l + 1 (.y).  Stages: lane bit 4 (cross-row swap), bit 3 (row
+// rotate by 8), bit 2 (row half-mirror), bits 1 and 0 (quad permutations);
+// the order of additions is fixed.
+__device__ __forceinline__ float2 reduce_scatter32x2(float (&v)[64], int lane) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 32]), false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = dpp_pair_add_ror8(v[i], v[i + 16]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = dpp_pair_add_mirror(v[i], v[i + 8]);
+    const bool b1 = lane & 2, b0 = lane & 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float keep = b1 ? v[i + 4] : v[i], send = b1 ? v[i] : v[i + 4];
+        v[i] = keep + dpp_f(send, 0x4E);  // quad_perm [2,3,0,1] (partner lane ^ 2)
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float keep = b0 ? v[i + 2] : v[i], send = b0 ? v[i] : v[i + 2];
+        v[i] = keep + dpp_f(send, 0xB1);  // quad_perm [1,0,3,2] (partner lane ^ 1)
+    }
+    return make_float2(v[0], v[1]);
+}
+
+template <int B>
+__global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k_composite_bwd2(Args a) {
+    static_assert(B <= WG2, "one staged entry per thread");
+    if (overflowed(a.status)) return;
+    const int f = blockIdx.y;
+    const int tile = blockIdx.x;
+    const int txi = tile % a.tiles_x, tyi = tile / a.tiles_x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int h = lane >> 5, hl = lane & 31;
+    const int quad = 2 * w + h;
+    const int lx = (h << 3) | (hl & 7), lyA = (w << 3) | (hl >> 3), lyB = lyA + 4;
+    const int px = txi * TILE + lx, pyA = tyi * TILE + lyA, pyB = tyi * TILE + lyB;
+    const bool inA = px < a.width && pyA < a.height, inB = px < a.width && pyB < a.height;
+    const int64_t seg = static_cast<int64_t>(f) * a.tiles + tile;
+    uint32_t s, e;
+    bucket_range(a, seg, s, e);
+    const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
+    const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
+
+    __shared__ Staged sh[B + 1];
+    __shared__ uint32_t shm[B];
+    __shared__ float acc[WG2 / 64][9][B];
+    __shared__ uint32_t wl[WG2 / 64][2][B + RS_GROUP];
+    __shared__ uint32_t qlast[4];
+    if (tid == 0) stage_inert(sh[B]);
+    for (int i = tid; i < (WG2 / 64) * 9 * B; i += WG2) (&acc[0][0][0])[i] = 0.0f;
+
+    // per-pixel state (pixels A and B of this lane), as in the quadrant adjoint
+    float TA = 1.0f, GSA = 0.0f, gA0 = 0.0f, gA1 = 0.0f, gA2 = 0.0f;
+    float TB = 1.0f, GSB = 0.0f, gB0 = 0.0f, gB1 = 0.0f, gB2 = 0.0f;
+    uint32_t lastA = 0, lastB = 0;
+    {
+        const int64_t P = static_cast<int64_t>(a.width) * a.height;
+        auto load = [&](int py, float& T, float& GS, float& g0, float& g1, float& g2, uint32_t& last) {
+            const int64_t pix = static_cast<int64_t>(py) * a.width + px;
+            T = a.tfin[static_cast<int64_t>(f) * P + pix];
+            last = a.nlast[static_cast<int64_t>(f) * P + pix];
+            const int64_t o3 = static_cast<int64_t>(f) * 3 * P + pix;
+            if (a.targets) {
+                g0 = (a.images[o3] - a.targets[o3]) * a.loss_scale;
+                g1 = (a.images[o3 + P] - a.targets[o3 + P]) * a.loss_scale;
+                g2 = (a.images[o3 + 2 * P] - a.targets[o3 + 2 * P]) * a.loss_scale;
+            } else {
+                g0 = a.dl_dimages[o3];
+                g1 = a.dl_dimages[o3 + P];
+                g2 = a.dl_dimages[o3 + 2 * P];
+            }
+            GS = T * (g0 * a.bg[0] + g1 * a.bg[1] + g2 * a.bg[2]);
+        };
+        if (inA) load(pyA, TA, GSA, gA0, gA1, gA2, lastA);
+        if (inB) load(pyB, TB, GSB, gB0, gB1, gB2, lastB);
+    }
+    // last contributor of each quadrant (maximum over its 64 pixels)
+    uint32_t qmax = max(lastA, lastB);
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) qmax = max(qmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(qmax), d)));
+    if (hl == 0) qlast[quad] = qmax;
+    __syncthreads();
+    const uint32_t used = max(max(qlast[0], qlast[1]), max(qlast[2], qlast[3]));
+    const uint32_t wq0 = qlast[2 * w], wq1 = qlast[2 * w + 1];
+    uint32_t gnext = 0;
+    {
+        const uint32_t b0f = used > B ? s + used - B : s;
+        if (tid < static_cast<int>(s + used - b0f)) gnext = a.sgid[b0f + tid];
+    }
+    for (uint32_t i = s + used + tid; i < e; i += WG2) {
+        const uint32_t slot = a.sslot[i];
+        if (slot >= a.k_cap) continue;
+        const float z[PART] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        store_partials(a.part, slot, z);
+    }
+    const float fx = static_cast<float>(lx), fyA = static_cast<float>(lyA), fyB = static_cast<float>(lyB);
+    constexpr uint32_t INERT = static_cast<uint32_t>(B) * STAGED_BYTES;
+
+    for (int64_t bend = static_cast<int64_t>(s) + used; bend > s; bend -= B) {
+        const uint32_t b0 = static_cast<uint32_t>(bend - B > s ? bend - B : s);
+        const uint32_t nb = static_cast<uint32_t>(bend - b0);
+        if (tid < static_cast<int>(nb)) {
+            Staged st;
+            float3 conic;
+            stage_entry(a, f, gnext, ox, oy, st, conic);
+            sh[tid] = st;
+            shm[tid] = quadrant_mask(st, conic, xlim, ylim);
+        }
+        __syncthreads();
+        const uint32_t slot = tid < static_cast<int>(nb) ? a.sslot[b0 + tid] : 0u;
+        if (b0 > s) {
+            const uint32_t b0n = b0 - s > B ? b0 - B : s;
+            if (tid < static_cast<int>(b0 - b0n)) gnext = a.sgid[b0n + tid];
+        }
+        // the two quadrants' lists of this wave, back to front
+        int cnt0 = 0, cnt1 = 0;
+        for (int j0 = static_cast<int>(nb) - 1; j0 >= 0; j0 -= 64) {
+            const int j = j0 - lane;
+            const uint32_t m = j >= 0 ? shm[j] : 0u;
+            const uint32_t rel = b0 + static_cast<uint32_t>(j) - s;
+            const bool on0 = ((m >> (2 * w)) & 1u) && rel < wq0;
+            const bool on1 = ((m >> (2 * w + 1)) & 1u) && rel < wq1;
+            const uint64_t bal0 = __ballot(on0), bal1 = __ballot(on1);
+            const uint64_t below = (1ull << lane) - 1ull;
+            if (on0) wl[w][0][cnt0 + __popcll(bal0 & below)] = static_cast<uint32_t>(j) * STAGED_BYTES;
+            if (on1) wl[w][1][cnt1 + __popcll(bal1 & below)] = static_cast<uint32_t>(j) * STAGED_BYTES;
+            cnt0 += __popcll(bal0);
+            cnt1 += __popcll(bal1);
+        }
+        const int npad = (max(cnt0, cnt1) + RS_GROUP - 1) / RS_GROUP * RS_GROUP;
+        for (int k = cnt0 + lane; k < npad; k += 64) wl[w][0][k] = INERT;
+        for (int k = cnt1 + lane; k < npad; k += 64) wl[w][1][k] = INERT;
+        const int mycnt = h ? cnt1 : cnt0;
+        auto limit = [&](uint32_t last) {
+            const int64_t rl = static_cast<int64_t>(last) - (static_cast<int64_t>(b0) - s);
+            return static_cast<int>(rl < 0 ? 0 : (rl > B ? B : rl)) * static_cast<int>(STAGED_BYTES);
+        };
+        const int limA = limit(lastA), limB = limit(lastB);
+        const uint32_t* mylist = wl[w][h];
+        __builtin_amdgcn_wave_barrier();
+        for (int g = 0; g < npad; g += RS_GROUP) {
+            float P[64];
+            P[63] = 0.0f;
+            uint32_t J[RS_GROUP];
+            float4 P0[RS_GROUP], P1[RS_GROUP];
+            float2 P2[RS_GROUP];
+#pragma unroll
+            for (int r = 0; r < RS_GROUP; ++r) J[r] = mylist[g + r];
+#pragma unroll
+            for (int r = 0; r < RS_GROUP; ++r) {
+                const Staged& st = staged_at(sh, J[r]);
+                P0[r] = st.p0;
+                P1[r] = st.p1;
+                P2[r] = make_float2(st.p2.x, st.p2.y);
+            }
+#pragma unroll
+            for (int r = 0; r < RS_GROUP; ++r) {
+                const float4 p0 = P0[r];
+                const float4 p1 = P1[r];
+                const float dx = fx - p0.x, dyA = fyA - p0.y, dyB = fyB - p0.y;
+                const float qA = footprint_q(dx, dyA, p0, p1);
+                const float qB = footprint_q(dx, dyB, p0, p1);
+                const bool onA = (static_cast<int>(J[r]) < limA) & (qA >= P2[r].y);
+                const bool onB = (static_cast<int>(J[r]) < limB) & (qB >= P2[r].y);
+                const float rawA = __builtin_amdgcn_exp2f(qA), rawB = __builtin_amdgcn_exp2f(qB);
+                const float alA = onA ? fminf(ALPHA_MAX, rawA) : 0.0f;
+                const float alB = onB ? fminf(ALPHA_MAX, rawB) : 0.0f;
+                const float invA = __builtin_amdgcn_rcpf(1.0f - alA), invB = __builtin_amdgcn_rcpf(1.0f - alB);
+                const float aiA = alA * invA, aiB = alB * invB;
+                const float wA = aiA * TA, wB = aiB * TB;  // alpha T_j
+                TA = TA * invA;
+                TB = TB * invB;
+                // colour partials summed over the two pixels; alpha dL/dalpha
+                // per pixel as in the quadrant adjoint
+                const float cA0 = wA * gA0, cA1 = wA * gA1, cA2 = wA * gA2;
+                const float wgcA = __builtin_fmaf(P2[r].x, cA2, __builtin_fmaf(p1.w, cA1, p1.z * cA0));
+                const float gcB = __builtin_fmaf(P2[r].x, gB2, __builtin_fmaf(p1.w, gB1, p1.z * gB0));
+                const float wgcB = wB * gcB;
+                P[r * 9 + 6] = __builtin_fmaf(wB, gB0, cA0);
+                P[r * 9 + 7] = __builtin_fmaf(wB, gB1, cA1);
+                P[r * 9 + 8] = __builtin_fmaf(wB, gB2, cA2);
+                const float DalA = __builtin_fmaf(-aiA, GSA, wgcA), DalB = __builtin_fmaf(-aiB, GSB, wgcB);
+                GSA = GSA + wgcA;
+                GSB = GSB + wgcB;
+                const float DA = rawA < ALPHA_MAX ? DalA : 0.0f;
+                const float DB = rawB < ALPHA_MAX ? DalB : 0.0f;
+                // moments over both pixels (they share dx)
+                const float Ds = DA + DB;
+                const float X = Ds * dx;
+                const float YA = DA * dyA, YB = DB * dyB;
+                const float Y = YA + YB;
+                P[r * 9 + 0] = X;
+                P[r * 9 + 1] = Y;
+                P[r * 9 + 2] = X * dx;
+                P[r * 9 + 3] = Y * dx;
+                P[r * 9 + 4] = __builtin_fmaf(YA, dyA, YB * dyB);
+                P[r * 9 + 5] = Ds;
+            }
+            const float2 tot = reduce_scatter32x2(P, lane);
+            const int i0 = 2 * hl, r0 = i0 / 9, r1 = (i0 + 1) / 9;
+            if (g + r0 < mycnt) atomicAdd(&acc[w][i0 - 9 * r0][mylist[g + r0] / STAGED_BYTES], tot.x);
+            if (i0 + 1 < 9 * RS_GROUP && g + r1 < mycnt)
+                atomicAdd(&acc[w][i0 + 1 - 9 * r1][mylist[g + r1] / STAGED_BYTES], tot.y);
+        }
+        __syncthreads();
+        if (tid < static_cast<int>(nb)) {
+            // the two waves' sums in a fixed order; the slots are cleared for
+            // the next batch
+            float v[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                v[k] = acc[0][k][tid] + acc[1][k][tid];
+                acc[0][k][tid] = 0.0f;
+                acc[1][k][tid] = 0.0f;
+            }
+            const Staged st = sh[tid];
+            finish_partials(v, st.p0.z * INV_K_EXP, 0.5f * st.p0.w * INV_K_EXP, st.p1.x * INV_K_EXP, st.p2.w);
+            if (slot < a.k_cap) store_partials(a.part, slot, v);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Compacted variant.  The quadrant loop above issues every staged entry to all
 // 64 lanes of a wave although a small Gaussian covers only a fraction of the
 // 8x8 quadrant.  Here each batch is processed in two phases:
@@ -1133,6 +1378,13 @@ hipError_t launch_composite_bwd(const Args& a, hipStream_t stream) {
             case 128: hipLaunchKernelGGL(k_composite_bwd_c<128>, grid, block, 0, stream, a); break;
             default: hipLaunchKernelGGL(k_composite_bwd_c<256>, grid, block, 0, stream, a); break;
         }
+        return hipGetLastError();
+    }
+    if (a.tune.compact & 8) {  // paired quadrants (batches of at most 128)
+        if (a.tune.bwd_batch == 64)
+            hipLaunchKernelGGL(k_composite_bwd2<64>, grid, dim3(WG2), 0, stream, a);
+        else
+            hipLaunchKernelGGL(k_composite_bwd2<128>, grid, dim3(WG2), 0, stream, a);
         return hipGetLastError();
     }
     switch (a.tune.bwd_batch) {

@@ -172,12 +172,14 @@ def test_empty_and_single_gaussian():
 
 
 # compact: 0 sub-block forward, 4 quadrant forward, 1 compacted forward;
-# + 2 compacted backward (else the quadrant backward)
+# + 2 compacted backward, + 8 paired-quadrant backward (else the quadrant
+# backward)
 @pytest.mark.parametrize("compact,batch,sort_cap", [(0, 256, 4096), (0, 128, 2048), (0, 64, 1024),
                                                     (4, 256, 4096), (4, 128, 2048), (4, 64, 1024),
                                                     (3, 256, 4096), (3, 128, 2048), (3, 64, 1024),
                                                     (1, 128, 2048), (2, 256, 2048), (6, 64, 1024),
-                                                    (4, 64, 512)])
+                                                    (4, 64, 512), (12, 64, 1024), (12, 128, 2048),
+                                                    (12, 256, 4096), (8, 128, 512)])
 def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
     """Batched path on a reduced clip (moving camera, several frames) under
     every setting the autotuner can choose."""
@@ -194,7 +196,8 @@ def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
 # global merges; two runs merged in LDS; one LDS pass at the largest capacity
 @pytest.mark.parametrize("n,cap,regime,compact", [(5000, 1024, "global", 4), (1600, 1024, "two runs", 4),
                                                   (3000, 4096, "one pass", 4), (1600, 512, "global", 4),
-                                                  (5000, 1024, "global", 6)])
+                                                  (5000, 1024, "global", 6), (5000, 1024, "global", 12),
+                                                  (1600, 512, "global", 12)])
 def test_long_tile_buckets(n, cap, regime, compact):
     """Many large Gaussians over a small image: buckets beyond the LDS sort
     capacity, between one and two capacities, and within the largest one."""
