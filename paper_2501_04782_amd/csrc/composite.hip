@@ -10,6 +10,8 @@
 // terminates and a workgroup stops staging once every pixel has terminated.
 #include "gv_internal.h"
 
+#include <type_traits>
+
 namespace gv {
 
 // One staged entry, 48 bytes.  The conic is stored pre-multiplied by
@@ -129,6 +131,30 @@ __device__ __forceinline__ uint32_t quadrant_mask(const Staged& st, float3 cn, i
 
 __device__ __forceinline__ uint32_t block_mask(const Staged& st, float3 cn, int xlim, int ylim) {
     return band_mask<4>(st, cn, xlim, ylim);
+}
+
+// Whether the entry's alpha can reach the clamp ALPHA_MAX at some pixel of
+// the tile.  For a positive-definite conic the exact exponent
+// K_EXP q + log2 o never exceeds log2 o.  footprint_q evaluates it with five
+// roundings of terms bounded by M = |K a| dx^2 + |2 K b| |dx dy| + |K c| dy^2
+// + |log2 o| over the tile's pixel offsets, so it errs by less than
+// 6 u M < 1e-6 M (u = 2^-24), and exp2 by about one ulp: alpha stays below
+// ALPHA_MAX at every pixel of the tile when log2 o + 1e-6 M is below
+// log2(ALPHA_MAX) - 1e-5.  A conic that is not clearly positive definite
+// after rounding may clamp.  The paired adjoint drops the clamp from its
+// per-pixel loop for a batch in which no entry of a wave's lists can reach
+// it, with identical results.
+constexpr uint32_t MAY_CLAMP_BIT = 0x80000000u;  // in the staged block masks
+constexpr float LOG2_ALPHA_MAX = -0.014499569695115091f;  // log2(0.99)
+
+__device__ __forceinline__ bool may_clamp(const Staged& st, float3 cn) {
+    const double a = cn.x, b = cn.y, c = cn.z;
+    if (!(a > 0.0) || !(a * c - b * b > 1e-6 * a * c)) return true;
+    const float lu = st.p0.x, lv = st.p0.y;
+    const float dx = fmaxf(fabsf(lu), fabsf(static_cast<float>(TILE - 1) - lu));
+    const float dy = fmaxf(fabsf(lv), fabsf(static_cast<float>(TILE - 1) - lv));
+    const float m = fabsf(st.p0.z) * dx * dx + fabsf(st.p0.w) * dx * dy + fabsf(st.p1.x) * dy * dy + fabsf(st.p1.y);
+    return !(st.p1.y + 1e-6f * m < LOG2_ALPHA_MAX - 1e-5f);
 }
 
 // Inert entry that pads the wave lists to whole groups (never reaches a pixel).
@@ -703,7 +729,7 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
             float3 conic;
             stage_entry(a, f, gnext, ox, oy, st, conic);
             sh[tid] = st;
-            shm[tid] = quadrant_mask(st, conic, xlim, ylim);
+            shm[tid] = quadrant_mask(st, conic, xlim, ylim) | (may_clamp(st, conic) ? MAY_CLAMP_BIT : 0u);
         }
         __syncthreads();
         const uint32_t slot = tid < static_cast<int>(nb) ? a.sslot[b0 + tid] : 0u;
@@ -713,6 +739,7 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
         // the two quadrants' lists of this wave, back to front
         int cnt0 = 0, cnt1 = 0;
+        bool clamp = false;  // some entry of the two lists may clamp (wave-uniform)
         for (int j0 = static_cast<int>(nb) - 1; j0 >= 0; j0 -= 64) {
             const int j = j0 - lane;
             const uint32_t m = j >= 0 ? shm[j] : 0u;
@@ -725,6 +752,7 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
             if (on1) wl[w][1][cnt1 + __popcll(bal1 & below)] = static_cast<uint32_t>(j) * STAGED_BYTES;
             cnt0 += __popcll(bal0);
             cnt1 += __popcll(bal1);
+            clamp = clamp || __ballot((on0 || on1) && (m & MAY_CLAMP_BIT)) != 0ull;
         }
         const int npad = (max(cnt0, cnt1) + RS_GROUP - 1) / RS_GROUP * RS_GROUP;
         for (int k = cnt0 + lane; k < npad; k += 64) wl[w][0][k] = INERT;
@@ -737,6 +765,10 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int limA = limit(lastA), limB = limit(lastB);
         const uint32_t* mylist = wl[w][h];
         __builtin_amdgcn_wave_barrier();
+        // the group loop, with or without the alpha clamp (identical results
+        // when no entry can reach it)
+        auto groups = [&](auto clamp_tag) {
+        constexpr bool CLAMP = decltype(clamp_tag)::value;
         for (int g = 0; g < npad; g += RS_GROUP) {
             float P[64];
             P[63] = 0.0f;
@@ -762,8 +794,8 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
                 const bool onA = (static_cast<int>(J[r]) < limA) & (qA >= P2[r].y);
                 const bool onB = (static_cast<int>(J[r]) < limB) & (qB >= P2[r].y);
                 const float rawA = __builtin_amdgcn_exp2f(qA), rawB = __builtin_amdgcn_exp2f(qB);
-                const float alA = onA ? fminf(ALPHA_MAX, rawA) : 0.0f;
-                const float alB = onB ? fminf(ALPHA_MAX, rawB) : 0.0f;
+                const float alA = onA ? (CLAMP ? fminf(ALPHA_MAX, rawA) : rawA) : 0.0f;
+                const float alB = onB ? (CLAMP ? fminf(ALPHA_MAX, rawB) : rawB) : 0.0f;
                 const float invA = __builtin_amdgcn_rcpf(1.0f - alA), invB = __builtin_amdgcn_rcpf(1.0f - alB);
                 const float aiA = alA * invA, aiB = alB * invB;
                 const float wA = aiA * TA, wB = aiB * TB;  // alpha T_j
@@ -781,8 +813,8 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
                 const float DalA = __builtin_fmaf(-aiA, GSA, wgcA), DalB = __builtin_fmaf(-aiB, GSB, wgcB);
                 GSA = GSA + wgcA;
                 GSB = GSB + wgcB;
-                const float DA = rawA < ALPHA_MAX ? DalA : 0.0f;
-                const float DB = rawB < ALPHA_MAX ? DalB : 0.0f;
+                const float DA = !CLAMP || rawA < ALPHA_MAX ? DalA : 0.0f;
+                const float DB = !CLAMP || rawB < ALPHA_MAX ? DalB : 0.0f;
                 // moments over both pixels (they share dx)
                 const float Ds = DA + DB;
                 const float X = Ds * dx;
@@ -801,6 +833,11 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
             if (i0 + 1 < 9 * RS_GROUP && g + r1 < mycnt)
                 atomicAdd(&acc[w][i0 + 1 - 9 * r1][mylist[g + r1] / STAGED_BYTES], tot.y);
         }
+        };
+        if (clamp)
+            groups(std::true_type{});
+        else
+            groups(std::false_type{});
         __syncthreads();
         if (tid < static_cast<int>(nb)) {
             // the two waves' sums in a fixed order; the slots are cleared for

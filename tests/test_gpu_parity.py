@@ -192,6 +192,37 @@ def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
         raster.set_tuning(old["batch"], old["sort_cap"], old["compact"], old["bwd_batch"])
 
 
+@pytest.mark.parametrize("compact", [12, 4, 8, 0])
+def test_alpha_clamp_paths(compact):
+    """Opaque Gaussians (opacity above 0.99) on the left half of the scene:
+    tiles there composite with the alpha clamp (alpha = 0.99, no opacity or
+    footprint gradient), tiles on the right without it, where the kernels drop
+    the clamp once no entry of a batch can reach it.  Both against the oracle,
+    under the paired and the one-quadrant adjoint and the quadrant and
+    4x4-block forwards."""
+    w = small_workload(51, 160, 96, 3000, 3, trajectory=True, z=(2.0, 10.0), ls=(-3.2, 0.5))
+    s = w["scene"]
+    left = s.means[0] < 0
+    s.opacity_logits[left] += 6.0
+    o = 1.0 / (1.0 + np.exp(-s.opacity_logits.astype(np.float64)))
+    assert (o[left] > 0.99).mean() > 0.5 and (o[~left] < 0.98).mean() > 0.99
+    # Gaussians whose alpha at the pixel centre nearest their centre is clamped
+    p = oracle.project(w["scene"], w["camera"], w["poses"][0].astype(np.float64), float(w["times"][0]))
+    vis = p["valid"] > 0
+    dx = np.floor(p["u"][vis]) + 0.5 - p["u"][vis]
+    dy = np.floor(p["v"][vis]) + 0.5 - p["v"][vis]
+    q = p["A00"][vis] * dx * dx + 2 * p["A01"][vis] * dx * dy + p["A11"][vis] * dy * dy
+    n_clamped = int((p["opacity"][vis] * np.exp(-0.5 * q) > 0.99).sum())
+    say(f"[alpha clamp] {n_clamped} Gaussians clamped at a pixel in frame 0")
+    assert n_clamped > 50
+    old = raster.get_tuning()
+    raster.set_tuning(256, 1024, compact, 128)
+    try:
+        check_clip_against_oracle(w, f"alpha clamp compact={compact}")
+    finally:
+        raster.set_tuning(old["batch"], old["sort_cap"], old["compact"], old["bwd_batch"])
+
+
 # (Gaussians, sort capacity, regime of the largest bucket): chunked LDS sort +
 # global merges; two runs merged in LDS; one LDS pass at the largest capacity
 @pytest.mark.parametrize("n,cap,regime,compact", [(5000, 1024, "global", 4), (1600, 1024, "two runs", 4),
