@@ -30,7 +30,7 @@ constexpr float SUB_Q_SLACK = 9.0f * (1.0f + 1e-4f) + 1e-4f;
 
 // Gaussians per workgroup of the LDS-histogram binning kernels, and the
 // largest tile grid whose histogram fits in LDS (64 KiB).
-constexpr int BIN_GROUP = 2048;
+constexpr int BIN_GROUP = 1024;
 constexpr int LDS_TILE_LIMIT = 16384;
 
 // Per (frame, Gaussian) projected record, 32 bytes (one aligned half-line).
