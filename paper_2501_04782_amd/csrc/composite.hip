@@ -671,17 +671,7 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ float acc[WG2 / 64][9][B];
     __shared__ uint32_t wl[WG2 / 64][2][B + RS_GROUP];
     __shared__ uint32_t qlast[4];
-    // the tile's origin and pixel limits, read by the staging threads once per
-    // batch (kept out of the registers the entry loop needs)
-    __shared__ double org[2];
-    __shared__ int lims[2];
-    if (tid == 0) {
-        stage_inert(sh[B]);
-        org[0] = ox;
-        org[1] = oy;
-        lims[0] = xlim;
-        lims[1] = ylim;
-    }
+    if (tid == 0) stage_inert(sh[B]);
     for (int i = tid; i < (WG2 / 64) * 9 * B; i += WG2) (&acc[0][0][0])[i] = 0.0f;
 
     // per-pixel state (pixels A and B of this lane), as in the quadrant adjoint
@@ -715,10 +705,8 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
     for (int d = 1; d < 32; d <<= 1) qmax = max(qmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(qmax), d)));
     if (hl == 0) qlast[quad] = qmax;
     __syncthreads();
-    // workgroup- and wave-uniform (scalar registers)
-    const uint32_t used = __builtin_amdgcn_readfirstlane(max(max(qlast[0], qlast[1]), max(qlast[2], qlast[3])));
-    const uint32_t wq0 = __builtin_amdgcn_readfirstlane(qlast[2 * w]);
-    const uint32_t wq1 = __builtin_amdgcn_readfirstlane(qlast[2 * w + 1]);
+    const uint32_t used = max(max(qlast[0], qlast[1]), max(qlast[2], qlast[3]));
+    const uint32_t wq0 = qlast[2 * w], wq1 = qlast[2 * w + 1];
     uint32_t gnext = 0;
     {
         const uint32_t b0f = used > B ? s + used - B : s;
@@ -739,11 +727,9 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (tid < static_cast<int>(nb)) {
             Staged st;
             float3 conic;
-            const volatile double* o2 = org;
-            const volatile int* l2 = lims;
-            stage_entry(a, f, gnext, o2[0], o2[1], st, conic);
+            stage_entry(a, f, gnext, ox, oy, st, conic);
             sh[tid] = st;
-            shm[tid] = quadrant_mask(st, conic, l2[0], l2[1]) | (may_clamp(st, conic) ? MAY_CLAMP_BIT : 0u);
+            shm[tid] = quadrant_mask(st, conic, xlim, ylim) | (may_clamp(st, conic) ? MAY_CLAMP_BIT : 0u);
         }
         __syncthreads();
         const uint32_t slot = tid < static_cast<int>(nb) ? a.sslot[b0 + tid] : 0u;
@@ -802,12 +788,11 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
             for (int r = 0; r < RS_GROUP; ++r) {
                 const float4 p0 = P0[r];
                 const float4 p1 = P1[r];
-                const float2 p2 = P2[r];  // (b, threshold)
                 const float dx = fx - p0.x, dyA = fyA - p0.y, dyB = fyB - p0.y;
                 const float qA = footprint_q(dx, dyA, p0, p1);
                 const float qB = footprint_q(dx, dyB, p0, p1);
-                const bool onA = (static_cast<int>(J[r]) < limA) & (qA >= p2.y);
-                const bool onB = (static_cast<int>(J[r]) < limB) & (qB >= p2.y);
+                const bool onA = (static_cast<int>(J[r]) < limA) & (qA >= P2[r].y);
+                const bool onB = (static_cast<int>(J[r]) < limB) & (qB >= P2[r].y);
                 const float rawA = __builtin_amdgcn_exp2f(qA), rawB = __builtin_amdgcn_exp2f(qB);
                 const float alA = onA ? (CLAMP ? fminf(ALPHA_MAX, rawA) : rawA) : 0.0f;
                 const float alB = onB ? (CLAMP ? fminf(ALPHA_MAX, rawB) : rawB) : 0.0f;
@@ -819,8 +804,8 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
                 // colour partials summed over the two pixels; alpha dL/dalpha
                 // per pixel as in the quadrant adjoint
                 const float cA0 = wA * gA0, cA1 = wA * gA1, cA2 = wA * gA2;
-                const float wgcA = __builtin_fmaf(p2.x, cA2, __builtin_fmaf(p1.w, cA1, p1.z * cA0));
-                const float gcB = __builtin_fmaf(p2.x, gB2, __builtin_fmaf(p1.w, gB1, p1.z * gB0));
+                const float wgcA = __builtin_fmaf(P2[r].x, cA2, __builtin_fmaf(p1.w, cA1, p1.z * cA0));
+                const float gcB = __builtin_fmaf(P2[r].x, gB2, __builtin_fmaf(p1.w, gB1, p1.z * gB0));
                 const float wgcB = wB * gcB;
                 P[r * 9 + 6] = __builtin_fmaf(wB, gB0, cA0);
                 P[r * 9 + 7] = __builtin_fmaf(wB, gB1, cA1);
