@@ -258,3 +258,46 @@ def test_tile_grid_beyond_lds_histogram():
     ge = compare_grads(out["grads"], g_ref, "large grid", mag=mag)
     pe = compare_poses(out["dL_dposes"], dposes_ref, "large grid")
     say(f"[large grid] grads={ge} pose={pe:.2e} intersections={ws.status()['intersections']}")
+
+
+def test_every_tuning_matches_default_full_size():
+    """Every setting the autotuner can choose, one axis at a time from the
+    default, on the benchmark clip with the fused L2 loss: images bitwise equal
+    to the default's (which the test above checks against the oracle on every
+    pixel), per-frame losses and all gradients equal up to the order of
+    summation.  The compacted backward, which the autotuner leaves out, is run
+    once as well."""
+    w = gv_synth.make_workload("clip540p_f50_n200k", targets=True)
+    scene, cam, poses, times = device_inputs(w)
+    targets = torch.from_numpy(w["targets"]).cuda()
+    ws = workspace_for(scene, cam, poses, times, margin=1.3)
+    base = dict(batch=256, sort_cap=1024, compact=12, bwd_batch=128)
+    settings = [dict(base, batch=b, compact=c | 8) for c in (0, 4, 1) for b in (64, 128, 256)]
+    settings += [dict(base, compact=c, bwd_batch=bb) for c, bb in ((4, 64), (4, 128), (4, 256), (12, 64), (6, 128))]
+    settings += [dict(base, sort_cap=cap) for cap in (512, 2048, 4096)]
+    old = raster.get_tuning()
+
+    def run(t):
+        raster.set_tuning(t["batch"], t["sort_cap"], t["compact"], t["bwd_batch"])
+        out = raster.render_batch(scene, cam, poses, times, ws, targets=targets)
+        torch.cuda.synchronize()
+        assert ws.status()["overflow"] == 0, t
+        return out
+
+    try:
+        ref = run(base)
+        ref_images = ref["images"].clone()
+        ref_loss = ref["loss"].cpu().numpy().astype(np.float64)
+        ref_grads = {k: v.cpu().numpy() for k, v in ref["grads"].items() if v is not None}
+        ref_dposes = ref["dL_dposes"].cpu().numpy()
+        for t in settings:
+            out = run(t)
+            assert torch.equal(out["images"], ref_images), t
+            dl = np.abs(out["loss"].cpu().numpy() - ref_loss) / ref_loss
+            assert dl.max() <= 1e-6, (t, dl.max())
+            ge = compare_grads(out["grads"], ref_grads, f"tuning {t}")
+            pe = compare_poses(out["dL_dposes"], ref_dposes, f"tuning {t}")
+            say(f"[tunings] {t}: images equal, loss {dl.max():.1e}, "
+                f"grads max rel {max(e for e, _ in ge.values()):.1e}, pose {pe:.1e}")
+    finally:
+        raster.set_tuning(old["batch"], old["sort_cap"], old["compact"], old["bwd_batch"])
