@@ -143,16 +143,19 @@ typedef struct {
  * (64, 128 or 256); sort_cap: longest per-tile list sorted in one LDS pass
  * (512, 1024, 2048 or 4096; lists up to twice that merge two LDS-sorted
  * runs, longer lists are sorted in chunks and merged in global memory);
- * compact: compositing kernel choice, 0..15.  With bit 2 set the forward lets
+ * compact: compositing kernel choice, 0..31.  With bit 2 set the forward lets
  * each wave walk the entries meeting its 8x8 quadrant; with it clear each
  * 16-lane row of a wave walks the entries meeting its 4x4 pixel block.  The
  * backward lets each wave walk one quadrant's entries (one pixel per lane),
- * or with bit 3 set two quadrants' entries, one per half-wave (two pixels
- * per lane; batches of 64 or 128, a bwd_batch of 256 runs as 128).  Bit 0
- * (forward) / bit 1 (backward), which take precedence, select kernels that
- * first build per-pixel entry lists from closed-form coverage masks;
+ * with bit 3 set two quadrants' entries, one per half-wave (two pixels per
+ * lane; batches of 64 or 128, a bwd_batch of 256 runs as 128), or with bit
+ * 4 set, which takes precedence over bit 3, all four quadrants' entries,
+ * one per 16-lane row (one wave per tile, four pixels per lane; batches of
+ * 64 whatever bwd_batch says).  Bit 0 (forward) / bit 1 (backward), which
+ * take precedence, select kernels that first build per-pixel entry lists
+ * from closed-form coverage masks;
  * bwd_batch: the backward's LDS batch (0 = same as batch).
- * Defaults: batch 256, sort_cap 1024, compact 12, bwd_batch 128.  Images are
+ * Defaults: batch 256, sort_cap 1024, compact 20, bwd_batch 64.  Images are
  * identical under every setting and gradients equal up to floating-point
  * rounding (order of summation, and the compacted backward's arithmetic);
  * only the speed differs. */

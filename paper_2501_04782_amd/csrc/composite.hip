@@ -32,9 +32,24 @@ constexpr float INV_K_EXP = 1.0f / K_EXP;
 // Exponent q' = K_EXP d^T A d + log2 o with d = pixel - centre (2^q' is the
 // unclamped alpha), and the entry's threshold.  Shared by every compositing
 // kernel, forward and adjoint, so that all of them re-derive the same values
-// and decisions.
+// and decisions.  Evaluated as dy (K c dy + K 2b dx) + (K a dx dx + log2 o):
+// the two terms in dx alone (footprint_row) are shared by the pixels of one
+// column.
+struct FootRow {
+    float t;  // K 2b dx
+    float s;  // K a dx dx + log2 o
+};
+
+__device__ __forceinline__ FootRow footprint_row(float dx, const float4& p0, const float4& p1) {
+    return FootRow{p0.w * dx, __builtin_fmaf(p0.z * dx, dx, p1.y)};
+}
+
+__device__ __forceinline__ float footprint_q(float dy, const FootRow& r, const float4& p1) {
+    return __builtin_fmaf(dy, __builtin_fmaf(p1.x, dy, r.t), r.s);
+}
+
 __device__ __forceinline__ float footprint_q(float dx, float dy, const float4& p0, const float4& p1) {
-    return __builtin_fmaf(p1.x * dy, dy, __builtin_fmaf(dx, __builtin_fmaf(p0.z, dx, p0.w * dy), p1.y));
+    return footprint_q(dy, footprint_row(dx, p0, p1), p1);
 }
 
 // log2 of the opacity as staged (-inf for o = 0, whose entries never pass)
@@ -858,6 +873,268 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint with one wave per tile.  A 64-thread workgroup owns a 16x16 tile:
+// lanes 16q .. 16q + 15 take quadrant q, each lane four pixels of one column
+// of it, rows r, r + 2, r + 4, r + 6 (r = 0 or 1).  Each 16-lane row walks its
+// own quadrant's list (the four lists padded with the inert entry to a common
+// length of whole groups); a lane adds its four pixels' partials in registers
+// (the pixels share dx and the exponent's terms in dx), and one
+// reduce-scatter over the 16 lanes of each row leaves lane l of a row with
+// the sums 2l and 2l + 1 of that row's RS4 entries: the reduce-scatter is paid
+// once per 256 pixels.  Quadrants 0 and 1 add their sums into one zeroed LDS
+// slot per entry and partial, quadrants 2 and 3 into another: two addends
+// give the same sum in either order, so the result does not depend on the
+// order of the LDS additions.
+// ---------------------------------------------------------------------------
+constexpr int WG4 = 64;
+constexpr int RS4 = 3;  // entries per group: 27 partials (+5 pads) per reduce-scatter
+
+// Sums over the 16 lanes of each row of 32 values at once: lane l (l < 16
+// within its row) ends with the row's totals of values 2l (.x) and 2l + 1
+// (.y).  Stages: lane bit 3 (row rotate by 8), bit 2 (row half-mirror), bits
+// 1 and 0 (quad permutations); the order of additions is fixed.
+__device__ __forceinline__ float2 reduce_scatter16x2(float (&v)[32], int lane) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = dpp_pair_add_ror8(v[i], v[i + 16]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = dpp_pair_add_mirror(v[i], v[i + 8]);
+    const bool b1 = lane & 2, b0 = lane & 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float keep = b1 ? v[i + 4] : v[i], send = b1 ? v[i] : v[i + 4];
+        v[i] = keep + dpp_f(send, 0x4E);  // quad_perm [2,3,0,1] (partner lane ^ 2)
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float keep = b0 ? v[i + 2] : v[i], send = b0 ? v[i] : v[i + 2];
+        v[i] = keep + dpp_f(send, 0xB1);  // quad_perm [1,0,3,2] (partner lane ^ 1)
+    }
+    return make_float2(v[0], v[1]);
+}
+
+template <int B>
+__global__ __launch_bounds__(WG4) __attribute__((amdgpu_waves_per_eu(4))) void k_composite_bwd4(Args a) {
+    static_assert(B <= WG4, "one staged entry per thread");
+    if (overflowed(a.status)) return;
+    const int f = blockIdx.y;
+    const int tile = blockIdx.x;
+    const int txi = tile % a.tiles_x, tyi = tile / a.tiles_x;
+    const int lane = threadIdx.x;
+    const int quad = lane >> 4, rl = lane & 15;
+    const int lx = ((quad & 1) << 3) | (rl & 7), ly0 = ((quad >> 1) << 3) | (rl >> 3);
+    const int px = txi * TILE + lx;
+    const int64_t seg = static_cast<int64_t>(f) * a.tiles + tile;
+    uint32_t s, e;
+    bucket_range(a, seg, s, e);
+    const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
+    const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
+
+    __shared__ Staged sh[B + 1];
+    __shared__ uint32_t shm[B];
+    __shared__ float acc[2][9][B];
+    __shared__ uint32_t wl[4][B + RS4];
+    __shared__ uint32_t qlast[4];
+    if (lane == 0) stage_inert(sh[B]);
+    for (int i = lane; i < 2 * 9 * B; i += WG4) (&acc[0][0][0])[i] = 0.0f;
+
+    // per-pixel state of the lane's four pixels, as in the quadrant adjoint
+    float T[4], GS[4], g0[4], g1[4], g2[4];
+    uint32_t last[4];
+    const int64_t P = static_cast<int64_t>(a.width) * a.height;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        T[k] = 1.0f;
+        GS[k] = g0[k] = g1[k] = g2[k] = 0.0f;
+        last[k] = 0u;
+        const int py = tyi * TILE + ly0 + 2 * k;
+        if (px < a.width && py < a.height) {
+            const int64_t pix = static_cast<int64_t>(py) * a.width + px;
+            T[k] = a.tfin[static_cast<int64_t>(f) * P + pix];
+            last[k] = a.nlast[static_cast<int64_t>(f) * P + pix];
+            const int64_t o3 = static_cast<int64_t>(f) * 3 * P + pix;
+            if (a.targets) {
+                g0[k] = (a.images[o3] - a.targets[o3]) * a.loss_scale;
+                g1[k] = (a.images[o3 + P] - a.targets[o3 + P]) * a.loss_scale;
+                g2[k] = (a.images[o3 + 2 * P] - a.targets[o3 + 2 * P]) * a.loss_scale;
+            } else {
+                g0[k] = a.dl_dimages[o3];
+                g1[k] = a.dl_dimages[o3 + P];
+                g2[k] = a.dl_dimages[o3 + 2 * P];
+            }
+            GS[k] = T[k] * (g0[k] * a.bg[0] + g1[k] * a.bg[1] + g2[k] * a.bg[2]);
+        }
+    }
+    // last contributor of each quadrant (maximum over its 64 pixels)
+    uint32_t qmax = max(max(last[0], last[1]), max(last[2], last[3]));
+#pragma unroll
+    for (int d = 1; d < 16; d <<= 1) qmax = max(qmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(qmax), d)));
+    if (rl == 0) qlast[quad] = qmax;
+    __syncthreads();
+    uint32_t wq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wq[q] = __builtin_amdgcn_readfirstlane(qlast[q]);
+    const uint32_t used = max(max(wq[0], wq[1]), max(wq[2], wq[3]));
+    uint32_t gnext = 0;
+    {
+        const uint32_t b0f = used > B ? s + used - B : s;
+        if (lane < static_cast<int>(s + used - b0f)) gnext = a.sgid[b0f + lane];
+    }
+    for (uint32_t i = s + used + lane; i < e; i += WG4) {
+        const uint32_t slot = a.sslot[i];
+        if (slot >= a.k_cap) continue;
+        const float z[PART] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        store_partials(a.part, slot, z);
+    }
+    const float fx = static_cast<float>(lx);
+    float fy[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fy[k] = static_cast<float>(ly0 + 2 * k);
+    constexpr uint32_t INERT = static_cast<uint32_t>(B) * STAGED_BYTES;
+    const int sl = quad >> 1;  // accumulation slot of this row's quadrant
+
+    for (int64_t bend = static_cast<int64_t>(s) + used; bend > s; bend -= B) {
+        const uint32_t b0 = static_cast<uint32_t>(bend - B > s ? bend - B : s);
+        const uint32_t nb = static_cast<uint32_t>(bend - b0);
+        if (lane < static_cast<int>(nb)) {
+            Staged st;
+            float3 conic;
+            stage_entry(a, f, gnext, ox, oy, st, conic);
+            sh[lane] = st;
+            shm[lane] = quadrant_mask(st, conic, xlim, ylim) | (may_clamp(st, conic) ? MAY_CLAMP_BIT : 0u);
+        }
+        __syncthreads();
+        const uint32_t slot = lane < static_cast<int>(nb) ? a.sslot[b0 + lane] : 0u;
+        if (b0 > s) {
+            const uint32_t b0n = b0 - s > B ? b0 - B : s;
+            if (lane < static_cast<int>(b0 - b0n)) gnext = a.sgid[b0n + lane];
+        }
+        // the four quadrants' lists, back to front
+        int cnt[4] = {0, 0, 0, 0};
+        bool clamp = false;  // some entry of the lists may clamp (uniform)
+        {
+            const int j = static_cast<int>(nb) - 1 - lane;  // nb <= 64: one pass
+            const uint32_t m = j >= 0 ? shm[j] : 0u;
+            const uint32_t rel = b0 + static_cast<uint32_t>(j) - s;
+            const uint64_t below = (1ull << lane) - 1ull;
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool on = ((m >> q) & 1u) && rel < wq[q];
+                const uint64_t bal = __ballot(on);
+                if (on) wl[q][__popcll(bal & below)] = static_cast<uint32_t>(j) * STAGED_BYTES;
+                cnt[q] = __popcll(bal);
+                any = any || on;
+            }
+            clamp = __ballot(any && (m & MAY_CLAMP_BIT)) != 0ull;
+        }
+        const int cmax = max(max(cnt[0], cnt[1]), max(cnt[2], cnt[3]));
+        const int npad = (cmax + RS4 - 1) / RS4 * RS4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            for (int k = cnt[q] + lane; k < npad; k += 64) wl[q][k] = INERT;
+        const int mycnt = quad == 0 ? cnt[0] : quad == 1 ? cnt[1] : quad == 2 ? cnt[2] : cnt[3];
+        int lim[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t r = static_cast<int64_t>(last[k]) - (static_cast<int64_t>(b0) - s);
+            lim[k] = static_cast<int>(r < 0 ? 0 : (r > B ? B : r)) * static_cast<int>(STAGED_BYTES);
+        }
+        const uint32_t* mylist = wl[quad];
+        __builtin_amdgcn_wave_barrier();
+        // the group loop, with or without the alpha clamp (identical results
+        // when no entry can reach it)
+        auto groups = [&](auto clamp_tag) {
+        constexpr bool CLAMP = decltype(clamp_tag)::value;
+        for (int g = 0; g < npad; g += RS4) {
+            float Pv[32];
+#pragma unroll
+            for (int i = 9 * RS4; i < 32; ++i) Pv[i] = 0.0f;
+            uint32_t J[RS4];
+            float4 P0[RS4], P1[RS4];
+            float2 P2[RS4];
+#pragma unroll
+            for (int r = 0; r < RS4; ++r) J[r] = mylist[g + r];
+#pragma unroll
+            for (int r = 0; r < RS4; ++r) {
+                const Staged& st = staged_at(sh, J[r]);
+                P0[r] = st.p0;
+                P1[r] = st.p1;
+                P2[r] = make_float2(st.p2.x, st.p2.y);
+            }
+#pragma unroll
+            for (int r = 0; r < RS4; ++r) {
+                const float4 p0 = P0[r];
+                const float4 p1 = P1[r];
+                const float2 p2 = P2[r];  // (b, threshold)
+                const float dx = fx - p0.x;
+                const FootRow fr = footprint_row(dx, p0, p1);
+                float Ds = 0.0f, Y = 0.0f, Ydy = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float dy = fy[k] - p0.y;
+                    const float q = footprint_q(dy, fr, p1);
+                    const bool on = (static_cast<int>(J[r]) < lim[k]) & (q >= p2.y);
+                    const float raw = __builtin_amdgcn_exp2f(q);
+                    const float al = on ? (CLAMP ? fminf(ALPHA_MAX, raw) : raw) : 0.0f;
+                    const float inv = __builtin_amdgcn_rcpf(1.0f - al);
+                    const float ai = al * inv;
+                    const float wk = ai * T[k];  // alpha T_j
+                    T[k] = T[k] * inv;
+                    const float gc = __builtin_fmaf(p2.x, g2[k], __builtin_fmaf(p1.w, g1[k], p1.z * g0[k]));
+                    const float wgc = wk * gc;
+                    c0 = __builtin_fmaf(wk, g0[k], c0);
+                    c1 = __builtin_fmaf(wk, g1[k], c1);
+                    c2 = __builtin_fmaf(wk, g2[k], c2);
+                    const float Dal = __builtin_fmaf(-ai, GS[k], wgc);
+                    GS[k] = GS[k] + wgc;
+                    const float D = !CLAMP || raw < ALPHA_MAX ? Dal : 0.0f;
+                    const float Yk = D * dy;
+                    Ds = Ds + D;
+                    Y = Y + Yk;
+                    Ydy = __builtin_fmaf(Yk, dy, Ydy);
+                }
+                const float X = Ds * dx;
+                Pv[r * 9 + 0] = X;
+                Pv[r * 9 + 1] = Y;
+                Pv[r * 9 + 2] = X * dx;
+                Pv[r * 9 + 3] = Y * dx;
+                Pv[r * 9 + 4] = Ydy;
+                Pv[r * 9 + 5] = Ds;
+                Pv[r * 9 + 6] = c0;
+                Pv[r * 9 + 7] = c1;
+                Pv[r * 9 + 8] = c2;
+            }
+            const float2 tot = reduce_scatter16x2(Pv, lane);
+            const int i0 = 2 * rl, r0 = i0 / 9, r1 = (i0 + 1) / 9;
+            if (i0 < 9 * RS4 && g + r0 < mycnt) atomicAdd(&acc[sl][i0 - 9 * r0][mylist[g + r0] / STAGED_BYTES], tot.x);
+            if (i0 + 1 < 9 * RS4 && g + r1 < mycnt)
+                atomicAdd(&acc[sl][i0 + 1 - 9 * r1][mylist[g + r1] / STAGED_BYTES], tot.y);
+        }
+        };
+        if (clamp)
+            groups(std::true_type{});
+        else
+            groups(std::false_type{});
+        __syncthreads();
+        if (lane < static_cast<int>(nb)) {
+            // the two slots' sums in a fixed order; the slots are cleared for
+            // the next batch
+            float v[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                v[k] = acc[0][k][lane] + acc[1][k][lane];
+                acc[0][k][lane] = 0.0f;
+                acc[1][k][lane] = 0.0f;
+            }
+            const Staged st = sh[lane];
+            finish_partials(v, st.p0.z * INV_K_EXP, 0.5f * st.p0.w * INV_K_EXP, st.p1.x * INV_K_EXP, st.p2.w);
+            if (slot < a.k_cap) store_partials(a.part, slot, v);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Compacted variant.  The quadrant loop above issues every staged entry to all
 // 64 lanes of a wave although a small Gaussian covers only a fraction of the
 // 8x8 quadrant.  Here each batch is processed in two phases:
@@ -1415,6 +1692,10 @@ hipError_t launch_composite_bwd(const Args& a, hipStream_t stream) {
             case 128: hipLaunchKernelGGL(k_composite_bwd_c<128>, grid, block, 0, stream, a); break;
             default: hipLaunchKernelGGL(k_composite_bwd_c<256>, grid, block, 0, stream, a); break;
         }
+        return hipGetLastError();
+    }
+    if (a.tune.compact & 16) {  // one wave per tile (batches of 64)
+        hipLaunchKernelGGL(k_composite_bwd4<64>, grid, dim3(WG4), 0, stream, a);
         return hipGetLastError();
     }
     if (a.tune.compact & 8) {  // paired quadrants (batches of at most 128)

@@ -74,8 +74,8 @@ struct Tuning {
     int sort_cap;   // 512 / 1024 / 2048 / 4096
     int bwd_batch;  // the same for the backward compositing kernel
     int compact;    // bit 0 / bit 1: compacted forward / backward compositing (coverage masks + per-lane entry
-                    // walks); else bit 2: quadrant forward (clear: 4x4-block forward); bit 3: the backward
-                    // walks two quadrant lists per wave (clear: one)
+                    // walks); else bit 2: quadrant forward (clear: 4x4-block forward); bit 4 / bit 3: the
+                    // backward walks four / two quadrant lists per wave (clear: one)
 };
 
 // Byte offsets of the workspace regions (host-computed).

@@ -135,7 +135,8 @@ def stage_key(stage: str, tuning: dict) -> str:
     if stage == "composite_fwd":
         return f"b{tuning['batch']}-" + ("compact" if c & 1 else "quad" if c & 4 else "block")
     if stage == "composite_bwd":
-        return f"b{tuning['bwd_batch']}-" + ("compact" if c & 2 else "pair" if c & 8 else "quad")
+        return f"b{tuning['bwd_batch']}-" + ("compact" if c & 2 else "tile" if c & 16 else "pair" if c & 8
+                                             else "quad")
     if stage == "sort":
         return f"cap{tuning['sort_cap']}"
     return "any"

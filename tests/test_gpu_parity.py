@@ -172,14 +172,15 @@ def test_empty_and_single_gaussian():
 
 
 # compact: 0 sub-block forward, 4 quadrant forward, 1 compacted forward;
-# + 2 compacted backward, + 8 paired-quadrant backward (else the quadrant
-# backward)
+# + 2 compacted backward, + 16 one-wave-per-tile backward, + 8 paired-quadrant
+# backward (else the quadrant backward)
 @pytest.mark.parametrize("compact,batch,sort_cap", [(0, 256, 4096), (0, 128, 2048), (0, 64, 1024),
                                                     (4, 256, 4096), (4, 128, 2048), (4, 64, 1024),
                                                     (3, 256, 4096), (3, 128, 2048), (3, 64, 1024),
                                                     (1, 128, 2048), (2, 256, 2048), (6, 64, 1024),
                                                     (4, 64, 512), (12, 64, 1024), (12, 128, 2048),
-                                                    (12, 256, 4096), (8, 128, 512)])
+                                                    (12, 256, 4096), (8, 128, 512), (20, 64, 1024),
+                                                    (20, 256, 2048), (16, 128, 512), (17, 64, 1024)])
 def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
     """Batched path on a reduced clip (moving camera, several frames) under
     every setting the autotuner can choose."""
@@ -192,14 +193,14 @@ def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
         raster.set_tuning(old["batch"], old["sort_cap"], old["compact"], old["bwd_batch"])
 
 
-@pytest.mark.parametrize("compact", [12, 4, 8, 0])
+@pytest.mark.parametrize("compact", [12, 4, 8, 0, 20])
 def test_alpha_clamp_paths(compact):
     """Opaque Gaussians (opacity above 0.99) on the left half of the scene:
     tiles there composite with the alpha clamp (alpha = 0.99, no opacity or
     footprint gradient), tiles on the right without it, where the kernels drop
     the clamp once no entry of a batch can reach it.  Both against the oracle,
-    under the paired and the one-quadrant adjoint and the quadrant and
-    4x4-block forwards."""
+    under the one-, two- and four-quadrants-per-wave adjoints and the quadrant
+    and 4x4-block forwards."""
     w = small_workload(51, 160, 96, 3000, 3, trajectory=True, z=(2.0, 10.0), ls=(-3.2, 0.5))
     s = w["scene"]
     left = s.means[0] < 0
@@ -228,7 +229,7 @@ def test_alpha_clamp_paths(compact):
 @pytest.mark.parametrize("n,cap,regime,compact", [(5000, 1024, "global", 4), (1600, 1024, "two runs", 4),
                                                   (3000, 4096, "one pass", 4), (1600, 512, "global", 4),
                                                   (5000, 1024, "global", 6), (5000, 1024, "global", 12),
-                                                  (1600, 512, "global", 12)])
+                                                  (1600, 512, "global", 12), (5000, 1024, "global", 20)])
 def test_long_tile_buckets(n, cap, regime, compact):
     """Many large Gaussians over a small image: buckets beyond the LDS sort
     capacity, between one and two capacities, and within the largest one."""
