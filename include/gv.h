@@ -143,9 +143,12 @@ typedef struct {
  * (64, 128 or 256); sort_cap: longest per-tile list sorted in one LDS pass
  * (512, 1024, 2048 or 4096; lists up to twice that merge two LDS-sorted
  * runs, longer lists are sorted in chunks and merged in global memory);
- * compact: compositing kernel choice, 0..31.  With bit 2 set the forward lets
+ * compact: compositing kernel choice, 0..63.  With bit 2 set the forward lets
  * each wave walk the entries meeting its 8x8 quadrant; with it clear each
- * 16-lane row of a wave walks the entries meeting its 4x4 pixel block.  The
+ * 16-lane row of a wave walks the entries meeting its 4x4 pixel block; with
+ * bit 5 set, which takes precedence over bit 2, one wave owns the tile and
+ * each 16-lane row walks one quadrant's entries (four pixels per lane;
+ * batches of 64 or 128, a batch of 256 runs as 128).  The
  * backward lets each wave walk one quadrant's entries (one pixel per lane),
  * with bit 3 set two quadrants' entries, one per half-wave (two pixels per
  * lane; batches of 64 or 128, a bwd_batch of 256 runs as 128), or with bit
@@ -155,7 +158,7 @@ typedef struct {
  * take precedence, select kernels that first build per-pixel entry lists
  * from closed-form coverage masks;
  * bwd_batch: the backward's LDS batch (0 = same as batch).
- * Defaults: batch 256, sort_cap 1024, compact 20, bwd_batch 64.  Images are
+ * Defaults: batch 128, sort_cap 1024, compact 52, bwd_batch 64.  Images are
  * identical under every setting and gradients equal up to floating-point
  * rounding (order of summation, and the compacted backward's arithmetic);
  * only the speed differs. */

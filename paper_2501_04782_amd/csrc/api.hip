@@ -31,7 +31,7 @@ hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t count, unsi
 
 static thread_local int32_t g_last_hip = 0;
 static std::mutex g_tune_mu;
-static Tuning g_tune = {256, 1024, 64, 20};  // the autotuner's choice on the 960x540 benchmark clip
+static Tuning g_tune = {128, 1024, 64, 52};  // the autotuner's choice on the 960x540 benchmark clip
 
 Tuning current_tuning() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -600,7 +600,7 @@ gv_status gv_set_tuning(const gv_tuning* t) {
     if (t->bwd_batch != 0 && !batch_ok(t->bwd_batch)) return GV_ERR_INVALID_ARG;
     if (t->sort_cap != 512 && t->sort_cap != 1024 && t->sort_cap != 2048 && t->sort_cap != 4096)
         return GV_ERR_INVALID_ARG;
-    if (t->compact < 0 || t->compact > 31) return GV_ERR_INVALID_ARG;
+    if (t->compact < 0 || t->compact > 63) return GV_ERR_INVALID_ARG;
     Tuning n = current_tuning();
     n.batch = t->batch;
     n.bwd_batch = t->bwd_batch ? t->bwd_batch : t->batch;
@@ -648,7 +648,7 @@ static bool cached_tuning(const char* path, const TuneKey& key, Tuning& out) {
 static bool tuning_valid(const Tuning& t) {
     return batch_ok(t.batch) && batch_ok(t.bwd_batch) &&
            (t.sort_cap == 512 || t.sort_cap == 1024 || t.sort_cap == 2048 || t.sort_cap == 4096) && t.compact >= 0 &&
-           t.compact <= 31;
+           t.compact <= 63;
 }
 
 gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* poses, const float* times,
@@ -699,29 +699,30 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
     // The stages are independent (no stage's output depends on another
     // stage's kernel variant), so every stage keeps its own fastest option,
     // timed on every run that used it.  Options: forward kernel (4x4-block,
-    // quadrant or compacted) x LDS batch (64, 128, 256); backward kernel
+    // quadrant, compacted, or one wave per tile) x LDS batch (64, 128, 256);
+    // backward kernel
     // (one quadrant per wave at batch 64, 128, 256; two quadrants per wave at
     // batch 64, 128; four quadrants per wave at batch 64); sort capacity
-    // (512 ... 4096).  Run c takes forward option c mod 9, backward option
-    // c mod 6 and sort option c mod 4, so twelve runs per round try every
-    // option of every stage.  The compacted backward (LDS atomics per lane)
+    // (512 ... 4096).  Run c takes forward option c, backward option c mod 6
+    // and sort option c mod 4, so twelve runs per round try every option of
+    // every stage.  The compacted backward (LDS atomics per lane)
     // measured ten times slower than the quadrant backward on every clip
     // tried and is left to gv_set_tuning.
     constexpr int NF = 12, NB = 6, NS = 4;
-    const int f_kernel[3] = {0, 4, 1};
+    const int f_kernel[4] = {0, 4, 1, 36};  // the per-tile forward keeps bit 2: visibility counts use the quadrant forward
     const int batches[3] = {64, 128, 256};
     const int b_batch[NB] = {64, 128, 256, 64, 128, 64};
     const int b_pair[NB] = {0, 0, 0, 8, 8, 16};
     const int caps[NS] = {512, 1024, 2048, 4096};
-    float fwd_ms[9] = {}, bwd_ms[NB] = {}, sort_ms[NS] = {};
-    int fwd_n[9] = {}, bwd_n[NB] = {}, sort_n[NS] = {};
+    float fwd_ms[NF] = {}, bwd_ms[NB] = {}, sort_ms[NS] = {};
+    int fwd_n[NF] = {}, bwd_n[NB] = {}, sort_n[NS] = {};
     // Round-robin over the runs, so that clock or cache drift during the
     // measurement affects all options alike; round 0 warms up.
     constexpr int REPS = 3;
     for (int r = 0; r <= REPS && result == GV_OK; ++r) {
         for (int c = 0; c < NF && result == GV_OK; ++c) {
             Tuning t = saved;
-            const int fc = c % 9;  // runs past the ninth repeat forward options
+            const int fc = c;
             t.compact = f_kernel[fc / 3] | b_pair[c % NB];
             t.batch = batches[fc % 3];
             t.bwd_batch = b_batch[c % NB];
@@ -740,8 +741,8 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
             if (r == 0) continue;
             float ms[GV_STAGES];
             for (int i = 0; i < GV_STAGES; ++i) hipEventElapsedTime(&ms[i], tm.ev[i], tm.ev[i + 1]);
-            fwd_ms[c % 9] += ms[4];
-            fwd_n[c % 9] += 1;
+            fwd_ms[c] += ms[4];
+            fwd_n[c] += 1;
             bwd_ms[c % NB] += ms[6];
             bwd_n[c % NB] += 1;
             sort_ms[c % NS] += ms[3];
@@ -751,7 +752,7 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
     best = saved;
     if (result == GV_OK) {
         int bf = 0, bb = 0, bs = 0;
-        for (int c = 1; c < 9; ++c)
+        for (int c = 1; c < NF; ++c)
             if (fwd_ms[c] / fwd_n[c] < fwd_ms[bf] / fwd_n[bf]) bf = c;
         for (int c = 1; c < NB; ++c)
             if (bwd_ms[c] / bwd_n[c] < bwd_ms[bb] / bwd_n[bb]) bb = c;

@@ -331,6 +331,183 @@ __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
     }
 }
 
+// Forward with one wave per tile: lanes 16q .. 16q + 15 take quadrant q, each
+// lane four pixels of one column of it (rows r, r + 2, r + 4, r + 6), and each
+// 16-lane row walks its own quadrant's list front to back (the four lists
+// padded with the inert entry to a common length).  The per-pixel arithmetic
+// and decisions are those of the quadrant forward (the pixels share the
+// exponent's terms in dx), so images, final transmittances and last indices
+// are identical; a lane reads each entry's staged data once for its four
+// pixels.
+constexpr int WGF4 = 64;
+constexpr int FWD4_GROUP = 4;
+
+template <int B>
+__global__ __launch_bounds__(WGF4) __attribute__((amdgpu_waves_per_eu(4))) void k_composite_fwd4(Args a) {
+    constexpr int SPT = B / WGF4;  // entries staged per thread
+    static_assert(SPT * WGF4 == B, "whole entries per thread");
+    if (overflowed(a.status)) return;
+    const int f = blockIdx.y;
+    const int tile = blockIdx.x;
+    const int txi = tile % a.tiles_x, tyi = tile / a.tiles_x;
+    const int lane = threadIdx.x;
+    const int quad = lane >> 4, rl = lane & 15;
+    const int lx = ((quad & 1) << 3) | (rl & 7), ly0 = ((quad >> 1) << 3) | (rl >> 3);
+    const int px = txi * TILE + lx;
+    const int64_t seg = static_cast<int64_t>(f) * a.tiles + tile;
+    uint32_t s, e;
+    bucket_range(a, seg, s, e);
+    const double ox = txi * TILE + 0.5, oy = tyi * TILE + 0.5;
+    const int xlim = a.width - 1 - txi * TILE, ylim = a.height - 1 - tyi * TILE;
+
+    __shared__ Staged sh[B + 1];
+    __shared__ uint32_t shm[B];
+    __shared__ uint32_t wl[4][B + FWD4_GROUP];
+    if (lane == 0) stage_inert(sh[B]);
+
+    float T[4], c0[4], c1[4], c2[4], fy[4];
+    uint32_t last[4];
+    bool done[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        T[k] = 1.0f;
+        c0[k] = c1[k] = c2[k] = 0.0f;
+        last[k] = 0u;
+        done[k] = !(px < a.width && tyi * TILE + ly0 + 2 * k < a.height);
+        fy[k] = static_cast<float>(ly0 + 2 * k);
+    }
+    const float fx = static_cast<float>(lx);
+    constexpr uint32_t INERT = static_cast<uint32_t>(B) * STAGED_BYTES;
+    const uint64_t below = (1ull << lane) - 1ull;
+
+    // each batch's entry ids are requested during the previous batch's loop
+    uint32_t gn[SPT];
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) {
+        const uint32_t t = static_cast<uint32_t>(lane + WGF4 * i);
+        gn[i] = t < min(static_cast<uint32_t>(B), e - s) ? a.sgid[s + t] : 0u;
+    }
+    for (uint32_t b0 = s; b0 < e; b0 += B) {
+        const bool alive = !(done[0] && done[1] && done[2] && done[3]);
+        const uint64_t alive_bal = __ballot(alive);
+        if (alive_bal == 0ull) break;  // every pixel of the tile has terminated
+        const uint32_t nb = min(static_cast<uint32_t>(B), e - b0);
+#pragma unroll
+        for (int i = 0; i < SPT; ++i) {
+            const uint32_t t = static_cast<uint32_t>(lane + WGF4 * i);
+            if (t < nb) {
+                Staged st;
+                float3 conic;
+                stage_entry(a, f, gn[i], ox, oy, st, conic);
+                sh[t] = st;
+                shm[t] = quadrant_mask(st, conic, xlim, ylim);
+            }
+        }
+        __syncthreads();
+        if (e - b0 > B) {
+#pragma unroll
+            for (int i = 0; i < SPT; ++i) {
+                const uint32_t t = static_cast<uint32_t>(lane + WGF4 * i);
+                if (t < min(static_cast<uint32_t>(B), e - b0 - B)) gn[i] = a.sgid[b0 + B + t];
+            }
+        }
+        // the four quadrants' lists, front to back; a quadrant whose pixels
+        // have all terminated takes none
+        int cnt[4] = {0, 0, 0, 0};
+        for (int j0 = 0; j0 < static_cast<int>(nb); j0 += 64) {
+            const int j = j0 + lane;
+            const uint32_t m = j < static_cast<int>(nb) ? shm[j] : 0u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool on = ((m >> q) & 1u) && ((alive_bal >> (16 * q)) & 0xFFFFull) != 0ull;
+                const uint64_t bal = __ballot(on);
+                if (on) wl[q][cnt[q] + __popcll(bal & below)] = static_cast<uint32_t>(j) * STAGED_BYTES;
+                cnt[q] += __popcll(bal);
+            }
+        }
+        const int cmax = max(max(cnt[0], cnt[1]), max(cnt[2], cnt[3]));
+        const int npad = (cmax + FWD4_GROUP - 1) / FWD4_GROUP * FWD4_GROUP;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            for (int k = cnt[q] + lane; k < npad; k += 64) wl[q][k] = INERT;
+        const uint32_t* mylist = wl[quad];
+        __builtin_amdgcn_wave_barrier();
+        // Branch-free groups, as in the quadrant forward; loff: byte offset of
+        // each pixel's last entry taken in this batch
+        int loff[4] = {-1, -1, -1, -1};
+        for (int g = 0; g < npad; g += FWD4_GROUP) {
+            uint32_t J[FWD4_GROUP];
+            float4 P0[FWD4_GROUP], P1[FWD4_GROUP];
+            float2 P2[FWD4_GROUP];
+#pragma unroll
+            for (int r = 0; r < FWD4_GROUP; ++r) J[r] = mylist[g + r];
+#pragma unroll
+            for (int r = 0; r < FWD4_GROUP; ++r) {
+                const Staged& st = staged_at(sh, J[r]);
+                P0[r] = st.p0;
+                P1[r] = st.p1;
+                P2[r] = make_float2(st.p2.x, st.p2.y);
+            }
+#pragma unroll
+            for (int r = 0; r < FWD4_GROUP; ++r) {
+                const float4 p0 = P0[r];
+                const float4 p1 = P1[r];
+                const float dx = fx - p0.x;
+                const FootRow fr = footprint_row(dx, p0, p1);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float dy = fy[k] - p0.y;
+                    const float q = footprint_q(dy, fr, p1);
+                    const bool hit = !done[k] && q >= P2[r].y;
+                    const float al = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(q));
+                    const float tn = __builtin_fmaf(-al, T[k], T[k]);
+                    const bool take = hit && tn >= T_MIN;  // else stop before this entry
+                    done[k] = done[k] || (hit != take);
+                    const float wgt = take ? al * T[k] : 0.0f;
+                    c0[k] = __builtin_fmaf(p1.z, wgt, c0[k]);
+                    c1[k] = __builtin_fmaf(p1.w, wgt, c1[k]);
+                    c2[k] = __builtin_fmaf(P2[r].x, wgt, c2[k]);
+                    T[k] = take ? tn : T[k];
+                    loff[k] = take ? static_cast<int>(J[r]) : loff[k];
+                }
+            }
+            if (__ballot(!(done[0] && done[1] && done[2] && done[3])) == 0ull) break;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (loff[k] >= 0) last[k] = b0 - s + static_cast<uint32_t>(loff[k]) / STAGED_BYTES + 1;
+        __syncthreads();  // the next batch overwrites the staged entries and lists
+    }
+
+    float sq = 0.0f;
+    const int64_t P = static_cast<int64_t>(a.width) * a.height;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int py = tyi * TILE + ly0 + 2 * k;
+        if (!(px < a.width && py < a.height)) continue;
+        const int64_t pix = static_cast<int64_t>(py) * a.width + px;
+        const float r0 = __builtin_fmaf(T[k], a.bg[0], c0[k]);
+        const float r1 = __builtin_fmaf(T[k], a.bg[1], c1[k]);
+        const float r2 = __builtin_fmaf(T[k], a.bg[2], c2[k]);
+        float* img = a.images + static_cast<int64_t>(f) * 3 * P + pix;
+        img[0] = r0;
+        img[P] = r1;
+        img[2 * P] = r2;
+        a.tfin[static_cast<int64_t>(f) * P + pix] = T[k];
+        a.nlast[static_cast<int64_t>(f) * P + pix] = last[k];
+        if (a.tfin_out) a.tfin_out[static_cast<int64_t>(f) * P + pix] = T[k];
+        if (a.targets && a.loss) {
+            const float* tg = a.targets + static_cast<int64_t>(f) * 3 * P + pix;
+            const float d0 = r0 - tg[0], d1 = r1 - tg[P], d2 = r2 - tg[2 * P];
+            sq += d0 * d0 + d1 * d1 + d2 * d2;
+        }
+    }
+    if (a.targets && a.loss) {
+        sq = wave_sum_to_lane63(sq);
+        if (lane == 63) a.loss_part[seg] = sq;
+    }
+}
+
 // Per-frame loss: fixed-order sum of the tiles' partial sums.
 __global__ __launch_bounds__(WG) void k_loss_finalize(Args a) {
     const int f = blockIdx.x;
@@ -1639,6 +1816,13 @@ hipError_t launch_composite_fwd(const Args& a, hipStream_t stream) {
             case 128: hipLaunchKernelGGL(k_composite_fwd_c<128>, grid, block, 0, stream, a); break;
             default: hipLaunchKernelGGL(k_composite_fwd_c<256>, grid, block, 0, stream, a); break;
         }
+        return hipGetLastError();
+    }
+    if ((c & 32) && !a.vis) {  // one wave per tile (batches of at most 128)
+        if (a.tune.batch == 64)
+            hipLaunchKernelGGL(k_composite_fwd4<64>, grid, dim3(WGF4), 0, stream, a);
+        else
+            hipLaunchKernelGGL(k_composite_fwd4<128>, grid, dim3(WGF4), 0, stream, a);
         return hipGetLastError();
     }
 #define GV_FWD_SWITCH(KERNEL, VIS)                                                                       \

@@ -133,7 +133,8 @@ def stage_key(stage: str, tuning: dict) -> str:
     """The part of the tuning that changes a stage's kernel (file-name safe)."""
     c = tuning['compact']
     if stage == "composite_fwd":
-        return f"b{tuning['batch']}-" + ("compact" if c & 1 else "quad" if c & 4 else "block")
+        return f"b{tuning['batch']}-" + ("compact" if c & 1 else "tile" if c & 32 else "quad" if c & 4
+                                         else "block")
     if stage == "composite_bwd":
         return f"b{tuning['bwd_batch']}-" + ("compact" if c & 2 else "tile" if c & 16 else "pair" if c & 8
                                              else "quad")

@@ -114,10 +114,10 @@ def test_tuning_table_validation():
     t = L.GvTuning()
     assert lib.gv_get_tuning(ctypes.byref(t)) == L.GV_OK
     old = (t.batch, t.sort_cap, t.compact, t.bwd_batch)
-    assert t.batch in (64, 128, 256) and t.sort_cap in (512, 1024, 2048, 4096) and 0 <= t.compact <= 31
+    assert t.batch in (64, 128, 256) and t.sort_cap in (512, 1024, 2048, 4096) and 0 <= t.compact <= 63
     assert t.bwd_batch in (64, 128, 256)
     t2 = L.GvTuning()
-    t2.batch, t2.sort_cap, t2.compact = 128, 2048, 32  # kernel choice out of range
+    t2.batch, t2.sort_cap, t2.compact = 128, 2048, 64  # kernel choice out of range
     assert lib.gv_set_tuning(ctypes.byref(t2)) == L.GV_ERR_INVALID_ARG
     t2.compact = 0
     t2.batch, t2.sort_cap = 100, 4096

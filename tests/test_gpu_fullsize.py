@@ -271,10 +271,10 @@ def test_every_tuning_matches_default_full_size():
     scene, cam, poses, times = device_inputs(w)
     targets = torch.from_numpy(w["targets"]).cuda()
     ws = workspace_for(scene, cam, poses, times, margin=1.3)
-    base = dict(batch=256, sort_cap=1024, compact=20, bwd_batch=64)
-    settings = [dict(base, batch=b, compact=c | 16) for c in (0, 4, 1) for b in (64, 128, 256)]
+    base = dict(batch=128, sort_cap=1024, compact=52, bwd_batch=64)
+    settings = [dict(base, batch=b, compact=c | 16) for c in (0, 4, 1, 36) for b in (64, 128, 256)]
     settings += [dict(base, compact=c, bwd_batch=bb)
-                 for c, bb in ((4, 64), (4, 128), (4, 256), (12, 64), (12, 128), (6, 128))]
+                 for c, bb in ((36, 64), (36, 128), (36, 256), (44, 64), (44, 128), (38, 128))]
     settings += [dict(base, sort_cap=cap) for cap in (512, 2048, 4096)]
     old = raster.get_tuning()
 

@@ -171,7 +171,8 @@ def test_empty_and_single_gaussian():
             check_clip_against_oracle(w, "single Gaussian")
 
 
-# compact: 0 sub-block forward, 4 quadrant forward, 1 compacted forward;
+# compact: 0 sub-block forward, 4 quadrant forward, 1 compacted forward, + 32
+# one-wave-per-tile forward;
 # + 2 compacted backward, + 16 one-wave-per-tile backward, + 8 paired-quadrant
 # backward (else the quadrant backward)
 @pytest.mark.parametrize("compact,batch,sort_cap", [(0, 256, 4096), (0, 128, 2048), (0, 64, 1024),
@@ -180,7 +181,8 @@ def test_empty_and_single_gaussian():
                                                     (1, 128, 2048), (2, 256, 2048), (6, 64, 1024),
                                                     (4, 64, 512), (12, 64, 1024), (12, 128, 2048),
                                                     (12, 256, 4096), (8, 128, 512), (20, 64, 1024),
-                                                    (20, 256, 2048), (16, 128, 512), (17, 64, 1024)])
+                                                    (20, 256, 2048), (16, 128, 512), (17, 64, 1024),
+                                                    (52, 64, 1024), (52, 128, 2048), (36, 256, 4096)])
 def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
     """Batched path on a reduced clip (moving camera, several frames) under
     every setting the autotuner can choose."""
@@ -193,7 +195,7 @@ def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
         raster.set_tuning(old["batch"], old["sort_cap"], old["compact"], old["bwd_batch"])
 
 
-@pytest.mark.parametrize("compact", [12, 4, 8, 0, 20])
+@pytest.mark.parametrize("compact", [12, 4, 8, 0, 20, 52])
 def test_alpha_clamp_paths(compact):
     """Opaque Gaussians (opacity above 0.99) on the left half of the scene:
     tiles there composite with the alpha clamp (alpha = 0.99, no opacity or
