@@ -1,13 +1,17 @@
 // Front-to-back alpha compositing of each 16x16 tile (forward) and its adjoint
 // (back to front, transmittance recomputed by division from the stored final
-// value).  One 256-thread workgroup per (frame, tile); wave w owns the 8x8
-// quadrant (w & 1, w >> 1).  The tile's depth-sorted entries are staged
-// through LDS in batches of B, each with a mask of the parts of the tile its
-// 3-sigma ellipse meets: in the quadrant kernels lane l owns pixel
-// (l & 7, l >> 3) of its quadrant and a wave walks the entries meeting the
-// quadrant; in the sub-block forward each 16-lane row owns a 4x4 block and
-// walks the entries meeting the block.  Lanes leave the loop when their pixel
-// terminates and a workgroup stops staging once every pixel has terminated.
+// value).  One workgroup per (frame, tile).  The tile's depth-sorted entries
+// are staged through LDS in batches of B, each with a mask of the parts of the
+// tile its 3-sigma ellipse meets, and each part of the tile walks the list of
+// the entries meeting it:
+//  - quadrant kernels (256 threads): wave w owns the 8x8 quadrant
+//    (w & 1, w >> 1), lane l its pixel (l & 7, l >> 3);
+//  - sub-block forward (256 threads): each 16-lane row owns a 4x4 block;
+//  - paired adjoint (128 threads): each half-wave owns a quadrant, two pixels
+//    per lane;
+//  - per-tile kernels (64 threads, the defaults): each 16-lane row of the one
+//    wave owns a quadrant, four pixels of one column per lane.
+// A workgroup stops staging once every pixel has terminated.
 #include "gv_internal.h"
 
 #include <type_traits>
