@@ -12,8 +12,6 @@
 
 namespace gv {
 
-constexpr int PB_THREADS = 128;
-
 // dR_e * dR_e/dq for the e-th entry (row-major) of the rotation matrix of the
 // unit quaternion (w, x, y, z); e is a compile-time constant after unrolling.
 __device__ __forceinline__ void add_rot_partial(int e, float v, const float q[4], float g[4]) {
@@ -291,18 +289,23 @@ __device__ __forceinline__ void sh_adjoint(const Args& a, int64_t g, const AdjIn
 }
 
 // SPLIT waves share each Gaussian: wave h of a workgroup takes the h-th
-// contiguous part of the frames for the workgroup's 128 / SPLIT Gaussians, and
-// the parts' accumulators are added in a fixed order at the end (more waves
-// in flight for this latency-bound kernel).  The dynamic variant keeps one
-// wave per Gaussian: its control-point window adds to memory as it moves.
-template <bool DYN>
-constexpr int pb_split() { return DYN ? 1 : 2; }
+// contiguous part of the frames for the workgroup's 64 Gaussians, and the
+// parts' accumulators are added in a fixed order at the end.  Shorter parts
+// keep more waves in flight for this latency-bound kernel and leave a shorter
+// tail when the last workgroups run alone.  The dynamic variant keeps one
+// wave per Gaussian (its control-point window adds to memory as it moves) and
+// the SH variant two parts (its coefficient accumulators take LDS).
+template <bool DYN, bool SH>
+constexpr int pb_split() { return DYN ? 1 : SH ? 2 : 4; }
+template <bool DYN, bool SH>
+constexpr int pb_threads() { return DYN ? 128 : 64 * pb_split<DYN, SH>(); }
 
 template <bool DYN, bool SH>
-__global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
+__global__ __launch_bounds__((pb_threads<DYN, SH>())) void k_project_bwd(Args a) {
     if (overflowed(a.status)) return;
     using LA = AccLayout<DYN>;
-    constexpr int SPLIT = pb_split<DYN>();
+    constexpr int PB_THREADS = pb_threads<DYN, SH>();
+    constexpr int SPLIT = pb_split<DYN, SH>();
     constexpr int GPB = PB_THREADS / SPLIT;  // Gaussians per workgroup
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int h = tid / GPB;                 // which part of the frames
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(PB_THREADS) void k_project_bwd(Args a) {
     __shared__ double acc[LA::N][PB_THREADS];
     // cameras of a chunk of frames (R 0-8, t 9-11, centre 12-14) and the
     // per-wave pose sums of each of its frames
-    constexpr int FC = 32;
+    constexpr int FC = SPLIT >= 4 ? 16 : 32;
     __shared__ float cam[SPLIT][FC][15];
     __shared__ float wpose[SPLIT][FC][PB_THREADS / 64 / SPLIT][12];
     __shared__ double iacc[4][PB_THREADS];  // intrinsics gradient, summed over frames
@@ -620,27 +623,39 @@ __global__ __launch_bounds__(256) void k_intr_finalize(Args a, int64_t n_blocks)
     }
 }
 
-// Upper bound over the variants (the split one has the most workgroups).
+// Gaussians per workgroup of each variant.
+template <bool DYN, bool SH>
+constexpr int pb_gaussians() { return pb_threads<DYN, SH>() / pb_split<DYN, SH>(); }
+static_assert(pb_gaussians<false, false>() == 64 && pb_gaussians<false, true>() == 64 &&
+                  pb_gaussians<true, false>() >= 64 && pb_gaussians<true, true>() >= 64,
+              "the static variants have the most workgroups");
+
+// Upper bound over the variants.
 int64_t project_bwd_blocks(int64_t n) {
-    constexpr int gpb = PB_THREADS / pb_split<false>();
+    constexpr int gpb = pb_gaussians<false, false>();
     return (n + gpb - 1) / gpb;
 }
 
-static int64_t blocks_for(int64_t n, bool dyn) {
-    const int gpb = PB_THREADS / (dyn ? pb_split<true>() : pb_split<false>());
+static int64_t blocks_for(int64_t n, bool dyn, bool sh) {
+    const int gpb = dyn ? (sh ? pb_gaussians<true, true>() : pb_gaussians<true, false>())
+                        : (sh ? pb_gaussians<false, true>() : pb_gaussians<false, false>());
     return (n + gpb - 1) / gpb;
 }
 
 hipError_t launch_project_bwd(const Args& a, hipStream_t stream) {
     const bool dyn = a.n_ctrl > 0 || a.scale_coeffs || a.quat_coeffs;
     const bool sh = a.sh_degree > 0;
-    const int64_t nb = blocks_for(a.n, dyn);
-    const dim3 grid(static_cast<uint32_t>(nb > 0 ? nb : 1)), block(PB_THREADS);
+    const int64_t nb = blocks_for(a.n, dyn, sh);
+    const dim3 grid(static_cast<uint32_t>(nb > 0 ? nb : 1));
     if (nb > 0) {
-        if (dyn && sh) hipLaunchKernelGGL((k_project_bwd<true, true>), grid, block, 0, stream, a);
-        else if (dyn) hipLaunchKernelGGL((k_project_bwd<true, false>), grid, block, 0, stream, a);
-        else if (sh) hipLaunchKernelGGL((k_project_bwd<false, true>), grid, block, 0, stream, a);
-        else hipLaunchKernelGGL((k_project_bwd<false, false>), grid, block, 0, stream, a);
+        if (dyn && sh)
+            hipLaunchKernelGGL((k_project_bwd<true, true>), grid, dim3(pb_threads<true, true>()), 0, stream, a);
+        else if (dyn)
+            hipLaunchKernelGGL((k_project_bwd<true, false>), grid, dim3(pb_threads<true, false>()), 0, stream, a);
+        else if (sh)
+            hipLaunchKernelGGL((k_project_bwd<false, true>), grid, dim3(pb_threads<false, true>()), 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_project_bwd<false, false>), grid, dim3(pb_threads<false, false>()), 0, stream, a);
     }
     if (a.g_poses)
         hipLaunchKernelGGL(k_pose_finalize, dim3(static_cast<uint32_t>(a.frames)), dim3(256), 0, stream, a, nb);
