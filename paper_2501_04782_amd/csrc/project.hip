@@ -183,7 +183,8 @@ struct WaveCells {
 
 // Binning with workgroup-local tile histograms in LDS: each workgroup
 // projects BIN_GROUP Gaussians of one frame, counts their intersections per
-// tile with LDS atomics, stores its histogram and adds it to the frame's tile
+// tile with LDS atomics (16-bit counts, two tiles per word: a count never
+// exceeds BIN_GROUP), stores its histogram and adds it to the frame's tile
 // counts with one global atomic per non-empty tile.  A Gaussian's passing
 // tiles are also recorded as a row-major mask over its rectangle (rectangles
 // of at most 64 tiles), which the scatter walks.
@@ -193,7 +194,8 @@ __global__ __launch_bounds__(256) void k_project_lds(Args a) {
     __shared__ WaveCells wc[4];
     const int f = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int t = threadIdx.x; t < a.tiles; t += 256) hist[t] = 0u;
+    const int words = (a.tiles + 1) >> 1;
+    for (int t = threadIdx.x; t < words; t += 256) hist[t] = 0u;
     __syncthreads();
     const CamD cam = load_camera(a.poses + 7 * f);
     const double tt = a.times ? static_cast<double>(a.times[f]) : static_cast<double>(a.t0);
@@ -221,7 +223,8 @@ __global__ __launch_bounds__(256) void k_project_lds(Args a) {
                 const int ry = static_cast<int>(cell) / So.rw;
                 const int tx = So.tx0 + (static_cast<int>(cell) - ry * So.rw), ty = So.ty0 + ry;
                 if (shape_meets_tile(a, So, tx, ty)) {
-                    atomicAdd(&hist[ty * a.tiles_x + tx], 1u);
+                    const int tl = ty * a.tiles_x + tx;
+                    atomicAdd(&hist[tl >> 1], 1u << ((tl & 1) << 4));
                     atomicAdd(&W.cnt[o], 1u);
                     if (So.rw * So.rh <= 64) atomicOr(&W.mask[o], 1ull << cell);
                 }
@@ -239,16 +242,17 @@ __global__ __launch_bounds__(256) void k_project_lds(Args a) {
     uint32_t* bh = a.bhist + (static_cast<int64_t>(f) * a.bin_blocks + blockIdx.x) * a.tiles;
     uint32_t* tc = a.tcnt + static_cast<int64_t>(f) * a.tiles;
     for (int t = threadIdx.x; t < a.tiles; t += 256) {
-        const uint32_t v = hist[t];
+        const uint32_t v = (hist[t >> 1] >> ((t & 1) << 4)) & 0xFFFFu;
         bh[t] = v;
         if (v) atomicAdd(&tc[t], v);
     }
 }
 
 // Write intersection (f, g) -> tile (tx, ty) with pre-sort slot goff + k at
-// position next(tile) of the tile's bucket, below end(tile).  The counts
-// bound every write; a mismatch is an internal error, reported instead of
-// written out of bounds.
+// position next(tile) of the tile's bucket, below end(tile) (the bucket's end
+// in the global-atomic scatter; the workspace's capacity in the LDS scatter,
+// whose reservations check the counts).  The counts bound every write; a
+// mismatch is an internal error, reported instead of written out of bounds.
 template <typename Next, typename End>
 __device__ __forceinline__ void emit_key(const Args& a, uint64_t key, uint32_t slot, int tx, int ty, Next next,
                                          End end) {
@@ -305,10 +309,8 @@ struct WaveKeys {
 // mask gets pre-sort slot goff + k, as the count pass ordered them.
 __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
     if (overflowed(a.status)) return;
-    // base[t]: next position of this workgroup's range in tile t's bucket;
-    // lim[t]: the end of that range
+    // base[t]: next position of this workgroup's range in tile t's bucket
     extern __shared__ uint32_t base[];
-    uint32_t* lim = base + a.tiles;
     __shared__ WaveKeys wk[4];
     const int f = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -340,13 +342,16 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
             if (t < a.tiles) {
                 const uint32_t b = v[k] ? lo[k] + o[k] : 0u;
                 base[t] = b;
-                lim[t] = v[k] ? min(b + v[k], hi[k]) : 0u;
+                if (v[k] && b + v[k] > hi[k]) a.status[ST_OVERFLOW] = 2u;  // counts disagree: internal error
             }
         }
     }
     __syncthreads();
+    // a workgroup emits exactly its histogram's count per tile; the end
+    // checked per key is only the workspace's (no write out of bounds even
+    // if the counts disagreed, which the reservation above reports)
     auto next = [&](int tl) { return atomicAdd(&base[tl], 1u); };
-    auto end = [&](int tl) { return lim[tl]; };
+    auto end = [&](int) { return static_cast<uint32_t>(a.k_cap); };
     const int64_t g0 = static_cast<int64_t>(blockIdx.x) * BIN_GROUP;
     WaveKeys& W = wk[w];
     // A Gaussian's count, record, rectangle, mask and slot offset, requested
@@ -504,7 +509,7 @@ hipError_t launch_project(const Args& a, hipStream_t stream) {
     const dim3 block(256);
     if (a.bhist) {
         const dim3 grid(static_cast<uint32_t>(a.bin_blocks), a.frames);
-        const size_t lds = sizeof(uint32_t) * a.tiles;
+        const size_t lds = sizeof(uint32_t) * ((a.tiles + 1) / 2);
         if (ext) hipLaunchKernelGGL(k_project_lds<true>, grid, block, lds, stream, a);
         else hipLaunchKernelGGL(k_project_lds<false>, grid, block, lds, stream, a);
     } else {
@@ -519,7 +524,7 @@ hipError_t launch_scatter(const Args& a, hipStream_t stream) {
     if (a.n <= 0) return hipSuccess;
     if (a.bhist) {
         hipLaunchKernelGGL(k_scatter_lds, dim3(static_cast<uint32_t>(a.bin_blocks), a.frames), dim3(256),
-                           2 * sizeof(uint32_t) * a.tiles, stream, a);
+                           sizeof(uint32_t) * a.tiles, stream, a);
     } else {
         hipLaunchKernelGGL(k_scatter, dim3(static_cast<uint32_t>((a.n + 255) / 256), a.frames), dim3(256), 0, stream,
                            a);
