@@ -93,6 +93,7 @@ Layout make_layout(const gv_camera& cam, int64_t n, int frames, int64_t k_cap) {
     L.sgid = take(4 * K);
     L.sslot = take(4 * K);
     L.part = take(4 * PART * K);
+    L.pused = take(4 * (K / 32 + 2));
     L.tkv = take(sizeof(KeySlot) * K);
     L.total = off;
     return L;
@@ -217,6 +218,7 @@ static gv_status make_args(const gv_scene* s, const gv_camera* c, int frames, co
     a.sgid = reinterpret_cast<uint32_t*>(b + L.sgid);
     a.sslot = reinterpret_cast<uint32_t*>(b + L.sslot);
     a.part = reinterpret_cast<float*>(b + L.part);
+    a.pused = reinterpret_cast<uint32_t*>(b + L.pused);
     a.tkv = reinterpret_cast<KeySlot*>(b + L.tkv);
     a.k_cap = L.k_cap;
     a.tune = current_tuning();
@@ -331,6 +333,7 @@ static gv_status enqueue_batch(const gv_scene* scene, const gv_camera* cam, cons
         for (int i = 0; i <= 6; ++i) mark(tm, i);
     }
     if (flags & GV_BWD) {
+        GV_TRY(launch_fill_u32(a.pused, 0u, a.k_cap / 32 + 2, st));
         GV_TRY(launch_composite_bwd(a, st));
         mark(tm, 7);
         GV_TRY(launch_project_bwd(a, st));
@@ -433,6 +436,7 @@ gv_status gv_render_bwd(const gv_scene* scene, const gv_camera* cam, const float
     set_grads(a, grads);
     a.g_poses = dL_dpose7;
     a.accumulate = (flags & GV_ACCUMULATE) ? 1 : 0;
+    GV_TRY(launch_fill_u32(a.pused, 0u, a.k_cap / 32 + 2, st));
     GV_TRY(launch_composite_bwd(a, st));
     GV_TRY(launch_project_bwd(a, st));
     return GV_OK;

@@ -663,12 +663,6 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
         if (tid < static_cast<int>(s + used - b0f)) gnext = a.sgid[b0f + tid];
     }
     // entries no pixel reached get zero partials
-    for (uint32_t i = s + used + tid; i < e; i += WG) {
-        const uint32_t slot = a.sslot[i];
-        if (slot >= a.k_cap) continue;
-        const float z[PART] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        store_partials(a.part, slot, z);
-    }
     const float fx = static_cast<float>(lx), fy = static_cast<float>(ly);
 
     for (int64_t bend = static_cast<int64_t>(s) + used; bend > s; bend -= B) {
@@ -790,7 +784,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd(Args a) {
             const Staged st = sh[tid];
             finish_partials(v, st.p0.z * INV_K_EXP, 0.5f * st.p0.w * INV_K_EXP, st.p1.x * INV_K_EXP, st.p2.w);
             if (slot < a.k_cap) {
-                store_partials(a.part, slot, v);
+                store_partials_marked(a, slot, v);
             }
         }
         __syncthreads();
@@ -907,12 +901,6 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
     {
         const uint32_t b0f = used > B ? s + used - B : s;
         if (tid < static_cast<int>(s + used - b0f)) gnext = a.sgid[b0f + tid];
-    }
-    for (uint32_t i = s + used + tid; i < e; i += WG2) {
-        const uint32_t slot = a.sslot[i];
-        if (slot >= a.k_cap) continue;
-        const float z[PART] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        store_partials(a.part, slot, z);
     }
     const float fx = static_cast<float>(lx), fyA = static_cast<float>(lyA), fyB = static_cast<float>(lyB);
     constexpr uint32_t INERT = static_cast<uint32_t>(B) * STAGED_BYTES;
@@ -1047,7 +1035,7 @@ __global__ __launch_bounds__(WG2) __attribute__((amdgpu_waves_per_eu(4))) void k
             }
             const Staged st = sh[tid];
             finish_partials(v, st.p0.z * INV_K_EXP, 0.5f * st.p0.w * INV_K_EXP, st.p1.x * INV_K_EXP, st.p2.w);
-            if (slot < a.k_cap) store_partials(a.part, slot, v);
+            if (slot < a.k_cap) store_partials_marked(a, slot, v);
         }
         __syncthreads();
     }
@@ -1159,12 +1147,6 @@ __global__ __launch_bounds__(WG4) __attribute__((amdgpu_waves_per_eu(4))) void k
     {
         const uint32_t b0f = used > B ? s + used - B : s;
         if (lane < static_cast<int>(s + used - b0f)) gnext = a.sgid[b0f + lane];
-    }
-    for (uint32_t i = s + used + lane; i < e; i += WG4) {
-        const uint32_t slot = a.sslot[i];
-        if (slot >= a.k_cap) continue;
-        const float z[PART] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        store_partials(a.part, slot, z);
     }
     const float fx = static_cast<float>(lx);
     float fy[4];
@@ -1309,7 +1291,7 @@ __global__ __launch_bounds__(WG4) __attribute__((amdgpu_waves_per_eu(4))) void k
             }
             const Staged st = sh[lane];
             finish_partials(v, st.p0.z * INV_K_EXP, 0.5f * st.p0.w * INV_K_EXP, st.p1.x * INV_K_EXP, st.p2.w);
-            if (slot < a.k_cap) store_partials(a.part, slot, v);
+            if (slot < a.k_cap) store_partials_marked(a, slot, v);
         }
         __syncthreads();
     }
@@ -1562,12 +1544,6 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
     if (last) atomicMax(&smax, last);
     __syncthreads();
     const uint32_t used = smax;
-    for (uint32_t i = s + used + tid; i < e; i += WG) {
-        const uint32_t slot = a.sslot[i];
-        if (slot >= a.k_cap) continue;
-        const float z[PART] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        store_partials(a.part, slot, z);
-    }
     const float fx = static_cast<float>(lx), fy = static_cast<float>(ly);
 
     for (int64_t bend = static_cast<int64_t>(s) + used; bend > s; bend -= B) {
@@ -1640,7 +1616,7 @@ __global__ __launch_bounds__(WG) void k_composite_bwd_c(Args a) {
                             sv[10][tid]);
             const uint32_t slot = a.sslot[b0 + tid];
             if (slot < a.k_cap) {
-                store_partials(a.part, slot, v);
+                store_partials_marked(a, slot, v);
             }
         }
         __syncthreads();

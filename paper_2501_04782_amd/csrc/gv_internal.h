@@ -89,7 +89,7 @@ struct Layout {
     int64_t bin_blocks;    // workgroups per frame of the LDS-histogram binning (0: global atomics)
     size_t status, col4, rec, rect, tmask, gcnt, goff, tcnt, toff, tcur, bhist, scan_tmp, tfin, nlast, loss_part, pose_part,
         intr_part, vis,
-        kv, sgid, sslot, part, tkv;
+        kv, sgid, sslot, part, pused, tkv;
     size_t total;
 };
 
@@ -145,6 +145,7 @@ struct Args {
     uint32_t* sgid;       // [K]
     uint32_t* sslot;      // [K]
     float* part;          // [K][PART] (du, dv, dA00, dA01, dA11, do, dr, dg, db) per pre-sort slot
+    uint32_t* pused;      // [K/32 + 2] bit per pre-sort slot: its partial record was written this pass
     KeySlot* tkv;         // [K] merge scratch of the sort
     int64_t k_cap;
     // image-space inputs/outputs
@@ -624,6 +625,16 @@ __device__ __forceinline__ int reduce_scatter16_index(int lane) {
 }
 
 // Entry range [s, e) of bucket `seg`, clamped to the intersection capacity.
+// Partial record of pre-sort slot `slot`, and its bit in pused.  The
+// adjoint writes records only for the entries up to each tile's last
+// contributor; the projection adjoint adds only the marked slots, so the
+// entries behind (about half of them on dense scenes) need no zero records.
+// The bits are cleared before the adjoint; OR is order-independent.
+__device__ __forceinline__ void store_partials_marked(const Args& a, uint32_t slot, const float (&v)[PART]) {
+    store_partials(a.part, slot, v);
+    atomicOr(&a.pused[slot >> 5], 1u << (slot & 31u));
+}
+
 __device__ __forceinline__ void bucket_range(const Args& a, int64_t seg, uint32_t& s, uint32_t& e) {
     const uint32_t cap = static_cast<uint32_t>(a.k_cap);
     e = min(a.toff[seg + 1], cap);

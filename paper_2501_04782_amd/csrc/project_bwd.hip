@@ -398,10 +398,17 @@ __global__ __launch_bounds__((pb_threads<DYN, SH>())) void k_project_bwd(Args a)
                 // PU records per round, loads issued together (past the end
                 // they repeat a valid record and are not added), summed in
                 // order k = 0, 1, ...; the first round is requested before the
-                // frame's projection inputs are computed, which do not need it
+                // frame's projection inputs are computed, which do not need it.
+                // Only the records the adjoint wrote this pass (bit set in
+                // pused) are added: the others belong to entries behind their
+                // tile's last contributor and hold stale values.
                 constexpr uint32_t PU = 8;
                 float r[PU][PART];
+                uint32_t w0 = 0u, w1 = 0u;  // pused words holding the round's bits
                 auto load_round = [&](uint32_t k0) {
+                    const uint32_t wi = (base + k0) >> 5;
+                    w0 = a.pused[wi];
+                    w1 = a.pused[wi + 1];
 #pragma unroll
                     for (uint32_t u = 0; u < PU; ++u) {
                         const uint32_t k = k0 + u < cnt ? k0 + u : k0;
@@ -417,9 +424,11 @@ __global__ __launch_bounds__((pb_threads<DYN, SH>())) void k_project_bwd(Args a)
                 frame_inputs<DYN>(a, g, rec, camR, camT, t, P);
                 double dd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
                 for (uint32_t k0 = 0;;) {
+                    const uint32_t bits = static_cast<uint32_t>(
+                        ((static_cast<uint64_t>(w1) << 32) | w0) >> ((base + k0) & 31u));
 #pragma unroll
                     for (uint32_t u = 0; u < PU; ++u)
-                        if (k0 + u < cnt)
+                        if (k0 + u < cnt && ((bits >> u) & 1u))
 #pragma unroll
                             for (int m = 0; m < PART; ++m) dd[m] += r[u][m];
                     k0 += PU;
