@@ -195,6 +195,43 @@ def test_clip_reduced_batch_matches_oracle(compact, batch, sort_cap):
         raster.set_tuning(old["batch"], old["sort_cap"], old["compact"], old["bwd_batch"])
 
 
+def test_poisoned_workspace_dense_scene():
+    """A dense, mostly opaque scene, where pixels stop early and most of a
+    tile's entries lie behind its last contributor: the adjoint writes partial
+    records only up to that point and the projection adjoint adds only the
+    records marked as written.  The workspace is filled with 0xFF bytes (NaN
+    floats, all-ones counters) before the call, so a stale record or any value
+    read before it is written would show in the images or the gradients."""
+    w = small_workload(52, 128, 96, 6000, 3, trajectory=True, z=(2.0, 8.0), ls=(-2.6, 0.2))
+    w["scene"].opacity_logits[:] += 3.0
+    refs = [oracle_frame(w, f) for f in range(w["frames"])]
+    sizes = np.concatenate([tile_buckets(w, f) for f in range(w["frames"])])
+    contrib = np.mean([r["n_contrib"].mean() for r in refs])
+    say(f"[poisoned ws] mean bucket {sizes.mean():.0f}, mean contributors per pixel {contrib:.1f}")
+    assert contrib < 0.3 * sizes.mean()
+    dl = upstream_for(w, refs, 5)
+    scene, cam, poses, times = device_inputs(w)
+    ws = workspace_for(scene, cam, poses, times)
+    ws.buf.fill_(255)
+    out = raster.render_batch(scene, cam, poses, times, ws, dL_dimages=torch.from_numpy(dl).cuda())
+    torch.cuda.synchronize()
+    assert ws.status()["overflow"] == 0
+    imgs = out["images"].cpu().numpy()
+    tally = PixelTally("poisoned ws")
+    crange = colour_range(w)
+    for f in range(w["frames"]):
+        compare_image(imgs[f], refs[f], f"poisoned ws frame {f}", crange, tally)
+    tally.finish()
+    g_ref, dposes_ref, _ = oracle.render_clip_grads(w["scene"], w["camera"], w["poses"].astype(np.float64),
+                                                    w["times"], range(w["frames"]), [None] * w["frames"],
+                                                    [planar_to_pixels(dl[f]) for f in range(w["frames"])])
+    for k, v in out["grads"].items():
+        if v is not None:
+            assert torch.isfinite(v).all(), k
+    compare_grads(out["grads"], g_ref, "poisoned ws")
+    compare_poses(out["dL_dposes"], dposes_ref, "poisoned ws")
+
+
 @pytest.mark.parametrize("compact", [12, 4, 8, 0, 20, 52])
 def test_alpha_clamp_paths(compact):
     """Opaque Gaussians (opacity above 0.99) on the left half of the scene:
