@@ -27,8 +27,8 @@ METRIC = "fwd+bwd frames/s at 960×540, 200k Gaussians (batched vs per-frame), %
 ODE_WORKLOAD = "clip540p_f100_n200k"
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
 # FP32 vector peaks: the published 157.3 TFLOP/s counts packed FP32 (two
-# operations per lane and instruction); this build disables packed FP32
-# instructions, so what it can issue is the non-packed rate,
+# operations per lane and instruction); the library is compiled without
+# packed FP32 instructions, so what it can issue is the non-packed rate,
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s.
 ALU_PEAK = 157.3e12
 ALU_PEAK_NONPACKED = 256 * 4 * 16 * 2 * 2.4e9
@@ -332,7 +332,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); the clip "
-              "would shard by frames across GPUs with one gradient all-reduce, which this build does not run.",
+              "would shard by frames across GPUs with one gradient all-reduce, which this library does not run.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -721,7 +721,7 @@ gv_status gv_autotune(const gv_scene* scene, const gv_camera* cam, const float* 
     float fwd_ms[NF] = {}, bwd_ms[NB] = {}, sort_ms[NS] = {};
     int fwd_n[NF] = {}, bwd_n[NB] = {}, sort_n[NS] = {};
     // Round-robin over the runs, so that clock or cache drift during the
-    // measurement affects all options alike; round 0 warms up.
+    // measurement affects all options alike; the first pass warms up.
     constexpr int REPS = 3;
     for (int r = 0; r <= REPS && result == GV_OK; ++r) {
         for (int c = 0; c < NF && result == GV_OK; ++c) {

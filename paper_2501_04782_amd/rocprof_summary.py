@@ -77,7 +77,7 @@ def cmd_stats(a):
     total = sum(sum(v) for v in d.values())
     rows = sorted(d.items(), key=lambda kv: -sum(kv[1]))
     print(f"# {a.title}\n")
-    print("Command (from the repository root on the GPU box):\n")
+    print("Command (from the repository root on the MI355X machine):\n")
     print("```\n" + a.command + "\n```\n")
     print("| kernel | calls | avg (ms) | total (ms) | % of GPU time |")
     print("|---|---|---|---|---|")
@@ -105,7 +105,7 @@ def cmd_traffic(a):
     w_kib = sum(write) / len(write)
     traffic = (f_kib * f_fac + w_kib * w_fac) * 1024.0
     print(f"# HBM traffic of `{a.kernel}` ({a.stage}), workload {a.workload}\n")
-    print("Commands (from the repository root on the GPU box, after `cd /tmp && export TMPDIR=/tmp`, "
+    print("Commands (from the repository root on the MI355X machine, after `cd /tmp && export TMPDIR=/tmp`, "
           "R = repository root):\n")
     print("```\n" + a.command + "\n```\n")
     print("| quantity | value |")
@@ -195,7 +195,7 @@ def cmd_kernel_counters(a):
         raise SystemExit(f"no dispatches of {a.kernel}")
     ms = sum(durs) / len(durs) / 1e6
     print(f"# SQ counters of `{a.kernel}` ({a.stage}), workload {a.workload}\n")
-    print("Commands (from the repository root on the GPU box, after `cd /tmp && export TMPDIR=/tmp`, "
+    print("Commands (from the repository root on the MI355X machine, after `cd /tmp && export TMPDIR=/tmp`, "
           "R = repository root):\n")
     print("```\n" + a.command + "\n```\n")
     print("| counter | per dispatch |")
@@ -243,7 +243,7 @@ def cmd_counters(a):
     dur = {k: sum(v) / len(v) for k, v in kernel_durations(a.trace).items()} if a.trace else {}
     cols = sorted({c for d in merged.values() for c in d})
     print(f"# {a.title}\n")
-    print("Commands (from the repository root on the GPU box):\n")
+    print("Commands (from the repository root on the MI355X machine):\n")
     print("```\n" + a.command + "\n```\n")
     print("Means per dispatch.  VALU share = SQ_INSTS_VALU x 4 cycles / (kernel time x 2.4 GHz x 1024 SIMDs).\n")
     print("| kernel | " + " | ".join(cols) + (" | avg ms | VALU share |" if dur else " |"))

@@ -1,7 +1,8 @@
-"""The oracle's tiled form against its per-pixel definition (the survey's
-pin T1): with each pixel visiting only the Gaussians whose footprint box meets
-its tile, colours, final transmittances, contributor counts, stakes and
-gradients are identical bit for bit, and decision margins are identical
+"""The oracle's tiled form against its per-pixel definition (an exact
+acceleration, the binning being conservative): with each pixel visiting only
+the Gaussians whose footprint box meets its tile, colours, final
+transmittances, contributor counts, stakes and gradients are identical bit
+for bit, and decision margins are identical
 wherever they are below 1e-3 (the only ones a comparison uses).  Tile sizes
 16, 8, 7 and 1, a tile larger than the image, ragged image sizes, adversarial
 scenes, dynamics and SH colour."""
