@@ -291,11 +291,12 @@ __global__ __launch_bounds__(WG) void k_composite_fwd(Args a) {
                 const float tn = __builtin_fmaf(-al, T, T);
                 const bool take = hit && tn >= T_MIN;  // else stop before this entry
                 done = done || (hit != take);
-                const float wgt = take ? al * T : 0.0f;
+                const float Tn = take ? tn : T;
+                const float wgt = T - Tn;  // alpha T to rounding; 0 when not taken
                 c0 = __builtin_fmaf(p1.z, wgt, c0);
                 c1 = __builtin_fmaf(p1.w, wgt, c1);
                 c2 = __builtin_fmaf(P2[r].x, wgt, c2);
-                T = take ? tn : T;
+                T = Tn;
                 loff = take ? static_cast<int>(jo[r]) : loff;
                 if (VIS && __ballot(take) != 0 && lane == 0) {
                     const uint32_t gid = __float_as_uint(staged_at(sh, jo[r]).p2.z);
@@ -467,11 +468,12 @@ __global__ __launch_bounds__(WGF4) __attribute__((amdgpu_waves_per_eu(4))) void 
                     const float tn = __builtin_fmaf(-al, T[k], T[k]);
                     const bool take = hit && tn >= T_MIN;  // else stop before this entry
                     done[k] = done[k] || (hit != take);
-                    const float wgt = take ? al * T[k] : 0.0f;
+                    const float Tn = take ? tn : T[k];
+                    const float wgt = T[k] - Tn;  // alpha T to rounding; 0 when not taken
                     c0[k] = __builtin_fmaf(p1.z, wgt, c0[k]);
                     c1[k] = __builtin_fmaf(p1.w, wgt, c1[k]);
                     c2[k] = __builtin_fmaf(P2[r].x, wgt, c2[k]);
-                    T[k] = take ? tn : T[k];
+                    T[k] = Tn;
                     loff[k] = take ? static_cast<int>(J[r]) : loff[k];
                 }
             }
@@ -1457,7 +1459,7 @@ __global__ __launch_bounds__(WG) void k_composite_fwd_c(Args a) {
                     done = true;
                     break;
                 }
-                const float wgt = al * T;
+                const float wgt = T - tn;  // alpha T to rounding, as in the other forwards
                 c0 = __builtin_fmaf(sv[6][j], wgt, c0);
                 c1 = __builtin_fmaf(sv[7][j], wgt, c1);
                 c2 = __builtin_fmaf(sv[8][j], wgt, c2);
@@ -1736,11 +1738,12 @@ __global__ __launch_bounds__(WG) void k_composite_fwd_sb(Args a) {
                 const float tn = __builtin_fmaf(-al, T, T);
                 const bool take = hit && tn >= T_MIN;  // else stop before this entry
                 done = done || (hit != take);
-                const float wgt = take ? al * T : 0.0f;
+                const float Tn = take ? tn : T;
+                const float wgt = T - Tn;  // alpha T to rounding; 0 when not taken
                 c0 = __builtin_fmaf(p1.z, wgt, c0);
                 c1 = __builtin_fmaf(p1.w, wgt, c1);
                 c2 = __builtin_fmaf(P2[r].x, wgt, c2);
-                T = take ? tn : T;
+                T = Tn;
                 loff = take ? static_cast<int>(jo[r]) : loff;
                 if (VIS) {
                     const uint64_t bal = __ballot(take);
