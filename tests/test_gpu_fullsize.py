@@ -10,6 +10,8 @@ final transmittance, losses and all gradients are compared at full size.
   capacity 512, where every bucket above 1024 entries takes the global-merge
   path of the per-tile sort;
 * the 32-frame 1920x1080 clip of 500k bf16 Gaussians with cubic means;
+* the B-spline dynamics and SH-colour clips (50 frames at 960x540), on five
+  whole frames each;
 * the camera-ODE fitting step (100 frames: ODE forward -> batched raster
   fwd+bwd -> ODE adjoint in one graph), with the trajectory error of the
   learned camera against the ground-truth pose table;
@@ -191,6 +193,37 @@ def test_clip1080p_bf16_cubic_full_size():
     ge = compare_grads(out["grads"], g_ref, "clip1080p", mag=mag)
     pe = compare_poses(out["dL_dposes"], dposes_ref, "clip1080p")
     say(f"[clip1080p] grads={ge} pose={pe:.2e} intersections={ws.status()['intersections']}")
+
+
+@pytest.mark.parametrize("name", ["clip540p_f50_n200k_dyn", "clip540p_f50_n200k_sh3"])
+def test_dynamics_and_sh_clips_full_size(name):
+    """The clips of the B-spline dynamics (Eq. 2-3: cubic B-spline means over
+    8 control points, polynomial log-scales and quaternions) and of SH colour
+    of degree 3 at full size (50 frames at 960x540, 200k Gaussians), in the
+    launch configuration bench.py times: every pixel of five whole frames
+    spread over the clip against the oracle, and every gradient for an
+    upstream gradient on those frames (zero on the others, so the sums over
+    frames cover exactly them)."""
+    w = gv_synth.make_workload(name, targets=False)
+    frames = (0, 12, 24, 37, w["frames"] - 1)
+    refs = [oracle_frame(w, f, tile=TILE) for f in frames]
+    H, W = w["camera"].height, w["camera"].width
+    rng = np.random.default_rng(50)
+    dls = []
+    dl = np.zeros((w["frames"], 3, H * W), np.float32)
+    for f, r in zip(frames, refs):
+        d = rng.normal(0, 1, (H * W, 3)).astype(np.float32).astype(np.float64)
+        d[held(r)] = 0.0
+        dls.append(d)
+        dl[f] = d.T
+    say(f"[{name}] gpu batch")
+    out, ws, _ = run_clip(w, dl=dl.reshape(w["frames"], 3, H, W))
+    check_frames(out["images"].cpu().numpy()[list(frames)], refs, w, name)
+    say(f"[{name}] oracle backward on frames {frames}")
+    g_ref, dposes_ref, mag = oracle_clip_grads(w, dls, frames=frames, tile=TILE)
+    ge = compare_grads(out["grads"], g_ref, name, mag=mag)
+    pe = compare_poses(out["dL_dposes"], dposes_ref, name)
+    say(f"[{name}] grads={ge} pose={pe:.2e} intersections={ws.status()['intersections']}")
 
 
 def test_camera_ode_fitting_step_full_size():
