@@ -85,6 +85,7 @@ Layout make_layout(const gv_camera& cam, int64_t n, int frames, int64_t k_cap) {
     L.tfin = take(4 * static_cast<size_t>(frames) * L.pixels);
     L.nlast = take(4 * static_cast<size_t>(frames) * L.pixels);
     L.loss_part = take(4 * static_cast<size_t>(FT));
+    L.shapes = take(sizeof(ShapeD) * static_cast<size_t>(n));
     L.pose_part = take(8 * 12 * static_cast<size_t>(L.pose_blocks) * frames);
     L.intr_part = take(8 * 4 * static_cast<size_t>(L.pose_blocks));
     L.vis = take((static_cast<size_t>(FN) + 3) / 4 * 4);
@@ -212,6 +213,7 @@ static gv_status make_args(const gv_scene* s, const gv_camera* c, int frames, co
     a.tfin = reinterpret_cast<float*>(b + L.tfin);
     a.nlast = reinterpret_cast<uint32_t*>(b + L.nlast);
     a.loss_part = reinterpret_cast<float*>(b + L.loss_part);
+    a.shapes = reinterpret_cast<ShapeD*>(b + L.shapes);
     a.pose_part = reinterpret_cast<double*>(b + L.pose_part);
     a.intr_part = reinterpret_cast<double*>(b + L.intr_part);
     a.kv = reinterpret_cast<KeySlot*>(b + L.kv);

@@ -88,7 +88,7 @@ struct Layout {
     int64_t pose_blocks;   // workgroups of the projection adjoint (upper bound)
     int64_t bin_blocks;    // workgroups per frame of the LDS-histogram binning (0: global atomics)
     size_t status, col4, rec, rect, tmask, gcnt, goff, tcnt, toff, tcur, bhist, scan_tmp, tfin, nlast, loss_part, pose_part,
-        intr_part, vis,
+        intr_part, vis, shapes,
         kv, sgid, sslot, part, pused, tkv;
     size_t total;
 };
@@ -96,6 +96,18 @@ struct Layout {
 Layout make_layout(const gv_camera& cam, int64_t n, int frames, int64_t k_cap);
 
 // Everything a kernel needs, passed by value.
+// Frame-independent part of a static Gaussian's projection, computed once
+// per call (k_static_shapes) with the very operations project_gaussian would
+// repeat in every frame: 3D covariance and opacity, whether the shape's
+// parameters (log-scales, quaternion, opacity logit, colour) are finite, and
+// whether the quaternion has a nonzero norm.
+struct ShapeD {
+    double Sig[6];
+    double o;
+    uint32_t fin, qn_ok;
+};
+static_assert(sizeof(ShapeD) == 64, "one 64-byte record per Gaussian");
+
 struct Args {
     // scene
     int64_t n;
@@ -146,6 +158,7 @@ struct Args {
     uint32_t* sslot;      // [K]
     float* part;          // [K][PART] (du, dv, dA00, dA01, dA11, do, dr, dg, db) per pre-sort slot
     uint32_t* pused;      // [K/32 + 2] bit per pre-sort slot: its partial record was written this pass
+    ShapeD* shapes;       // [N] static shapes of this call (scenes without dynamics or SH), or nullptr
     KeySlot* tkv;         // [K] merge scratch of the sort
     int64_t k_cap;
     // image-space inputs/outputs
@@ -356,6 +369,34 @@ struct ProjD {
     bool nonfinite;
 };
 
+// q-norm, unit quaternion, scales, opacity, R and Sigma = (R S)(R S)^T
+// (Sec. 3.1) of a Gaussian from its raw parameters (raw[3..5] log-scales,
+// raw[6..9] quaternion, raw[10] opacity logit); false if the quaternion's
+// norm is not positive.  The per-frame projection and the once-per-call
+// static shapes share it, so both give the same values.
+__device__ __forceinline__ bool shape_from_params(const double* raw, ProjD& P) {
+    P.qn = sqrt(raw[6] * raw[6] + raw[7] * raw[7] + raw[8] * raw[8] + raw[9] * raw[9]);
+    if (!(P.qn > 0.0)) return false;
+    for (int k = 0; k < 4; ++k) P.qh[k] = raw[6 + k] / P.qn;
+    for (int k = 0; k < 3; ++k) P.s[k] = exp(raw[3 + k]);
+    P.eta = raw[10];
+    P.o = 1.0 / (1.0 + exp(-raw[10]));
+    rot_from_quat(P.qh[0], P.qh[1], P.qh[2], P.qh[3], P.R);
+    // Sigma = M M^T with M = R diag(s)
+    double M[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M[i * 3 + j] = P.R[i * 3 + j] * P.s[j];
+    P.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+    P.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+    P.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+    P.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+    P.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+    P.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+    return true;
+}
+
+__device__ __forceinline__ bool project_shaped(const Args& a, const CamD& cam, ProjD& P);
+
 // Returns true if the Gaussian is in front of the near plane with a valid
 // footprint.  P.nonfinite marks non-finite inputs.  EXT compiles in the
 // optional B-spline / polynomial dynamics and the SH colour (the static
@@ -441,25 +482,41 @@ __device__ __forceinline__ bool project_gaussian(const Args& a, int64_t g, const
     }
     P.nonfinite = !fin;
     if (!fin || !cam.ok || !in_domain) return false;
-    P.qn = sqrt(raw[6] * raw[6] + raw[7] * raw[7] + raw[8] * raw[8] + raw[9] * raw[9]);
-    if (!(P.qn > 0.0)) return false;
-    for (int k = 0; k < 4; ++k) P.qh[k] = raw[6 + k] / P.qn;
-    for (int k = 0; k < 3; ++k) P.s[k] = exp(raw[3 + k]);
-    P.eta = raw[10];
-    P.o = 1.0 / (1.0 + exp(-raw[10]));
-    rot_from_quat(P.qh[0], P.qh[1], P.qh[2], P.qh[3], P.R);
-    {
-        // Sigma = M M^T with M = R diag(s)
-        double M[9];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) M[i * 3 + j] = P.R[i * 3 + j] * P.s[j];
-        P.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
-        P.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
-        P.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
-        P.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
-        P.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
-        P.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+    if (!shape_from_params(raw, P)) return false;
+    return project_shaped(a, cam, P);
+}
+
+// The static path with the frame-independent shape precomputed (a.shapes):
+// only the mean (and its cubic in t) is read per frame.
+__device__ __forceinline__ bool project_gaussian_shaped(const Args& a, int64_t g, const CamD& cam, double t,
+                                                        ProjD& P) {
+    const int64_t n = a.n;
+    const ShapeD& S = a.shapes[g];
+    bool fin = S.fin != 0u;
+    for (int k = 0; k < 3; ++k) {
+        double mu = load_param(a.means, a.dtype, k * n + g);
+        fin = fin && isfinite(mu);
+        if (a.mean_coeffs) {
+            const double c1 = load_param(a.mean_coeffs, a.dtype, (0 * 3 + k) * n + g);
+            const double c2 = load_param(a.mean_coeffs, a.dtype, (1 * 3 + k) * n + g);
+            const double c3 = load_param(a.mean_coeffs, a.dtype, (2 * 3 + k) * n + g);
+            fin = fin && isfinite(c1) && isfinite(c2) && isfinite(c3);
+            // same left-to-right order as mu0 + a1 t + a2 t t + a3 t t t
+            mu = mu + c1 * t + c2 * t * t + c3 * t * t * t;
+        }
+        P.mu[k] = mu;
     }
+    P.nonfinite = !fin;
+    if (!fin || !cam.ok) return false;
+    if (!S.qn_ok) return false;
+    for (int k = 0; k < 6; ++k) P.Sig[k] = S.Sig[k];
+    P.o = S.o;
+    return project_shaped(a, cam, P);
+}
+
+// Camera-space mean, perspective projection, 2D covariance and conic of a
+// Gaussian whose mean (P.mu) and 3D covariance (P.Sig) are set.
+__device__ __forceinline__ bool project_shaped(const Args& a, const CamD& cam, ProjD& P) {
     const double* Rc = cam.R;
     // m = tc + Rc mu, summed in this order (with no contraction the fp32
     // rounding of m_z, the depth sort key, is then reproducible bit for bit)

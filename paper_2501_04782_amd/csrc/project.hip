@@ -10,6 +10,30 @@
 
 namespace gv {
 
+// The frame-independent shape of every Gaussian of a static scene (no
+// dynamics, no SH), once per call instead of once per frame.
+__global__ __launch_bounds__(256) void k_static_shapes(Args a) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= a.n) return;
+    const int64_t n = a.n;
+    double raw[14];
+    for (int k = 0; k < 3; ++k) raw[k] = 0.0;
+    for (int k = 0; k < 3; ++k) raw[3 + k] = load_param(a.log_scales, a.dtype, k * n + g);
+    for (int k = 0; k < 4; ++k) raw[6 + k] = load_param(a.quats, a.dtype, k * n + g);
+    raw[10] = load_param(a.opacity_logits, a.dtype, g);
+    for (int k = 0; k < 3; ++k) raw[11 + k] = load_param(a.colors, a.dtype, k * n + g);
+    bool fin = true;
+    for (int k = 3; k < 14; ++k) fin = fin && isfinite(raw[k]);
+    ShapeD S;
+    ProjD P;
+    const bool ok = fin && shape_from_params(raw, P);
+    for (int k = 0; k < 6; ++k) S.Sig[k] = ok ? P.Sig[k] : 0.0;
+    S.o = ok ? P.o : 0.0;
+    S.fin = fin ? 1u : 0u;
+    S.qn_ok = ok ? 1u : 0u;
+    a.shapes[g] = S;
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t count) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < count) p[i] = value;
@@ -52,7 +76,10 @@ __device__ __forceinline__ bool project_one(const Args& a, int f, int64_t g, con
         a.col4[g] = co;
     }
     ProjD P;
-    const bool vis = project_gaussian<EXT>(a, g, cam, t, P);
+    // the static instantiation takes the shapes launch_project computed first
+    bool vis;
+    if constexpr (EXT) vis = project_gaussian<true>(a, g, cam, t, P);
+    else vis = project_gaussian_shaped(a, g, cam, t, P);
     if (EXT && vis && a.sh_degree > 0) {
         ColorOp co;
         co.r = static_cast<float>(P.col[0]);
@@ -507,6 +534,8 @@ hipError_t launch_project(const Args& a, hipStream_t stream) {
     if (a.n <= 0) return hipSuccess;
     const bool ext = a.n_ctrl > 0 || a.scale_coeffs || a.quat_coeffs || a.sh_degree > 0;
     const dim3 block(256);
+    if (!ext)
+        hipLaunchKernelGGL(k_static_shapes, dim3(static_cast<uint32_t>((a.n + 255) / 256)), block, 0, stream, a);
     if (a.bhist) {
         const dim3 grid(static_cast<uint32_t>(a.bin_blocks), a.frames);
         const size_t lds = sizeof(uint32_t) * ((a.tiles + 1) / 2);
