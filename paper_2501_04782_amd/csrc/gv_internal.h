@@ -399,8 +399,9 @@ __device__ __forceinline__ bool project_shaped(const Args& a, const CamD& cam, P
 
 // Returns true if the Gaussian is in front of the near plane with a valid
 // footprint.  P.nonfinite marks non-finite inputs.  EXT compiles in the
-// optional B-spline / polynomial dynamics and the SH colour (the static
-// instantiation keeps the register budget of the common case).
+// optional B-spline / polynomial dynamics and the SH colour; the projection
+// kernel takes project_gaussian_shaped instead for scenes without them, whose
+// frame-independent shape is precomputed once per call.
 template <bool EXT>
 __device__ __forceinline__ bool project_gaussian(const Args& a, int64_t g, const CamD& cam, double t, ProjD& P) {
     const int64_t n = a.n;
