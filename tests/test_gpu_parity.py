@@ -268,7 +268,9 @@ def test_alpha_clamp_paths(compact):
 @pytest.mark.parametrize("n,cap,regime,compact", [(5000, 1024, "global", 4), (1600, 1024, "two runs", 4),
                                                   (3000, 4096, "one pass", 4), (1600, 512, "global", 4),
                                                   (5000, 1024, "global", 6), (5000, 1024, "global", 12),
-                                                  (1600, 512, "global", 12), (5000, 1024, "global", 20)])
+                                                  (1600, 512, "global", 12), (5000, 1024, "global", 20),
+                                                  (3000, 2048, "two runs", 52), (5000, 2048, "global", 52),
+                                                  (5000, 4096, "two runs", 52), (9000, 4096, "global", 52)])
 def test_long_tile_buckets(n, cap, regime, compact):
     """Many large Gaussians over a small image: buckets beyond the LDS sort
     capacity, between one and two capacities, and within the largest one."""
