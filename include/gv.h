@@ -205,7 +205,7 @@ gv_status gv_render_fwd(const gv_scene *scene, const gv_camera *cam, const float
  * the library, one per GPU (each device holds its own copy until the process
  * ends).  Arguments, outputs, the one synchronisation and the error codes are
  * those of gv_render_fwd, plus: GV_ERR_WORKSPACE (nothing enqueued) when the
- * frame's fixed arrays exceed the scratch (about 137 B per Gaussian, 8 B per
+ * frame's fixed arrays exceed the scratch (about 141 B per Gaussian, 8 B per
  * pixel and 12 B per 16x16 tile), GV_ERR_CAPACITY when its (Gaussian, tile)
  * intersections do not fit in the rest (76 B and one bit each).  All calls on one GPU
  * share that GPU's array: calls that overlap on one GPU (from different

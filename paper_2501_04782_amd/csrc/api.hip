@@ -73,6 +73,7 @@ Layout make_layout(const gv_camera& cam, int64_t n, int frames, int64_t k_cap) {
     L.status = take(ST_WORDS * sizeof(uint32_t));
     L.col4 = take(sizeof(ColorOp) * static_cast<size_t>(FN));  // per frame: view-dependent colour
     L.rec = take(sizeof(Record) * static_cast<size_t>(FN));
+    L.dkey = take(4 * static_cast<size_t>(FN));
     L.tmask = take(8 * static_cast<size_t>(FN));
     L.rect = take(sizeof(uint2) * static_cast<size_t>(FN));
     L.gcnt = take(4 * static_cast<size_t>(FN));
@@ -201,6 +202,7 @@ static gv_status make_args(const gv_scene* s, const gv_camera* c, int frames, co
     a.col4 = reinterpret_cast<ColorOp*>(b + L.col4);
     a.col_stride = s->sh_degree > 0 ? s->n : 0;
     a.rec = reinterpret_cast<Record*>(b + L.rec);
+    a.dkey = reinterpret_cast<float*>(b + L.dkey);
     a.rect = reinterpret_cast<uint2*>(b + L.rect);
     a.tmask = reinterpret_cast<uint64_t*>(b + L.tmask);
     a.gcnt = reinterpret_cast<uint32_t*>(b + L.gcnt);

@@ -87,7 +87,7 @@ struct Layout {
     int64_t scan_blocks;   // for the (frames*n) scan
     int64_t pose_blocks;   // workgroups of the projection adjoint (upper bound)
     int64_t bin_blocks;    // workgroups per frame of the LDS-histogram binning (0: global atomics)
-    size_t status, col4, rec, rect, tmask, gcnt, goff, tcnt, toff, tcur, bhist, scan_tmp, tfin, nlast, loss_part, pose_part,
+    size_t status, col4, rec, dkey, rect, tmask, gcnt, goff, tcnt, toff, tcur, bhist, scan_tmp, tfin, nlast, loss_part, pose_part,
         intr_part, vis, shapes,
         kv, sgid, sslot, part, pused, tkv;
     size_t total;
@@ -137,6 +137,7 @@ struct Args {
     ColorOp* col4;        // [F][N] (colour seen from each frame's camera) when view-dependent, else [N]
     int64_t col_stride;   // N with view-dependent colour, else 0: frame f reads col4[f * col_stride + g]
     Record* rec;          // [F][N]
+    float* dkey;          // [F][N]: the record's depth alone, for the scatter's keys
     uint2* rect;          // [F][N]: (x0 | x1 << 16, y0 | y1 << 16) in tiles
     uint64_t* tmask;      // [F][N]: tiles that passed the ellipse test, row-major bits over the rectangle
                           // (rectangles of at most 64 tiles; larger ones are tested again by the scatter)

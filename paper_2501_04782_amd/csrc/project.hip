@@ -105,6 +105,7 @@ __device__ __forceinline__ bool project_one(const Args& a, int f, int64_t g, con
     if (!tile_span(P.u - hx, P.u + hx, a.tiles_x, tx0, tx1) || !tile_span(P.v - hy, P.v + hy, a.tiles_y, ty0, ty1))
         return false;
     a.rec[i] = r;
+    a.dkey[i] = r.depth;
     a.rect[i] = make_uint2(static_cast<uint32_t>(tx0) | (static_cast<uint32_t>(tx1) << 16),
                            static_cast<uint32_t>(ty0) | (static_cast<uint32_t>(ty1) << 16));
     S.u = r.u;
@@ -297,8 +298,8 @@ __device__ __forceinline__ void emit_key(const Args& a, uint64_t key, uint32_t s
 }
 
 // Key (fp32 depth bits << 32 | Gaussian index) of (f, g).
-__device__ __forceinline__ uint64_t sort_key(const Record& r, int64_t g) {
-    return (static_cast<uint64_t>(__float_as_uint(r.depth)) << 32) | static_cast<uint64_t>(g);
+__device__ __forceinline__ uint64_t sort_key(float depth, int64_t g) {
+    return (static_cast<uint64_t>(__float_as_uint(depth)) << 32) | static_cast<uint64_t>(g);
 }
 
 // Intersections of a Gaussian whose rectangle exceeds 64 tiles (no mask):
@@ -306,7 +307,7 @@ __device__ __forceinline__ uint64_t sort_key(const Record& r, int64_t g) {
 template <typename Next, typename End>
 __device__ __forceinline__ void scatter_big(const Args& a, int64_t g, const Record& r, const BinShape& S,
                                             uint32_t cnt, uint32_t goff, Next next, End end) {
-    const uint64_t key = sort_key(r, g);
+    const uint64_t key = sort_key(r.depth, g);
     uint32_t k = 0;
     for (int ty = S.ty0; ty < S.ty0 + S.rh; ++ty)
         for (int tx = S.tx0; tx < S.tx0 + S.rw; ++tx)
@@ -381,13 +382,13 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
     auto end = [&](int) { return static_cast<uint32_t>(a.k_cap); };
     const int64_t g0 = static_cast<int64_t>(blockIdx.x) * BIN_GROUP;
     WaveKeys& W = wk[w];
-    // A Gaussian's count, record, rectangle, mask and slot offset, requested
+    // A Gaussian's count, depth, rectangle, mask and slot offset, requested
     // together (one memory round trip; a Gaussian without intersections
     // ignores them), and the next round's requested before this round's keys
-    // are dealt out.
+    // are dealt out.  Only a Gaussian too large for a mask reads its record.
     struct In {
         uint32_t cnt;
-        Record r;
+        float depth;
         uint2 rc;
         uint64_t tm;
         uint32_t go;
@@ -396,20 +397,20 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
         const int64_t g = g0 + k * 256 + threadIdx.x;
         const int64_t i = static_cast<int64_t>(f) * a.n + (g < a.n ? g : 0);
         x.cnt = g < a.n ? a.gcnt[i] : 0u;
-        x.r = a.rec[i];
+        x.depth = a.dkey[i];
         x.rc = a.rect[i];
         x.tm = a.tmask[i];
         x.go = a.goff[i];
     };
     In nxt;
     load_in(0, nxt);
+    uint32_t big = 0u;  // rounds whose Gaussian has no mask, scattered after the loop
 #pragma unroll 1
     for (int k = 0; k < BIN_GROUP / 256; ++k) {
         const int64_t g = g0 + k * 256 + threadIdx.x;
         const In cur = nxt;
         if (k + 1 < BIN_GROUP / 256) load_in(k + 1, nxt);
         const uint32_t cnt = cur.cnt;
-        const Record& r = cur.r;
         const uint2 rc = cur.rc;
         const uint64_t tm = cur.tm;
         const uint32_t go = cur.go;
@@ -420,7 +421,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
         W.start[lane] = start;
         if (small) {
             W.mask[lane] = tm;
-            W.key[lane] = sort_key(r, g);
+            W.key[lane] = sort_key(cur.depth, g);
             W.goff[lane] = go;
             W.tx0[lane] = rc.x & 0xffff;
             W.ty0[lane] = rc.y & 0xffff;
@@ -443,7 +444,16 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
             }
         }
         __builtin_amdgcn_wave_barrier();
-        if (cnt && !small) scatter_big(a, g, r, shape_from_record(r, rc), cnt, go, next, end);
+        if (cnt && !small) big |= 1u << k;
+    }
+    // out of the pipelined loop, whose registers the rectangle walk would add to
+    while (big) {
+        const int k = __builtin_ctz(big);
+        big &= big - 1u;
+        const int64_t g = g0 + k * 256 + threadIdx.x;
+        const int64_t i = static_cast<int64_t>(f) * a.n + g;
+        const Record r = a.rec[i];
+        scatter_big(a, g, r, shape_from_record(r, a.rect[i]), a.gcnt[i], a.goff[i], next, end);
     }
 }
 
