@@ -171,6 +171,22 @@ def test_empty_and_single_gaussian():
             check_clip_against_oracle(w, "single Gaussian")
 
 
+def test_rectangles_beyond_the_tile_mask():
+    """Gaussians whose tile rectangle exceeds 64 tiles have no tile mask: the
+    count pass and the scatter re-test their rectangles cell by cell.  Four
+    large Gaussians near the centre of the 12 x 10-tile image (3-sigma half
+    widths of 67-99 px, rectangles of about 90-120 tiles) lie among 500
+    ordinary ones in front of and behind them, over two frames of a moving
+    camera."""
+    w = small_workload(31, 192, 160, 504, 2, trajectory=True, bg=(0.1, 0.3, 0.2))
+    s = w["scene"]
+    for k, (x, y, z) in enumerate([(0.0, 0.0, 3.0), (0.2, -0.1, 3.5), (-0.3, 0.2, 4.0), (0.1, 0.3, 4.5)]):
+        s.means[:, k] = [x, y, z]
+        s.log_scales[:, k] = [np.log(0.5 + 0.1 * k), np.log(0.45), np.log(0.4 + 0.05 * k)]
+        s.opacity_logits[k] = -1.0  # opacity 0.27: what lies behind still shows
+    check_clip_against_oracle(w, "rectangles beyond the tile mask")
+
+
 # compact: 0 sub-block forward, 4 quadrant forward, 1 compacted forward, + 32
 # one-wave-per-tile forward;
 # + 2 compacted backward, + 16 one-wave-per-tile backward, + 8 paired-quadrant
