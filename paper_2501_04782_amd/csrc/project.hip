@@ -404,6 +404,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(Args a) {
     };
     In nxt;
     load_in(0, nxt);
+    static_assert(BIN_GROUP / 256 <= 32, "one bit per round");
     uint32_t big = 0u;  // rounds whose Gaussian has no mask, scattered after the loop
 #pragma unroll 1
     for (int k = 0; k < BIN_GROUP / 256; ++k) {
